@@ -1,0 +1,228 @@
+/*
+ * qc.h — C ABI of libqc.so, a dense state-vector simulator for AMD MI355X
+ * (gfx950).
+ *
+ * The operations follow the circuit model of QCLAB (Keip, Camps,
+ * Van Beeumen, "QCLAB: A Matlab Toolbox for Quantum Computing", 2025):
+ * a register of n qubits holds 2^n complex amplitudes, gates act as
+ * I_l (x) U' (x) I_r (section 3.2), measurement probabilities are sums of
+ * |amplitude|^2 over the indices of an outcome (section 3.3).
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * - Qubit labels are the paper's: qubit 0 is the leftmost Kronecker factor,
+ *   i.e. bit n-1 of the amplitude index; qubit q is bit n-1-q (section 3.1,
+ *   and the teleportation input kron(v, bell) of section 5.1).
+ * - A state is a caller-owned, contiguous device buffer of 2^n amplitudes,
+ *   interleaved (re, im): float pairs for QC_C64, double pairs for QC_C128.
+ *   The library borrows it for the duration of the enqueued work; it never
+ *   allocates, frees or resizes a state.
+ * - Gate matrices are HOST arrays of FP64, row-major, interleaved:
+ *   u[2*(r*d + c)] and u[2*(r*d + c) + 1] are the real and imaginary parts
+ *   of U[r][c], d = 2^k.  The local basis index r takes its most significant
+ *   bit from the first listed qubit.  Matrices are consumed (converted and
+ *   staged) before the call returns; the caller may reuse them at once.
+ *   The library does not check unitarity.
+ * - Reduction outputs are DEVICE FP64 buffers owned by the caller; their
+ *   values are valid once `stream` reaches the call.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Every call is asynchronous with respect to the host, except where noted.
+ * - Every call returns a status (QC_OK = 0 or a negative QC_ERR_* code).
+ *   Arguments are validated on the host before anything is enqueued: a call
+ *   that fails validation enqueues nothing and leaves the state untouched.
+ *   qc_last_error() gives a human-readable reason (per host thread).
+ *   No C++ exception crosses this interface.
+ * - The library owns a small per-device workspace (reduction partials and a
+ *   staging ring for matrices), allocated on first use.  Calls that use it
+ *   must not run concurrently on different streams of the same device.
+ */
+#ifndef QC_H_
+#define QC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- element types -------------------------------------------------- */
+#define QC_C64  1   /* complex64: two float32 per amplitude  */
+#define QC_C128 2   /* complex128: two float64 per amplitude */
+
+/* ---- status codes --------------------------------------------------- */
+#define QC_OK               0
+#define QC_ERR_ARG         -1   /* malformed argument (null pointer, size) */
+#define QC_ERR_QUBIT       -2   /* qubit label out of range or repeated    */
+#define QC_ERR_DTYPE       -3   /* unknown or mismatched element type      */
+#define QC_ERR_UNSUPPORTED -4   /* valid request this build does not serve */
+#define QC_ERR_HIP         -5   /* HIP runtime error (see qc_last_error)   */
+#define QC_ERR_NOMEM       -6   /* workspace allocation failed             */
+
+/* Largest register the library accepts (2^36 amplitudes). */
+#define QC_MAX_QUBITS 36
+/* Largest gate handled by the fused path (2^5 x 2^5 matrices). */
+#define QC_MAX_FUSED 5
+/* Most control qubits on one gate. */
+#define QC_MAX_CTRLS 16
+
+/* A borrowed view of a caller-owned state vector. */
+typedef struct {
+    void   *amp;    /* device pointer, 2^n interleaved complex amplitudes */
+    int32_t n;      /* number of qubits, 1..QC_MAX_QUBITS                 */
+    int32_t dtype;  /* QC_C64 or QC_C128                                  */
+} qc_state_t;
+
+/* One gate of a circuit handed to qc_apply_circuit / qc_fuse_plan.
+ * Register operator: Pc (x) U + (I - Pc) (x) I, with U on `targets`
+ * (targets[0] = most significant bit of U's local index) and Pc the
+ * projector onto ctrls[j] == ctrl_vals[j] for all j (a value of 0 is an
+ * "open" control, as in the MCX gates of section 5.4). */
+typedef struct {
+    int32_t n_targets;                 /* 1..QC_MAX_FUSED                */
+    int32_t n_ctrls;                   /* 0..QC_MAX_CTRLS                */
+    int32_t targets[QC_MAX_FUSED];
+    int32_t ctrls[QC_MAX_CTRLS];
+    int32_t ctrl_vals[QC_MAX_CTRLS];   /* 0 or 1                         */
+    const double *matrix;              /* host, 2^n_targets square, FP64 */
+} qc_gate_t;
+
+/* Execution strategies for qc_apply_circuit. */
+#define QC_EXEC_UNFUSED 0   /* one launch (one state sweep) per gate          */
+#define QC_EXEC_FUSED   1   /* fuse into <= fuse_k-qubit blocks (FP64 products),
+                               one sweep per block                            */
+
+/* Counters filled by qc_apply_circuit (may be NULL). */
+typedef struct {
+    int64_t gates;          /* gates in the input list                      */
+    int64_t launches;       /* kernels enqueued                             */
+    int64_t sweeps;         /* full passes over the state                   */
+    int64_t fused_blocks;   /* dense blocks applied (QC_EXEC_FUSED)         */
+    double  state_bytes;    /* algorithmic HBM bytes of all sweeps          */
+} qc_exec_stats_t;
+
+/* Gate kinds of a parametrised program (qc_adjoint_grad). */
+#define QC_OP_RX   1    /* exp(-i t X / 2) on q0, t = theta[param]        */
+#define QC_OP_RY   2    /* exp(-i t Y / 2) on q0                          */
+#define QC_OP_RZ   3    /* exp(-i t Z / 2) on q0                          */
+#define QC_OP_H    4    /* Hadamard on q0                                 */
+#define QC_OP_X    5
+#define QC_OP_Y    6
+#define QC_OP_Z    7
+#define QC_OP_CZ   8    /* controlled Z on (q0, q1)                       */
+#define QC_OP_CNOT 9    /* control q0, target q1                          */
+
+typedef struct {
+    int32_t kind;   /* QC_OP_*                                          */
+    int32_t q0;     /* first qubit                                      */
+    int32_t q1;     /* second qubit (two-qubit kinds), else ignored     */
+    int32_t param;  /* index into theta for RX/RY/RZ, else ignored      */
+} qc_op_t;
+
+/* ---- diagnostics ---------------------------------------------------- */
+
+/* Static string for a status code. */
+const char *qc_status_string(int status);
+/* Reason for the last failing call on this host thread ("" if none). */
+const char *qc_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int qc_version(void);
+
+/* ---- state preparation (section 3.1 "Initialization") --------------- */
+
+/* s := |basis_index>, the basis state whose index bits are the qubit
+ * values (qubit 0 = most significant).  QC_ERR_ARG if
+ * basis_index >= 2^n. */
+int qc_state_init(qc_state_t s, uint64_t basis_index, void *stream);
+
+/* dst := src, converting precision when the element types differ (FP64 ->
+ * FP32 rounds to nearest).  Both states must have the same n and must not
+ * overlap. */
+int qc_state_copy(qc_state_t dst, qc_state_t src, void *stream);
+
+/* Error report of a against a reference b (same n, any element types):
+ * out_dev[0] = sum |a_i - b_i|^2, out_dev[1] = sum |b_i|^2,
+ * out_dev[2] = max_i |a_i - b_i|, all accumulated in FP64.  Deterministic. */
+int qc_state_diff(qc_state_t a, qc_state_t b, double *out_dev, void *stream);
+
+/* ---- gate application (section 3.2 "Application of Gates") ---------- */
+
+/* psi := (I_l (x) U (x) I_r) psi for a 2x2 U on qubit q (u: 8 doubles). */
+int qc_apply_1q(qc_state_t s, int q, const double *u, void *stream);
+
+/* Two-qubit gate: U (4x4, 32 doubles) on qubits (qa, qb), any two distinct
+ * qubits in either order; qa is the most significant bit of U's index. */
+int qc_apply_2q(qc_state_t s, int qa, int qb, const double *u, void *stream);
+
+/* Multi-controlled one-qubit gate: U acts on `target` in the subspace where
+ * every ctrl[j] equals ctrl_val[j] (0 or 1; 0 = open control), identity
+ * elsewhere.  This covers CNOT, CZ, CP and the MCX gates of section 5.4.
+ * A diagonal U with U[0][0] == 1 only rescales the target-1 part of the
+ * control subspace and touches no other amplitude. */
+int qc_apply_controlled(qc_state_t s, int n_ctrl, const int *ctrl, const int *ctrl_val,
+                        int target, const double *u, void *stream);
+
+/* Dense k-qubit gate, 1 <= k <= QC_MAX_FUSED: U (2^k x 2^k) on the listed
+ * qubits (qubits[0] = most significant bit of U's index).  For QC_C64 and
+ * k >= 3 the product runs on FP32 matrix cores (MFMA); FP64 on the vector
+ * units otherwise. */
+int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, void *stream);
+
+/* Apply a gate list in order.  mode QC_EXEC_UNFUSED launches one kernel per
+ * gate; QC_EXEC_FUSED first groups consecutive gates into blocks of at most
+ * fuse_k qubits (host FP64 matrix products, see qc_fuse_plan) and applies
+ * each block with qc_apply_fused_k.  stats may be NULL. */
+int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode,
+                     int fuse_k, qc_exec_stats_t *stats, void *stream);
+
+/* Host-only planning step of QC_EXEC_FUSED (no device work): partition the
+ * gate list into blocks of at most fuse_k qubits in a dependency-respecting
+ * order.  block_of[g] receives the block index of gate g; *n_blocks the
+ * number of blocks.  block_of must hold n_gates entries. */
+int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
+                 int *block_of, int *n_blocks);
+
+/* ---- measurement and reductions (section 3.3 "Measurement") --------- */
+
+/* Marginal outcome distribution over the m listed qubits:
+ * out_dev[s] = sum of |psi_i|^2 over the indices i whose listed qubits read
+ * s (qubits[0] = most significant bit of s), FP64, 2^m entries.  With
+ * m == n this is the full distribution.  m in [1, n]; m <= 24 unless m == n. */
+int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream);
+
+/* Pauli-string expectation values.  paulis holds n_terms strings of n
+ * characters from {I,X,Y,Z} back to back (character q acts on qubit q);
+ * coeff holds n_terms FP64 coefficients (host).
+ * out_dev[0] = sum_t coeff[t] * Re <psi|P_t|psi>; if per_term != 0,
+ * out_dev[1 + t] = Re <psi|P_t|psi> as well.  FP64 accumulation,
+ * deterministic order.  The state is not renormalised. */
+int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
+                    int per_term, double *out_dev, void *stream);
+
+/* ---- differentiation ------------------------------------------------ */
+
+/* Adjoint-method gradient of E(theta) = <phi|H|phi>, phi = U_L..U_1 psi_in,
+ * H = sum_t coeff[t] P_t (Pauli strings as in qc_expect_pauli).
+ * psi holds psi_in on entry; lam is a caller-owned state of the same n and
+ * type used as the adjoint vector.  On return psi holds psi_in again up to
+ * rounding (the backward pass un-computes the forward pass).
+ * energy_dev[0] = E; grad_dev[p] = dE/dtheta[p] (FP64, n_params entries;
+ * a parameter used by several gates gets the sum).  theta is a host FP64
+ * array.  Method: Jones & Gacon, arXiv:2009.02823 (the paper has none). */
+int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
+                    const double *theta, int n_params, int n_terms, const char *paulis,
+                    const double *coeff, double *energy_dev, double *grad_dev, void *stream);
+
+/* ---- kernel timing (for roofline reports) ---------------------------- */
+
+/* Start (on != 0) or stop recording HIP events around every kernel the
+ * library launches.  Starting clears earlier records. */
+int qc_timing_enable(int on);
+/* Synchronise on the recorded events and report, for the kernel family
+ * `name` (for example "fused_mfma_c64"), the number of launches and their
+ * total duration in milliseconds.  Blocks the host. */
+int qc_timing_query(const char *name, int64_t *count, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QC_H_ */

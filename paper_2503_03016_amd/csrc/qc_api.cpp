@@ -1,0 +1,878 @@
+// C ABI of libqc (declared in include/qc.h): argument validation, the
+// per-device workspace and staging ring, kernel timing, the host-side gate
+// fuser and the circuit executor.  Device work is delegated to the
+// launchers in qc_gates.hip, qc_fused_mfma.hip, qc_reduce.hip and
+// qc_adjoint.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qc.h"
+#include "qc_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(QC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- workspace
+
+constexpr size_t kWorkElems = size_t(8) << 20;     // 64 MiB of FP64 partials
+constexpr size_t kRingBytes = size_t(64) << 20;    // staging ring
+constexpr int kMaxDevices = 64;
+
+struct DevCtx {
+    bool ready = false;
+    double *work = nullptr;
+    char *ring_dev = nullptr;
+    char *ring_host = nullptr;
+    size_t ring_head = 0;
+};
+
+DevCtx g_dev[kMaxDevices];
+std::mutex g_mu;
+
+int get_ctx(DevCtx **out) {
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (d < 0 || d >= kMaxDevices) return fail(QC_ERR_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCtx &c = g_dev[d];
+    if (!c.ready) {
+        if (hipMalloc(&c.work, kWorkElems * sizeof(double)) != hipSuccess)
+            return fail(QC_ERR_NOMEM, "workspace allocation failed");
+        if (hipMalloc(&c.ring_dev, kRingBytes) != hipSuccess)
+            return fail(QC_ERR_NOMEM, "staging ring allocation failed");
+        if (hipHostMalloc(&c.ring_host, kRingBytes, hipHostMallocDefault) != hipSuccess)
+            return fail(QC_ERR_NOMEM, "pinned staging allocation failed");
+        c.ring_head = 0;
+        c.ready = true;
+    }
+    *out = &c;
+    return QC_OK;
+}
+
+// Copy a small host array into device memory owned by the ring.  The copy
+// is ordered on `s` before any kernel the caller enqueues afterwards.  When
+// the ring wraps, the device is drained first so no slot still in use by an
+// earlier copy or kernel is overwritten.
+int stage(DevCtx *c, const void *src, size_t bytes, hipStream_t s, void **dev) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (need > kRingBytes) return fail(QC_ERR_ARG, "staged array too large");
+    if (c->ring_head + need > kRingBytes) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        c->ring_head = 0;
+    }
+    std::memcpy(c->ring_host + c->ring_head, src, bytes);
+    hipError_t e = hipMemcpyAsync(c->ring_dev + c->ring_head, c->ring_host + c->ring_head, bytes,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    *dev = c->ring_dev + c->ring_head;
+    c->ring_head += need;
+    return QC_OK;
+}
+
+// ---------------------------------------------------------------- timing
+
+std::atomic<bool> g_timing{false};
+struct TimerRec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+std::vector<TimerRec> g_trecs;
+std::map<std::string, std::pair<int64_t, double>> g_tsum;
+std::mutex g_tmu;
+
+// ---------------------------------------------------------------- validation
+
+int check_state(const qc_state_t &s) {
+    if (!s.amp) return fail(QC_ERR_ARG, "state amplitude pointer is NULL");
+    if (s.n < 1 || s.n > QC_MAX_QUBITS) return fail(QC_ERR_ARG, "qubit count out of range");
+    if (s.dtype != QC_C64 && s.dtype != QC_C128) return fail(QC_ERR_DTYPE, "unknown dtype");
+    return QC_OK;
+}
+
+// labels must be in [0, n) and pairwise distinct
+int check_qubits(int n, const int *q, int m, const char *what) {
+    if (m > 0 && !q) return fail(QC_ERR_ARG, std::string(what) + " pointer is NULL");
+    uint64_t seen = 0;
+    for (int i = 0; i < m; ++i) {
+        if (q[i] < 0 || q[i] >= n)
+            return fail(QC_ERR_QUBIT, std::string(what) + " label out of range");
+        const uint64_t bit = uint64_t(1) << q[i];
+        if (seen & bit) return fail(QC_ERR_QUBIT, std::string(what) + " labels repeat");
+        seen |= bit;
+    }
+    return QC_OK;
+}
+
+inline int bitpos(int n, int q) { return n - 1 - q; }
+
+// ---------------------------------------------------------------- host math
+
+// Apply a gate (targets/controls given as block-local bit positions, MSB
+// first for targets) to a small dense vector of 2^k amplitudes.
+void host_apply(std::vector<cd> &v, int k, int nt, const int *tbit, int nc, const int *cbit,
+                const int *cval, const cd *u) {
+    const int d = 1 << nt;
+    uint64_t fixed = 0, want = 0;
+    for (int j = 0; j < nt; ++j) fixed |= uint64_t(1) << tbit[j];
+    for (int j = 0; j < nc; ++j) {
+        fixed |= uint64_t(1) << cbit[j];
+        if (cval[j]) want |= uint64_t(1) << cbit[j];
+    }
+    std::vector<uint64_t> off(d);
+    for (int r = 0; r < d; ++r) {
+        uint64_t o = 0;
+        for (int j = 0; j < nt; ++j)
+            if ((r >> (nt - 1 - j)) & 1) o |= uint64_t(1) << tbit[j];
+        off[r] = o;
+    }
+    std::vector<cd> in(d);
+    const uint64_t dim = uint64_t(1) << k;
+    for (uint64_t i = 0; i < dim; ++i) {
+        if ((i & fixed) != want) continue;   // not a group base
+        for (int c = 0; c < d; ++c) in[c] = v[i | off[c]];
+        for (int r = 0; r < d; ++r) {
+            cd acc = 0.0;
+            for (int c = 0; c < d; ++c) acc += u[r * d + c] * in[c];
+            v[i | off[r]] = acc;
+        }
+    }
+}
+
+std::vector<cd> to_cd(const double *u, int d) {
+    std::vector<cd> m(size_t(d) * d);
+    for (size_t i = 0; i < m.size(); ++i) m[i] = cd(u[2 * i], u[2 * i + 1]);
+    return m;
+}
+
+// Dense matrix (2^k, row-major) of a list of gates acting inside the block
+// whose qubits (labels, qubits[0] = MSB) are `bq`.
+std::vector<cd> block_matrix(int k, const int *bq, const std::vector<const qc_gate_t *> &gs) {
+    const int dim = 1 << k;
+    auto local = [&](int label) {
+        for (int j = 0; j < k; ++j)
+            if (bq[j] == label) return k - 1 - j;
+        return -1;
+    };
+    // columns of the product, evolved as 2^k small states
+    std::vector<std::vector<cd>> cols(dim, std::vector<cd>(dim, 0.0));
+    for (int c = 0; c < dim; ++c) cols[c][c] = 1.0;
+    for (const qc_gate_t *g : gs) {
+        int tb[QC_MAX_FUSED], cb[QC_MAX_CTRLS];
+        for (int j = 0; j < g->n_targets; ++j) tb[j] = local(g->targets[j]);
+        for (int j = 0; j < g->n_ctrls; ++j) cb[j] = local(g->ctrls[j]);
+        const std::vector<cd> u = to_cd(g->matrix, 1 << g->n_targets);
+        for (int c = 0; c < dim; ++c)
+            host_apply(cols[c], k, g->n_targets, tb, g->n_ctrls, cb, g->ctrl_vals, u.data());
+    }
+    std::vector<cd> m(size_t(dim) * dim);
+    for (int r = 0; r < dim; ++r)
+        for (int c = 0; c < dim; ++c) m[size_t(r) * dim + c] = cols[c][r];
+    return m;
+}
+
+uint64_t gate_mask(const qc_gate_t &g) {
+    uint64_t m = 0;
+    for (int j = 0; j < g.n_targets; ++j) m |= uint64_t(1) << g.targets[j];
+    for (int j = 0; j < g.n_ctrls; ++j) m |= uint64_t(1) << g.ctrls[j];
+    return m;
+}
+
+int check_gate(int n, const qc_gate_t &g) {
+    if (g.n_targets < 1 || g.n_targets > QC_MAX_FUSED)
+        return fail(QC_ERR_ARG, "gate target count out of range");
+    if (g.n_ctrls < 0 || g.n_ctrls > QC_MAX_CTRLS)
+        return fail(QC_ERR_ARG, "gate control count out of range");
+    if (!g.matrix) return fail(QC_ERR_ARG, "gate matrix is NULL");
+    int all[QC_MAX_FUSED + QC_MAX_CTRLS];
+    for (int j = 0; j < g.n_targets; ++j) all[j] = g.targets[j];
+    for (int j = 0; j < g.n_ctrls; ++j) {
+        all[g.n_targets + j] = g.ctrls[j];
+        if (g.ctrl_vals[j] != 0 && g.ctrl_vals[j] != 1)
+            return fail(QC_ERR_ARG, "control value must be 0 or 1");
+    }
+    return check_qubits(n, all, g.n_targets + g.n_ctrls, "gate qubit");
+}
+
+// Greedy dependency-respecting partition into blocks of <= k qubits.
+// A gate joins the block under construction when none of its qubits is
+// held by an earlier gate left out of the block and the union of qubits
+// stays within k; a gate left out blocks its qubits for later gates.
+void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, std::vector<int> &block_of,
+               int &n_blocks) {
+    block_of.assign(ng, -1);
+    n_blocks = 0;
+    const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    std::vector<int> pending(ng);
+    for (int i = 0; i < ng; ++i) pending[i] = i;
+    while (!pending.empty()) {
+        uint64_t held = 0, blocked = 0;
+        std::vector<int> rest;
+        rest.reserve(pending.size());
+        bool scanning = true;
+        for (int idx : pending) {
+            const uint64_t m = gate_mask(gs[idx]);
+            const int cnt = __builtin_popcountll(m);
+            if (scanning && !(m & blocked) && __builtin_popcountll(held | m) <= k &&
+                (cnt <= k || held == 0)) {
+                held |= m;
+                block_of[idx] = n_blocks;
+                if (cnt > k) scanning = false;   // oversize gate stands alone
+            } else {
+                blocked |= m;
+                rest.push_back(idx);
+                if ((blocked & all) == all) scanning = false;   // nothing can join any more
+            }
+        }
+        ++n_blocks;
+        pending.swap(rest);
+    }
+}
+
+double sweep_bytes(int n, int dtype) {
+    return 2.0 * double(uint64_t(1) << n) * (dtype == QC_C64 ? 8.0 : 16.0);
+}
+
+}  // namespace
+
+// ======================================================================
+// services used by the launchers
+// ======================================================================
+namespace qcx {
+
+int timer_begin(const char *name, hipStream_t s) {
+    if (!g_timing.load(std::memory_order_relaxed)) return -1;
+    TimerRec r;
+    r.name = name;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    (void)hipEventRecord(r.a, s);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_trecs.push_back(r);
+    return int(g_trecs.size()) - 1;
+}
+
+void timer_end(int token, hipStream_t s) {
+    if (token < 0) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (size_t(token) < g_trecs.size()) (void)hipEventRecord(g_trecs[token].b, s);
+}
+
+}  // namespace qcx
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+const char *qc_status_string(int status) {
+    switch (status) {
+    case QC_OK: return "ok";
+    case QC_ERR_ARG: return "invalid argument";
+    case QC_ERR_QUBIT: return "invalid qubit";
+    case QC_ERR_DTYPE: return "invalid dtype";
+    case QC_ERR_UNSUPPORTED: return "unsupported";
+    case QC_ERR_HIP: return "HIP error";
+    case QC_ERR_NOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+const char *qc_last_error(void) { return t_err.c_str(); }
+
+int qc_version(void) { return 10000; }
+
+int qc_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (on) {
+        for (auto &r : g_trecs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        g_trecs.clear();
+        g_tsum.clear();
+    }
+    g_timing.store(on != 0);
+    return QC_OK;
+}
+
+int qc_timing_query(const char *name, int64_t *count, double *total_ms) {
+    if (!name || !count || !total_ms) return fail(QC_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &r : g_trecs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        auto &acc = g_tsum[r.name];
+        acc.first += 1;
+        acc.second += double(ms);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_trecs.clear();
+    auto it = g_tsum.find(name);
+    *count = it == g_tsum.end() ? 0 : it->second.first;
+    *total_ms = it == g_tsum.end() ? 0.0 : it->second.second;
+    return QC_OK;
+}
+
+int qc_state_init(qc_state_t s, uint64_t basis_index, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (basis_index >= (uint64_t(1) << s.n)) return fail(QC_ERR_ARG, "basis index out of range");
+    hipError_t e = qcx::launch_init(s.amp, s.dtype, s.n, basis_index, (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "init");
+}
+
+int qc_state_copy(qc_state_t dst, qc_state_t src, void *stream) {
+    int rc = check_state(dst);
+    if (rc) return rc;
+    if ((rc = check_state(src))) return rc;
+    if (dst.n != src.n) return fail(QC_ERR_ARG, "states differ in qubit count");
+    const uint64_t count = uint64_t(1) << dst.n;
+    const char *a = (const char *)dst.amp, *b = (const char *)src.amp;
+    const size_t la = count * (dst.dtype == QC_C64 ? 8 : 16), lb = count * (src.dtype == QC_C64 ? 8 : 16);
+    if (a < b + lb && b < a + la) return fail(QC_ERR_ARG, "states overlap");
+    hipError_t e = qcx::launch_copy(dst.amp, dst.dtype, src.amp, src.dtype, count,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "copy");
+}
+
+int qc_state_diff(qc_state_t a, qc_state_t b, double *out_dev, void *stream) {
+    int rc = check_state(a);
+    if (rc) return rc;
+    if ((rc = check_state(b))) return rc;
+    if (a.n != b.n) return fail(QC_ERR_ARG, "states differ in qubit count");
+    if (!out_dev) return fail(QC_ERR_ARG, "output pointer is NULL");
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    hipError_t e = qcx::launch_diff(a.amp, a.dtype, b.amp, b.dtype, uint64_t(1) << a.n, out_dev,
+                                    c->work, (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "diff");
+}
+
+int qc_apply_1q(qc_state_t s, int q, const double *u, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!u) return fail(QC_ERR_ARG, "matrix is NULL");
+    if ((rc = check_qubits(s.n, &q, 1, "target"))) return rc;
+    const int tp = bitpos(s.n, q);
+    hipError_t e = qcx::launch_small_gate(s.amp, s.dtype, s.n, 1, &tp, 0, nullptr, nullptr, u,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "apply_1q");
+}
+
+int qc_apply_2q(qc_state_t s, int qa, int qb, const double *u, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!u) return fail(QC_ERR_ARG, "matrix is NULL");
+    if (s.n < 2) return fail(QC_ERR_QUBIT, "two-qubit gate on a one-qubit register");
+    const int q[2] = {qa, qb};
+    if ((rc = check_qubits(s.n, q, 2, "target"))) return rc;
+    const int tp[2] = {bitpos(s.n, qa), bitpos(s.n, qb)};
+    hipError_t e = qcx::launch_small_gate(s.amp, s.dtype, s.n, 2, tp, 0, nullptr, nullptr, u,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "apply_2q");
+}
+
+int qc_apply_controlled(qc_state_t s, int n_ctrl, const int *ctrl, const int *ctrl_val,
+                        int target, const double *u, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!u) return fail(QC_ERR_ARG, "matrix is NULL");
+    if (n_ctrl < 0 || n_ctrl > QC_MAX_CTRLS || n_ctrl + 1 > s.n)
+        return fail(QC_ERR_ARG, "control count out of range");
+    if (n_ctrl > 0 && (!ctrl || !ctrl_val)) return fail(QC_ERR_ARG, "control arrays are NULL");
+    int all[QC_MAX_CTRLS + 1];
+    all[0] = target;
+    for (int j = 0; j < n_ctrl; ++j) {
+        all[1 + j] = ctrl[j];
+        if (ctrl_val[j] != 0 && ctrl_val[j] != 1)
+            return fail(QC_ERR_ARG, "control value must be 0 or 1");
+    }
+    if ((rc = check_qubits(s.n, all, n_ctrl + 1, "qubit"))) return rc;
+    int cp[QC_MAX_CTRLS + 1], cv[QC_MAX_CTRLS + 1];
+    for (int j = 0; j < n_ctrl; ++j) {
+        cp[j] = bitpos(s.n, ctrl[j]);
+        cv[j] = ctrl_val[j];
+    }
+    hipError_t e;
+    const bool diag_one = u[2] == 0.0 && u[3] == 0.0 && u[4] == 0.0 && u[5] == 0.0 &&
+                          u[0] == 1.0 && u[1] == 0.0;
+    if (diag_one) {
+        // only the target-1 part of the control subspace changes
+        cp[n_ctrl] = bitpos(s.n, target);
+        cv[n_ctrl] = 1;
+        e = qcx::launch_phase(s.amp, s.dtype, s.n, n_ctrl + 1, cp, cv, u[6], u[7],
+                              (hipStream_t)stream);
+    } else {
+        const int tp = bitpos(s.n, target);
+        e = qcx::launch_small_gate(s.amp, s.dtype, s.n, 1, &tp, n_ctrl, cp, cv, u,
+                                   (hipStream_t)stream);
+    }
+    return e == hipSuccess ? QC_OK : hip_fail(e, "apply_controlled");
+}
+
+}  // extern "C"
+
+namespace {
+
+// FP32 matrix-core operand layout of a 32x32 complex U (see qc_fused_mfma.hip).
+void mfma_operand_c64(const std::vector<cd> &u, std::vector<float> &out);
+
+int fused_apply(qc_state_t s, int k, const int *qubits, const std::vector<cd> &u,
+                hipStream_t stream) {
+    DevCtx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    qcx::FusedGeom g{};
+    g.k = k;
+    int pos[QC_MAX_FUSED];
+    for (int j = 0; j < k; ++j) pos[j] = bitpos(s.n, qubits[j]);
+    int srt[QC_MAX_FUSED];
+    std::copy(pos, pos + k, srt);
+    std::sort(srt, srt + k);
+    g.n_pos = k;
+    for (int j = 0; j < k; ++j) g.pos[j] = uint8_t(srt[j]);
+    for (int r = 0; r < (1 << k); ++r) {
+        uint64_t o = 0;
+        for (int j = 0; j < k; ++j)
+            if ((r >> (k - 1 - j)) & 1) o |= uint64_t(1) << pos[j];
+        g.tgt_off[r] = o;
+    }
+    void *dev = nullptr;
+    hipError_t e;
+    if (s.dtype == QC_C64 && k == 5 && s.n >= 10) {
+        std::vector<float> op;
+        mfma_operand_c64(u, op);
+        if ((rc = stage(c, op.data(), op.size() * sizeof(float), stream, &dev))) return rc;
+        e = qcx::launch_fused_mfma_c64(s.amp, s.n, g, static_cast<const float *>(dev), stream);
+    } else if (s.dtype == QC_C64) {
+        std::vector<float> f(u.size() * 2);
+        for (size_t i = 0; i < u.size(); ++i) {
+            f[2 * i] = float(u[i].real());
+            f[2 * i + 1] = float(u[i].imag());
+        }
+        if ((rc = stage(c, f.data(), f.size() * sizeof(float), stream, &dev))) return rc;
+        e = qcx::launch_fused_valu(s.amp, s.dtype, s.n, g, dev, stream);
+    } else {
+        if ((rc = stage(c, u.data(), u.size() * sizeof(cd), stream, &dev))) return rc;
+        e = qcx::launch_fused_valu(s.amp, s.dtype, s.n, g, dev, stream);
+    }
+    return e == hipSuccess ? QC_OK : hip_fail(e, "apply_fused_k");
+}
+
+}  // namespace
+
+extern "C" {
+
+int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!u) return fail(QC_ERR_ARG, "matrix is NULL");
+    if (k < 1 || k > QC_MAX_FUSED) return fail(QC_ERR_ARG, "k out of range");
+    if (k > s.n) return fail(QC_ERR_QUBIT, "more gate qubits than register qubits");
+    if ((rc = check_qubits(s.n, qubits, k, "target"))) return rc;
+    return fused_apply(s, k, qubits, to_cd(u, 1 << k), (hipStream_t)stream);
+}
+
+int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *block_of,
+                 int *n_blocks) {
+    if (n < 1 || n > QC_MAX_QUBITS) return fail(QC_ERR_ARG, "qubit count out of range");
+    if (n_gates < 0 || (n_gates > 0 && (!gates || !block_of)) || !n_blocks)
+        return fail(QC_ERR_ARG, "NULL argument");
+    if (fuse_k < 1 || fuse_k > QC_MAX_FUSED) return fail(QC_ERR_ARG, "fuse_k out of range");
+    for (int i = 0; i < n_gates; ++i) {
+        int rc = check_gate(n, gates[i]);
+        if (rc) return rc;
+    }
+    std::vector<int> bo;
+    int nb = 0;
+    fuse_plan(n, n_gates, gates, fuse_k, bo, nb);
+    std::copy(bo.begin(), bo.end(), block_of);
+    *n_blocks = nb;
+    return QC_OK;
+}
+
+int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode, int fuse_k,
+                     qc_exec_stats_t *stats, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(QC_ERR_ARG, "gate list is NULL");
+    if (mode != QC_EXEC_UNFUSED && mode != QC_EXEC_FUSED) return fail(QC_ERR_ARG, "unknown mode");
+    if (mode == QC_EXEC_FUSED && (fuse_k < 1 || fuse_k > QC_MAX_FUSED || fuse_k > s.n))
+        return fail(QC_ERR_ARG, "fuse_k out of range");
+    for (int i = 0; i < n_gates; ++i)
+        if ((rc = check_gate(s.n, gates[i]))) return rc;
+    qc_exec_stats_t st{};
+    st.gates = n_gates;
+    const hipStream_t hs = (hipStream_t)stream;
+    const double sweep = sweep_bytes(s.n, s.dtype);
+    if (mode == QC_EXEC_UNFUSED) {
+        for (int i = 0; i < n_gates; ++i) {
+            const qc_gate_t &g = gates[i];
+            const int nq = g.n_targets + g.n_ctrls;
+            if (g.n_targets == 1) {
+                rc = g.n_ctrls ? qc_apply_controlled(s, g.n_ctrls, g.ctrls, g.ctrl_vals, g.targets[0],
+                                                     g.matrix, stream)
+                               : qc_apply_1q(s, g.targets[0], g.matrix, stream);
+                const double *u = g.matrix;
+                const bool phase_only = g.n_ctrls && u[2] == 0 && u[3] == 0 && u[4] == 0 &&
+                                        u[5] == 0 && u[0] == 1.0 && u[1] == 0;
+                st.state_bytes += sweep / double(uint64_t(1) << (g.n_ctrls + (phase_only ? 1 : 0)));
+            } else if (g.n_targets == 2 && g.n_ctrls == 0) {
+                rc = qc_apply_2q(s, g.targets[0], g.targets[1], g.matrix, stream);
+                st.state_bytes += sweep;
+            } else if (nq <= QC_MAX_FUSED) {
+                int bq[QC_MAX_FUSED];
+                for (int j = 0; j < g.n_targets; ++j) bq[j] = g.targets[j];
+                for (int j = 0; j < g.n_ctrls; ++j) bq[g.n_targets + j] = g.ctrls[j];
+                std::vector<const qc_gate_t *> one{&g};
+                rc = fused_apply(s, nq, bq, block_matrix(nq, bq, one), hs);
+                st.state_bytes += sweep;
+            } else {
+                rc = fail(QC_ERR_UNSUPPORTED, "gate with more than 5 qubits and targets > 1");
+            }
+            if (rc) return rc;
+            st.launches += 1;
+            st.sweeps += 1;
+        }
+    } else {
+        std::vector<int> bo;
+        int nb = 0;
+        fuse_plan(s.n, n_gates, gates, fuse_k, bo, nb);
+        std::vector<std::vector<const qc_gate_t *>> members(nb);
+        for (int i = 0; i < n_gates; ++i) members[bo[i]].push_back(&gates[i]);
+        for (int b = 0; b < nb; ++b) {
+            uint64_t m = 0;
+            for (auto *g : members[b]) m |= gate_mask(*g);
+            int bq[64], k = 0;
+            for (int q = 0; q < s.n; ++q)
+                if ((m >> q) & 1) bq[k++] = q;
+            if (k > QC_MAX_FUSED) return fail(QC_ERR_UNSUPPORTED, "gate wider than the fused path");
+            // complex64 blocks are widened to 5 qubits so that every block
+            // runs on the matrix-core kernel (the extra qubits carry identity)
+            for (int q = 0; s.dtype == QC_C64 && fuse_k == 5 && k < fuse_k && q < s.n; ++q)
+                if (!((m >> q) & 1)) {
+                    m |= uint64_t(1) << q;
+                    bq[k++] = q;
+                }
+            std::sort(bq, bq + k);
+            rc = fused_apply(s, k, bq, block_matrix(k, bq, members[b]), hs);
+            if (rc) return rc;
+            st.launches += 1;
+            st.sweeps += 1;
+            st.fused_blocks += 1;
+            st.state_bytes += sweep;
+        }
+    }
+    if (stats) *stats = st;
+    return QC_OK;
+}
+
+int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!out_dev) return fail(QC_ERR_ARG, "output pointer is NULL");
+    if (m < 1 || m > s.n) return fail(QC_ERR_ARG, "m out of range");
+    if (m != s.n && m > 24) return fail(QC_ERR_UNSUPPORTED, "marginal over more than 24 qubits");
+    if ((rc = check_qubits(s.n, qubits, m, "qubit"))) return rc;
+    int pos[QC_MAX_QUBITS];
+    bool identity = (m == s.n);
+    for (int j = 0; j < m; ++j) {
+        pos[j] = bitpos(s.n, qubits[j]);
+        if (qubits[j] != j) identity = false;
+    }
+    hipError_t e;
+    if (m == s.n) {
+        e = qcx::launch_probs_full(s.amp, s.dtype, s.n, pos, identity, out_dev, (hipStream_t)stream);
+    } else {
+        DevCtx *c;
+        if ((rc = get_ctx(&c))) return rc;
+        e = qcx::launch_probs_marginal(s.amp, s.dtype, s.n, m, pos, out_dev, c->work, kWorkElems,
+                                       (hipStream_t)stream);
+    }
+    return e == hipSuccess ? QC_OK : hip_fail(e, "probs");
+}
+
+int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
+                    int per_term, double *out_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (n_terms < 1 || n_terms > 65536) return fail(QC_ERR_ARG, "term count out of range");
+    if (!paulis || !coeff || !out_dev) return fail(QC_ERR_ARG, "NULL argument");
+    const int n = s.n;
+    std::vector<uint64_t> xm(n_terms), zm(n_terms);
+    std::vector<int> ph(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        uint64_t x = 0, z = 0;
+        int ny = 0;
+        for (int q = 0; q < n; ++q) {
+            const char ch = paulis[size_t(t) * n + q];
+            const uint64_t b = uint64_t(1) << bitpos(n, q);
+            switch (ch) {
+            case 'I': break;
+            case 'X': x |= b; break;
+            case 'Y': x |= b; z |= b; ++ny; break;
+            case 'Z': z |= b; break;
+            default: return fail(QC_ERR_ARG, "Pauli character not in {I,X,Y,Z}");
+            }
+        }
+        xm[t] = x;
+        zm[t] = z;
+        ph[t] = ny & 3;
+    }
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    const hipStream_t hs = (hipStream_t)stream;
+    double *vals = c->work;                         // n_terms values
+    double *part = c->work + ((n_terms + 255) & ~255);  // per-block partials
+    // group terms by x mask, preserving first-seen order
+    std::vector<int> order(n_terms);
+    for (int t = 0; t < n_terms; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xm[a] < xm[b]; });
+    // term values are written in grouped order, then permuted by combine
+    std::vector<int> where(n_terms);
+    for (int i = 0; i < n_terms; ++i) where[order[i]] = i;
+    size_t i0 = 0;
+    while (i0 < order.size()) {
+        size_t i1 = i0;
+        while (i1 < order.size() && xm[order[i1]] == xm[order[i0]] &&
+               i1 - i0 < size_t(qcx::kExpectMaxTerms))
+            ++i1;
+        const uint64_t x = xm[order[i0]];
+        const int hpos = x ? 63 - __builtin_clzll(x) : -1;
+        uint64_t zz[qcx::kExpectMaxTerms];
+        int pp[qcx::kExpectMaxTerms];
+        for (size_t i = i0; i < i1; ++i) {
+            zz[i - i0] = zm[order[i]];
+            pp[i - i0] = ph[order[i]];
+        }
+        hipError_t e = qcx::launch_expect_group(s.amp, s.dtype, n, x, hpos, int(i1 - i0), zz, pp,
+                                                vals + i0, part, hs);
+        if (e != hipSuccess) return hip_fail(e, "expect");
+        i0 = i1;
+    }
+    // combine in the caller's term order: out[0] = sum_t c_t v_t, out[1+t] = v_t
+    std::vector<double> tab(size_t(2) * n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        tab[t] = coeff[t];
+        tab[n_terms + t] = double(where[t]);
+    }
+    void *cdev = nullptr;
+    if ((rc = stage(c, tab.data(), tab.size() * sizeof(double), hs, &cdev))) return rc;
+    hipError_t e = qcx::launch_expect_combine(vals, static_cast<const double *>(cdev), n_terms,
+                                              per_term, out_dev, hs);
+    if (e != hipSuccess) return hip_fail(e, "expect_combine");
+    return QC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Operand layout for the FP32 matrix-core kernel: see qc_fused_mfma.hip for
+// the register mapping.  Three real 32x32 matrices in the order Ur, Ui,
+// Ur + Ui (the three products of the 3M complex multiplication).
+void mfma_operand_c64(const std::vector<cd> &u, std::vector<float> &out) {
+    out.assign(3 * 32 * 32, 0.f);
+    for (int r = 0; r < 32; ++r)
+        for (int c = 0; c < 32; ++c) {
+            const cd v = u[size_t(r) * 32 + c];
+            out[0 * 1024 + r * 32 + c] = float(v.real());
+            out[1 * 1024 + r * 32 + c] = float(v.imag());
+            out[2 * 1024 + r * 32 + c] = float(v.real() + v.imag());
+        }
+}
+
+// FP64 matrix of a one-qubit program op (rotations take theta[param]).
+void op_matrix(const qc_op_t &op, const double *theta, qcx::Mat2d &m) {
+    const double r2 = std::sqrt(0.5);
+    double t = 0.0;
+    if (op.kind == QC_OP_RX || op.kind == QC_OP_RY || op.kind == QC_OP_RZ) t = theta[op.param];
+    const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+    for (int i = 0; i < 4; ++i) m.re[i] = m.im[i] = 0.0;
+    switch (op.kind) {
+    case QC_OP_RX: m.re[0] = c; m.im[1] = -s; m.im[2] = -s; m.re[3] = c; break;
+    case QC_OP_RY: m.re[0] = c; m.re[1] = -s; m.re[2] = s; m.re[3] = c; break;
+    case QC_OP_RZ: m.re[0] = c; m.im[0] = -s; m.re[3] = c; m.im[3] = s; break;
+    case QC_OP_H: m.re[0] = r2; m.re[1] = r2; m.re[2] = r2; m.re[3] = -r2; break;
+    case QC_OP_X: m.re[1] = 1; m.re[2] = 1; break;
+    case QC_OP_Y: m.im[1] = -1; m.im[2] = 1; break;
+    default: m.re[0] = 1; m.re[3] = -1; break;   // Z
+    }
+}
+
+void mat_dagger(const qcx::Mat2d &a, qcx::Mat2d &d) {
+    const int tr[4] = {0, 2, 1, 3};
+    for (int i = 0; i < 4; ++i) {
+        d.re[i] = a.re[tr[i]];
+        d.im[i] = -a.im[tr[i]];
+    }
+}
+
+// Apply a program op (or its inverse) to one state.
+hipError_t apply_op(const qc_state_t &s, const qc_op_t &op, const double *theta, bool inverse,
+                    hipStream_t hs) {
+    const int n = s.n;
+    if (op.kind == QC_OP_CZ) {
+        const int pos[2] = {bitpos(n, op.q0), bitpos(n, op.q1)}, val[2] = {1, 1};
+        return qcx::launch_phase(s.amp, s.dtype, n, 2, pos, val, -1.0, 0.0, hs);
+    }
+    if (op.kind == QC_OP_CNOT) {
+        const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+        const int tp = bitpos(n, op.q1), cp = bitpos(n, op.q0), cv = 1;
+        return qcx::launch_small_gate(s.amp, s.dtype, n, 1, &tp, 1, &cp, &cv, x, hs);
+    }
+    qcx::Mat2d m, d;
+    op_matrix(op, theta, m);
+    if (inverse) {
+        mat_dagger(m, d);
+        m = d;
+    }
+    double u[8];
+    for (int i = 0; i < 4; ++i) {
+        u[2 * i] = m.re[i];
+        u[2 * i + 1] = m.im[i];
+    }
+    const int tp = bitpos(n, op.q0);
+    return qcx::launch_small_gate(s.amp, s.dtype, n, 1, &tp, 0, nullptr, nullptr, u, hs);
+}
+
+bool is_rotation(int kind) { return kind == QC_OP_RX || kind == QC_OP_RY || kind == QC_OP_RZ; }
+
+}  // namespace
+
+extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
+                               const double *theta, int n_params, int n_terms,
+                               const char *paulis, const double *coeff, double *energy_dev,
+                               double *grad_dev, void *stream) {
+    int rc = check_state(psi);
+    if (rc) return rc;
+    if ((rc = check_state(lam))) return rc;
+    if (psi.n != lam.n || psi.dtype != lam.dtype)
+        return fail(QC_ERR_ARG, "psi and lam must have the same size and dtype");
+    {
+        const size_t bytes = (size_t(1) << psi.n) * (psi.dtype == QC_C64 ? 8 : 16);
+        const char *a = (const char *)psi.amp, *b = (const char *)lam.amp;
+        if (a < b + bytes && b < a + bytes) return fail(QC_ERR_ARG, "psi and lam overlap");
+    }
+    if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QC_ERR_ARG, "op list is NULL");
+    if (n_params < 0 || (n_params > 0 && (!theta || !grad_dev)))
+        return fail(QC_ERR_ARG, "theta or grad pointer is NULL");
+    if (!energy_dev) return fail(QC_ERR_ARG, "energy pointer is NULL");
+    if (n_terms < 1 || !paulis || !coeff) return fail(QC_ERR_ARG, "Hamiltonian is empty");
+    const int n = psi.n;
+    int n_rot = 0;
+    for (int k = 0; k < n_ops; ++k) {
+        const qc_op_t &o = ops[k];
+        if (o.kind < QC_OP_RX || o.kind > QC_OP_CNOT) return fail(QC_ERR_ARG, "unknown op kind");
+        const bool two = o.kind == QC_OP_CZ || o.kind == QC_OP_CNOT;
+        const int q[2] = {o.q0, o.q1};
+        if ((rc = check_qubits(n, q, two ? 2 : 1, "op qubit"))) return rc;
+        if (is_rotation(o.kind)) {
+            if (o.param < 0 || o.param >= n_params)
+                return fail(QC_ERR_ARG, "rotation parameter index out of range");
+            ++n_rot;
+        }
+    }
+    std::vector<qcx::PauliTermDev> terms(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        qcx::PauliTermDev T{};
+        int ny = 0;
+        for (int q = 0; q < n; ++q) {
+            const uint64_t b = uint64_t(1) << bitpos(n, q);
+            switch (paulis[size_t(t) * n + q]) {
+            case 'I': break;
+            case 'X': T.x |= b; break;
+            case 'Y': T.x |= b; T.z |= b; ++ny; break;
+            case 'Z': T.z |= b; break;
+            default: return fail(QC_ERR_ARG, "Pauli character not in {I,X,Y,Z}");
+            }
+        }
+        T.ph = ny & 3;
+        T.c = coeff[t];
+        terms[t] = T;
+    }
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    const unsigned cols = qcx::adjoint_grid(n);
+    const size_t need = size_t(n_rot) * cols + size_t(n_rot) + 1024;
+    if (need > kWorkElems) return fail(QC_ERR_UNSUPPORTED, "too many rotations for the workspace");
+    const hipStream_t hs = (hipStream_t)stream;
+    hipError_t e;
+    // forward: phi = U_L .. U_1 psi
+    for (int k = 0; k < n_ops; ++k)
+        if ((e = apply_op(psi, ops[k], theta, false, hs)) != hipSuccess) return hip_fail(e, "forward");
+    // energy, then lam = H phi
+    if ((rc = qc_expect_pauli(psi, n_terms, paulis, coeff, 0, energy_dev, stream))) return rc;
+    void *tdev = nullptr;
+    if ((rc = stage(c, terms.data(), terms.size() * sizeof(qcx::PauliTermDev), hs, &tdev))) return rc;
+    e = qcx::launch_pauli_apply(psi.amp, lam.amp, psi.dtype, n,
+                                static_cast<const qcx::PauliTermDev *>(tdev), n_terms, hs);
+    if (e != hipSuccess) return hip_fail(e, "pauli_apply");
+    // backward: per rotation, Im <lam|G|phi> fused with the un-apply
+    double *partial = c->work;
+    double *g_op = c->work + size_t(n_rot) * cols;
+    int row = n_rot;
+    for (int k = n_ops - 1; k >= 0; --k) {
+        const qc_op_t &o = ops[k];
+        if (is_rotation(o.kind)) {
+            qcx::Mat2d m, d;
+            op_matrix(o, theta, m);
+            mat_dagger(m, d);
+            --row;
+            const int gen = o.kind == QC_OP_RX ? 1 : (o.kind == QC_OP_RY ? 2 : 3);
+            e = qcx::launch_adjoint_step(psi.amp, lam.amp, psi.dtype, n, bitpos(n, o.q0), gen, d,
+                                         partial + size_t(row) * cols, hs);
+        } else {
+            e = apply_op(psi, o, theta, true, hs);
+            if (e == hipSuccess) e = apply_op(lam, o, theta, true, hs);
+        }
+        if (e != hipSuccess) return hip_fail(e, "backward");
+    }
+    // grad[p] = sum of the rotation rows that use parameter p
+    std::vector<int> csr(size_t(n_params) + 1 + size_t(n_rot), 0);
+    {
+        std::vector<std::vector<int>> users(n_params);
+        int r = 0;
+        for (int k = 0; k < n_ops; ++k)
+            if (is_rotation(ops[k].kind)) users[ops[k].param].push_back(r++);
+        int at = 0;
+        for (int p = 0; p < n_params; ++p) {
+            csr[p] = at;
+            for (int u : users[p]) csr[size_t(n_params) + 1 + at++] = u;
+        }
+        csr[n_params] = at;
+    }
+    void *cdev = nullptr;
+    if ((rc = stage(c, csr.data(), csr.size() * sizeof(int), hs, &cdev))) return rc;
+    const int *ptr = static_cast<const int *>(cdev);
+    e = qcx::launch_grad_finalize(partial, n_rot, int(cols), g_op, ptr, ptr + n_params + 1,
+                                  n_params, grad_dev, hs);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "grad_finalize");
+}

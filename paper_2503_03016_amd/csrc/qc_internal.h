@@ -1,0 +1,125 @@
+// Internal declarations of libqc: device-side helpers and the launchers that
+// the C ABI layer (qc_api.cpp) calls.  Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace qcx {
+
+// ---- element types ---------------------------------------------------------
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ inline cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__host__ __device__ inline cx<R> cfma(cx<R> a, cx<R> b, cx<R> acc) {
+    // acc + a * b
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+    return acc;
+}
+
+// Index of group g once zero bits are inserted at the ascending bit
+// positions pos[0..m-1] (positions refer to the final index).
+__host__ __device__ inline uint64_t insert_zeros(uint64_t g, const uint8_t *pos, int m) {
+    for (int j = 0; j < m; ++j) {
+        const int p = pos[j];
+        const uint64_t lo = g & ((uint64_t(1) << p) - 1);
+        g = ((g >> p) << (p + 1)) | lo;
+    }
+    return g;
+}
+
+__host__ __device__ inline uint64_t insert_zero(uint64_t g, int p) {
+    const uint64_t lo = g & ((uint64_t(1) << p) - 1);
+    return ((g >> p) << (p + 1)) | lo;
+}
+
+// ---- limits ----------------------------------------------------------------
+constexpr int kMaxPos = 40;        // fixed bit positions of one gate launch
+constexpr int kExpectMaxTerms = 32;
+constexpr int kReduceBlocks = 1024;  // fixed grid of deterministic reductions
+
+// ---- launch arguments ------------------------------------------------------
+// Gate with K target bits and any number of fixed (control) bits.
+template <typename R, int K>
+struct SmallGateArgs {
+    cx<R> *amp;
+    uint64_t n_groups;         // 2^(n - K - n_ctrl)
+    uint64_t or_bits;          // control values placed at their bit positions
+    uint64_t tgt_off[1 << K];  // offset of local index r (bit deposit)
+    cx<R> u[(1 << K) * (1 << K)];
+    uint8_t pos[kMaxPos];      // ascending positions of targets + controls
+    int n_pos;
+};
+
+struct FusedGeom {
+    int k;
+    int n_pos;
+    uint8_t pos[8];            // ascending target positions
+    uint64_t tgt_off[32];      // offset of local index r
+};
+
+// One Pauli term of a Hamiltonian on the device: P = i^ph X^x Z^z (masks of
+// bit positions), coefficient c.
+struct PauliTermDev {
+    uint64_t x, z;
+    double c;
+    int ph;     // number of Y factors mod 4
+    int pad;
+};
+
+// 2x2 complex matrix in FP64, row-major (entries 0..3 = U00 U01 U10 U11).
+struct Mat2d {
+    double re[4], im[4];
+};
+
+// ---- launchers (return hipSuccess or the launch error) ----------------------
+hipError_t launch_init(void *amp, int dtype, int n, uint64_t basis, hipStream_t s);
+hipError_t launch_copy(void *dst, int dt_dst, const void *src, int dt_src, uint64_t count,
+                       hipStream_t s);
+hipError_t launch_small_gate(void *amp, int dtype, int n, int k, const int *tpos_msb_first,
+                             int n_ctrl, const int *cpos, const int *cval, const double *u,
+                             hipStream_t s);
+hipError_t launch_phase(void *amp, int dtype, int n, int m, const int *pos, const int *val,
+                        double phase_re, double phase_im, hipStream_t s);
+hipError_t launch_fused_valu(void *amp, int dtype, int n, const FusedGeom &g,
+                             const void *u_dev, hipStream_t s);
+hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
+                                 hipStream_t s);
+hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_pos,
+                             bool identity, double *out, hipStream_t s);
+hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const int *pos,
+                                 double *out, double *work, size_t work_elems, hipStream_t s);
+hipError_t launch_expect_group(const void *amp, int dtype, int n, uint64_t xmask, int hpos,
+                               int n_terms, const uint64_t *zmask, const int *phase,
+                               double *term_vals, double *work, hipStream_t s);
+hipError_t launch_expect_combine(const double *term_vals, const double *coeff_dev, int n_terms,
+                                 int per_term, double *out, hipStream_t s);
+hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_t count,
+                       double *out, double *work, hipStream_t s);
+
+unsigned adjoint_grid(int n);
+hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
+                              const PauliTermDev *terms, int nt, hipStream_t s);
+hipError_t launch_adjoint_step(void *phi, void *lam, int dtype, int n, int p, int gen,
+                               const Mat2d &ud, double *partial, hipStream_t s);
+hipError_t launch_grad_finalize(const double *partial, int rows, int cols, double *g_op,
+                                const int *ptr, const int *idx, int n_params, double *grad,
+                                hipStream_t s);
+
+// ---- library services implemented in qc_api.cpp -----------------------------
+int timer_begin(const char *name, hipStream_t s);
+void timer_end(int token, hipStream_t s);
+
+}  // namespace qcx

@@ -1,0 +1,318 @@
+"""Thin ctypes binding of libqc.so (include/qc.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI.  Torch tensors provide device memory and the
+current stream; nothing here computes on a state.  If libqc.so is missing
+this module raises at import time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqc.so")
+
+QC_C64, QC_C128 = 1, 2
+QC_EXEC_UNFUSED, QC_EXEC_FUSED = 0, 1
+QC_MAX_FUSED, QC_MAX_CTRLS = 5, 16
+STATUS = {0: "QC_OK", -1: "QC_ERR_ARG", -2: "QC_ERR_QUBIT", -3: "QC_ERR_DTYPE",
+          -4: "QC_ERR_UNSUPPORTED", -5: "QC_ERR_HIP", -6: "QC_ERR_NOMEM"}
+OP_KIND = {"RX": 1, "RY": 2, "RZ": 3, "H": 4, "X": 5, "Y": 6, "Z": 7, "CZ": 8, "CNOT": 9}
+
+EXPORTS = [
+    "qc_status_string", "qc_last_error", "qc_version", "qc_state_init", "qc_state_copy",
+    "qc_state_diff", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled", "qc_apply_fused_k",
+    "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
+    "qc_timing_enable", "qc_timing_query",
+]
+
+
+class QcError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s failed: %s (%s)" % (where, STATUS.get(status, status), detail))
+        self.status = status
+
+
+class QcState(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_void_p), ("n", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+class QcGate(ctypes.Structure):
+    _fields_ = [("n_targets", ctypes.c_int32), ("n_ctrls", ctypes.c_int32),
+                ("targets", ctypes.c_int32 * QC_MAX_FUSED),
+                ("ctrls", ctypes.c_int32 * QC_MAX_CTRLS),
+                ("ctrl_vals", ctypes.c_int32 * QC_MAX_CTRLS),
+                ("matrix", ctypes.POINTER(ctypes.c_double))]
+
+
+class QcStats(ctypes.Structure):
+    _fields_ = [("gates", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("sweeps", ctypes.c_int64), ("fused_blocks", ctypes.c_int64),
+                ("state_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class QcOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("param", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqc.so is not built (run __graft_entry__.build() or "
+                          "python paper_2503_03016_amd/build.py); there is no fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+    ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    S = QcState
+    sig = {
+        "qc_status_string": ([i], ctypes.c_char_p),
+        "qc_last_error": ([], ctypes.c_char_p),
+        "qc_version": ([], i),
+        "qc_state_init": ([S, u64, vp], i),
+        "qc_state_copy": ([S, S, vp], i),
+        "qc_state_diff": ([S, S, vp, vp], i),
+        "qc_apply_1q": ([S, i, dp, vp], i),
+        "qc_apply_2q": ([S, i, i, dp, vp], i),
+        "qc_apply_controlled": ([S, i, ip, ip, i, dp, vp], i),
+        "qc_apply_fused_k": ([S, i, ip, dp, vp], i),
+        "qc_apply_circuit": ([S, i, ctypes.POINTER(QcGate), i, i, ctypes.POINTER(QcStats), vp], i),
+        "qc_fuse_plan": ([i, i, ctypes.POINTER(QcGate), i, ip, ip], i),
+        "qc_probs": ([S, i, ip, vp, vp], i),
+        "qc_expect_pauli": ([S, i, ctypes.c_char_p, dp, i, vp, vp], i),
+        "qc_adjoint_grad": ([S, S, ctypes.POINTER(QcOp), i, dp, i, i, ctypes.c_char_p, dp, vp,
+                             vp, vp], i),
+        "qc_timing_enable": ([i], i),
+        "qc_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), dp], i),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise QcError(rc, where, lib.qc_last_error().decode())
+
+
+def _ints(xs: Sequence[int]):
+    xs = [int(x) for x in xs]
+    return (ctypes.c_int * max(1, len(xs)))(*xs)
+
+
+def _mat(u) -> Tuple[np.ndarray, ctypes.POINTER(ctypes.c_double)]:
+    a = np.ascontiguousarray(np.asarray(u, dtype=np.complex128)).view(np.float64).reshape(-1)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream(t: Optional[torch.Tensor] = None):
+    dev = t.device if t is not None else torch.device("cuda")
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def state_view(psi: torch.Tensor) -> QcState:
+    """Describe a contiguous complex64/complex128 CUDA tensor of 2^n entries."""
+    if not isinstance(psi, torch.Tensor) or psi.device.type != "cuda":
+        raise TypeError("state must be a CUDA tensor")
+    if psi.dim() != 1 or not psi.is_contiguous():
+        raise ValueError("state must be a contiguous 1-D tensor")
+    n = int(psi.numel()).bit_length() - 1
+    if (1 << n) != psi.numel():
+        raise ValueError("state length must be a power of two")
+    if psi.dtype == torch.complex64:
+        dt = QC_C64
+    elif psi.dtype == torch.complex128:
+        dt = QC_C128
+    else:
+        raise TypeError("state dtype must be complex64 or complex128")
+    return QcState(psi.data_ptr(), n, dt)
+
+
+def new_state(n: int, dtype=torch.complex64, device="cuda") -> torch.Tensor:
+    return torch.empty(1 << n, dtype=dtype, device=device)
+
+
+# ------------------------------------------------------------- entry points
+
+def state_init(psi: torch.Tensor, basis_index: int = 0) -> torch.Tensor:
+    _check(lib.qc_state_init(state_view(psi), int(basis_index), _stream(psi)), "qc_state_init")
+    return psi
+
+
+def state_copy(dst: torch.Tensor, src: torch.Tensor) -> torch.Tensor:
+    _check(lib.qc_state_copy(state_view(dst), state_view(src), _stream(dst)), "qc_state_copy")
+    return dst
+
+
+def state_diff(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """[sum |a-b|^2, sum |b|^2, max |a-b|] (FP64, on the device)."""
+    out = torch.empty(3, dtype=torch.float64, device=a.device)
+    _check(lib.qc_state_diff(state_view(a), state_view(b), ctypes.c_void_p(out.data_ptr()),
+                             _stream(a)), "qc_state_diff")
+    return out
+
+
+def apply_1q(psi: torch.Tensor, q: int, u) -> torch.Tensor:
+    m, p = _mat(u)
+    _check(lib.qc_apply_1q(state_view(psi), int(q), p, _stream(psi)), "qc_apply_1q")
+    return psi
+
+
+def apply_2q(psi: torch.Tensor, qa: int, qb: int, u) -> torch.Tensor:
+    m, p = _mat(u)
+    _check(lib.qc_apply_2q(state_view(psi), int(qa), int(qb), p, _stream(psi)), "qc_apply_2q")
+    return psi
+
+
+def apply_controlled(psi: torch.Tensor, ctrl: Sequence[int], ctrl_val: Sequence[int],
+                     target: int, u) -> torch.Tensor:
+    m, p = _mat(u)
+    _check(lib.qc_apply_controlled(state_view(psi), len(ctrl), _ints(ctrl), _ints(ctrl_val),
+                                   int(target), p, _stream(psi)), "qc_apply_controlled")
+    return psi
+
+
+def apply_fused_k(psi: torch.Tensor, qubits: Sequence[int], u) -> torch.Tensor:
+    m, p = _mat(u)
+    _check(lib.qc_apply_fused_k(state_view(psi), len(qubits), _ints(qubits), p, _stream(psi)),
+           "qc_apply_fused_k")
+    return psi
+
+
+class GateList:
+    """qc_gate_t array built from (targets, ctrls, ctrl_vals, matrix) tuples;
+    keeps the host matrices alive while the library reads them."""
+
+    def __init__(self, gates: Iterable[Tuple[Sequence[int], Sequence[int], Sequence[int], np.ndarray]]):
+        gates = list(gates)
+        self.arr = (QcGate * max(1, len(gates)))()
+        self.keep: List[np.ndarray] = []
+        for g, (t, c, cv, u) in zip(self.arr, gates):
+            if len(t) > QC_MAX_FUSED or len(c) > QC_MAX_CTRLS:
+                raise ValueError("gate too wide for qc_gate_t")
+            g.n_targets, g.n_ctrls = len(t), len(c)
+            for j, q in enumerate(t):
+                g.targets[j] = int(q)
+            for j, (q, v) in enumerate(zip(c, cv)):
+                g.ctrls[j] = int(q)
+                g.ctrl_vals[j] = int(v)
+            m, p = _mat(u)
+            self.keep.append(m)
+            g.matrix = p
+        self.count = len(gates)
+
+
+def apply_circuit(psi: torch.Tensor, gates: GateList, mode: int = QC_EXEC_UNFUSED,
+                  fuse_k: int = 5) -> dict:
+    st = QcStats()
+    _check(lib.qc_apply_circuit(state_view(psi), gates.count, gates.arr, int(mode), int(fuse_k),
+                                ctypes.byref(st), _stream(psi)), "qc_apply_circuit")
+    return st.as_dict()
+
+
+def fuse_plan(n: int, gates: GateList, fuse_k: int = 5) -> Tuple[List[int], int]:
+    block_of = (ctypes.c_int * max(1, gates.count))()
+    nb = ctypes.c_int()
+    _check(lib.qc_fuse_plan(int(n), gates.count, gates.arr, int(fuse_k), block_of,
+                            ctypes.byref(nb)), "qc_fuse_plan")
+    return list(block_of[:gates.count]), nb.value
+
+
+def probs(psi: torch.Tensor, qubits: Optional[Sequence[int]] = None) -> torch.Tensor:
+    sv = state_view(psi)
+    qs = list(range(sv.n)) if qubits is None else list(qubits)
+    out = torch.empty(1 << len(qs), dtype=torch.float64, device=psi.device)
+    _check(lib.qc_probs(sv, len(qs), _ints(qs), ctypes.c_void_p(out.data_ptr()), _stream(psi)),
+           "qc_probs")
+    return out
+
+
+def _terms(terms, n):
+    strings = "".join(p for p, _ in terms)
+    if len(strings) != n * len(terms):
+        raise ValueError("every Pauli string needs n characters")
+    coeff = np.ascontiguousarray([float(c) for _, c in terms], dtype=np.float64)
+    return strings.encode(), coeff
+
+
+def expect_pauli(psi: torch.Tensor, terms, per_term: bool = False) -> torch.Tensor:
+    """terms: list of (Pauli string, coefficient).  Returns a device FP64
+    tensor [sum_t c_t <P_t>, (<P_t> for each t if per_term)]."""
+    sv = state_view(psi)
+    s, coeff = _terms(terms, sv.n)
+    out = torch.empty(1 + (len(terms) if per_term else 0), dtype=torch.float64, device=psi.device)
+    _check(lib.qc_expect_pauli(sv, len(terms), s, coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               int(bool(per_term)), ctypes.c_void_p(out.data_ptr()), _stream(psi)),
+           "qc_expect_pauli")
+    return out
+
+
+def make_ops(ops) -> Tuple[ctypes.Array, int]:
+    """qc_op_t array from workloads.Op entries of kinds RX/RY/RZ/H/X/Y/Z/CZ/CNOT."""
+    arr = (QcOp * max(1, len(ops)))()
+    for o, op in zip(arr, ops):
+        if op.kind not in OP_KIND:
+            raise ValueError("op kind %s is not supported by qc_adjoint_grad" % op.kind)
+        o.kind = OP_KIND[op.kind]
+        o.q0 = int(op.qubits[0])
+        o.q1 = int(op.qubits[1]) if len(op.qubits) > 1 else 0
+        o.param = int(op.pidx) if op.pidx is not None else -1
+    return arr, len(ops)
+
+
+def adjoint_grad(psi: torch.Tensor, lam: torch.Tensor, ops, theta, terms):
+    """Returns (energy, grad) as device FP64 tensors; psi holds the input
+    state on entry and (up to rounding) again on return."""
+    sv, lv = state_view(psi), state_view(lam)
+    arr, nops = make_ops(ops)
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    s, coeff = _terms(terms, sv.n)
+    energy = torch.empty(1, dtype=torch.float64, device=psi.device)
+    grad = torch.empty(th.size, dtype=torch.float64, device=psi.device)
+    _check(lib.qc_adjoint_grad(sv, lv, arr, nops, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               int(th.size), len(terms), s,
+                               coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_void_p(energy.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                               _stream(psi)), "qc_adjoint_grad")
+    return energy, grad
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(lib.qc_timing_enable(int(bool(on))), "qc_timing_enable")
+
+
+def timing_query(name: str) -> Tuple[int, float]:
+    cnt = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib.qc_timing_query(name.encode(), ctypes.byref(cnt), ctypes.byref(ms)),
+           "qc_timing_query")
+    return cnt.value, ms.value
+
+
+# the C entry-point names, for callers who prefer them
+qc_state_init = state_init
+qc_state_copy = state_copy
+qc_state_diff = state_diff
+qc_apply_1q = apply_1q
+qc_apply_2q = apply_2q
+qc_apply_controlled = apply_controlled
+qc_apply_fused_k = apply_fused_k
+qc_apply_circuit = apply_circuit
+qc_fuse_plan = fuse_plan
+qc_probs = probs
+qc_expect_pauli = expect_pauli
+qc_adjoint_grad = adjoint_grad
+qc_timing_enable = timing_enable
+qc_timing_query = timing_query

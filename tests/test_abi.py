@@ -1,0 +1,158 @@
+"""C ABI checks that need no GPU: every symbol declared in include/qc.h is
+exported by libqc.so, malformed arguments are rejected on the host with the
+documented status before anything is enqueued, and the host-only fusion
+planner (qc_fuse_plan) returns a valid dependency-respecting partition."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def qc():
+    from paper_2503_03016_amd import qc as mod
+    return mod
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("qc_state_init", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled",
+                     "qc_apply_fused_k", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(qc):
+    lib = ctypes.CDLL(qc.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(qc.EXPORTS)
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def st(qc, n=4, dtype=1, amp=FAKE):
+    return qc.QcState(amp, n, dtype)
+
+
+def test_status_strings(qc):
+    assert qc.lib.qc_status_string(0) == b"ok"
+    assert qc.lib.qc_status_string(-2) == b"invalid qubit"
+    assert qc.lib.qc_version() >= 10000
+
+
+def test_state_validation(qc):
+    lib = qc.lib
+    assert lib.qc_state_init(st(qc, amp=None), 0, None) == -1
+    assert lib.qc_state_init(st(qc, n=0), 0, None) == -1
+    assert lib.qc_state_init(st(qc, n=37), 0, None) == -1
+    assert lib.qc_state_init(st(qc, dtype=3), 0, None) == -3
+    assert lib.qc_state_init(st(qc, n=4), 16, None) == -1
+    assert b"basis" in lib.qc_last_error()
+
+
+def test_gate_validation(qc):
+    lib = qc.lib
+    u, p = qc._mat(np.eye(2))
+    u4, p4 = qc._mat(np.eye(4))
+    assert lib.qc_apply_1q(st(qc), 4, p, None) == -2
+    assert lib.qc_apply_1q(st(qc), -1, p, None) == -2
+    assert lib.qc_apply_1q(st(qc), 0, None, None) == -1
+    assert lib.qc_apply_2q(st(qc), 1, 1, p4, None) == -2
+    assert lib.qc_apply_2q(st(qc), 0, 4, p4, None) == -2
+    assert lib.qc_apply_2q(st(qc, n=1), 0, 0, p4, None) == -2
+    c = qc._ints([1])
+    bad = qc._ints([2])
+    assert lib.qc_apply_controlled(st(qc), 1, c, bad, 0, p, None) == -1
+    assert lib.qc_apply_controlled(st(qc), 1, c, qc._ints([1]), 1, p, None) == -2
+    assert lib.qc_apply_controlled(st(qc), 4, qc._ints([0, 1, 2, 3]), qc._ints([1] * 4), 0, p,
+                                   None) == -1
+    u32, p32 = qc._mat(np.eye(32))
+    assert lib.qc_apply_fused_k(st(qc), 6, qc._ints(range(6)), p32, None) == -1
+    assert lib.qc_apply_fused_k(st(qc), 5, qc._ints(range(5)), p32, None) == -2
+    assert lib.qc_apply_fused_k(st(qc, n=6), 2, qc._ints([3, 3]), p4, None) == -2
+
+
+def test_reduction_validation(qc):
+    lib = qc.lib
+    out = ctypes.c_void_p(FAKE)
+    assert lib.qc_probs(st(qc), 0, qc._ints([0]), out, None) == -1
+    assert lib.qc_probs(st(qc), 5, qc._ints(range(5)), out, None) == -1
+    assert lib.qc_probs(st(qc), 2, qc._ints([1, 1]), out, None) == -2
+    assert lib.qc_probs(st(qc), 1, qc._ints([0]), None, None) == -1
+    assert lib.qc_probs(st(qc, n=30), 25, qc._ints(range(25)), out, None) == -4
+    coeff = np.ones(1)
+    cp = coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.qc_expect_pauli(st(qc), 1, b"XYZQ", cp, 0, out, None) == -1
+    assert lib.qc_expect_pauli(st(qc), 0, b"", cp, 0, out, None) == -1
+
+
+def test_adjoint_validation(qc):
+    lib = qc.lib
+    ops, nops = qc.make_ops([W.Op("RY", (0,), pidx=3)])
+    th = np.zeros(2)
+    tp = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    coeff = np.ones(1)
+    cp = coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = ctypes.c_void_p(FAKE)
+    a, b = st(qc, amp=FAKE), st(qc, amp=FAKE * 4096)
+    # parameter index 3 with only 2 parameters
+    assert lib.qc_adjoint_grad(a, b, ops, nops, tp, 2, 1, b"ZIII", cp, out, out, None) == -1
+    # psi and lam must not overlap
+    assert lib.qc_adjoint_grad(a, a, ops, nops, tp, 4, 1, b"ZIII", cp, out, out, None) == -1
+    ops2, n2 = qc.make_ops([W.Op("CZ", (1, 1))])
+    assert lib.qc_adjoint_grad(a, b, ops2, n2, tp, 2, 1, b"ZIII", cp, out, out, None) == -2
+
+
+def _gate_list(qc, ops):
+    from paper_2503_03016_amd import gates as G
+    return qc.GateList(G.gate_tuples(ops))
+
+
+def _check_partition(ops, block_of, nb, k):
+    qsets = {}
+    for op, b in zip(ops, block_of):
+        assert 0 <= b < nb
+        qsets.setdefault(b, set()).update(op.qubits)
+    assert all(len(s) <= k for s in qsets.values())
+    last = {}
+    for op, b in zip(ops, block_of):
+        for q in op.qubits:
+            assert last.get(q, -1) <= b, "a gate moved ahead of an earlier gate on its qubit"
+            last[q] = b
+
+
+@pytest.mark.parametrize("n,layers,k", [(12, 20, 5), (16, 8, 4), (32, 40, 5), (10, 6, 3)])
+def test_fuse_plan_is_a_valid_partition(qc, n, layers, k):
+    ops = W.brickwork(n, layers, seed=n, entangler="CZ")
+    gl = _gate_list(qc, ops)
+    block_of, nb = qc.fuse_plan(n, gl, k)
+    _check_partition(ops, block_of, nb, k)
+    assert nb < len(ops)
+
+
+def test_fuse_plan_qft_and_mcx(qc):
+    n = 12
+    ops = W.qft(n) + [W.Op("MCX", (3, 4, 2), ctrl_val=(0, 1))]
+    gl = _gate_list(qc, ops)
+    block_of, nb = qc.fuse_plan(n, gl, 5)
+    _check_partition(ops, block_of, nb, 5)
+
+
+def test_fuse_plan_rejects_bad_gates(qc):
+    gl = _gate_list(qc, [W.Op("CNOT", (0, 0))])
+    with pytest.raises(qc.QcError):
+        qc.fuse_plan(4, gl, 5)

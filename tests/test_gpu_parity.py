@@ -1,0 +1,353 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle, element by
+element, on seeded inputs.
+
+Tolerances (written per test):
+* complex128: max |amplitude error| <= 1e-12 (absolute, unit-norm states).
+* complex64: relative 2-norm error <= 1e-5 for circuits of depth <= 40;
+  single gates and small circuits are held to tighter bounds derived from
+  FP32 rounding (about 1e-7 per gate, times the number of gates).
+* FP64 reductions: probabilities 1e-13 (c128) / 1e-6 (c64), expectations
+  1e-11 * (number of terms) (c128) / 2 ||H|| * state error (c64).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from dense_ref import random_unitary
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qc():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2503_03016_amd import qc as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2503_03016_amd import gates
+    return gates
+
+
+DT = {"c128": torch.complex128, "c64": torch.complex64}
+
+
+def dev(psi, dtype):
+    return torch.from_numpy(np.ascontiguousarray(psi)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def check(got, ref, dtype, ngates=1):
+    if dtype == torch.complex128:
+        err = np.max(np.abs(got - ref))
+        assert err <= 1e-12, err
+    else:
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        bound = min(1e-5, 2e-7 * max(1, ngates) ** 0.5 * 4)
+        assert rel <= bound, (rel, bound)
+
+
+# ---------------------------------------------------------------- basics
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_init_and_copy(qc, dt):
+    n = 11
+    psi = qc.new_state(n, DT[dt])
+    for b in (0, 1, 1234, (1 << n) - 1):
+        qc.state_init(psi, b)
+        ref = np.zeros(1 << n, complex)
+        ref[b] = 1
+        assert np.array_equal(host(psi), ref)
+    src = dev(W.random_state(n, 5), torch.complex128)
+    dst = qc.new_state(n, DT[dt])
+    qc.state_copy(dst, src)
+    want = src.to(DT[dt]).cpu().numpy().astype(np.complex128)
+    assert np.array_equal(host(dst), want)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 7, 13])
+def test_apply_1q_every_target(qc, dt, n):
+    rng = np.random.default_rng(n)
+    psi0 = W.random_state(n, 100 + n)
+    for q in range(n):
+        u = random_unitary(2, rng)
+        t = dev(psi0, DT[dt])
+        qc.apply_1q(t, q, u)
+        check(host(t), oracle.apply(psi0, [q], u), DT[dt])
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_2q_pairs(qc, dt):
+    n = 9
+    rng = np.random.default_rng(2)
+    psi0 = W.random_state(n, 9)
+    for a in range(n):
+        for b in range(n):
+            if a == b or (a + b) % 3:
+                continue
+            u = random_unitary(4, rng)
+            t = dev(psi0, DT[dt])
+            qc.apply_2q(t, a, b, u)
+            check(host(t), oracle.apply(psi0, [a, b], u), DT[dt])
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_controlled(qc, dt):
+    n = 10
+    rng = np.random.default_rng(3)
+    psi0 = W.random_state(n, 10)
+    for nc in (1, 2, 3, 5):
+        for trial in range(3):
+            perm = list(rng.permutation(n))
+            ctrl, tgt = perm[:nc], perm[nc]
+            cv = list(rng.integers(0, 2, nc))
+            u = random_unitary(2, rng)
+            t = dev(psi0, DT[dt])
+            qc.apply_controlled(t, ctrl, cv, tgt, u)
+            check(host(t), oracle.apply(psi0, [tgt], u, ctrl, cv), DT[dt])
+    # diagonal with U00 == 1 takes the phase-only path (CZ, CP)
+    for ph in (math.pi, 0.7):
+        u = np.diag([1.0, np.exp(1j * ph)])
+        t = dev(psi0, DT[dt])
+        qc.apply_controlled(t, [2, 7], [1, 0], 4, u)
+        check(host(t), oracle.apply(psi0, [4], u, [2, 7], [1, 0]), DT[dt])
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_apply_fused_k_random_qubits(qc, dt, k):
+    n = 12
+    rng = np.random.default_rng(40 + k)
+    psi0 = W.random_state(n, 12)
+    for trial in range(4):
+        qs = list(rng.permutation(n)[:k])
+        u = random_unitary(1 << k, rng)
+        t = dev(psi0, DT[dt])
+        qc.apply_fused_k(t, qs, u)
+        check(host(t), oracle.apply(psi0, qs, u), DT[dt], ngates=4)
+
+
+@pytest.mark.parametrize("n", [10, 11, 14, 17])
+def test_fused_mfma_target_positions(qc, n):
+    """The complex64 matrix-core path for every kind of target placement:
+    all-low bits, all-high bits, mixed, reversed order, a single tile."""
+    rng = np.random.default_rng(n)
+    psi0 = W.random_state(n, 1000 + n)
+    cases = [list(range(n - 5, n)), list(range(5)), [n - 1, 0, n // 2, 2, n - 3],
+             list(reversed(range(n - 5, n))), list(rng.permutation(n)[:5])]
+    for qs in cases:
+        u = random_unitary(32, rng)
+        t = dev(psi0, torch.complex64)
+        qc.apply_fused_k(t, qs, u)
+        check(host(t), oracle.apply(psi0, qs, u), torch.complex64, ngates=8)
+
+
+# ---------------------------------------------------------------- circuits
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_brickwork12_config(qc, G, dt, mode):
+    """12-qubit brickwork, 20 layers of Haar U(2) + CNOT (350 gates) from
+    |0..0>: full state and all 4096 probabilities."""
+    n, ops = W.config_brickwork12()
+    ref = oracle.run(ops, oracle.basis_state(n, 0))
+    t = qc.new_state(n, DT[dt])
+    qc.state_init(t, 0)
+    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=mode, fuse_k=5)
+    assert st["gates"] == len(ops)
+    check(host(t), ref, DT[dt], ngates=len(ops))
+    p = qc.probs(t).cpu().numpy()
+    tol = 1e-13 if dt == "c128" else 1e-6
+    assert np.max(np.abs(p - oracle.probs(ref))) < tol
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_qft_random_state(qc, G, dt, mode):
+    n = 14
+    psi0 = W.random_state(n, 28)
+    ops = W.qft(n)
+    ref = oracle.run(ops, psi0)
+    t = dev(psi0, DT[dt])
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=mode, fuse_k=5)
+    check(host(t), ref, DT[dt], ngates=len(ops))
+
+
+def test_qft28_sampled_amplitudes(qc, G):
+    """28-qubit QFT on the seeded Gaussian state (4 GiB complex128): sampled
+    output amplitudes against the oracle's discrete Fourier sum, and the
+    complex64 run against the complex128 run."""
+    n, ops, psi0 = W.config_qft28()
+    gl = qc.GateList(G.gate_tuples(ops))
+    t = dev(psi0, torch.complex128)
+    qc.apply_circuit(t, gl, mode=0)
+    t64 = dev(psi0, torch.complex64)
+    qc.apply_circuit(t64, gl, mode=1, fuse_k=5)
+    torch.cuda.synchronize()
+    for y in (0, 1, 123456789 % (1 << n), (1 << n) - 1):
+        ref = oracle.qft_amplitude(psi0, y)
+        got = complex(t[y].item())
+        assert abs(got - ref) < 1e-12, (y, got, ref)
+    d = qc.state_diff(t64, t).cpu().numpy()
+    assert math.sqrt(d[0] / d[1]) < 1e-5
+    del t, t64
+    torch.cuda.empty_cache()
+
+
+def test_paper_examples_on_gpu(qc, G):
+    """Bell, Grover and the error-correction circuit of the paper, run
+    through the GPU path (the measured qubits of the error-correction
+    circuit have a certain outcome, so measuring them leaves the state as
+    is)."""
+    # Bell: P = 0.5 / 0.5 on |00>, |11>
+    t = qc.new_state(2, torch.complex128)
+    qc.state_init(t, 0)
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples([W.Op("H", (0,)), W.Op("CNOT", (0, 1))])))
+    np.testing.assert_allclose(qc.probs(t).cpu().numpy(), [0.5, 0, 0, 0.5], atol=1e-15)
+    # Grover on two qubits finds |11> with probability 1
+    H0, H1 = W.Op("H", (0,)), W.Op("H", (1,))
+    ops = [H0, H1, W.Op("CZ", (0, 1)), H0, H1, W.Op("Z", (0,)), W.Op("Z", (1,)),
+           W.Op("CZ", (0, 1)), H0, H1]
+    qc.state_init(t, 0)
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)))
+    np.testing.assert_allclose(qc.probs(t).cpu().numpy(), [0, 0, 0, 1], atol=1e-15)
+    # error correction: syndrome '11' with probability 1, final state
+    v = np.array([1.0, 1j]) / math.sqrt(2)
+    init = np.kron(v, np.eye(16)[:, 0])
+    ops = [W.Op("CNOT", (0, 1)), W.Op("CNOT", (0, 2)), W.Op("X", (0,)), W.Op("CNOT", (0, 3)),
+           W.Op("CNOT", (1, 3)), W.Op("CNOT", (0, 4)), W.Op("CNOT", (2, 4)),
+           W.Op("MCX", (3, 4, 2), ctrl_val=(0, 1)), W.Op("MCX", (3, 4, 1), ctrl_val=(1, 0)),
+           W.Op("MCX", (3, 4, 0), ctrl_val=(1, 1))]
+    t = dev(init, torch.complex128)
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)))
+    np.testing.assert_allclose(qc.probs(t, [3, 4]).cpu().numpy(), [0, 0, 0, 1], atol=1e-15)
+    ref = np.zeros(32, complex)
+    ref[0b00011], ref[0b11111] = 1 / math.sqrt(2), 1j / math.sqrt(2)
+    np.testing.assert_allclose(host(t), ref, atol=1e-15)
+
+
+# ---------------------------------------------------------------- reductions
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_probs_full_and_marginal(qc, dt):
+    n = 13
+    psi0 = W.random_state(n, 13)
+    t = dev(psi0, DT[dt])
+    ref_state = host(t)   # the rounded state the GPU actually holds
+    tol = 1e-15
+    np.testing.assert_allclose(qc.probs(t).cpu().numpy(), oracle.probs(ref_state), atol=tol)
+    for qs in ([0], [12], [5, 2], [12, 0, 6], list(range(8)), list(reversed(range(n))),
+               [3, 9, 1, 11, 7, 0]):
+        got = qc.probs(t, qs).cpu().numpy()
+        np.testing.assert_allclose(got, oracle.probs(ref_state, qs), atol=1e-14)
+    assert abs(qc.probs(t, [4]).cpu().numpy().sum() - 1) < (1e-13 if dt == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_expect_pauli_random_terms(qc, dt):
+    n = 11
+    rng = np.random.default_rng(4)
+    psi0 = W.random_state(n, 21)
+    t = dev(psi0, DT[dt])
+    st = host(t)
+    terms = [("".join(rng.choice(list("IXYZ"), n)), float(rng.normal())) for _ in range(40)]
+    terms += [("I" * n, 0.5), ("X" * n, 1.0), ("Y" * n, -1.0), ("Z" * n, 2.0)]
+    out = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    ref_terms = np.array([oracle.expect_pauli(st, p).real for p, _ in terms])
+    np.testing.assert_allclose(out[1:], ref_terms, atol=1e-13)
+    assert abs(out[0] - sum(c * r for (_, c), r in zip(terms, ref_terms))) < 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_tfim_energy_after_hea(qc, G, dt):
+    n = 14
+    theta = np.random.default_rng(5).uniform(0, 2 * math.pi, 4 * n * 2)
+    ops = W.hea(n, 4)
+    ref = oracle.run(ops, oracle.basis_state(n, 0), theta)
+    terms = W.tfim_terms(n)
+    e_ref = oracle.energy(ref, terms)
+    t = qc.new_state(n, DT[dt])
+    qc.state_init(t, 0)
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops, theta)))
+    e = qc.expect_pauli(t, terms)[0].item()
+    tol = 1e-11 * len(terms) if dt == "c128" else 2 * (2 * n - 1) * 1e-5
+    assert abs(e - e_ref) < tol
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_state_diff(qc, dt):
+    n = 12
+    a0, b0 = W.random_state(n, 1), W.random_state(n, 2)
+    a, b = dev(a0, DT[dt]), dev(b0, torch.complex128)
+    d = qc.state_diff(a, b).cpu().numpy()
+    ah = host(a)
+    assert abs(d[0] - np.sum(np.abs(ah - b0) ** 2)) < 1e-12
+    assert abs(d[1] - np.sum(np.abs(b0) ** 2)) < 1e-12
+    assert abs(d[2] - np.max(np.abs(ah - b0))) < 1e-12
+
+
+# ---------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_gradient_vs_parameter_shift(qc, dt):
+    n, layers = 8, 3
+    ops = W.hea(n, layers)
+    terms = W.tfim_terms(n)
+    theta = np.random.default_rng(24).uniform(0, 2 * math.pi, layers * n * 2)
+    psi0 = oracle.basis_state(n, 0)
+    g_ref = oracle.param_shift_grad(ops, theta, terms, psi0)
+    e_ref = oracle.energy(oracle.run(ops, psi0, theta), terms)
+    psi = qc.new_state(n, DT[dt])
+    lam = qc.new_state(n, DT[dt])
+    qc.state_init(psi, 0)
+    e, g = qc.adjoint_grad(psi, lam, ops, theta, terms)
+    e, g = e.item(), g.cpu().numpy()
+    if dt == "c128":
+        assert abs(e - e_ref) < 1e-11
+        np.testing.assert_allclose(g, g_ref, atol=1e-9)
+        # the backward pass un-computes the forward pass
+        back = host(psi)
+        assert np.max(np.abs(back - psi0)) < 1e-12
+    else:
+        bound = 2 * (2 * n - 1) * 1e-5
+        assert abs(e - e_ref) < bound
+        assert np.max(np.abs(g - g_ref)) < bound
+
+
+def test_adjoint_shared_parameters_and_all_kinds(qc):
+    n = 5
+    ops = [W.Op("H", (0,)), W.Op("RX", (1,), pidx=0), W.Op("RY", (2,), pidx=0),
+           W.Op("CNOT", (1, 3)), W.Op("RZ", (3,), pidx=1), W.Op("Y", (4,)), W.Op("CZ", (0, 4)),
+           W.Op("RY", (4,), pidx=2), W.Op("X", (2,)), W.Op("Z", (1,)), W.Op("RX", (0,), pidx=1)]
+    terms = [("ZZIII", 1.0), ("IXYII", -0.5), ("YIIZX", 0.3), ("IIIIX", 2.0)]
+    theta = np.array([0.3, -1.2, 2.2])
+    psi0 = W.random_state(n, 77)
+    g_ref = oracle.param_shift_grad(ops, theta, terms, psi0)
+    psi = dev(psi0, torch.complex128)
+    lam = qc.new_state(n, torch.complex128)
+    e, g = qc.adjoint_grad(psi, lam, ops, theta, terms)
+    np.testing.assert_allclose(g.cpu().numpy(), g_ref, atol=1e-12)
+    assert abs(e.item() - oracle.energy(oracle.run(ops, psi0, theta), terms)) < 1e-12
+
+
+def test_deterministic_reductions(qc):
+    n = 16
+    t = dev(W.random_state(n, 3), torch.complex64)
+    terms = W.tfim_terms(n)
+    a = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    b = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    assert np.array_equal(a, b)
+    p1 = qc.probs(t, [3, 1]).cpu().numpy()
+    p2 = qc.probs(t, [3, 1]).cpu().numpy()
+    assert np.array_equal(p1, p2)
