@@ -90,6 +90,10 @@ typedef struct {
 #define QC_EXEC_UNFUSED 0   /* one launch (one state sweep) per gate          */
 #define QC_EXEC_FUSED   1   /* fuse into <= fuse_k-qubit blocks (FP64 products),
                                one sweep per block                            */
+#define QC_EXEC_TILED   2   /* group gates into runs whose non-diagonal
+                               targets fit one LDS tile of 2^12 (complex128)
+                               or 2^13 (complex64) amplitudes; one sweep per
+                               run, gates applied one by one inside LDS      */
 
 /* Counters filled by qc_apply_circuit (may be NULL). */
 typedef struct {
@@ -170,7 +174,10 @@ int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, vo
 /* Apply a gate list in order.  mode QC_EXEC_UNFUSED launches one kernel per
  * gate; QC_EXEC_FUSED first groups consecutive gates into blocks of at most
  * fuse_k qubits (host FP64 matrix products, see qc_fuse_plan) and applies
- * each block with qc_apply_fused_k.  stats may be NULL. */
+ * each block with qc_apply_fused_k; QC_EXEC_TILED applies runs of gates in
+ * LDS tiles (fuse_k is ignored).  Gates may be reordered only past gates on
+ * disjoint qubits, so the result is the ordered product.  stats may be
+ * NULL. */
 int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode,
                      int fuse_k, qc_exec_stats_t *stats, void *stream);
 

@@ -466,7 +466,7 @@ int fused_apply(qc_state_t s, int k, const int *qubits, const std::vector<cd> &u
     }
     void *dev = nullptr;
     hipError_t e;
-    if (s.dtype == QC_C64 && k == 5 && s.n >= 10) {
+    if (s.dtype == QC_C64 && k == 5 && s.n >= 12) {
         std::vector<float> op;
         mfma_operand_c64(u, op);
         if ((rc = stage(c, op.data(), op.size() * sizeof(float), stream, &dev))) return rc;
@@ -484,6 +484,188 @@ int fused_apply(qc_state_t s, int k, const int *qubits, const std::vector<cd> &u
         e = qcx::launch_fused_valu(s.amp, s.dtype, s.n, g, dev, stream);
     }
     return e == hipSuccess ? QC_OK : hip_fail(e, "apply_fused_k");
+}
+
+// One gate, one launch (the plain per-gate path).
+int apply_gate_unfused(qc_state_t s, const qc_gate_t &g, qc_exec_stats_t &st, void *stream) {
+    const double sweep = sweep_bytes(s.n, s.dtype);
+    const int nq = g.n_targets + g.n_ctrls;
+    int rc;
+    if (g.n_targets == 1) {
+        rc = g.n_ctrls ? qc_apply_controlled(s, g.n_ctrls, g.ctrls, g.ctrl_vals, g.targets[0],
+                                             g.matrix, stream)
+                       : qc_apply_1q(s, g.targets[0], g.matrix, stream);
+        const double *u = g.matrix;
+        const bool phase_only = g.n_ctrls && u[2] == 0 && u[3] == 0 && u[4] == 0 && u[5] == 0 &&
+                                u[0] == 1.0 && u[1] == 0;
+        st.state_bytes += sweep / double(uint64_t(1) << (g.n_ctrls + (phase_only ? 1 : 0)));
+    } else if (g.n_targets == 2 && g.n_ctrls == 0) {
+        rc = qc_apply_2q(s, g.targets[0], g.targets[1], g.matrix, stream);
+        st.state_bytes += sweep;
+    } else if (nq <= QC_MAX_FUSED) {
+        int bq[QC_MAX_FUSED];
+        for (int j = 0; j < g.n_targets; ++j) bq[j] = g.targets[j];
+        for (int j = 0; j < g.n_ctrls; ++j) bq[g.n_targets + j] = g.ctrls[j];
+        std::vector<const qc_gate_t *> one{&g};
+        rc = fused_apply(s, nq, bq, block_matrix(nq, bq, one), (hipStream_t)stream);
+        st.state_bytes += sweep;
+    } else {
+        rc = fail(QC_ERR_UNSUPPORTED, "gate with more than 5 qubits and targets > 1");
+    }
+    if (rc == QC_OK) {
+        st.launches += 1;
+        st.sweeps += 1;
+    }
+    return rc;
+}
+
+// ---- LDS tile runs -----------------------------------------------------------
+
+struct TileClass {
+    bool tileable;      // one- or two-target gate
+    uint64_t tbits;     // bit positions that must be tile bits
+    uint64_t touch;     // qubit labels the gate involves
+};
+
+bool is_diag_1q(const double *u) { return u[2] == 0 && u[3] == 0 && u[4] == 0 && u[5] == 0; }
+
+TileClass tile_class(int n, const qc_gate_t &g) {
+    TileClass c{};
+    c.touch = gate_mask(g);
+    if (g.n_targets == 1) {
+        c.tileable = true;
+        c.tbits = is_diag_1q(g.matrix) ? 0 : uint64_t(1) << bitpos(n, g.targets[0]);
+    } else if (g.n_targets == 2) {
+        c.tileable = true;
+        c.tbits = (uint64_t(1) << bitpos(n, g.targets[0])) | (uint64_t(1) << bitpos(n, g.targets[1]));
+    }
+    return c;
+}
+
+// Convert a gate into tile ops for the tile bit set P (bit-position mask).
+void tile_ops_for(int n, const qc_gate_t &g, uint64_t P, std::vector<qcx::TileOp> &out) {
+    auto cidx = [&](int p) { return __builtin_popcountll(P & ((uint64_t(1) << p) - 1)); };
+    auto in_tile = [&](int p) { return (P >> p) & 1; };
+    qcx::TileOp op{};
+    for (int j = 0; j < g.n_ctrls; ++j) {
+        const int p = bitpos(n, g.ctrls[j]);
+        if (in_tile(p)) {
+            op.cmask_lo |= 1u << cidx(p);
+            if (g.ctrl_vals[j]) op.cval_lo |= 1u << cidx(p);
+        } else {
+            op.cmask_hi |= uint64_t(1) << p;
+            if (g.ctrl_vals[j]) op.cval_hi |= uint64_t(1) << p;
+        }
+    }
+    const double *u = g.matrix;
+    auto add_cond = [&](qcx::TileOp &o, int p, int v) {
+        if (in_tile(p)) {
+            o.cmask_lo |= 1u << cidx(p);
+            if (v) o.cval_lo |= 1u << cidx(p);
+        } else {
+            o.cmask_hi |= uint64_t(1) << p;
+            if (v) o.cval_hi |= uint64_t(1) << p;
+        }
+    };
+    if (g.n_targets == 1) {
+        const int tp = bitpos(n, g.targets[0]);
+        if (!is_diag_1q(u)) {
+            op.kind = qcx::TILE_DENSE1;
+            op.b0 = cidx(tp);
+            for (int i = 0; i < 8; ++i) op.u[i] = u[i];
+            out.push_back(op);
+        } else if (u[0] == 1.0 && u[1] == 0.0) {
+            op.kind = qcx::TILE_PHASE;
+            add_cond(op, tp, 1);
+            op.u[0] = u[6];
+            op.u[1] = u[7];
+            out.push_back(op);
+        } else if (in_tile(tp)) {
+            op.kind = qcx::TILE_DIAG1;
+            op.b0 = cidx(tp);
+            op.u[0] = u[0];
+            op.u[1] = u[1];
+            op.u[2] = u[6];
+            op.u[3] = u[7];
+            out.push_back(op);
+        } else {
+            for (int v = 0; v < 2; ++v) {
+                qcx::TileOp o = op;
+                o.kind = qcx::TILE_PHASE;
+                add_cond(o, tp, v);
+                o.u[0] = u[v ? 6 : 0];
+                o.u[1] = u[v ? 7 : 1];
+                out.push_back(o);
+            }
+        }
+    } else {
+        op.kind = qcx::TILE_DENSE2;
+        op.b0 = cidx(bitpos(n, g.targets[0]));
+        op.b1 = cidx(bitpos(n, g.targets[1]));
+        for (int i = 0; i < 32; ++i) op.u[i] = u[i];
+        out.push_back(op);
+    }
+}
+
+int tile_bits_for(const qc_state_t &s) { return std::min(s.n, s.dtype == QC_C64 ? 13 : 12); }
+
+// Greedy run formation: starting from the earliest pending gate, a gate
+// joins the run when none of its qubits is held by an earlier gate left out
+// and its non-diagonal targets still fit in the m tile bits.
+int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st,
+                  void *stream) {
+    DevCtx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    const int n = s.n;
+    const int m = tile_bits_for(s);
+    const int low = std::min(m, 5);      // always-resident low bits: runs of >= 32 amplitudes
+    const uint64_t low_mask = (uint64_t(1) << low) - 1;
+    const uint64_t all = (uint64_t(1) << n) - 1;
+    const hipStream_t hs = (hipStream_t)stream;
+    std::vector<int> pending(ng);
+    for (int i = 0; i < ng; ++i) pending[i] = i;
+    std::vector<qcx::TileOp> ops;
+    while (!pending.empty()) {
+        const TileClass first = tile_class(n, gs[pending[0]]);
+        if (!first.tileable) {
+            if ((rc = apply_gate_unfused(s, gs[pending[0]], st, stream))) return rc;
+            pending.erase(pending.begin());
+            continue;
+        }
+        uint64_t P = low_mask, blocked = 0;
+        std::vector<int> run, rest;
+        for (int idx : pending) {
+            const TileClass tc = tile_class(n, gs[idx]);
+            if (!(tc.touch & blocked) && tc.tileable &&
+                __builtin_popcountll(P | tc.tbits) <= m && blocked != all) {
+                P |= tc.tbits;
+                run.push_back(idx);
+            } else {
+                blocked |= tc.touch;
+                rest.push_back(idx);
+            }
+        }
+        for (int p = 0; __builtin_popcountll(P) < m && p < n; ++p) P |= uint64_t(1) << p;
+        ops.clear();
+        for (int idx : run) tile_ops_for(n, gs[idx], P, ops);
+        qcx::TileArgs a{};
+        a.m = m;
+        a.n_ops = int(ops.size());
+        a.n_tiles = uint64_t(1) << (n - m);
+        for (int p = 0, j = 0; p < n; ++p)
+            if ((P >> p) & 1) a.pos[j++] = uint8_t(p);
+        void *dev = nullptr;
+        if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
+        hipError_t e = qcx::launch_tile_run(s.amp, s.dtype, n, a,
+                                            static_cast<const qcx::TileOp *>(dev), hs);
+        if (e != hipSuccess) return hip_fail(e, "tile_run");
+        st.launches += 1;
+        st.sweeps += 1;
+        st.state_bytes += sweep_bytes(n, s.dtype);
+        pending.swap(rest);
+    }
+    return QC_OK;
 }
 
 }  // namespace
@@ -523,7 +705,8 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     int rc = check_state(s);
     if (rc) return rc;
     if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(QC_ERR_ARG, "gate list is NULL");
-    if (mode != QC_EXEC_UNFUSED && mode != QC_EXEC_FUSED) return fail(QC_ERR_ARG, "unknown mode");
+    if (mode != QC_EXEC_UNFUSED && mode != QC_EXEC_FUSED && mode != QC_EXEC_TILED)
+        return fail(QC_ERR_ARG, "unknown mode");
     if (mode == QC_EXEC_FUSED && (fuse_k < 1 || fuse_k > QC_MAX_FUSED || fuse_k > s.n))
         return fail(QC_ERR_ARG, "fuse_k out of range");
     for (int i = 0; i < n_gates; ++i)
@@ -533,34 +716,10 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     const hipStream_t hs = (hipStream_t)stream;
     const double sweep = sweep_bytes(s.n, s.dtype);
     if (mode == QC_EXEC_UNFUSED) {
-        for (int i = 0; i < n_gates; ++i) {
-            const qc_gate_t &g = gates[i];
-            const int nq = g.n_targets + g.n_ctrls;
-            if (g.n_targets == 1) {
-                rc = g.n_ctrls ? qc_apply_controlled(s, g.n_ctrls, g.ctrls, g.ctrl_vals, g.targets[0],
-                                                     g.matrix, stream)
-                               : qc_apply_1q(s, g.targets[0], g.matrix, stream);
-                const double *u = g.matrix;
-                const bool phase_only = g.n_ctrls && u[2] == 0 && u[3] == 0 && u[4] == 0 &&
-                                        u[5] == 0 && u[0] == 1.0 && u[1] == 0;
-                st.state_bytes += sweep / double(uint64_t(1) << (g.n_ctrls + (phase_only ? 1 : 0)));
-            } else if (g.n_targets == 2 && g.n_ctrls == 0) {
-                rc = qc_apply_2q(s, g.targets[0], g.targets[1], g.matrix, stream);
-                st.state_bytes += sweep;
-            } else if (nq <= QC_MAX_FUSED) {
-                int bq[QC_MAX_FUSED];
-                for (int j = 0; j < g.n_targets; ++j) bq[j] = g.targets[j];
-                for (int j = 0; j < g.n_ctrls; ++j) bq[g.n_targets + j] = g.ctrls[j];
-                std::vector<const qc_gate_t *> one{&g};
-                rc = fused_apply(s, nq, bq, block_matrix(nq, bq, one), hs);
-                st.state_bytes += sweep;
-            } else {
-                rc = fail(QC_ERR_UNSUPPORTED, "gate with more than 5 qubits and targets > 1");
-            }
-            if (rc) return rc;
-            st.launches += 1;
-            st.sweeps += 1;
-        }
+        for (int i = 0; i < n_gates; ++i)
+            if ((rc = apply_gate_unfused(s, gates[i], st, stream))) return rc;
+    } else if (mode == QC_EXEC_TILED) {
+        if ((rc = tiled_execute(s, n_gates, gates, st, stream))) return rc;
     } else {
         std::vector<int> bo;
         int nb = 0;

@@ -6,25 +6,25 @@
 // most significant bit of t), column c runs over the other bits.  This is
 // the I_l (x) U' (x) I_r product of QCLAB section 3.2 for a 5-qubit U'.
 //
-// Work decomposition: one wavefront owns a tile of 32 rows x 32 columns
-// (1024 amplitudes).  Tile bits = the 5 target bits plus the 5 lowest
-// other bits; bits 0..4 are therefore always tile bits, so every tile is a
-// set of contiguous runs of at least 32 amplitudes (256 bytes) in HBM.
+// Work decomposition: a workgroup of 4 wavefronts owns a tile of 32 rows x
+// 128 columns (4096 amplitudes, 32 KiB).  Tile bits = the 5 target bits plus
+// the 7 lowest other bits; bits 0..6 are therefore always tile bits, so a
+// tile is a set of contiguous runs of at least 128 amplitudes (1 KiB) in
+// HBM whatever the target positions.
 //
-//  1. Global -> registers in memory order (lane l, step s: tile element
-//     j = l + 64 s), fully coalesced whatever the target positions.
-//  2. Registers -> LDS at a swizzled slot sw(j) = j ^ M(j >> 5), with M a
-//     5x5 GF(2) matrix chosen on the host so that both the memory-order
-//     accesses and the matrix-operand accesses (32 lanes = 32 columns of one
-//     row) hit 32 distinct 8-byte slots, i.e. no LDS bank conflicts.
-//  3. LDS -> operand registers and 48 v_mfma_f32_32x32x2_f32: the complex
-//     product uses the 3M form  P1 = Ur Xr, P2 = Ui Xi,
-//     P3 = (Ur + Ui)(Xr + Xi),  Yr = P1 - P2,  Yi = P3 - P1 - P2
-//     (3 real 32x32x32 products instead of 4).
+//  1. Global -> registers in memory order, 16 bytes per lane (tile element
+//     pair j, j+1 with j = 2 tid + 512 s), fully coalesced.
+//  2. Registers -> LDS at the swizzled slot sw(j) = j ^ M(j >> 5), M a 5x7
+//     GF(2) matrix chosen on the host so that the 32 columns of one matrix
+//     row read by a half-wavefront land in 32 distinct 8-byte slots (no LDS
+//     bank conflicts) wherever the target bits are.
+//  3. Wave w multiplies columns 32w..32w+31: LDS -> operand registers, 48
+//     v_mfma_f32_32x32x2_f32 in the 3M form  P1 = Ur Xr, P2 = Ui Xi,
+//     P3 = (Ur + Ui)(Xr + Xi),  Yr = P1 - P2,  Yi = P3 - P1 - P2.
 //  4. Accumulators -> LDS (same swizzle) -> registers in memory order ->
-//     global, again fully coalesced.
-// The U operands stay in VGPRs for the whole kernel; the next tile's global
-// loads are in flight while the current tile is multiplied.
+//     global, 16 bytes per lane.
+// U stays in VGPRs for the whole kernel; the next tile's loads are in
+// flight while the current tile is multiplied.
 //
 // Register layouts of v_mfma_f32_32x32x2_f32 (one block, wave64):
 //   A (32x2):  lane l holds A[l % 32][l / 32]
@@ -42,34 +42,40 @@ namespace qcx {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWG = 256;
+constexpr int kTileBits = 12;     // 5 target bits + 7 column bits
+constexpr int kColBits = 7;
+constexpr int kSwzBits = kTileBits - 5;
 
 struct MfmaArgs {
     cx<float> *amp;
     const float *a_ops;         // [3][32][32]: Ur, Ui, Ur + Ui (row = output t)
     uint64_t n_tiles;
-    uint64_t off_s[16];         // address offset of tile element (s << 6)
-    uint8_t tile_pos[10];       // ascending bit positions of the tile bits
-    uint16_t mcol[5];           // swizzle matrix columns
-    uint16_t col_dep[5];        // compressed index of column bit i
+    uint64_t off_s[8];          // address offset of tile element 512 s
+    uint8_t tile_pos[kTileBits];  // ascending bit positions of the tile bits
+    uint16_t mcol[kSwzBits];    // swizzle matrix columns (bits 5..11 of j)
+    uint16_t col_dep[kColBits];  // compressed index of column bit i
     uint16_t t16, t4;           // compressed index of target local 16 and 4
-    uint16_t sw_mem_s[16];      // sw(s << 6)
+    uint16_t sw_mem_s[8];       // sw(512 s)
     uint16_t sw_rd_s[16];       // sw(dep_T(s))
     uint16_t sw_out_s[16];      // sw(dep_T(8 (r/4) + r % 4))
 };
 
 __device__ inline uint32_t swz(uint32_t j, const uint16_t *mcol) {
-    uint32_t h = j >> 5, m = 0;
+    uint32_t m = 0;
 #pragma unroll
-    for (int b = 0; b < 5; ++b)
-        if ((h >> b) & 1) m ^= mcol[b];
+    for (int b = 0; b < kSwzBits; ++b)
+        if ((j >> (5 + b)) & 1) m ^= mcol[b];
     return j ^ m;
 }
 
-constexpr int kWave = 64;
-
-__global__ __launch_bounds__(kWave) void k_fused_mfma_c64(const MfmaArgs a) {
-    __shared__ float2 lds[1024];
-    const int l = threadIdx.x;
+__global__ __launch_bounds__(kWG) void k_fused_mfma_c64(const MfmaArgs a) {
+    __shared__ float2 lds[1 << kTileBits];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int l = tid & 63;
     const int h = l >> 5;
     const int nidx = l & 31;
 
@@ -83,40 +89,48 @@ __global__ __launch_bounds__(kWave) void k_fused_mfma_c64(const MfmaArgs a) {
         as[s] = a.a_ops[2048 + idx];
     }
 
-    // per-lane address and LDS slot constants
-    uint64_t off_lane = 0;
+    // memory-order constants: this thread moves elements 2 tid + 512 s (+1)
+    uint64_t off_thr = 0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
-        if ((l >> b) & 1) off_lane |= uint64_t(1) << a.tile_pos[b];
+    for (int b = 0; b < 8; ++b)
+        if ((tid >> b) & 1) off_thr |= uint64_t(1) << a.tile_pos[b + 1];
+    const uint32_t sw_thr = swz(uint32_t(2 * tid), a.mcol);
+    // operand constants: column n = nidx + 32 wave
+    const int ncol = nidx + 32 * wave;
     uint32_t cdep = 0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
-        if ((nidx >> i) & 1) cdep |= uint32_t(1) << a.col_dep[i];
-    const uint32_t sw_mem_l = swz(uint32_t(l), a.mcol);
+    for (int i = 0; i < kColBits; ++i)
+        if ((ncol >> i) & 1) cdep |= uint32_t(1) << a.col_dep[i];
     const uint32_t sw_rd_l = swz(cdep | (h ? a.t16 : 0u), a.mcol);
     const uint32_t sw_out_l = swz(cdep | (h ? a.t4 : 0u), a.mcol);
 
     uint64_t tile = blockIdx.x;
     if (tile >= a.n_tiles) return;
-    float2 g[16];
-    uint64_t base = insert_zeros(tile, a.tile_pos, 10);
+    floatx4 g[8];
+    uint64_t base = insert_zeros(tile, a.tile_pos, kTileBits);
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-        g[s] = *reinterpret_cast<const float2 *>(&a.amp[base + off_lane + a.off_s[s]]);
+    for (int s = 0; s < 8; ++s)
+        g[s] = __builtin_nontemporal_load(
+            reinterpret_cast<const floatx4 *>(&a.amp[base + off_thr + a.off_s[s]]));
 
     for (;;) {
         // 2. stage the tile in LDS
 #pragma unroll
-        for (int s = 0; s < 16; ++s) lds[sw_mem_l ^ a.sw_mem_s[s]] = g[s];
+        for (int s = 0; s < 8; ++s) {
+            const uint32_t slot = sw_thr ^ a.sw_mem_s[s];
+            lds[slot] = make_float2(g[s][0], g[s][1]);
+            lds[slot ^ 1u] = make_float2(g[s][2], g[s][3]);
+        }
         __syncthreads();
         // prefetch the next tile while this one is multiplied
         const uint64_t next = tile + gridDim.x;
         const bool more = next < a.n_tiles;
-        const uint64_t nbase = more ? insert_zeros(next, a.tile_pos, 10) : 0;
+        const uint64_t nbase = more ? insert_zeros(next, a.tile_pos, kTileBits) : 0;
         if (more) {
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                g[s] = *reinterpret_cast<const float2 *>(&a.amp[nbase + off_lane + a.off_s[s]]);
+            for (int s = 0; s < 8; ++s)
+                g[s] = __builtin_nontemporal_load(
+                    reinterpret_cast<const floatx4 *>(&a.amp[nbase + off_thr + a.off_s[s]]));
         }
         // 3. operands and 3M products
         floatx16 p1 = {0}, p2 = {0}, p3 = {0};
@@ -138,9 +152,12 @@ __global__ __launch_bounds__(kWave) void k_fused_mfma_c64(const MfmaArgs a) {
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
-            *reinterpret_cast<float2 *>(&a.amp[base + off_lane + a.off_s[s]]) =
-                lds[sw_mem_l ^ a.sw_mem_s[s]];
+        for (int s = 0; s < 8; ++s) {
+            const uint32_t slot = sw_thr ^ a.sw_mem_s[s];
+            const float2 y0 = lds[slot], y1 = lds[slot ^ 1u];
+            const floatx4 v = {y0.x, y0.y, y1.x, y1.y};
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(&a.amp[base + off_thr + a.off_s[s]]));
+        }
         if (!more) break;
         __syncthreads();
         tile = next;
@@ -150,7 +167,7 @@ __global__ __launch_bounds__(kWave) void k_fused_mfma_c64(const MfmaArgs a) {
 
 // ---- host-side geometry ------------------------------------------------------
 
-// GF(2) rank of up to 5 column vectors of 5 bits
+// GF(2) rank of up to 8 vectors of 5 bits
 int rank5(const uint32_t *cols, int n) {
     uint32_t v[8];
     for (int i = 0; i < n; ++i) v[i] = cols[i];
@@ -169,31 +186,30 @@ int rank5(const uint32_t *cols, int n) {
 }
 
 uint32_t apply_m(uint32_t j, const uint16_t *mcol) {
-    uint32_t h = j >> 5, m = 0;
-    for (int b = 0; b < 5; ++b)
-        if ((h >> b) & 1) m ^= mcol[b];
+    uint32_t m = 0;
+    for (int b = 0; b < kSwzBits; ++b)
+        if ((j >> (5 + b)) & 1) m ^= mcol[b];
     return j ^ m;
 }
 
-// Choose M so that the 32 column slots of a matrix row are 32 distinct
-// low-5-bit values after swizzling: the map n -> low5(sw(dep_C(n))) must be
-// invertible over GF(2).
+// Choose M so that the 32 columns n0 = 0..31 of a matrix row map to 32
+// distinct low-5-bit slots: n0 -> low5(sw(dep_C(n0))) invertible over GF(2).
 void choose_swizzle(const uint16_t *col_dep, uint16_t *mcol) {
     auto ok = [&](const uint16_t *m) {
         uint32_t img[5];
         for (int i = 0; i < 5; ++i) img[i] = apply_m(uint32_t(1) << col_dep[i], m) & 31u;
         return rank5(img, 5) == 5;
     };
-    uint16_t m[5] = {0, 0, 0, 0, 0};
-    if (ok(m)) { std::copy(m, m + 5, mcol); return; }
-    for (int b = 0; b < 5; ++b) m[b] = uint16_t(1u << b);
-    if (ok(m)) { std::copy(m, m + 5, mcol); return; }
+    uint16_t m[kSwzBits] = {};
+    if (ok(m)) { std::copy(m, m + kSwzBits, mcol); return; }
+    for (int b = 0; b < kSwzBits; ++b) m[b] = uint16_t(b < 5 ? 1u << b : 0u);
+    if (ok(m)) { std::copy(m, m + kSwzBits, mcol); return; }
     std::mt19937 rng(12345);
-    for (int tries = 0; tries < 100000; ++tries) {
-        for (int b = 0; b < 5; ++b) m[b] = uint16_t(rng() & 31u);
-        if (ok(m)) { std::copy(m, m + 5, mcol); return; }
+    for (int tries = 0; tries < 200000; ++tries) {
+        for (int b = 0; b < kSwzBits; ++b) m[b] = uint16_t(rng() & 31u);
+        if (ok(m)) { std::copy(m, m + kSwzBits, mcol); return; }
     }
-    for (int b = 0; b < 5; ++b) mcol[b] = uint16_t(1u << b);  // unreachable in practice
+    for (int b = 0; b < kSwzBits; ++b) mcol[b] = 0;  // correct, possibly with conflicts
 }
 
 int query_grid_cap() {
@@ -202,7 +218,7 @@ int query_grid_cap() {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        cap = cus * 16;
+        cap = cus * 4;
     }
     return cap;
 }
@@ -211,11 +227,11 @@ int query_grid_cap() {
 
 hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
                                  hipStream_t s) {
-    if (g.k != 5 || n < 10) return hipErrorInvalidValue;
+    if (g.k != 5 || n < kTileBits) return hipErrorInvalidValue;
     MfmaArgs a{};
     a.amp = static_cast<cx<float> *>(amp);
     a.a_ops = a_dev;
-    a.n_tiles = uint64_t(1) << (n - 10);
+    a.n_tiles = uint64_t(1) << (n - kTileBits);
     // target positions, most significant local bit first
     int tpos[5];
     for (int j = 0; j < 5; ++j) {
@@ -224,26 +240,26 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
     }
     uint64_t tmask = 0;
     for (int j = 0; j < 5; ++j) tmask |= uint64_t(1) << tpos[j];
-    int cpos[5], nc = 0;
-    for (int p = 0; p < n && nc < 5; ++p)
+    int cpos[kColBits], nc = 0;
+    for (int p = 0; p < n && nc < kColBits; ++p)
         if (!((tmask >> p) & 1)) cpos[nc++] = p;
-    int tile[10];
+    int tile[kTileBits];
     for (int j = 0; j < 5; ++j) tile[j] = tpos[j];
-    for (int j = 0; j < 5; ++j) tile[5 + j] = cpos[j];
-    std::sort(tile, tile + 10);
+    for (int j = 0; j < kColBits; ++j) tile[5 + j] = cpos[j];
+    std::sort(tile, tile + kTileBits);
     auto cidx = [&](int p) {
-        for (int i = 0; i < 10; ++i)
+        for (int i = 0; i < kTileBits; ++i)
             if (tile[i] == p) return i;
         return -1;
     };
-    for (int i = 0; i < 10; ++i) a.tile_pos[i] = uint8_t(tile[i]);
-    for (int sidx = 0; sidx < 16; ++sidx) {
+    for (int i = 0; i < kTileBits; ++i) a.tile_pos[i] = uint8_t(tile[i]);
+    for (int sidx = 0; sidx < 8; ++sidx) {
         uint64_t off = 0;
-        for (int b = 0; b < 4; ++b)
-            if ((sidx >> b) & 1) off |= uint64_t(1) << tile[6 + b];
+        for (int b = 0; b < 3; ++b)
+            if ((sidx >> b) & 1) off |= uint64_t(1) << tile[9 + b];
         a.off_s[sidx] = off;
     }
-    for (int i = 0; i < 5; ++i) a.col_dep[i] = uint16_t(cidx(cpos[i]));
+    for (int i = 0; i < kColBits; ++i) a.col_dep[i] = uint16_t(cidx(cpos[i]));
     auto dep_t = [&](int t) {
         uint32_t j = 0;
         for (int q = 0; q < 5; ++q)
@@ -253,8 +269,8 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
     choose_swizzle(a.col_dep, a.mcol);
     a.t16 = uint16_t(dep_t(16));
     a.t4 = uint16_t(dep_t(4));
+    for (int sidx = 0; sidx < 8; ++sidx) a.sw_mem_s[sidx] = uint16_t(apply_m(uint32_t(sidx) << 9, a.mcol));
     for (int sidx = 0; sidx < 16; ++sidx) {
-        a.sw_mem_s[sidx] = uint16_t(apply_m(uint32_t(sidx) << 6, a.mcol));
         a.sw_rd_s[sidx] = uint16_t(apply_m(dep_t(sidx), a.mcol));
         a.sw_out_s[sidx] = uint16_t(apply_m(dep_t(8 * (sidx / 4) + sidx % 4), a.mcol));
     }
@@ -262,7 +278,7 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
     const uint64_t cap = uint64_t(query_grid_cap());
     if (grid > cap) grid = cap;
     const int tok = timer_begin("fused_mfma_c64", s);
-    hipLaunchKernelGGL(k_fused_mfma_c64, dim3(unsigned(grid)), dim3(kWave), 0, s, a);
+    hipLaunchKernelGGL(k_fused_mfma_c64, dim3(unsigned(grid)), dim3(kWG), 0, s, a);
     timer_end(tok, s);
     return hipGetLastError();
 }

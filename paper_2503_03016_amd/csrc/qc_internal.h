@@ -84,6 +84,63 @@ struct Mat2d {
     double re[4], im[4];
 };
 
+// One gate of an LDS tile run (positions are compressed tile positions).
+enum TileKind { TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3 };
+constexpr int kTileMaxBits = 16;
+struct TileOp {
+    int32_t kind;
+    int32_t b0, b1;            // targets (b0 = most significant bit of the local index)
+    int32_t pad;
+    uint32_t cmask_lo, cval_lo;  // conditions on tile bits (compressed)
+    uint64_t cmask_hi, cval_hi;  // conditions on bits outside the tile (global)
+    double u[32];              // complex FP64 entries, interleaved
+};
+struct TileArgs {
+    uint64_t n_tiles;
+    int m;                     // tile bits
+    int n_ops;
+    uint8_t pos[kTileMaxBits];  // ascending global bit positions of the tile bits
+};
+
+// ---- batched persistent launch: device program ---------------------------
+enum BatchFlags { BATCH_INIT = 1, BATCH_STORE = 2 };
+struct BatchPhase {
+    uint64_t n_tiles;
+    int32_t m, op_begin, op_count, term_begin, term_count, flags;
+    uint8_t pos[kTileMaxBits];     // ascending global bit positions of the tile bits
+};
+struct BatchTerm {
+    uint64_t z_hi;     // z bits outside the tile (global positions)
+    uint32_t xc, zc;   // x and z inside the tile (compressed positions)
+    double c;          // coefficient
+    int32_t ph;        // number of Y factors mod 4
+    int32_t xtop;      // top bit of xc, -1 when xc == 0
+};
+struct BatchCircuit {
+    uint64_t arena_off;   // element offset of the state in the arena
+    int32_t n, phase_begin, phase_count, large;
+};
+constexpr int kBatchGroup = 8;     // workgroups per group
+struct BatchJob {
+    int32_t kind;                  // 0: bundle of small circuits, 1: one large circuit
+    int32_t circ[kBatchGroup];     // circuit per workgroup (bundle) or circ[0]; -1 = none
+};
+struct BatchArgs {
+    const BatchCircuit *circ;
+    const BatchPhase *phases;
+    const TileOp *ops;
+    const BatchTerm *terms;
+    const BatchJob *jobs;
+    const int32_t *group_jobs;     // CSR over groups (n_groups + 1 entries)
+    void *arena;
+    double *energy;
+    double *partial;               // circuits x G
+    unsigned *barrier;             // n_groups counters, then the error flag
+    unsigned *error;
+    int n_groups;
+    int G;
+};
+
 // ---- launchers (return hipSuccess or the launch error) ----------------------
 hipError_t launch_init(void *amp, int dtype, int n, uint64_t basis, hipStream_t s);
 hipError_t launch_copy(void *dst, int dt_dst, const void *src, int dt_src, uint64_t count,
@@ -108,6 +165,13 @@ hipError_t launch_expect_combine(const double *term_vals, const double *coeff_de
                                  int per_term, double *out, hipStream_t s);
 hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_t count,
                        double *out, double *work, hipStream_t s);
+
+hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
+                           hipStream_t s);
+
+int batch_resident_blocks(int dtype, size_t lds_bytes);
+hipError_t launch_batch(const BatchArgs &a, int dtype, unsigned grid, size_t lds_bytes,
+                        hipStream_t s);
 
 unsigned adjoint_grid(int n);
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,

@@ -1,0 +1,68 @@
+// LDS tile kernel: one pass over the state applies a whole run of gates.
+//
+// A tile is the set of 2^m amplitudes that share every index bit outside a
+// chosen set P of m "tile bits" (P always contains the lowest bits, so a
+// tile is a union of contiguous runs in HBM).  Every gate of the run has its
+// non-diagonal action (its targets) inside P; diagonal gates and controls
+// may sit on any bit, because every bit of every amplitude of a tile is
+// known once the tile is resident.  The kernel loads the tile into LDS with
+// coalesced loads, applies the gates one after the other (one barrier per
+// gate, see qc_tile_ops.h), and writes the tile back: a run of G gates costs
+// one HBM read and one HBM write of the state instead of G of each.
+#include "qc_tile_ops.h"
+
+#include "../../include/qc.h"
+
+namespace qcx {
+
+namespace {
+
+using tile::kBlock;
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs a,
+                                                     const TileOp *ops) {
+    extern __shared__ unsigned char smem[];
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    const int T = 1 << a.m;
+    // the low 8 compressed bits of this thread's elements are fixed
+    const uint64_t off_lo =
+        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < 8 ? a.m : 8);
+    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const uint64_t base = insert_zeros(t, a.pos, a.m);
+        for (int j = threadIdx.x; j < T; j += kBlock)
+            lds[j] = amp[base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m)];
+        __syncthreads();
+        tile::apply_ops<R>(lds, a.m, base, ops, a.n_ops);
+        for (int j = threadIdx.x; j < T; j += kBlock)
+            amp[base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m)] = lds[j];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
+                           hipStream_t s) {
+    if (a.m < 1 || a.m > n || a.m > kTileMaxBits) return hipErrorInvalidValue;
+    const size_t elem = dtype == QC_C64 ? 8 : 16;
+    const size_t lds = (size_t(1) << a.m) * elem;
+    if (lds > 65536) return hipErrorInvalidValue;
+    uint64_t grid = a.n_tiles;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t cap = uint64_t(cus) * 8;
+    if (grid > cap) grid = cap;
+    const int tok = timer_begin(dtype == QC_C64 ? "tile_run_c64" : "tile_run_c128", s);
+    if (dtype == QC_C64)
+        hipLaunchKernelGGL((k_tile_run<float>), dim3(unsigned(grid)), dim3(kBlock), lds, s,
+                           static_cast<cx<float> *>(amp), a, ops_dev);
+    else
+        hipLaunchKernelGGL((k_tile_run<double>), dim3(unsigned(grid)), dim3(kBlock), lds, s,
+                           static_cast<cx<double> *>(amp), a, ops_dev);
+    timer_end(tok, s);
+    return hipGetLastError();
+}
+
+}  // namespace qcx

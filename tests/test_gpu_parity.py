@@ -138,7 +138,7 @@ def test_apply_fused_k_random_qubits(qc, dt, k):
         check(host(t), oracle.apply(psi0, qs, u), DT[dt], ngates=4)
 
 
-@pytest.mark.parametrize("n", [10, 11, 14, 17])
+@pytest.mark.parametrize("n", [12, 13, 16, 20])
 def test_fused_mfma_target_positions(qc, n):
     """The complex64 matrix-core path for every kind of target placement:
     all-low bits, all-high bits, mixed, reversed order, a single tile."""
@@ -156,7 +156,42 @@ def test_fused_mfma_target_positions(qc, n):
 # ---------------------------------------------------------------- circuits
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n", [6, 13, 17])
+def test_tiled_runs_mixed_gates(qc, G, dt, n):
+    """LDS tile runs: dense 1q/2q gates, diagonal gates on bits inside and
+    outside the tile, controls inside and outside the tile, open controls,
+    gates that cannot join a run (3-qubit), across several tiles."""
+    rng = np.random.default_rng(n)
+    ops = []
+    for _ in range(60):
+        kind = rng.integers(0, 8)
+        q = [int(x) for x in rng.permutation(n)[:4]]
+        if kind == 0:
+            ops.append(W.Op("U", (q[0],), matrix=random_unitary(2, rng)))
+        elif kind == 1:
+            ops.append(W.Op("U", (q[0], q[1]), matrix=random_unitary(4, rng)))
+        elif kind == 2:
+            ops.append(W.Op("CZ", (q[0], q[1])))
+        elif kind == 3:
+            ops.append(W.Op("CP", (q[0], q[1]), angle=float(rng.uniform(0, 6))))
+        elif kind == 4:
+            ops.append(W.Op("RZ", (q[0],), angle=float(rng.uniform(0, 6))))
+        elif kind == 5:
+            ops.append(W.Op("MCX", (q[0], q[1], q[2]), ctrl_val=(int(rng.integers(0, 2)), 1)))
+        elif kind == 6 and n >= 4:
+            ops.append(W.Op("U", (q[0], q[1], q[2]), matrix=random_unitary(8, rng)))
+        else:
+            ops.append(W.Op("CNOT", (q[0], q[1])))
+    psi0 = W.random_state(n, 50 + n)
+    ref = oracle.run(ops, psi0)
+    t = dev(psi0, DT[dt])
+    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=2)
+    assert st["sweeps"] < len(ops)
+    check(host(t), ref, DT[dt], ngates=len(ops))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_brickwork12_config(qc, G, dt, mode):
     """12-qubit brickwork, 20 layers of Haar U(2) + CNOT (350 gates) from
     |0..0>: full state and all 4096 probabilities."""
@@ -173,7 +208,7 @@ def test_brickwork12_config(qc, G, dt, mode):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_qft_random_state(qc, G, dt, mode):
     n = 14
     psi0 = W.random_state(n, 28)
