@@ -205,6 +205,29 @@ int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stre
 int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
                     int per_term, double *out_dev, void *stream);
 
+/* Collapse onto outcome `outcome` (0 or 1) of qubit q and renormalise
+ * (section 3.3): with P = sum over indices whose qubit q reads `outcome`
+ * of |psi_i|^2 (FP64), those amplitudes are divided by sqrt(P) and every
+ * other amplitude is set to 0.  prob_dev[0] receives P (device FP64; may be
+ * NULL).  If P == 0 the state is left unchanged (an impossible outcome). */
+int qc_collapse(qc_state_t s, int q, int outcome, double *prob_dev, void *stream);
+
+/* State of the unlisted qubits when the m listed qubits hold `values`
+ * (0/1 each), the reducedStatevector of section 5.1: dst (n - m qubits, the
+ * same element type, remaining qubits in their original order) receives
+ * the amplitudes of src whose listed qubits read `values`, without
+ * renormalisation.  1 <= m < n. */
+int qc_reduced_state(qc_state_t src, int m, const int *qubits, const int *values, qc_state_t dst,
+                     void *stream);
+
+/* Shot sampling from the measurement distribution of all qubits (the
+ * counts of section 5.2).  u_dev holds `shots` caller-supplied uniforms in
+ * [0, 1) (device FP64); out_dev[k] (device int64) receives the first basis
+ * index whose cumulative weight, in index order, exceeds u_dev[k] times
+ * the total weight.  The cumulative weights are FP64.  Needs 12 <= n <= 33
+ * (QC_ERR_UNSUPPORTED otherwise). */
+int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, void *stream);
+
 /* ---- differentiation ------------------------------------------------ */
 
 /* Adjoint-method gradient of E(theta) = <phi|H|phi>, phi = U_L..U_1 psi_in,
@@ -218,6 +241,47 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
 int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
                     const double *theta, int n_params, int n_terms, const char *paulis,
                     const double *coeff, double *energy_dev, double *grad_dev, void *stream);
+
+/* ---- batched persistent launch --------------------------------------- */
+
+/* One circuit of a batch: it starts from |0...0>, applies its gates (one or
+ * two targets each, any controls) and ends with the energy
+ * <H> = sum_t coeff[t] <psi|P_t|psi> (Pauli strings as in qc_expect_pauli).
+ * All host arrays are read during qc_batch_create only. */
+typedef struct {
+    int32_t n;                 /* qubits, 1..30                                */
+    int32_t n_gates;
+    const qc_gate_t *gates;    /* n_targets 1 or 2                             */
+    int32_t n_terms;
+    const char *paulis;        /* n_terms * n characters                       */
+    const double *coeff;       /* n_terms                                      */
+} qc_circuit_t;
+
+typedef struct qc_batch qc_batch_t;   /* opaque, owns a device-resident program */
+
+/* Plan a batch and upload its device program (host-synchronous; allocates
+ * device memory).  Circuits whose state fits one LDS tile (n <= 13 for
+ * QC_C64, n <= 12 for QC_C128) run entirely inside one workgroup; larger
+ * ones run on a group of 8 co-resident workgroups over a state kept in the
+ * arena.  keep_states != 0 also writes every final state to the arena. */
+int qc_batch_create(int n_circuits, const qc_circuit_t *circuits, int dtype, int keep_states,
+                    qc_batch_t **out);
+/* Bytes of caller-owned device memory qc_run_batch needs as its arena, the
+ * persistent grid size and the number of phases in the program. */
+int qc_batch_info(const qc_batch_t *b, uint64_t *arena_bytes, int *grid, int *phases);
+/* Run every circuit of the batch in ONE persistent kernel launch (plus a
+ * tiny kernel that clears the barrier counters).  energy_dev receives one
+ * FP64 energy per circuit.  No allocation, no host synchronisation and no
+ * memset: the call may be captured in a HIP graph.  Concurrent runs of the
+ * same batch object race on its barrier counters. */
+int qc_run_batch(qc_batch_t *b, void *arena_dev, double *energy_dev, void *stream);
+/* View of circuit i's final state inside the arena (keep_states, or
+ * circuits too large for one tile). */
+int qc_batch_state(const qc_batch_t *b, void *arena_dev, int i, qc_state_t *view);
+/* Device error flags of the last run (host-synchronous): bit 0 is set when
+ * a group barrier timed out (the energies of that run are then invalid). */
+int qc_batch_status(qc_batch_t *b, int *flags);
+int qc_batch_destroy(qc_batch_t *b);
 
 /* ---- kernel timing (for roofline reports) ---------------------------- */
 

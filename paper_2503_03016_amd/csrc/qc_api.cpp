@@ -850,6 +850,56 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
     return QC_OK;
 }
 
+int qc_collapse(qc_state_t s, int q, int outcome, double *prob_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (outcome != 0 && outcome != 1) return fail(QC_ERR_ARG, "outcome must be 0 or 1");
+    if ((rc = check_qubits(s.n, &q, 1, "qubit"))) return rc;
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    const hipStream_t hs = (hipStream_t)stream;
+    const int p = bitpos(s.n, q);
+    // P(0), P(1) into the workspace tail, then the rescale reads them there
+    double *pr = c->work + kWorkElems - 2;
+    hipError_t e = qcx::launch_probs_marginal(s.amp, s.dtype, s.n, 1, &p, pr, c->work,
+                                              kWorkElems - 2, hs);
+    if (e == hipSuccess) e = qcx::launch_collapse(s.amp, s.dtype, s.n, p, outcome, pr, prob_dev, hs);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "collapse");
+}
+
+int qc_reduced_state(qc_state_t src, int m, const int *qubits, const int *values, qc_state_t dst,
+                     void *stream) {
+    int rc = check_state(src);
+    if (rc) return rc;
+    if ((rc = check_state(dst))) return rc;
+    if (m < 1 || m >= src.n) return fail(QC_ERR_ARG, "m out of range");
+    if (!values) return fail(QC_ERR_ARG, "values pointer is NULL");
+    if ((rc = check_qubits(src.n, qubits, m, "qubit"))) return rc;
+    if (dst.n != src.n - m || dst.dtype != src.dtype)
+        return fail(QC_ERR_ARG, "destination must have n - m qubits and the same dtype");
+    int pos[QC_MAX_QUBITS], val[QC_MAX_QUBITS];
+    for (int j = 0; j < m; ++j) {
+        if (values[j] != 0 && values[j] != 1) return fail(QC_ERR_ARG, "values must be 0 or 1");
+        pos[j] = bitpos(src.n, qubits[j]);
+        val[j] = values[j];
+    }
+    hipError_t e = qcx::launch_reduced(src.amp, dst.amp, src.dtype, src.n, m, pos, val,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "reduced_state");
+}
+
+int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (shots < 0 || (shots > 0 && (!u_dev || !out_dev))) return fail(QC_ERR_ARG, "NULL argument");
+    if (s.n < 12 || s.n > 33) return fail(QC_ERR_UNSUPPORTED, "sampling needs 12 <= n <= 33");
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    hipError_t e = qcx::launch_sample(s.amp, s.dtype, s.n, u_dev, shots, out_dev, c->work,
+                                      kWorkElems, (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "sample");
+}
+
 }  // extern "C"
 
 namespace {
@@ -1035,3 +1085,353 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
                                   n_params, grad_dev, hs);
     return e == hipSuccess ? QC_OK : hip_fail(e, "grad_finalize");
 }
+
+// ======================================================================
+// batched persistent launch: host planner
+// ======================================================================
+
+struct qc_batch {
+    int dtype = 0, keep = 0, n_circ = 0, grid = 0, n_groups = 0, G = 0, mmax = 0, n_phases = 0;
+    size_t lds_bytes = 0;
+    uint64_t arena_elems = 0;
+    std::vector<qcx::BatchCircuit> circ_h;
+    qcx::BatchCircuit *circ = nullptr;
+    qcx::BatchPhase *phases = nullptr;
+    qcx::TileOp *ops = nullptr;
+    qcx::BatchTerm *terms = nullptr;
+    qcx::BatchJob *jobs = nullptr;
+    int32_t *group_jobs = nullptr;
+    double *partial = nullptr;
+    unsigned *barrier = nullptr;
+};
+
+namespace {
+
+struct HostTerm {
+    uint64_t x, z;
+    int ph;
+    double c;
+};
+
+uint32_t compress_mask(uint64_t mask, uint64_t P) {
+    uint32_t out = 0;
+    int j = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((P >> p) & 1) {
+            if ((mask >> p) & 1) out |= 1u << j;
+            ++j;
+        }
+    return out;
+}
+
+qcx::BatchTerm make_term(const HostTerm &t, uint64_t P) {
+    qcx::BatchTerm b{};
+    b.xc = compress_mask(t.x, P);
+    b.zc = compress_mask(t.z & P, P);
+    b.z_hi = t.z & ~P;
+    b.c = t.c;
+    b.ph = t.ph;
+    b.xtop = b.xc ? 31 - __builtin_clz(b.xc) : -1;
+    return b;
+}
+
+qcx::BatchPhase make_phase(int n, int m, uint64_t P, int op_begin, int op_count, int flags) {
+    qcx::BatchPhase ph{};
+    ph.n_tiles = uint64_t(1) << (n - m);
+    ph.m = m;
+    ph.op_begin = op_begin;
+    ph.op_count = op_count;
+    ph.flags = flags;
+    for (int p = 0, j = 0; p < n; ++p)
+        if ((P >> p) & 1) ph.pos[j++] = uint8_t(p);
+    return ph;
+}
+
+// Phases of one circuit: gate runs (as in the tiled executor), then the
+// energy terms on the tile bits that hold their X/Y factors.
+int plan_circuit(const qc_circuit_t &c, int mmax, bool keep, std::vector<qcx::BatchPhase> &phases,
+                 std::vector<qcx::TileOp> &ops, std::vector<qcx::BatchTerm> &terms, double &cost) {
+    const int n = c.n;
+    const int m = std::min(n, mmax);
+    const int low = std::min(m, 5);
+    const uint64_t low_mask = (uint64_t(1) << low) - 1;
+    const bool large = n > m;
+    const int store = (large || keep) ? qcx::BATCH_STORE : 0;
+    for (int i = 0; i < c.n_gates; ++i) {
+        int rc = check_gate(n, c.gates[i]);
+        if (rc) return rc;
+        if (c.gates[i].n_targets > 2)
+            return fail(QC_ERR_UNSUPPORTED, "batched circuits take gates with at most 2 targets");
+    }
+    std::vector<HostTerm> ht(c.n_terms);
+    for (int t = 0; t < c.n_terms; ++t) {
+        HostTerm h{};
+        int ny = 0;
+        for (int q = 0; q < n; ++q) {
+            const uint64_t b = uint64_t(1) << bitpos(n, q);
+            switch (c.paulis[size_t(t) * n + q]) {
+            case 'I': break;
+            case 'X': h.x |= b; break;
+            case 'Y': h.x |= b; h.z |= b; ++ny; break;
+            case 'Z': h.z |= b; break;
+            default: return fail(QC_ERR_ARG, "Pauli character not in {I,X,Y,Z}");
+            }
+        }
+        h.ph = ny & 3;
+        h.c = c.coeff[t];
+        ht[t] = h;
+    }
+    cost = 0.0;
+    std::vector<int> pending(c.n_gates);
+    for (int i = 0; i < c.n_gates; ++i) pending[i] = i;
+    uint64_t last_P = 0;
+    bool first = true;
+    do {
+        uint64_t P = low_mask, blocked = 0;
+        std::vector<int> run, rest;
+        for (int idx : pending) {
+            const TileClass tc = tile_class(n, c.gates[idx]);
+            if (!(tc.touch & blocked) && __builtin_popcountll(P | tc.tbits) <= m) {
+                P |= tc.tbits;
+                run.push_back(idx);
+            } else {
+                blocked |= tc.touch;
+                rest.push_back(idx);
+            }
+        }
+        for (int p = 0; __builtin_popcountll(P) < m && p < n; ++p) P |= uint64_t(1) << p;
+        const int op_begin = int(ops.size());
+        for (int idx : run) tile_ops_for(n, c.gates[idx], P, ops);
+        const int nops = int(ops.size()) - op_begin;
+        phases.push_back(make_phase(n, m, P, op_begin, nops, (first ? qcx::BATCH_INIT : 0) | store));
+        cost += double(uint64_t(1) << n) * (nops + 2);
+        first = false;
+        last_P = P;
+        pending.swap(rest);
+    } while (!pending.empty());
+    // energy terms: on the last gate phase when their X/Y bits are tile bits,
+    // else on read-only phases whose tile bits cover them
+    std::vector<int> left;
+    {
+        qcx::BatchPhase &ph = phases.back();
+        ph.term_begin = int(terms.size());
+        for (int t = 0; t < c.n_terms; ++t) {
+            if ((ht[t].x & ~last_P) == 0) terms.push_back(make_term(ht[t], last_P));
+            else left.push_back(t);
+        }
+        ph.term_count = int(terms.size()) - ph.term_begin;
+        cost += double(uint64_t(1) << n) * ph.term_count;
+    }
+    while (!left.empty()) {
+        uint64_t P = low_mask;
+        std::vector<int> take, rest;
+        for (int t : left) {
+            if (__builtin_popcountll(P | ht[t].x) <= m) {
+                P |= ht[t].x;
+                take.push_back(t);
+            } else {
+                rest.push_back(t);
+            }
+        }
+        if (take.empty()) return fail(QC_ERR_UNSUPPORTED, "Pauli term wider than one tile");
+        for (int p = 0; __builtin_popcountll(P) < m && p < n; ++p) P |= uint64_t(1) << p;
+        qcx::BatchPhase ph = make_phase(n, m, P, int(ops.size()), 0, 0);
+        ph.term_begin = int(terms.size());
+        for (int t : take) terms.push_back(make_term(ht[t], P));
+        ph.term_count = int(take.size());
+        phases.push_back(ph);
+        cost += double(uint64_t(1) << n) * (ph.term_count + 1);
+        left.swap(rest);
+    }
+    return QC_OK;
+}
+
+template <typename T>
+int upload(const std::vector<T> &v, T **dev) {
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (hipMalloc(dev, bytes) != hipSuccess) return fail(QC_ERR_NOMEM, "batch program allocation");
+    if (!v.empty()) {
+        hipError_t e = hipMemcpy(*dev, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    return QC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qc_batch_destroy(qc_batch_t *b) {
+    if (!b) return QC_OK;
+    (void)hipFree(b->circ);
+    (void)hipFree(b->phases);
+    (void)hipFree(b->ops);
+    (void)hipFree(b->terms);
+    (void)hipFree(b->jobs);
+    (void)hipFree(b->group_jobs);
+    (void)hipFree(b->partial);
+    (void)hipFree(b->barrier);
+    delete b;
+    return QC_OK;
+}
+
+int qc_batch_create(int n_circuits, const qc_circuit_t *circuits, int dtype, int keep_states,
+                    qc_batch_t **out) {
+    if (!out) return fail(QC_ERR_ARG, "output handle pointer is NULL");
+    *out = nullptr;
+    if (n_circuits < 1 || !circuits) return fail(QC_ERR_ARG, "empty batch");
+    if (dtype != QC_C64 && dtype != QC_C128) return fail(QC_ERR_DTYPE, "unknown dtype");
+    const int mmax = dtype == QC_C64 ? 13 : 12;
+    const int G = qcx::kBatchGroup;
+    std::vector<qcx::BatchCircuit> circ(n_circuits);
+    std::vector<qcx::BatchPhase> phases;
+    std::vector<qcx::TileOp> ops;
+    std::vector<qcx::BatchTerm> terms;
+    std::vector<double> cost(n_circuits);
+    uint64_t arena = 0;
+    for (int i = 0; i < n_circuits; ++i) {
+        const qc_circuit_t &c = circuits[i];
+        if (c.n < 1 || c.n > 30) return fail(QC_ERR_ARG, "batched circuit size out of range");
+        if (c.n_gates < 0 || (c.n_gates > 0 && !c.gates)) return fail(QC_ERR_ARG, "gate list is NULL");
+        if (c.n_terms < 1 || !c.paulis || !c.coeff) return fail(QC_ERR_ARG, "Hamiltonian is empty");
+        const int begin = int(phases.size());
+        int rc = plan_circuit(c, mmax, keep_states != 0, phases, ops, terms, cost[i]);
+        if (rc) return rc;
+        circ[i].n = c.n;
+        circ[i].phase_begin = begin;
+        circ[i].phase_count = int(phases.size()) - begin;
+        circ[i].large = c.n > mmax;
+        circ[i].arena_off = arena;
+        if (circ[i].large || keep_states) arena += uint64_t(1) << c.n;
+    }
+    // persistent grid: resident workgroups only, in whole groups on 8 XCDs
+    const size_t elem = dtype == QC_C64 ? 8 : 16;
+    const size_t lds = (size_t(1) << mmax) * elem;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return fail(QC_ERR_HIP, "cannot query the compute-unit count");
+    const int per_cu = std::min(qcx::batch_resident_blocks(dtype, lds), 2);
+    if (per_cu < 1) return fail(QC_ERR_UNSUPPORTED, "batch kernel cannot be resident");
+    const int grid = (per_cu * cus) / (8 * G) * (8 * G);
+    if (grid < 8 * G) return fail(QC_ERR_UNSUPPORTED, "device too small for the batch grid");
+    const int n_groups = grid / G;
+    // jobs: bundles of G small circuits, one job per large circuit
+    struct Job { qcx::BatchJob j; double cost; };
+    std::vector<Job> jobs;
+    std::vector<int> small, large;
+    for (int i = 0; i < n_circuits; ++i) (circ[i].large ? large : small).push_back(i);
+    std::stable_sort(small.begin(), small.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (size_t s0 = 0; s0 < small.size(); s0 += G) {
+        Job J{};
+        J.j.kind = 0;
+        for (int r = 0; r < G; ++r) J.j.circ[r] = -1;
+        for (int r = 0; r < G && s0 + r < small.size(); ++r) {
+            J.j.circ[r] = small[s0 + r];
+            J.cost = std::max(J.cost, cost[small[s0 + r]]);
+        }
+        jobs.push_back(J);
+    }
+    for (int i : large) {
+        Job J{};
+        J.j.kind = 1;
+        for (int r = 0; r < G; ++r) J.j.circ[r] = -1;
+        J.j.circ[0] = i;
+        J.cost = cost[i] / G;
+        jobs.push_back(J);
+    }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.cost > b.cost; });
+    std::vector<double> load(n_groups, 0.0);
+    std::vector<std::vector<qcx::BatchJob>> per_group(n_groups);
+    for (const Job &J : jobs) {
+        const int g = int(std::min_element(load.begin(), load.end()) - load.begin());
+        load[g] += J.cost;
+        per_group[g].push_back(J.j);
+    }
+    std::vector<qcx::BatchJob> job_list;
+    std::vector<int32_t> group_jobs(n_groups + 1, 0);
+    for (int g = 0; g < n_groups; ++g) {
+        group_jobs[g] = int32_t(job_list.size());
+        for (auto &j : per_group[g]) job_list.push_back(j);
+    }
+    group_jobs[n_groups] = int32_t(job_list.size());
+
+    qc_batch_t *b = new qc_batch_t();
+    b->dtype = dtype;
+    b->keep = keep_states != 0;
+    b->n_circ = n_circuits;
+    b->grid = grid;
+    b->n_groups = n_groups;
+    b->G = G;
+    b->mmax = mmax;
+    b->lds_bytes = lds;
+    b->arena_elems = arena;
+    b->n_phases = int(phases.size());
+    b->circ_h = circ;
+    int rc;
+    std::vector<double> zeros(size_t(n_circuits) * G, 0.0);
+    std::vector<unsigned> zbar(n_groups + 1, 0u);
+    if ((rc = upload(circ, &b->circ)) || (rc = upload(phases, &b->phases)) ||
+        (rc = upload(ops, &b->ops)) || (rc = upload(terms, &b->terms)) ||
+        (rc = upload(job_list, &b->jobs)) || (rc = upload(group_jobs, &b->group_jobs)) ||
+        (rc = upload(zeros, &b->partial)) || (rc = upload(zbar, &b->barrier))) {
+        qc_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return QC_OK;
+}
+
+int qc_batch_info(const qc_batch_t *b, uint64_t *arena_bytes, int *grid, int *phases) {
+    if (!b) return fail(QC_ERR_ARG, "batch handle is NULL");
+    if (arena_bytes) *arena_bytes = b->arena_elems * (b->dtype == QC_C64 ? 8 : 16);
+    if (grid) *grid = b->grid;
+    if (phases) *phases = b->n_phases;
+    return QC_OK;
+}
+
+int qc_run_batch(qc_batch_t *b, void *arena_dev, double *energy_dev, void *stream) {
+    if (!b) return fail(QC_ERR_ARG, "batch handle is NULL");
+    if (!energy_dev) return fail(QC_ERR_ARG, "energy pointer is NULL");
+    if (b->arena_elems && !arena_dev) return fail(QC_ERR_ARG, "batch needs an arena");
+    qcx::BatchArgs a{};
+    a.circ = b->circ;
+    a.phases = b->phases;
+    a.ops = b->ops;
+    a.terms = b->terms;
+    a.jobs = b->jobs;
+    a.group_jobs = b->group_jobs;
+    a.arena = arena_dev;
+    a.energy = energy_dev;
+    a.partial = b->partial;
+    a.barrier = b->barrier;
+    a.error = b->barrier + b->n_groups;
+    a.n_groups = b->n_groups;
+    a.G = b->G;
+    hipError_t e = qcx::launch_batch(a, b->dtype, unsigned(b->grid), b->lds_bytes, (hipStream_t)stream);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "run_batch");
+}
+
+int qc_batch_state(const qc_batch_t *b, void *arena_dev, int i, qc_state_t *view) {
+    if (!b || !view || !arena_dev) return fail(QC_ERR_ARG, "NULL argument");
+    if (i < 0 || i >= b->n_circ) return fail(QC_ERR_ARG, "circuit index out of range");
+    const qcx::BatchCircuit &c = b->circ_h[i];
+    if (!c.large && !b->keep) return fail(QC_ERR_ARG, "this circuit's state is not kept");
+    view->amp = static_cast<char *>(arena_dev) + c.arena_off * (b->dtype == QC_C64 ? 8 : 16);
+    view->n = c.n;
+    view->dtype = b->dtype;
+    return QC_OK;
+}
+
+int qc_batch_status(qc_batch_t *b, int *flags) {
+    if (!b || !flags) return fail(QC_ERR_ARG, "NULL argument");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    unsigned v = 0;
+    e = hipMemcpy(&v, b->barrier + b->n_groups, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    *flags = int(v);
+    return QC_OK;
+}
+
+}  // extern "C"

@@ -169,6 +169,13 @@ hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s);
 
+hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const double *prob,
+                           double *prob_out, hipStream_t s);
+hipError_t launch_reduced(const void *src, void *dst, int dtype, int n, int m, const int *pos,
+                          const int *val, hipStream_t s);
+hipError_t launch_sample(const void *amp, int dtype, int n, const double *u, int shots,
+                         int64_t *out, double *work, size_t work_elems, hipStream_t s);
+
 int batch_resident_blocks(int dtype, size_t lds_bytes);
 hipError_t launch_batch(const BatchArgs &a, int dtype, unsigned grid, size_t lds_bytes,
                         hipStream_t s);

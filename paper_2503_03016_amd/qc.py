@@ -28,7 +28,9 @@ EXPORTS = [
     "qc_status_string", "qc_last_error", "qc_version", "qc_state_init", "qc_state_copy",
     "qc_state_diff", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled", "qc_apply_fused_k",
     "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
-    "qc_timing_enable", "qc_timing_query",
+    "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
+    "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
+    "qc_sample",
 ]
 
 
@@ -57,6 +59,12 @@ class QcStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class QcCircuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gates", ctypes.POINTER(QcGate)), ("n_terms", ctypes.c_int32),
+                ("paulis", ctypes.c_char_p), ("coeff", ctypes.POINTER(ctypes.c_double))]
 
 
 class QcOp(ctypes.Structure):
@@ -91,6 +99,15 @@ def _load():
                              vp, vp], i),
         "qc_timing_enable": ([i], i),
         "qc_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), dp], i),
+        "qc_batch_create": ([i, ctypes.POINTER(QcCircuit), i, i, ctypes.POINTER(vp)], i),
+        "qc_batch_info": ([vp, ctypes.POINTER(ctypes.c_uint64), ip, ip], i),
+        "qc_run_batch": ([vp, vp, vp, vp], i),
+        "qc_batch_state": ([vp, vp, i, ctypes.POINTER(QcState)], i),
+        "qc_batch_status": ([vp, ip], i),
+        "qc_batch_destroy": ([vp], i),
+        "qc_collapse": ([S, i, i, vp, vp], i),
+        "qc_reduced_state": ([S, i, ip, ip, S, vp], i),
+        "qc_sample": ([S, i, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -259,6 +276,35 @@ def expect_pauli(psi: torch.Tensor, terms, per_term: bool = False) -> torch.Tens
     return out
 
 
+def collapse(psi: torch.Tensor, q: int, outcome: int) -> torch.Tensor:
+    """Collapse onto outcome of qubit q and renormalise in place; returns
+    P(outcome) as a device FP64 tensor of one element."""
+    p = torch.empty(1, dtype=torch.float64, device=psi.device)
+    _check(lib.qc_collapse(state_view(psi), int(q), int(outcome), ctypes.c_void_p(p.data_ptr()),
+                           _stream(psi)), "qc_collapse")
+    return p
+
+
+def reduced_state(psi: torch.Tensor, qubits: Sequence[int], values) -> torch.Tensor:
+    """Amplitudes of the other qubits when `qubits` hold `values`."""
+    sv = state_view(psi)
+    vals = [int(v) for v in values]
+    out = torch.empty(1 << (sv.n - len(qubits)), dtype=psi.dtype, device=psi.device)
+    _check(lib.qc_reduced_state(sv, len(qubits), _ints(qubits), _ints(vals), state_view(out),
+                                _stream(psi)), "qc_reduced_state")
+    return out
+
+
+def sample(psi: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """Basis indices drawn by inverse CDF for the uniforms u (device FP64)."""
+    if u.dtype != torch.float64 or u.device != psi.device or not u.is_contiguous():
+        raise TypeError("u must be a contiguous FP64 tensor on the state's device")
+    out = torch.empty(u.numel(), dtype=torch.int64, device=psi.device)
+    _check(lib.qc_sample(state_view(psi), int(u.numel()), ctypes.c_void_p(u.data_ptr()),
+                         ctypes.c_void_p(out.data_ptr()), _stream(psi)), "qc_sample")
+    return out
+
+
 def make_ops(ops) -> Tuple[ctypes.Array, int]:
     """qc_op_t array from workloads.Op entries of kinds RX/RY/RZ/H/X/Y/Z/CZ/CNOT."""
     arr = (QcOp * max(1, len(ops)))()
@@ -301,6 +347,67 @@ def timing_query(name: str) -> Tuple[int, float]:
     return cnt.value, ms.value
 
 
+class Batch:
+    """A batch of circuits run in one persistent launch (qc_batch_* / qc_run_batch).
+
+    circuits: list of (n, gate tuples, terms) with gate tuples as accepted by
+    GateList and terms as in expect_pauli.  The arena (caller-owned device
+    memory for the states of large circuits) is a torch tensor owned here."""
+
+    def __init__(self, circuits, dtype=torch.complex64, keep_states: bool = False,
+                 device="cuda"):
+        self.dtype = dtype
+        dt = QC_C64 if dtype == torch.complex64 else QC_C128
+        arr = (QcCircuit * len(circuits))()
+        self._keep = []
+        for c, (n, gts, terms) in zip(arr, circuits):
+            gl = GateList(gts)
+            s, coeff = _terms(terms, n)
+            self._keep += [gl, s, coeff]
+            c.n, c.n_gates, c.gates = n, gl.count, gl.arr
+            c.n_terms, c.paulis = len(terms), s
+            c.coeff = coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        _check(lib.qc_batch_create(len(circuits), arr, dt, int(bool(keep_states)), ctypes.byref(h)),
+               "qc_batch_create")
+        self.handle = h
+        self._keep = None
+        nbytes, grid, phases = ctypes.c_uint64(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.qc_batch_info(h, ctypes.byref(nbytes), ctypes.byref(grid), ctypes.byref(phases)),
+               "qc_batch_info")
+        self.arena_bytes, self.grid, self.phases = nbytes.value, grid.value, phases.value
+        elem = 8 if dt == QC_C64 else 16
+        self.arena = torch.empty(max(1, self.arena_bytes // elem), dtype=dtype, device=device)
+        self.count = len(circuits)
+
+    def run(self, energy: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if energy is None:
+            energy = torch.empty(self.count, dtype=torch.float64, device=self.arena.device)
+        _check(lib.qc_run_batch(self.handle, ctypes.c_void_p(self.arena.data_ptr()),
+                                ctypes.c_void_p(energy.data_ptr()), _stream(self.arena)),
+               "qc_run_batch")
+        return energy
+
+    def state(self, i: int) -> torch.Tensor:
+        v = QcState()
+        _check(lib.qc_batch_state(self.handle, ctypes.c_void_p(self.arena.data_ptr()), int(i),
+                                  ctypes.byref(v)), "qc_batch_state")
+        elem = 8 if self.dtype == torch.complex64 else 16
+        off = (v.amp - self.arena.data_ptr()) // elem
+        return self.arena[off: off + (1 << v.n)]
+
+    def status(self) -> int:
+        f = ctypes.c_int()
+        _check(lib.qc_batch_status(self.handle, ctypes.byref(f)), "qc_batch_status")
+        return f.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.qc_batch_destroy(h)
+            self.handle = None
+
+
 # the C entry-point names, for callers who prefer them
 qc_state_init = state_init
 qc_state_copy = state_copy
@@ -316,3 +423,6 @@ qc_expect_pauli = expect_pauli
 qc_adjoint_grad = adjoint_grad
 qc_timing_enable = timing_enable
 qc_timing_query = timing_query
+qc_collapse = collapse
+qc_reduced_state = reduced_state
+qc_sample = sample

@@ -117,6 +117,31 @@ def test_adjoint_validation(qc):
     assert lib.qc_adjoint_grad(a, b, ops2, n2, tp, 2, 1, b"ZIII", cp, out, out, None) == -2
 
 
+def test_batch_validation(qc):
+    """qc_batch_create rejects malformed circuits while planning, before any
+    device call."""
+    from paper_2503_03016_amd import gates as G
+
+    def create(n, ops, terms, dtype=1):
+        gl = qc.GateList(G.gate_tuples(ops))
+        s, coeff = qc._terms(terms, n)
+        arr = (qc.QcCircuit * 1)()
+        arr[0].n, arr[0].n_gates, arr[0].gates = n, gl.count, gl.arr
+        arr[0].n_terms, arr[0].paulis = len(terms), s
+        arr[0].coeff = coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        return qc.lib.qc_batch_create(1, arr, dtype, 0, ctypes.byref(h))
+
+    assert create(31, [], [("Z" * 31, 1.0)]) == -1
+    assert create(4, [], [("ZQZZ", 1.0)]) == -1
+    assert create(4, [W.Op("CNOT", (1, 1))], [("ZZZZ", 1.0)]) == -2
+    u8 = np.eye(8)
+    assert create(4, [W.Op("U", (0, 1, 2), matrix=u8)], [("ZZZZ", 1.0)]) == -4
+    assert create(4, [], [("ZZZZ", 1.0)], dtype=5) == -3
+    h = ctypes.c_void_p()
+    assert qc.lib.qc_batch_create(0, None, 1, 0, ctypes.byref(h)) == -1
+
+
 def _gate_list(qc, ops):
     from paper_2503_03016_amd import gates as G
     return qc.GateList(G.gate_tuples(ops))
