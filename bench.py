@@ -83,6 +83,115 @@ def cpu_baseline(n_cpu: int, layers: int, budget_s: float):
     }
 
 
+def _time(fn, reps: int = 3, warm: int = 1) -> float:
+    """Median milliseconds of fn() over reps runs (HIP events, current stream)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    out.sort()
+    return out[len(out) // 2]
+
+
+def secondary_workloads() -> dict:
+    """The other four synthetic configurations, timed on the GPU (state
+    contents do not change the work, so QFT starts from |0...0>)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2503_03016_amd import gates as G
+    from paper_2503_03016_amd import qc
+
+    res = {}
+    # 12-qubit brickwork, 20 layers, complex128: whole circuit in one LDS tile
+    n, ops = W.config_brickwork12()
+    gl = qc.GateList(G.gate_tuples(ops))
+    psi = qc.new_state(n, torch.complex128)
+    r = {}
+    for name, mode in (("unfused", qc.QC_EXEC_UNFUSED), ("tiled", qc.QC_EXEC_TILED)):
+        st = {}
+
+        def run():
+            qc.state_init(psi, 0)
+            st.update(qc.apply_circuit(psi, gl, mode=mode))
+            qc.probs(psi)
+        ms = _time(run, reps=5)
+        r[name] = {"us": round(ms * 1e3, 1), "sweeps": st["sweeps"],
+                   "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
+    b = qc.Batch([(n, G.gate_tuples(ops), W.tfim_terms(n))], dtype=torch.complex128)
+    ms = _time(lambda: b.run(), reps=5)
+    r["one_workgroup_batch"] = {"us": round(ms * 1e3, 1),
+                                "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
+    res["brickwork12_c128"] = r
+    del psi, b
+    log("secondary: brickwork12 done")
+
+    # 28-qubit QFT, complex128 and complex64
+    n = 28
+    ops = W.qft(n)
+    gl = qc.GateList(G.gate_tuples(ops))
+    r = {}
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        psi = qc.new_state(n, dt)
+        for name, mode in (("unfused", qc.QC_EXEC_UNFUSED), ("tiled", qc.QC_EXEC_TILED),
+                           ("fused", qc.QC_EXEC_FUSED)):
+            st = {}
+
+            def run():
+                st.update(qc.apply_circuit(psi, gl, mode=mode, fuse_k=5))
+            qc.state_init(psi, 0)
+            ms = _time(run, reps=1)
+            r["%s_%s" % (dname, name)] = {
+                "ms": round(ms, 2), "sweeps": st["sweeps"],
+                "GBps": round(st["state_bytes"] / (ms / 1e3) / 1e9, 1),
+                "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
+        del psi
+        torch.cuda.empty_cache()
+    res["qft28"] = r
+    log("secondary: qft28 done")
+
+    # batch of 512 circuits, one persistent launch, complex64
+    cfg = W.batch_config()
+    t0 = time.perf_counter()
+    circuits = [(cn, G.gate_tuples(W.hea(cn, 8), th), W.tfim_terms(cn)) for cn, th in cfg]
+    b = qc.Batch(circuits, dtype=torch.complex64)
+    create_s = time.perf_counter() - t0
+    ms = _time(lambda: b.run(), reps=3)
+    gates = sum(8 * (3 * cn - 1) for cn, _ in cfg)
+    res["batch512_c64"] = {"ms": round(ms, 3), "circuits_per_s": round(512 / (ms / 1e3), 1),
+                           "gates_per_s": round(gates / (ms / 1e3), 1), "gates": gates,
+                           "grid": b.grid, "phases": b.phases,
+                           "host_plan_and_upload_s": round(create_s, 2)}
+    del b
+    log("secondary: batch512 done")
+
+    # adjoint gradient, 24 qubits, 16 layers, 768 parameters
+    n, ops, theta, terms = W.adjoint_config()
+    r = {}
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        psi = qc.new_state(n, dt)
+        lam = qc.new_state(n, dt)
+
+        def run():
+            qc.state_init(psi, 0)
+            qc.adjoint_grad(psi, lam, ops, theta, terms)
+        ms = _time(run, reps=3)
+        r[dname] = {"ms": round(ms, 2), "ops": len(ops), "params": int(len(theta))}
+        del psi, lam
+    res["adjoint24"] = r
+    log("secondary: adjoint24 done")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +203,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=24)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-copy", action="store_true",
+                    help="skip the plain-copy calibration run (bandwidth ceiling)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the other four workloads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,8 +226,11 @@ def main() -> int:
     n, layers = args.n, args.layers
     _, ops = W.config_brickwork32(n, layers)
     gl = qc.GateList(G.gate_tuples(ops))
+    t0 = time.perf_counter()
     _, nblocks = qc.fuse_plan(n, gl, 5)
-    log("workload: %d qubits, %d gates, %d fused blocks" % (n, len(ops), nblocks))
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    log("workload: %d qubits, %d gates, %d fused blocks (plan %.1f ms)"
+        % (n, len(ops), nblocks, plan_ms))
 
     psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -159,6 +275,26 @@ def main() -> int:
     traffic = load_traffic(n)
     p0h = p0.cpu().tolist()
 
+    copy = None
+    if not args.no_copy:
+        # plain device copy of the same state: the achievable-bandwidth
+        # reference for the fused sweeps (and the scale of HBM byte counters)
+        dst = torch.empty_like(psi)
+        qc.state_copy(dst, psi)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(3):
+            qc.state_copy(dst, psi)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1) / 3
+        copy = {"ms": round(cms, 4), "GBps": round(2 * S / (cms / 1e3) / 1e9, 1)}
+        log("copy ceiling: %.3f ms, %.1f GB/s" % (cms, copy["GBps"]))
+        del dst
+        torch.cuda.empty_cache()
+
     ref = {}
     if not args.no_ref:
         ref_psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
@@ -189,6 +325,12 @@ def main() -> int:
         del ref_psi
         torch.cuda.empty_cache()
 
+    secondary = None
+    if not args.no_secondary:
+        del psi
+        torch.cuda.empty_cache()
+        secondary = secondary_workloads()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_n, layers, args.cpu_budget)
@@ -214,7 +356,9 @@ def main() -> int:
             "sweeps_per_step": int(st["sweeps"]) + 2, "seed": 32,
         },
         "gates_per_s": round(gates_per_s, 1),
+        "host_fusion_plan_ms": round(plan_ms, 2),
         "prob_q0": [round(x, 9) for x in p0h],
+        "copy_ceiling": copy,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_fused_mfma_c64",
@@ -222,6 +366,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "frac_of_copy_ceiling": (round(achieved / copy["GBps"], 4)
+                                     if (achieved and copy) else None),
             "traffic": traffic,
             "launches": cnt,
             "avg_launch_ms": round(avg_launch_ms, 4),
@@ -230,6 +376,7 @@ def main() -> int:
         "cpu_baseline": cpu,
     }
     out.update(ref)
+    out["secondary_workloads"] = secondary
     print(json.dumps(out), flush=True)
     return 0
 

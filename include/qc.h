@@ -283,6 +283,30 @@ int qc_batch_state(const qc_batch_t *b, void *arena_dev, int i, qc_state_t *view
 int qc_batch_status(qc_batch_t *b, int *flags);
 int qc_batch_destroy(qc_batch_t *b);
 
+/* ---- autotuning ----------------------------------------------------- */
+
+/* Launch-shape knobs (process-wide; the defaults suit MI355X). */
+#define QC_KNOB_MFMA_WG_PER_CU 1   /* persistent workgroups per CU, fused MFMA kernel (1..5) */
+#define QC_KNOB_TILE_WG_PER_CU 2   /* workgroups per CU, LDS tile-run kernel (1..16)        */
+int qc_set_knob(int knob, int value);
+int qc_get_knob(int knob, int *value);
+
+typedef struct {
+    int32_t mode;            /* QC_EXEC_*                          */
+    int32_t fuse_k;          /* block width for QC_EXEC_FUSED      */
+    int32_t mfma_wg_per_cu;  /* knob value used                    */
+    int32_t sweeps;          /* state sweeps of the strategy       */
+    float   ms;              /* median time of one run             */
+} qc_tune_entry_t;
+
+/* Time every execution strategy for this gate list on `scratch` (its
+ * contents are overwritten: each run starts from |0...0>), `reps` timed
+ * runs after one warm-up each, and report them fastest first.  Writes at
+ * most max_entries entries, their count to *n_entries; the knobs are left
+ * at the fastest entry's values.  Host-synchronous. */
+int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int reps,
+                qc_tune_entry_t *entries, int max_entries, int *n_entries, void *stream);
+
 /* ---- kernel timing (for roofline reports) ---------------------------- */
 
 /* Start (on != 0) or stop recording HIP events around every kernel the

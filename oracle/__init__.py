@@ -360,6 +360,18 @@ def fd_grad(ops, theta, terms, psi0, indices=None, eps: float = 1e-4) -> np.ndar
     return g
 
 
+# --------------------------------------------------------------- sampling
+
+def sample(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Inverse-CDF sampling of the measurement distribution of all qubits:
+    for each uniform u_k in [0, 1) the first basis index whose cumulative
+    probability (index order) exceeds u_k times the total probability."""
+    p = probs(psi)
+    cdf = np.cumsum(p)
+    x = np.asarray(u, dtype=np.float64) * cdf[-1]
+    return np.searchsorted(cdf, x, side="right").astype(np.int64)
+
+
 # ------------------------------------------------------------------- QFT
 
 def qft_amplitude(psi: np.ndarray, y: int) -> complex:

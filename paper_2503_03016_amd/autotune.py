@@ -1,0 +1,81 @@
+"""Autotuner front end: picks the execution strategy (unfused, LDS tile
+runs, fused k = 2..5) and the matrix-core kernel's workgroups per CU for a
+circuit family by timing them with qc_autotune, and caches the choice in a
+JSON file keyed by device, qubit count, element type and circuit signature.
+
+The cache path is $QC_TUNE_CACHE, else ~/.cache/qc_tune.json.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Optional
+
+import torch
+
+from . import qc
+
+MODE_NAMES = {qc.QC_EXEC_UNFUSED: "unfused", qc.QC_EXEC_FUSED: "fused", qc.QC_EXEC_TILED: "tiled"}
+
+
+def cache_path() -> str:
+    return os.environ.get("QC_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "qc_tune.json"))
+
+
+def circuit_key(n: int, dtype: torch.dtype, gate_tuples, family: Optional[str] = None) -> str:
+    """Device + size + type + structure (targets and controls, not values)."""
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    if family is None:
+        h = hashlib.sha1()
+        for t, c, cv, _ in gate_tuples:
+            h.update(repr((tuple(t), tuple(c), tuple(cv))).encode())
+        family = h.hexdigest()[:16]
+    return "%s|n=%d|%s|%s" % (dev, n, str(dtype).replace("torch.", ""), family)
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def tune(n: int, dtype: torch.dtype, gate_tuples, family: Optional[str] = None,
+         reps: int = 3, force: bool = False) -> dict:
+    """Best configuration for this circuit family (from the cache when
+    present).  Tuning runs on a scratch state of the same size."""
+    key = circuit_key(n, dtype, gate_tuples, family)
+    cache = _load()
+    if key in cache and not force:
+        return cache[key]
+    scratch = qc.new_state(n, dtype)
+    table = qc.autotune(scratch, qc.GateList(gate_tuples), reps=reps)
+    del scratch
+    best = dict(table[0])
+    best["mode_name"] = MODE_NAMES.get(best["mode"], str(best["mode"]))
+    best["table"] = table
+    cache[key] = best
+    _store(cache)
+    return best
+
+
+def apply_tuned(psi: torch.Tensor, gate_tuples, family: Optional[str] = None) -> dict:
+    """Apply a circuit with its tuned configuration."""
+    n = qc.state_view(psi).n
+    cfg = tune(n, psi.dtype, gate_tuples, family)
+    if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_wg_per_cu"):
+        qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, cfg["mfma_wg_per_cu"])
+    return qc.apply_circuit(psi, qc.GateList(gate_tuples), mode=cfg["mode"],
+                            fuse_k=cfg["fuse_k"] or 5)

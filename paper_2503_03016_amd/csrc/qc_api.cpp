@@ -104,6 +104,10 @@ std::vector<TimerRec> g_trecs;
 std::map<std::string, std::pair<int64_t, double>> g_tsum;
 std::mutex g_tmu;
 
+// launch-shape knobs (QC_KNOB_*)
+std::atomic<int> g_knob_mfma{4};
+std::atomic<int> g_knob_tile{8};
+
 // ---------------------------------------------------------------- validation
 
 int check_state(const qc_state_t &s) {
@@ -221,32 +225,82 @@ int check_gate(int n, const qc_gate_t &g) {
 // A gate joins the block under construction when none of its qubits is
 // held by an earlier gate left out of the block and the union of qubits
 // stays within k; a gate left out blocks its qubits for later gates.
+// Members (positions in `pending`) of a block seeded by pending[seed]: the
+// pending list is scanned in order; a gate joins when none of its qubits is
+// held by an earlier pending gate left out of the block ("blocked") and it
+// fits: inside the label set `window` when one is given, else within k
+// qubits of the block grown so far.  The seed has no pending predecessor on
+// its qubits, so the block can be applied before every gate left out.
+void grow_block(const std::vector<int> &pending, const std::vector<uint64_t> &masks, int seed,
+                uint64_t window, int k, uint64_t all, std::vector<int> &members) {
+    members.clear();
+    const uint64_t sm = masks[pending[seed]];
+    uint64_t held = window ? window : sm, blocked = 0;
+    const bool oversize = __builtin_popcountll(sm) > k;
+    for (int i = 0; i < int(pending.size()); ++i) {
+        if (i == seed) {
+            members.push_back(i);
+            continue;
+        }
+        const uint64_t m = masks[pending[i]];
+        bool fits = !(m & blocked) && !oversize;
+        if (fits) fits = window ? (m & ~window) == 0 : __builtin_popcountll(held | m) <= k;
+        if (fits) {
+            held |= m;
+            members.push_back(i);
+        } else {
+            blocked |= m;
+            if ((blocked & all) == all) break;   // nothing can join any more
+        }
+    }
+}
+
+// Partition into dependency-respecting blocks of <= k qubits.  Each block is
+// chosen among candidates seeded by the first gates that have no pending
+// predecessor ("front" gates): a block grown greedily from the seed, and
+// blocks confined to each window of k consecutive qubit labels that holds
+// the seed.  The candidate absorbing the most gates wins.
 void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, std::vector<int> &block_of,
                int &n_blocks) {
+    constexpr int kMaxFront = 32;
     block_of.assign(ng, -1);
     n_blocks = 0;
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
-    std::vector<int> pending(ng);
+    std::vector<uint64_t> masks(ng);
+    for (int i = 0; i < ng; ++i) masks[i] = gate_mask(gs[i]);
+    std::vector<int> pending(ng), best, cand, front;
     for (int i = 0; i < ng; ++i) pending[i] = i;
     while (!pending.empty()) {
-        uint64_t held = 0, blocked = 0;
-        std::vector<int> rest;
-        rest.reserve(pending.size());
-        bool scanning = true;
-        for (int idx : pending) {
-            const uint64_t m = gate_mask(gs[idx]);
-            const int cnt = __builtin_popcountll(m);
-            if (scanning && !(m & blocked) && __builtin_popcountll(held | m) <= k &&
-                (cnt <= k || held == 0)) {
-                held |= m;
-                block_of[idx] = n_blocks;
-                if (cnt > k) scanning = false;   // oversize gate stands alone
-            } else {
-                blocked |= m;
-                rest.push_back(idx);
-                if ((blocked & all) == all) scanning = false;   // nothing can join any more
+        front.clear();
+        uint64_t seen = 0;
+        for (int i = 0; i < int(pending.size()) && int(front.size()) < kMaxFront; ++i) {
+            const uint64_t m = masks[pending[i]];
+            if (!(m & seen)) front.push_back(i);
+            seen |= m;
+            if ((seen & all) == all) break;
+        }
+        best.clear();
+        for (int f : front) {
+            const uint64_t sm = masks[pending[f]];
+            grow_block(pending, masks, f, 0, k, all, cand);
+            if (cand.size() > best.size()) best = cand;
+            if (__builtin_popcountll(sm) > k || k >= n) continue;
+            const int lo = __builtin_ctzll(sm), hi = 63 - __builtin_clzll(sm);
+            for (int a = std::max(0, hi - k + 1); a <= std::min(lo, n - k); ++a) {
+                const uint64_t w = ((uint64_t(1) << k) - 1) << a;
+                grow_block(pending, masks, f, w, k, all, cand);
+                if (cand.size() > best.size()) best = cand;
             }
         }
+        std::vector<char> taken(pending.size(), 0);
+        for (int i : best) {
+            taken[i] = 1;
+            block_of[pending[i]] = n_blocks;
+        }
+        std::vector<int> rest;
+        rest.reserve(pending.size() - best.size());
+        for (int i = 0; i < int(pending.size()); ++i)
+            if (!taken[i]) rest.push_back(pending[i]);
         ++n_blocks;
         pending.swap(rest);
     }
@@ -262,6 +316,10 @@ double sweep_bytes(int n, int dtype) {
 // services used by the launchers
 // ======================================================================
 namespace qcx {
+
+int knob(int which) {
+    return which == QC_KNOB_MFMA_WG_PER_CU ? g_knob_mfma.load() : g_knob_tile.load();
+}
 
 int timer_begin(const char *name, hipStream_t s) {
     if (!g_timing.load(std::memory_order_relaxed)) return -1;
@@ -337,6 +395,28 @@ int qc_timing_query(const char *name, int64_t *count, double *total_ms) {
     auto it = g_tsum.find(name);
     *count = it == g_tsum.end() ? 0 : it->second.first;
     *total_ms = it == g_tsum.end() ? 0.0 : it->second.second;
+    return QC_OK;
+}
+
+int qc_set_knob(int knob, int value) {
+    if (knob == QC_KNOB_MFMA_WG_PER_CU) {
+        if (value < 1 || value > 5) return fail(QC_ERR_ARG, "MFMA workgroups per CU must be 1..5");
+        g_knob_mfma.store(value);
+        return QC_OK;
+    }
+    if (knob == QC_KNOB_TILE_WG_PER_CU) {
+        if (value < 1 || value > 16) return fail(QC_ERR_ARG, "tile workgroups per CU must be 1..16");
+        g_knob_tile.store(value);
+        return QC_OK;
+    }
+    return fail(QC_ERR_ARG, "unknown knob");
+}
+
+int qc_get_knob(int knob, int *value) {
+    if (!value) return fail(QC_ERR_ARG, "NULL argument");
+    if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU)
+        return fail(QC_ERR_ARG, "unknown knob");
+    *value = qcx::knob(knob);
     return QC_OK;
 }
 
@@ -1431,6 +1511,67 @@ int qc_batch_status(qc_batch_t *b, int *flags) {
     e = hipMemcpy(&v, b->barrier + b->n_groups, sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     *flags = int(v);
+    return QC_OK;
+}
+
+int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int reps,
+                qc_tune_entry_t *entries, int max_entries, int *n_entries, void *stream) {
+    int rc = check_state(scratch);
+    if (rc) return rc;
+    if (!n_entries || (max_entries > 0 && !entries)) return fail(QC_ERR_ARG, "NULL argument");
+    if (reps < 1 || reps > 100) return fail(QC_ERR_ARG, "reps must be 1..100");
+    if (n_gates < 1 || !gates) return fail(QC_ERR_ARG, "empty gate list");
+    for (int i = 0; i < n_gates; ++i)
+        if ((rc = check_gate(scratch.n, gates[i]))) return rc;
+    struct Cand { int mode, k, wg; };
+    std::vector<Cand> cands{{QC_EXEC_UNFUSED, 0, 0}, {QC_EXEC_TILED, 0, 0}};
+    for (int k = 2; k <= std::min(QC_MAX_FUSED, scratch.n); ++k) {
+        if (scratch.dtype == QC_C64 && k == 5 && scratch.n >= 12)
+            for (int wg = 2; wg <= 5; ++wg) cands.push_back({QC_EXEC_FUSED, 5, wg});
+        else
+            cands.push_back({QC_EXEC_FUSED, k, 0});
+    }
+    const int saved_wg = g_knob_mfma.load();
+    const hipStream_t hs = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(QC_ERR_HIP, "hipEventCreate");
+    std::vector<qc_tune_entry_t> out;
+    for (const Cand &c : cands) {
+        if (c.wg) g_knob_mfma.store(c.wg);
+        qc_exec_stats_t st{};
+        std::vector<float> t;
+        for (int r = 0; r <= reps && rc == QC_OK; ++r) {
+            if ((rc = qc_state_init(scratch, 0, stream))) break;
+            (void)hipEventRecord(e0, hs);
+            rc = qc_apply_circuit(scratch, n_gates, gates, c.mode, c.k ? c.k : 5, &st, stream);
+            (void)hipEventRecord(e1, hs);
+            if (rc) break;
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(QC_ERR_HIP, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t.push_back(ms);   // the first run is the warm-up
+        }
+        if (rc) break;
+        std::sort(t.begin(), t.end());
+        qc_tune_entry_t e{};
+        e.mode = c.mode;
+        e.fuse_k = c.k;
+        e.mfma_wg_per_cu = c.wg ? c.wg : saved_wg;
+        e.sweeps = int32_t(st.sweeps);
+        e.ms = t[t.size() / 2];
+        out.push_back(e);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_knob_mfma.store(saved_wg);
+    if (rc) return rc;
+    std::stable_sort(out.begin(), out.end(),
+                     [](const qc_tune_entry_t &a, const qc_tune_entry_t &b) { return a.ms < b.ms; });
+    if (!out.empty()) g_knob_mfma.store(out[0].mfma_wg_per_cu);
+    const int n = std::min<int>(int(out.size()), max_entries);
+    for (int i = 0; i < n; ++i) entries[i] = out[i];
+    *n_entries = n;
     return QC_OK;
 }
 

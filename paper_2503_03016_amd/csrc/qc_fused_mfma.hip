@@ -218,9 +218,9 @@ int query_grid_cap() {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        cap = cus * 4;
+        cap = cus;
     }
-    return cap;
+    return cap * knob(QC_KNOB_MFMA_WG_PER_CU);
 }
 
 }  // namespace

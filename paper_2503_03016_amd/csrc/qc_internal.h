@@ -190,6 +190,7 @@ hipError_t launch_grad_finalize(const double *partial, int rows, int cols, doubl
                                 hipStream_t s);
 
 // ---- library services implemented in qc_api.cpp -----------------------------
+int knob(int which);   // current value of a QC_KNOB_* launch-shape knob
 int timer_begin(const char *name, hipStream_t s);
 void timer_end(int token, hipStream_t s);
 

@@ -52,7 +52,7 @@ hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t cap = uint64_t(cus) * 8;
+    const uint64_t cap = uint64_t(cus) * uint64_t(knob(QC_KNOB_TILE_WG_PER_CU));
     if (grid > cap) grid = cap;
     const int tok = timer_begin(dtype == QC_C64 ? "tile_run_c64" : "tile_run_c128", s);
     if (dtype == QC_C64)

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqc.so")
 
 QC_C64, QC_C128 = 1, 2
-QC_EXEC_UNFUSED, QC_EXEC_FUSED = 0, 1
+QC_EXEC_UNFUSED, QC_EXEC_FUSED, QC_EXEC_TILED = 0, 1, 2
 QC_MAX_FUSED, QC_MAX_CTRLS = 5, 16
 STATUS = {0: "QC_OK", -1: "QC_ERR_ARG", -2: "QC_ERR_QUBIT", -3: "QC_ERR_DTYPE",
           -4: "QC_ERR_UNSUPPORTED", -5: "QC_ERR_HIP", -6: "QC_ERR_NOMEM"}
@@ -30,8 +30,9 @@ EXPORTS = [
     "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
-    "qc_sample",
+    "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune",
 ]
+QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU = 1, 2
 
 
 class QcError(RuntimeError):
@@ -65,6 +66,15 @@ class QcCircuit(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_gates", ctypes.c_int32),
                 ("gates", ctypes.POINTER(QcGate)), ("n_terms", ctypes.c_int32),
                 ("paulis", ctypes.c_char_p), ("coeff", ctypes.POINTER(ctypes.c_double))]
+
+
+class QcTuneEntry(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32),
+                ("mfma_wg_per_cu", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class QcOp(ctypes.Structure):
@@ -108,6 +118,10 @@ def _load():
         "qc_collapse": ([S, i, i, vp, vp], i),
         "qc_reduced_state": ([S, i, ip, ip, S, vp], i),
         "qc_sample": ([S, i, vp, vp, vp], i),
+        "qc_set_knob": ([i, i], i),
+        "qc_get_knob": ([i, ip], i),
+        "qc_autotune": ([S, i, ctypes.POINTER(QcGate), i, ctypes.POINTER(QcTuneEntry), i, ip, vp],
+                        i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -303,6 +317,25 @@ def sample(psi: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
     _check(lib.qc_sample(state_view(psi), int(u.numel()), ctypes.c_void_p(u.data_ptr()),
                          ctypes.c_void_p(out.data_ptr()), _stream(psi)), "qc_sample")
     return out
+
+
+def set_knob(knob: int, value: int) -> None:
+    _check(lib.qc_set_knob(int(knob), int(value)), "qc_set_knob")
+
+
+def get_knob(knob: int) -> int:
+    v = ctypes.c_int()
+    _check(lib.qc_get_knob(int(knob), ctypes.byref(v)), "qc_get_knob")
+    return v.value
+
+
+def autotune(scratch: torch.Tensor, gates: GateList, reps: int = 3) -> List[dict]:
+    """Time every execution strategy (qc_autotune); fastest first."""
+    ents = (QcTuneEntry * 32)()
+    cnt = ctypes.c_int()
+    _check(lib.qc_autotune(state_view(scratch), gates.count, gates.arr, int(reps), ents, 32,
+                           ctypes.byref(cnt), _stream(scratch)), "qc_autotune")
+    return [ents[i].as_dict() for i in range(cnt.value)]
 
 
 def make_ops(ops) -> Tuple[ctypes.Array, int]:

@@ -27,6 +27,22 @@ def qc():
     return mod
 
 
+def test_package_modules_import_and_constants_match_header():
+    import importlib
+    for mod in ("qc", "gates", "simulate", "autograd", "autotune"):
+        importlib.import_module("paper_2503_03016_amd." + mod)
+    from paper_2503_03016_amd import qc as q
+    text = open(HEADER).read()
+    for name in ("QC_C64", "QC_C128", "QC_EXEC_UNFUSED", "QC_EXEC_FUSED", "QC_EXEC_TILED",
+                 "QC_MAX_FUSED", "QC_MAX_CTRLS", "QC_KNOB_MFMA_WG_PER_CU",
+                 "QC_KNOB_TILE_WG_PER_CU"):
+        m = re.search(r"#define\s+%s\s+(-?\d+)" % name, text)
+        assert m and getattr(q, name) == int(m.group(1)), name
+    for kind, code in q.OP_KIND.items():
+        m = re.search(r"#define\s+QC_OP_%s\s+(\d+)" % kind, text)
+        assert m and int(m.group(1)) == code, kind
+
+
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for required in ("qc_state_init", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled",
@@ -115,6 +131,22 @@ def test_adjoint_validation(qc):
     assert lib.qc_adjoint_grad(a, a, ops, nops, tp, 4, 1, b"ZIII", cp, out, out, None) == -1
     ops2, n2 = qc.make_ops([W.Op("CZ", (1, 1))])
     assert lib.qc_adjoint_grad(a, b, ops2, n2, tp, 2, 1, b"ZIII", cp, out, out, None) == -2
+
+
+def test_knobs(qc):
+    old = qc.get_knob(qc.QC_KNOB_MFMA_WG_PER_CU)
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 0) == -1
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 6) == -1
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_TILE_WG_PER_CU, 17) == -1
+    assert qc.lib.qc_set_knob(99, 1) == -1
+    qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 3)
+    assert qc.get_knob(qc.QC_KNOB_MFMA_WG_PER_CU) == 3
+    qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, old)
+    ents = (qc.QcTuneEntry * 4)()
+    cnt = ctypes.c_int()
+    gl = qc.GateList([((0,), (), (), np.eye(2))])
+    assert qc.lib.qc_autotune(st(qc), 1, gl.arr, 0, ents, 4, ctypes.byref(cnt), None) == -1
+    assert qc.lib.qc_autotune(st(qc), 0, gl.arr, 3, ents, 4, ctypes.byref(cnt), None) == -1
 
 
 def test_batch_validation(qc):

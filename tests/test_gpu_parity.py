@@ -445,6 +445,27 @@ def test_adjoint_config24_vs_central_differences(qc, G, dt):
         assert np.max(np.abs(g64.cpu().numpy() - g128)) < bound
 
 
+def test_autotune_picks_a_correct_fast_strategy(qc, G, tmp_path, monkeypatch):
+    from paper_2503_03016_amd import autotune
+    monkeypatch.setenv("QC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n = 16
+    ops = W.brickwork(n, 6, seed=16, entangler="CZ")
+    gts = G.gate_tuples(ops)
+    best = autotune.tune(n, torch.complex64, gts, family="brickwork16x6")
+    table = best["table"]
+    assert len(table) >= 6 and all(table[i]["ms"] <= table[i + 1]["ms"] for i in range(len(table) - 1))
+    assert best["ms"] == table[0]["ms"]
+    assert (tmp_path / "tune.json").exists()
+    again = autotune.tune(n, torch.complex64, gts, family="brickwork16x6")
+    assert again["ms"] == best["ms"]          # served from the cache
+    psi = qc.new_state(n, torch.complex64)
+    qc.state_init(psi, 0)
+    autotune.apply_tuned(psi, gts, family="brickwork16x6")
+    ref = oracle.run(ops, oracle.basis_state(n, 0))
+    check(host(psi), ref, torch.complex64, ngates=len(ops))
+    qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 4)
+
+
 def test_autograd_energy_function(qc):
     from paper_2503_03016_amd.autograd import AdjointCircuit, energy
     n, layers = 6, 2

@@ -365,6 +365,28 @@ def test_parameter_shift_vs_finite_differences():
     np.testing.assert_allclose(g_ps, g_fd, atol=1e-8)
 
 
+def test_sampling_closed_forms():
+    n = 6
+    N = 1 << n
+    # a basis state always yields its own index
+    assert np.all(oracle.sample(oracle.basis_state(n, 37), np.linspace(0, 0.999, 50)) == 37)
+    # the uniform superposition maps u in [k/N, (k+1)/N) to k
+    plus = np.full(N, 1 / math.sqrt(N), dtype=complex)
+    u = (np.arange(N) + 0.5) / N
+    assert np.array_equal(oracle.sample(plus, u), np.arange(N))
+    # empirical frequencies converge to |psi|^2 (chi-square, 63 dof)
+    psi = random_state(n, np.random.default_rng(4))
+    idx = oracle.sample(psi, np.random.default_rng(5).uniform(size=200000))
+    counts = np.bincount(idx, minlength=N)
+    exp = 200000 * np.abs(psi) ** 2
+    chi2 = np.sum((counts - exp) ** 2 / exp)
+    assert chi2 < 120   # p ~ 1e-5 for 63 degrees of freedom
+    # zero-probability indices are never drawn
+    half = np.zeros(N, dtype=complex)
+    half[::2] = 1 / math.sqrt(N / 2)
+    assert np.all(oracle.sample(half, np.random.default_rng(6).uniform(size=1000)) % 2 == 0)
+
+
 def test_oracle_rejects_bad_arguments():
     psi = oracle.basis_state(3, 0)
     with pytest.raises(ValueError):
