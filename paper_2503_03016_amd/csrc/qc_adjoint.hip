@@ -5,10 +5,15 @@
 // U_k = exp(-i theta G / 2) with G in {X, Y, Z}:
 //   dE/dtheta_k = 2 Re <lam_k| dU_k/dtheta |phi_{k-1}> = Im <lam_k| G |phi_k>,
 // where phi_k is the state after gate k and lam_k = U_{k+1}^+ .. U_L^+ H phi.
-// The backward sweep keeps (phi, lam) at step k, takes the FP64 reduction
-// Im <lam|G|phi> and un-applies U_k to both vectors in the same pass over
-// memory (read 2 vectors, write 2 vectors).
-#include "qc_internal.h"
+//
+// The backward sweep runs the reversed, adjoint gate list on BOTH vectors
+// in LDS tile runs: a tile of phi and the matching tile of lam are loaded
+// together, and for every rotation of the run the FP64 partial
+// Im <lam|G|phi> over the tile is taken right before its inverse is applied
+// to both tiles.  A run of G gates costs 4 state-sizes of HBM traffic in
+// total instead of 4 per gate.  Partials are kept per (rotation,
+// workgroup) and summed in a fixed order afterwards.
+#include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
 
@@ -16,7 +21,7 @@ namespace qcx {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = tile::kBlock;
 constexpr int kWaves = kBlock / 64;
 
 __device__ inline double wave_sum(double v) {
@@ -53,52 +58,81 @@ __global__ __launch_bounds__(kBlock) void k_pauli_apply(const cx<R> *psi, cx<R> 
     }
 }
 
-// One backward step for a one-qubit parametrised gate on bit p with
-// generator G (1 = X, 2 = Y, 3 = Z): partial Im <lam|G|phi> per block, then
-// phi <- Ud phi, lam <- Ud lam with Ud = U^+.
+// Im <lam|G|phi> over the pairs of compressed bit b of one tile (partial of
+// this thread); G: 1 = X, 2 = Y, 3 = Z.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_adjoint_step(cx<R> *phi, cx<R> *lam, uint64_t n_pairs,
-                                                         int p, int gen, const Mat2d ud,
-                                                         double *partial) {
-    __shared__ double lds[kWaves];
+__device__ inline double grad_partial(const cx<R> *f, const cx<R> *l, int m, int b, int gen) {
     double acc = 0.0;
-    const uint64_t bit = uint64_t(1) << p;
-    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < n_pairs; g += stride) {
-        const uint64_t i0 = insert_zero(g, p), i1 = i0 | bit;
-        const cx<R> f0 = phi[i0], f1 = phi[i1], l0 = lam[i0], l1 = lam[i1];
-        const double f0r = f0.re, f0i = f0.im, f1r = f1.re, f1i = f1.im;
-        const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+    for (int g = threadIdx.x; g < (1 << (m - 1)); g += kBlock) {
+        const uint32_t i0 = uint32_t(insert_zero(uint64_t(g), b)), i1 = i0 | (1u << b);
+        const double f0r = f[i0].re, f0i = f[i0].im, f1r = f[i1].re, f1i = f[i1].im;
+        const double l0r = l[i0].re, l0i = l[i0].im, l1r = l[i1].re, l1i = l[i1].im;
         // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-        if (gen == 3) {
+        if (gen == 3)
             acc += (l0r * f0i - l0i * f0r) - (l1r * f1i - l1i * f1r);
-        } else if (gen == 1) {
+        else if (gen == 1)
             acc += (l0r * f1i - l0i * f1r) + (l1r * f0i - l1i * f0r);
-        } else {
+        else
             acc += -(l0r * f1r + l0i * f1i) + (l1r * f0r + l1i * f0i);
-        }
-        const R u0r = R(ud.re[0]), u0i = R(ud.im[0]), u1r = R(ud.re[1]), u1i = R(ud.im[1]);
-        const R u2r = R(ud.re[2]), u2i = R(ud.im[2]), u3r = R(ud.re[3]), u3i = R(ud.im[3]);
-        const cx<R> U0{u0r, u0i}, U1{u1r, u1i}, U2{u2r, u2i}, U3{u3r, u3i};
-        const cx<R> zero{R(0), R(0)};
-        phi[i0] = cfma(U1, f1, cfma(U0, f0, zero));
-        phi[i1] = cfma(U3, f1, cfma(U2, f0, zero));
-        lam[i0] = cfma(U1, l1, cfma(U0, l0, zero));
-        lam[i1] = cfma(U3, l1, cfma(U2, l0, zero));
     }
-    double v = wave_sum(acc);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) lds[wave] = v;
+    return acc;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
+                                                          const TileOp *ops,
+                                                          const int32_t *slot_row, int n_slots,
+                                                          double *partial, int cols) {
+    extern __shared__ unsigned char smem[];
+    __shared__ double acc[kAdjointMaxSlots];
+    __shared__ double red[kWaves];
+    const int T = 1 << a.m;
+    cx<R> *lp = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *ll = lp + T;
+    for (int s = threadIdx.x; s < n_slots; s += kBlock) acc[s] = 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int w = 0; w < kWaves; ++w) r += lds[w];
-        partial[blockIdx.x] = r;
+    const uint64_t off_lo =
+        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < 8 ? a.m : 8);
+    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const uint64_t base = insert_zeros(t, a.pos, a.m);
+        for (int j = threadIdx.x; j < T; j += kBlock) {
+            const uint64_t at = base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m);
+            lp[j] = phi[at];
+            ll[j] = lam[at];
+        }
+        __syncthreads();
+        for (int o = 0; o < a.n_ops; ++o) {
+            const TileOp &op = ops[o];
+            if ((base & op.cmask_hi) != op.cval_hi) continue;   // uniform per tile
+            if (op.kind == TILE_GRAD) {
+                double v = wave_sum(grad_partial<R>(lp, ll, a.m, op.b0, op.b1));
+                if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double s = 0.0;
+                    for (int w = 0; w < kWaves; ++w) s += red[w];
+                    acc[op.pad] += s;
+                }
+                __syncthreads();
+            } else {
+                tile::apply_one<R>(lp, a.m, op);
+                tile::apply_one<R>(ll, a.m, op);
+                __syncthreads();
+            }
+        }
+        for (int j = threadIdx.x; j < T; j += kBlock) {
+            const uint64_t at = base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m);
+            phi[at] = lp[j];
+            lam[at] = ll[j];
+        }
+        __syncthreads();
     }
+    for (int s = threadIdx.x; s < n_slots; s += kBlock)
+        partial[size_t(slot_row[s]) * cols + blockIdx.x] = acc[s];
 }
 
 // g_op[i] = sum of row i of the partials (fixed order), then
-// grad[p] = sum over the ops of parameter p (CSR, op order).
+// grad[p] = sum over the rotations of parameter p (CSR, op order).
 __global__ __launch_bounds__(kBlock) void k_grad_rows(const double *partial, int cols,
                                                       double *g_op) {
     __shared__ double lds[kWaves];
@@ -125,16 +159,15 @@ __global__ void k_grad_scatter(const double *g_op, const int *ptr, const int *id
     grad[p] = s;
 }
 
-unsigned grid_for(uint64_t items) {
-    uint64_t b = (items + kBlock * 8 - 1) / (kBlock * 8);
-    if (b < 1) b = 1;
-    if (b > unsigned(kReduceBlocks)) b = kReduceBlocks;
-    return unsigned(b);
-}
-
 }  // namespace
 
-unsigned adjoint_grid(int n) { return grid_for(uint64_t(1) << (n - 1)); }
+unsigned adjoint_tile_grid(uint64_t n_tiles) {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t cap = uint64_t(cus) * 4;
+    return unsigned(n_tiles < cap ? n_tiles : cap);
+}
 
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
                               const PauliTermDev *terms, int nt, hipStream_t s) {
@@ -154,19 +187,22 @@ hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(void *phi, void *lam, int dtype, int n, int p, int gen,
-                               const Mat2d &ud, double *partial, hipStream_t s) {
-    const uint64_t pairs = uint64_t(1) << (n - 1);
-    const unsigned grid = grid_for(pairs);
-    const int tok = timer_begin("adjoint_step", s);
+hipError_t launch_adjoint_tiles(void *phi, void *lam, int dtype, const TileArgs &a,
+                                const TileOp *ops_dev, const int32_t *slot_row_dev, int n_slots,
+                                double *partial, unsigned cols, hipStream_t s) {
+    if (n_slots > kAdjointMaxSlots) return hipErrorInvalidValue;
+    const size_t elem = dtype == QC_C64 ? 8 : 16;
+    const size_t lds = 2 * (size_t(1) << a.m) * elem;
+    if (lds > 65536) return hipErrorInvalidValue;
+    const int tok = timer_begin(dtype == QC_C64 ? "adjoint_tiles_c64" : "adjoint_tiles_c128", s);
     if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_adjoint_step<float>), dim3(grid), dim3(kBlock), 0, s,
-                           static_cast<cx<float> *>(phi), static_cast<cx<float> *>(lam), pairs, p, gen,
-                           ud, partial);
+        hipLaunchKernelGGL((k_adjoint_tiles<float>), dim3(cols), dim3(kBlock), lds, s,
+                           static_cast<cx<float> *>(phi), static_cast<cx<float> *>(lam), a, ops_dev,
+                           slot_row_dev, n_slots, partial, int(cols));
     else
-        hipLaunchKernelGGL((k_adjoint_step<double>), dim3(grid), dim3(kBlock), 0, s,
-                           static_cast<cx<double> *>(phi), static_cast<cx<double> *>(lam), pairs, p,
-                           gen, ud, partial);
+        hipLaunchKernelGGL((k_adjoint_tiles<double>), dim3(cols), dim3(kBlock), lds, s,
+                           static_cast<cx<double> *>(phi), static_cast<cx<double> *>(lam), a,
+                           ops_dev, slot_row_dev, n_slots, partial, int(cols));
     timer_end(tok, s);
     return hipGetLastError();
 }

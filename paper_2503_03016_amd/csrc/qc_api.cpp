@@ -692,24 +692,26 @@ int tile_bits_for(const qc_state_t &s) { return std::min(s.n, s.dtype == QC_C64 
 // Greedy run formation: starting from the earliest pending gate, a gate
 // joins the run when none of its qubits is held by an earlier gate left out
 // and its non-diagonal targets still fit in the m tile bits.
-int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st,
-                  void *stream) {
-    DevCtx *c;
-    int rc = get_ctx(&c);
-    if (rc) return rc;
-    const int n = s.n;
-    const int m = tile_bits_for(s);
+struct TileRun {
+    uint64_t P;              // tile bits (bit-position mask); 0 for a standalone gate
+    std::vector<int> gates;  // gate indices in order
+};
+
+// Greedy run formation: starting from the earliest pending gate, a gate
+// joins the run when none of its qubits is held by an earlier gate left out
+// and its non-diagonal targets (plus extra_tbits[i], if given) still fit in
+// the m tile bits.  Gates that cannot be tiled become standalone runs.
+void form_runs(int n, int m, int ng, const qc_gate_t *gs, const uint64_t *extra_tbits,
+               std::vector<TileRun> &runs) {
     const int low = std::min(m, 5);      // always-resident low bits: runs of >= 32 amplitudes
     const uint64_t low_mask = (uint64_t(1) << low) - 1;
     const uint64_t all = (uint64_t(1) << n) - 1;
-    const hipStream_t hs = (hipStream_t)stream;
     std::vector<int> pending(ng);
     for (int i = 0; i < ng; ++i) pending[i] = i;
-    std::vector<qcx::TileOp> ops;
+    runs.clear();
     while (!pending.empty()) {
-        const TileClass first = tile_class(n, gs[pending[0]]);
-        if (!first.tileable) {
-            if ((rc = apply_gate_unfused(s, gs[pending[0]], st, stream))) return rc;
+        if (!tile_class(n, gs[pending[0]]).tileable) {
+            runs.push_back({0, {pending[0]}});
             pending.erase(pending.begin());
             continue;
         }
@@ -717,9 +719,10 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         std::vector<int> run, rest;
         for (int idx : pending) {
             const TileClass tc = tile_class(n, gs[idx]);
-            if (!(tc.touch & blocked) && tc.tileable &&
-                __builtin_popcountll(P | tc.tbits) <= m && blocked != all) {
-                P |= tc.tbits;
+            const uint64_t tb = tc.tbits | (extra_tbits ? extra_tbits[idx] : 0);
+            if (!(tc.touch & blocked) && tc.tileable && __builtin_popcountll(P | tb) <= m &&
+                blocked != all) {
+                P |= tb;
                 run.push_back(idx);
             } else {
                 blocked |= tc.touch;
@@ -727,14 +730,40 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
             }
         }
         for (int p = 0; __builtin_popcountll(P) < m && p < n; ++p) P |= uint64_t(1) << p;
+        runs.push_back({P, run});
+        pending.swap(rest);
+    }
+}
+
+qcx::TileArgs tile_args(int n, int m, uint64_t P, int n_ops) {
+    qcx::TileArgs a{};
+    a.m = m;
+    a.n_ops = n_ops;
+    a.n_tiles = uint64_t(1) << (n - m);
+    for (int p = 0, j = 0; p < n; ++p)
+        if ((P >> p) & 1) a.pos[j++] = uint8_t(p);
+    return a;
+}
+
+int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st,
+                  void *stream) {
+    DevCtx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    const int n = s.n;
+    const int m = tile_bits_for(s);
+    const hipStream_t hs = (hipStream_t)stream;
+    std::vector<TileRun> runs;
+    form_runs(n, m, ng, gs, nullptr, runs);
+    std::vector<qcx::TileOp> ops;
+    for (const TileRun &r : runs) {
+        if (r.P == 0) {
+            if ((rc = apply_gate_unfused(s, gs[r.gates[0]], st, stream))) return rc;
+            continue;
+        }
         ops.clear();
-        for (int idx : run) tile_ops_for(n, gs[idx], P, ops);
-        qcx::TileArgs a{};
-        a.m = m;
-        a.n_ops = int(ops.size());
-        a.n_tiles = uint64_t(1) << (n - m);
-        for (int p = 0, j = 0; p < n; ++p)
-            if ((P >> p) & 1) a.pos[j++] = uint8_t(p);
+        for (int idx : r.gates) tile_ops_for(n, gs[idx], r.P, ops);
+        const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
         void *dev = nullptr;
         if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
         hipError_t e = qcx::launch_tile_run(s.amp, s.dtype, n, a,
@@ -743,7 +772,6 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         st.launches += 1;
         st.sweeps += 1;
         st.state_bytes += sweep_bytes(n, s.dtype);
-        pending.swap(rest);
     }
     return QC_OK;
 }
@@ -1024,34 +1052,6 @@ void mat_dagger(const qcx::Mat2d &a, qcx::Mat2d &d) {
     }
 }
 
-// Apply a program op (or its inverse) to one state.
-hipError_t apply_op(const qc_state_t &s, const qc_op_t &op, const double *theta, bool inverse,
-                    hipStream_t hs) {
-    const int n = s.n;
-    if (op.kind == QC_OP_CZ) {
-        const int pos[2] = {bitpos(n, op.q0), bitpos(n, op.q1)}, val[2] = {1, 1};
-        return qcx::launch_phase(s.amp, s.dtype, n, 2, pos, val, -1.0, 0.0, hs);
-    }
-    if (op.kind == QC_OP_CNOT) {
-        const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
-        const int tp = bitpos(n, op.q1), cp = bitpos(n, op.q0), cv = 1;
-        return qcx::launch_small_gate(s.amp, s.dtype, n, 1, &tp, 1, &cp, &cv, x, hs);
-    }
-    qcx::Mat2d m, d;
-    op_matrix(op, theta, m);
-    if (inverse) {
-        mat_dagger(m, d);
-        m = d;
-    }
-    double u[8];
-    for (int i = 0; i < 4; ++i) {
-        u[2 * i] = m.re[i];
-        u[2 * i + 1] = m.im[i];
-    }
-    const int tp = bitpos(n, op.q0);
-    return qcx::launch_small_gate(s.amp, s.dtype, n, 1, &tp, 0, nullptr, nullptr, u, hs);
-}
-
 bool is_rotation(int kind) { return kind == QC_OP_RX || kind == QC_OP_RY || kind == QC_OP_RZ; }
 
 }  // namespace
@@ -1109,14 +1109,57 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
     }
     DevCtx *c;
     if ((rc = get_ctx(&c))) return rc;
-    const unsigned cols = qcx::adjoint_grid(n);
+    // two vectors share one 64 KiB LDS tile budget in the backward pass
+    const int mb = std::min(n, psi.dtype == QC_C64 ? 12 : 11);
+    const unsigned cols = qcx::adjoint_tile_grid(uint64_t(1) << (n - mb));
     const size_t need = size_t(n_rot) * cols + size_t(n_rot) + 1024;
     if (need > kWorkElems) return fail(QC_ERR_UNSUPPORTED, "too many rotations for the workspace");
     const hipStream_t hs = (hipStream_t)stream;
     hipError_t e;
-    // forward: phi = U_L .. U_1 psi
-    for (int k = 0; k < n_ops; ++k)
-        if ((e = apply_op(psi, ops[k], theta, false, hs)) != hipSuccess) return hip_fail(e, "forward");
+    // gate lists: forward U_1..U_L and backward U_L^+..U_1^+ (one or two
+    // qubits, at most one control), with FP64 matrices kept alive here
+    std::vector<qc_gate_t> fwd(n_ops), bwd(n_ops);
+    std::vector<double> mats(size_t(n_ops) * 16);
+    std::vector<uint64_t> extra(n_ops, 0);
+    std::vector<int> rot_row(n_ops, -1), gen_of(n_ops, 0);
+    for (int k = 0, r = 0; k < n_ops; ++k) {
+        const qc_op_t &o = ops[k];
+        qc_gate_t g{};
+        g.n_targets = 1;
+        double *uf = &mats[size_t(k) * 16], *ub = uf + 8;
+        if (o.kind == QC_OP_CZ || o.kind == QC_OP_CNOT) {
+            g.targets[0] = o.q1;
+            g.n_ctrls = 1;
+            g.ctrls[0] = o.q0;
+            g.ctrl_vals[0] = 1;
+            const double z[8] = {1, 0, 0, 0, 0, 0, -1, 0}, x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+            std::copy(o.kind == QC_OP_CZ ? z : x, (o.kind == QC_OP_CZ ? z : x) + 8, uf);
+            std::copy(uf, uf + 8, ub);      // self-inverse
+        } else {
+            g.targets[0] = o.q0;
+            qcx::Mat2d m, d;
+            op_matrix(o, theta, m);
+            mat_dagger(m, d);
+            for (int i = 0; i < 4; ++i) {
+                uf[2 * i] = m.re[i];
+                uf[2 * i + 1] = m.im[i];
+                ub[2 * i] = d.re[i];
+                ub[2 * i + 1] = d.im[i];
+            }
+        }
+        g.matrix = uf;
+        fwd[k] = g;
+        g.matrix = ub;
+        bwd[n_ops - 1 - k] = g;
+        if (is_rotation(o.kind)) {
+            rot_row[n_ops - 1 - k] = r++;
+            gen_of[n_ops - 1 - k] = o.kind == QC_OP_RX ? 1 : (o.kind == QC_OP_RY ? 2 : 3);
+            extra[n_ops - 1 - k] = uint64_t(1) << bitpos(n, o.q0);   // reduction needs the bit
+        }
+    }
+    // forward: phi = U_L .. U_1 psi in LDS tile runs
+    qc_exec_stats_t st{};
+    if ((rc = tiled_execute(psi, n_ops, fwd.data(), st, stream))) return rc;
     // energy, then lam = H phi
     if ((rc = qc_expect_pauli(psi, n_terms, paulis, coeff, 0, energy_dev, stream))) return rc;
     void *tdev = nullptr;
@@ -1124,25 +1167,47 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
     e = qcx::launch_pauli_apply(psi.amp, lam.amp, psi.dtype, n,
                                 static_cast<const qcx::PauliTermDev *>(tdev), n_terms, hs);
     if (e != hipSuccess) return hip_fail(e, "pauli_apply");
-    // backward: per rotation, Im <lam|G|phi> fused with the un-apply
+    // backward: tile runs over (phi, lam); each rotation's Im <lam|G|phi> is
+    // taken in LDS right before its inverse is applied
     double *partial = c->work;
     double *g_op = c->work + size_t(n_rot) * cols;
-    int row = n_rot;
-    for (int k = n_ops - 1; k >= 0; --k) {
-        const qc_op_t &o = ops[k];
-        if (is_rotation(o.kind)) {
-            qcx::Mat2d m, d;
-            op_matrix(o, theta, m);
-            mat_dagger(m, d);
-            --row;
-            const int gen = o.kind == QC_OP_RX ? 1 : (o.kind == QC_OP_RY ? 2 : 3);
-            e = qcx::launch_adjoint_step(psi.amp, lam.amp, psi.dtype, n, bitpos(n, o.q0), gen, d,
-                                         partial + size_t(row) * cols, hs);
-        } else {
-            e = apply_op(psi, o, theta, true, hs);
-            if (e == hipSuccess) e = apply_op(lam, o, theta, true, hs);
+    std::vector<TileRun> runs;
+    form_runs(n, mb, n_ops, bwd.data(), extra.data(), runs);
+    std::vector<qcx::TileOp> tops;
+    std::vector<int32_t> slot_row;
+    auto flush = [&](uint64_t P) -> int {
+        if (tops.empty()) return QC_OK;
+        const qcx::TileArgs a = tile_args(n, mb, P, int(tops.size()));
+        void *odev = nullptr, *sdev = nullptr;
+        int r2 = stage(c, tops.data(), tops.size() * sizeof(qcx::TileOp), hs, &odev);
+        if (!r2 && !slot_row.empty())
+            r2 = stage(c, slot_row.data(), slot_row.size() * sizeof(int32_t), hs, &sdev);
+        if (r2) return r2;
+        hipError_t e2 = qcx::launch_adjoint_tiles(psi.amp, lam.amp, psi.dtype, a,
+                                                  static_cast<const qcx::TileOp *>(odev),
+                                                  static_cast<const int32_t *>(sdev),
+                                                  int(slot_row.size()), partial, cols, hs);
+        tops.clear();
+        slot_row.clear();
+        return e2 == hipSuccess ? QC_OK : hip_fail(e2, "adjoint_tiles");
+    };
+    for (const TileRun &r : runs) {
+        if (r.P == 0) return fail(QC_ERR_UNSUPPORTED, "adjoint op cannot be tiled");
+        for (int j : r.gates) {
+            if (rot_row[j] >= 0) {
+                if (int(slot_row.size()) == qcx::kAdjointMaxSlots && (rc = flush(r.P))) return rc;
+                const uint64_t Pm = r.P;
+                qcx::TileOp gop{};
+                gop.kind = qcx::TILE_GRAD;
+                gop.b0 = __builtin_popcountll(Pm & ((uint64_t(1) << bitpos(n, bwd[j].targets[0])) - 1));
+                gop.b1 = gen_of[j];
+                gop.pad = int32_t(slot_row.size());
+                slot_row.push_back(rot_row[j]);
+                tops.push_back(gop);
+            }
+            tile_ops_for(n, bwd[j], r.P, tops);
         }
-        if (e != hipSuccess) return hip_fail(e, "backward");
+        if ((rc = flush(r.P))) return rc;
     }
     // grad[p] = sum of the rotation rows that use parameter p
     std::vector<int> csr(size_t(n_params) + 1 + size_t(n_rot), 0);

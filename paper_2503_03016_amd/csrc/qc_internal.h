@@ -85,7 +85,9 @@ struct Mat2d {
 };
 
 // One gate of an LDS tile run (positions are compressed tile positions).
-enum TileKind { TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3 };
+// TILE_GRAD (adjoint kernel only): accumulate Im <lam|G|phi> for generator
+// G (b1: 1 = X, 2 = Y, 3 = Z) on compressed bit b0 into slot `pad`.
+enum TileKind { TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4 };
 constexpr int kTileMaxBits = 16;
 struct TileOp {
     int32_t kind;
@@ -180,11 +182,13 @@ int batch_resident_blocks(int dtype, size_t lds_bytes);
 hipError_t launch_batch(const BatchArgs &a, int dtype, unsigned grid, size_t lds_bytes,
                         hipStream_t s);
 
-unsigned adjoint_grid(int n);
+constexpr int kAdjointMaxSlots = 512;   // rotations per adjoint tile run
+unsigned adjoint_tile_grid(uint64_t n_tiles);
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
                               const PauliTermDev *terms, int nt, hipStream_t s);
-hipError_t launch_adjoint_step(void *phi, void *lam, int dtype, int n, int p, int gen,
-                               const Mat2d &ud, double *partial, hipStream_t s);
+hipError_t launch_adjoint_tiles(void *phi, void *lam, int dtype, const TileArgs &a,
+                                const TileOp *ops_dev, const int32_t *slot_row_dev, int n_slots,
+                                double *partial, unsigned cols, hipStream_t s);
 hipError_t launch_grad_finalize(const double *partial, int rows, int cols, double *g_op,
                                 const int *ptr, const int *idx, int n_params, double *grad,
                                 hipStream_t s);
