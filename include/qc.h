@@ -175,9 +175,9 @@ int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, vo
  * gate; QC_EXEC_FUSED first groups consecutive gates into blocks of at most
  * fuse_k qubits (host FP64 matrix products, see qc_fuse_plan) and applies
  * each block with qc_apply_fused_k; QC_EXEC_TILED applies runs of gates in
- * LDS tiles (fuse_k is ignored).  Gates may be reordered only past gates on
- * disjoint qubits, so the result is the ordered product.  stats may be
- * NULL. */
+ * LDS tiles (fuse_k is ignored).  fuse_k must be 1..QC_MAX_FUSED and is
+ * capped at n.  Gates may be reordered only past gates on disjoint qubits,
+ * so the result is the ordered product.  stats may be NULL. */
 int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode,
                      int fuse_k, qc_exec_stats_t *stats, void *stream);
 

@@ -92,11 +92,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
     for (int s = threadIdx.x; s < n_slots; s += kBlock) acc[s] = 0.0;
     __syncthreads();
     const uint64_t off_lo =
-        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < 8 ? a.m : 8);
+        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
     for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
         for (int j = threadIdx.x; j < T; j += kBlock) {
-            const uint64_t at = base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m);
+            const uint64_t at = base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m);
             lp[j] = phi[at];
             ll[j] = lam[at];
         }
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             }
         }
         for (int j = threadIdx.x; j < T; j += kBlock) {
-            const uint64_t at = base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m);
+            const uint64_t at = base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m);
             phi[at] = lp[j];
             lam[at] = ll[j];
         }

@@ -815,8 +815,9 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(QC_ERR_ARG, "gate list is NULL");
     if (mode != QC_EXEC_UNFUSED && mode != QC_EXEC_FUSED && mode != QC_EXEC_TILED)
         return fail(QC_ERR_ARG, "unknown mode");
-    if (mode == QC_EXEC_FUSED && (fuse_k < 1 || fuse_k > QC_MAX_FUSED || fuse_k > s.n))
+    if (mode == QC_EXEC_FUSED && (fuse_k < 1 || fuse_k > QC_MAX_FUSED))
         return fail(QC_ERR_ARG, "fuse_k out of range");
+    if (fuse_k > s.n) fuse_k = s.n;   // blocks cannot be wider than the register
     for (int i = 0; i < n_gates; ++i)
         if ((rc = check_gate(s.n, gates[i]))) return rc;
     qc_exec_stats_t st{};

@@ -107,8 +107,12 @@ __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *l
     cx<R> *state = static_cast<cx<R> *>(a.arena) + C.arena_off;
     double acc = 0.0;
     for (int p = C.phase_begin; p < C.phase_begin + C.phase_count; ++p) {
-        const BatchPhase &P = a.phases[p];
+        const BatchPhase P = a.phases[p];   // one uniform copy per phase
         const int T = 1 << P.m;
+        // element j = threadIdx.x + 256 k: the low 8 compressed bits are this
+        // thread's, the high ones come from k
+        const int lo_bits = P.m < tile::kLoBits ? P.m : tile::kLoBits;
+        const uint64_t off_lo = tile::deposit(uint32_t(threadIdx.x) & uint32_t(T - 1), P.pos, lo_bits);
         for (uint64_t t = rank; t < P.n_tiles; t += G) {
             const uint64_t base = insert_zeros(t, P.pos, P.m);
             if (P.flags & BATCH_INIT) {
@@ -118,16 +122,24 @@ __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *l
                     lds[j] = v;
                 }
             } else {
-                for (int j = threadIdx.x; j < T; j += kBlock)
-                    lds[j] = state[base + tile::deposit(uint32_t(j), P.pos, P.m)];
+                for (int j = threadIdx.x; j < T; j += kBlock) {
+                    uint64_t off = off_lo;
+                    for (int b = tile::kLoBits; b < P.m; ++b)
+                        if ((j >> b) & 1) off |= uint64_t(1) << P.pos[b];
+                    lds[j] = state[base + off];
+                }
             }
             __syncthreads();
             tile::apply_ops<R>(lds, P.m, base, a.ops + P.op_begin, P.op_count);
             if (P.term_count) acc += tile_energy<R>(lds, P.m, base, a.terms + P.term_begin,
                                                     P.term_count);
             if (P.flags & BATCH_STORE)
-                for (int j = threadIdx.x; j < T; j += kBlock)
-                    state[base + tile::deposit(uint32_t(j), P.pos, P.m)] = lds[j];
+                for (int j = threadIdx.x; j < T; j += kBlock) {
+                    uint64_t off = off_lo;
+                    for (int b = tile::kLoBits; b < P.m; ++b)
+                        if ((j >> b) & 1) off |= uint64_t(1) << P.pos[b];
+                    state[base + off] = lds[j];
+                }
             __syncthreads();
         }
         if (G > 1) group_barrier(bar, G, gen, a.error);

@@ -27,15 +27,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
     const int T = 1 << a.m;
     // the low 8 compressed bits of this thread's elements are fixed
     const uint64_t off_lo =
-        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < 8 ? a.m : 8);
+        tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
     for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
         for (int j = threadIdx.x; j < T; j += kBlock)
-            lds[j] = amp[base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m)];
+            lds[j] = amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)];
         __syncthreads();
         tile::apply_ops<R>(lds, a.m, base, ops, a.n_ops);
         for (int j = threadIdx.x; j < T; j += kBlock)
-            amp[base + off_lo + tile::deposit(uint32_t(j) >> 8 << 8, a.pos, a.m)] = lds[j];
+            amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)] = lds[j];
         __syncthreads();
     }
 }

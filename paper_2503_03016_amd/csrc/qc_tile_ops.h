@@ -6,6 +6,9 @@
 // 3.2 restricted to the 2^m amplitudes of the tile; positions are
 // compressed tile positions, controls outside the tile are tested once per
 // tile against the tile's base index.
+//
+// Each thread handles kItems independent amplitude groups per step, all
+// loads first, so the LDS latency of one group is hidden behind the others.
 #pragma once
 
 #include "qc_internal.h"
@@ -13,11 +16,17 @@
 namespace qcx {
 namespace tile {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;     // threads per workgroup of the tile kernels
+constexpr int kLoBits = 9;      // log2(kBlock)
+constexpr int kItems = 4;       // independent groups per thread per step
 
 template <typename R>
 __device__ inline cx<R> ld_u(const double *u, int i) {
     return cx<R>{R(u[2 * i]), R(u[2 * i + 1])};
+}
+
+__device__ inline uint32_t ins0(uint32_t g, int p) {
+    return ((g >> p) << (p + 1)) | (g & ((1u << p) - 1u));
 }
 
 // Apply one op to the tile in `lds` (no barrier).  Ops whose conditions on
@@ -25,52 +34,104 @@ __device__ inline cx<R> ld_u(const double *u, int i) {
 template <typename R>
 __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
     const int T = 1 << m;
+    const uint32_t cm = op.cmask_lo, cv = op.cval_lo;
     switch (op.kind) {
     case TILE_DENSE1: {
         const int b = op.b0;
+        const uint32_t bit = 1u << b;
         const cx<R> u0 = ld_u<R>(op.u, 0), u1 = ld_u<R>(op.u, 1), u2 = ld_u<R>(op.u, 2),
                     u3 = ld_u<R>(op.u, 3);
-        for (int g = threadIdx.x; g < (T >> 1); g += kBlock) {
-            const uint32_t i0 = uint32_t(insert_zero(uint64_t(g), b));
-            if ((i0 & op.cmask_lo) != op.cval_lo) continue;
-            const uint32_t i1 = i0 | (1u << b);
-            const cx<R> a0 = lds[i0], a1 = lds[i1];
-            const cx<R> z{R(0), R(0)};
-            lds[i0] = cfma(u1, a1, cfma(u0, a0, z));
-            lds[i1] = cfma(u3, a1, cfma(u2, a0, z));
+        const int npairs = T >> 1;
+        for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
+            uint32_t i0[kItems];
+            bool ok[kItems];
+            cx<R> a0[kItems], a1[kItems];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const int g = g0 + k * kBlock;
+                i0[k] = ins0(uint32_t(g), b);
+                ok[k] = g < npairs && (i0[k] & cm) == cv;
+                if (ok[k]) {
+                    a0[k] = lds[i0[k]];
+                    a1[k] = lds[i0[k] | bit];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                if (!ok[k]) continue;
+                const cx<R> z{R(0), R(0)};
+                lds[i0[k]] = cfma(u1, a1[k], cfma(u0, a0[k], z));
+                lds[i0[k] | bit] = cfma(u3, a1[k], cfma(u2, a0[k], z));
+            }
         }
     } break;
     case TILE_DENSE2: {
         const int b0 = op.b0, b1 = op.b1;
         const int lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
         const uint32_t o1 = 1u << b1, o2 = 1u << b0;   // local index r = 2 bit(b0) + bit(b1)
-        for (int g = threadIdx.x; g < (T >> 2); g += kBlock) {
-            const uint32_t base = uint32_t(insert_zero(insert_zero(uint64_t(g), lo), hi));
-            if ((base & op.cmask_lo) != op.cval_lo) continue;
-            const uint32_t idx[4] = {base, base | o1, base | o2, base | o1 | o2};
-            cx<R> a[4];
+        const int ngroups = T >> 2;
+        for (int g0 = threadIdx.x; g0 < ngroups; g0 += kBlock * 2) {
+            uint32_t base[2];
+            bool ok[2];
+            cx<R> a[2][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = lds[idx[r]];
+            for (int k = 0; k < 2; ++k) {
+                const int g = g0 + k * kBlock;
+                base[k] = ins0(ins0(uint32_t(g), lo), hi);
+                ok[k] = g < ngroups && (base[k] & cm) == cv;
+                if (ok[k]) {
+                    a[k][0] = lds[base[k]];
+                    a[k][1] = lds[base[k] | o1];
+                    a[k][2] = lds[base[k] | o2];
+                    a[k][3] = lds[base[k] | o1 | o2];
+                }
+            }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                cx<R> acc{R(0), R(0)};
+            for (int k = 0; k < 2; ++k) {
+                if (!ok[k]) continue;
+                const uint32_t idx[4] = {base[k], base[k] | o1, base[k] | o2, base[k] | o1 | o2};
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc = cfma(ld_u<R>(op.u, 4 * r + c), a[c], acc);
-                lds[idx[r]] = acc;
+                for (int r = 0; r < 4; ++r) {
+                    cx<R> acc{R(0), R(0)};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc = cfma(ld_u<R>(op.u, 4 * r + c), a[k][c], acc);
+                    lds[idx[r]] = acc;
+                }
             }
         }
     } break;
     case TILE_PHASE: {
         const cx<R> ph = ld_u<R>(op.u, 0);
-        for (int i = threadIdx.x; i < T; i += kBlock)
-            if ((uint32_t(i) & op.cmask_lo) == op.cval_lo) lds[i] = cmul(ph, lds[i]);
+        for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
+            cx<R> v[kItems];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const int i = i0 + k * kBlock;
+                if (i < T && (uint32_t(i) & cm) == cv) v[k] = lds[i];
+            }
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const int i = i0 + k * kBlock;
+                if (i < T && (uint32_t(i) & cm) == cv) lds[i] = cmul(ph, v[k]);
+            }
+        }
     } break;
     case TILE_DIAG1: {  // amp *= d[bit b]
         const cx<R> d0 = ld_u<R>(op.u, 0), d1 = ld_u<R>(op.u, 1);
         const int b = op.b0;
-        for (int i = threadIdx.x; i < T; i += kBlock)
-            if ((uint32_t(i) & op.cmask_lo) == op.cval_lo)
-                lds[i] = cmul(((i >> b) & 1) ? d1 : d0, lds[i]);
+        for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
+            cx<R> v[kItems];
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const int i = i0 + k * kBlock;
+                if (i < T && (uint32_t(i) & cm) == cv) v[k] = lds[i];
+            }
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const int i = i0 + k * kBlock;
+                if (i < T && (uint32_t(i) & cm) == cv) lds[i] = cmul(((i >> b) & 1) ? d1 : d0, v[k]);
+            }
+        }
     } break;
     default: break;   // TILE_GRAD and unknown kinds do not change the state
     }
@@ -92,6 +153,14 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
 __device__ inline uint64_t deposit(uint32_t j, const uint8_t *pos, int m) {
     uint64_t off = 0;
     for (int b = 0; b < m; ++b)
+        if ((j >> b) & 1) off |= uint64_t(1) << pos[b];
+    return off;
+}
+
+// address offset of the bits >= kLoBits of compressed tile index j
+__device__ inline uint64_t deposit_hi(uint32_t j, const uint8_t *pos, int m) {
+    uint64_t off = 0;
+    for (int b = kLoBits; b < m; ++b)
         if ((j >> b) & 1) off |= uint64_t(1) << pos[b];
     return off;
 }

@@ -404,6 +404,7 @@ class Batch:
         _check(lib.qc_batch_create(len(circuits), arr, dt, int(bool(keep_states)), ctypes.byref(h)),
                "qc_batch_create")
         self.handle = h
+        self._destroy = lib.qc_batch_destroy   # usable during interpreter shutdown
         self._keep = None
         nbytes, grid, phases = ctypes.c_uint64(), ctypes.c_int(), ctypes.c_int()
         _check(lib.qc_batch_info(h, ctypes.byref(nbytes), ctypes.byref(grid), ctypes.byref(phases)),
@@ -436,8 +437,9 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib.qc_batch_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self.handle = None
 
 

@@ -1,0 +1,131 @@
+"""Edge cases and large sizes on the GPU: empty inputs, one-qubit
+registers, controls on every other qubit, repeated qubits, and the
+fused complex64 path against the unfused complex128 path near full size
+(the unfused kernels themselves are oracle-checked at smaller sizes)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from dense_ref import random_unitary
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qc():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2503_03016_amd import qc as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2503_03016_amd import gates
+    return gates
+
+
+def dev(psi, dtype):
+    return torch.from_numpy(np.ascontiguousarray(psi)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_empty_gate_list_is_identity(qc, mode):
+    psi0 = W.random_state(9, 1)
+    t = dev(psi0, torch.complex128)
+    st = qc.apply_circuit(t, qc.GateList([]), mode=mode, fuse_k=5)
+    assert st["gates"] == 0 and st["launches"] == 0
+    assert np.array_equal(host(t), psi0)
+
+
+def test_one_qubit_register_everywhere(qc, G):
+    v = np.array([0.6, 0.8j])
+    u = random_unitary(2, np.random.default_rng(1))
+    for dtype in (torch.complex64, torch.complex128):
+        for mode in (0, 1, 2):
+            t = dev(v, dtype)
+            qc.apply_circuit(t, qc.GateList([((0,), (), (), u)]), mode=mode, fuse_k=5)
+            np.testing.assert_allclose(host(t), u @ v, atol=1e-6)
+        t = dev(v, dtype)
+        np.testing.assert_allclose(qc.probs(t).cpu().numpy(), [0.36, 0.64], atol=1e-7)
+        e = qc.expect_pauli(t, [("Z", 1.0), ("X", 2.0), ("Y", -1.0), ("I", 0.5)], per_term=True)
+        e = e.cpu().numpy()
+        ref = [oracle.expect_pauli(v, p).real for p in "ZXYI"]
+        np.testing.assert_allclose(e[1:], ref, atol=1e-7)
+        qc.state_init(t, 1)
+        assert np.array_equal(host(t), [0, 1])
+
+
+def test_controls_on_every_other_qubit(qc):
+    n = 11
+    psi0 = W.random_state(n, 4)
+    rng = np.random.default_rng(2)
+    u = random_unitary(2, rng)
+    for tgt in (0, 5, 10):
+        ctrl = [q for q in range(n) if q != tgt]
+        cv = [int(x) for x in rng.integers(0, 2, n - 1)]
+        t = dev(psi0, torch.complex128)
+        qc.apply_controlled(t, ctrl, cv, tgt, u)
+        np.testing.assert_allclose(host(t), oracle.apply(psi0, [tgt], u, ctrl, cv), atol=1e-12)
+        # the phase-only path with every other qubit controlling
+        ph = np.diag([1.0, np.exp(0.3j)])
+        t = dev(psi0, torch.complex128)
+        qc.apply_controlled(t, ctrl, cv, tgt, ph)
+        np.testing.assert_allclose(host(t), oracle.apply(psi0, [tgt], ph, ctrl, cv), atol=1e-12)
+
+
+def test_repeated_gates_on_one_qubit_fuse_to_identity(qc, G):
+    """A gate followed by its inverse many times on the same qubits, in
+    every mode: the result is the input state."""
+    n = 13
+    rng = np.random.default_rng(5)
+    gts = []
+    for _ in range(20):
+        u = random_unitary(4, rng)
+        gts += [((3, 11), (), (), u), ((3, 11), (), (), u.conj().T)]
+    psi0 = W.random_state(n, 6)
+    for mode in (0, 1, 2):
+        t = dev(psi0, torch.complex128)
+        qc.apply_circuit(t, qc.GateList(gts), mode=mode, fuse_k=5)
+        np.testing.assert_allclose(host(t), psi0, atol=1e-12)
+
+
+def test_fused_c64_vs_unfused_c128_at_30_qubits(qc, G):
+    """30-qubit brickwork, depth 40 (1780 gates): the fused complex64 path
+    against the unfused complex128 path, relative 2-norm error <= 1e-5, and
+    the state norm within the FP32 bound."""
+    n, ops = W.config_brickwork32(n=30, layers=40)
+    gl = qc.GateList(G.gate_tuples(ops))
+    ref = qc.new_state(n, torch.complex128)
+    qc.state_init(ref, 0)
+    qc.apply_circuit(ref, gl, mode=qc.QC_EXEC_UNFUSED)
+    t = qc.new_state(n, torch.complex64)
+    qc.state_init(t, 0)
+    st = qc.apply_circuit(t, gl, mode=qc.QC_EXEC_FUSED, fuse_k=5)
+    assert st["fused_blocks"] < len(ops) / 10
+    d = qc.state_diff(t, ref).cpu().numpy()
+    assert math.sqrt(d[0] / d[1]) < 1e-5
+    assert abs(d[1] - 1.0) < 1e-10           # the complex128 run keeps the norm
+    p = qc.probs(t, [0, 29]).cpu().numpy()
+    assert abs(p.sum() - 1.0) < 1e-5
+    del t, ref
+    torch.cuda.empty_cache()
+
+
+def test_unfused_c128_vs_oracle_at_22_qubits(qc, G):
+    """The unfused complex128 kernels that anchor the chain of trust, on the
+    same circuit family at 22 qubits against the oracle."""
+    n, ops = W.config_brickwork32(n=22, layers=6)
+    ref = oracle.run(ops, oracle.basis_state(n, 0))
+    t = qc.new_state(n, torch.complex128)
+    qc.state_init(t, 0)
+    qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=qc.QC_EXEC_UNFUSED)
+    assert np.max(np.abs(host(t) - ref)) < 1e-12
