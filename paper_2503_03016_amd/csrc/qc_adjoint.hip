@@ -114,6 +114,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
                     acc[op.pad] += s;
                 }
                 __syncthreads();
+            } else if (op.kind == TILE_PHASES) {
+                tile::apply_phases<R>(lp, a.m, base, op);
+                tile::apply_phases<R>(ll, a.m, base, op);
+                __syncthreads();
             } else {
                 tile::apply_one<R>(lp, a.m, op);
                 tile::apply_one<R>(ll, a.m, op);

@@ -622,69 +622,176 @@ TileClass tile_class(int n, const qc_gate_t &g) {
     return c;
 }
 
-// Convert a gate into tile ops for the tile bit set P (bit-position mask).
-void tile_ops_for(int n, const qc_gate_t &g, uint64_t P, std::vector<qcx::TileOp> &out) {
-    auto cidx = [&](int p) { return __builtin_popcountll(P & ((uint64_t(1) << p) - 1)); };
-    auto in_tile = [&](int p) { return (P >> p) & 1; };
-    qcx::TileOp op{};
-    for (int j = 0; j < g.n_ctrls; ++j) {
-        const int p = bitpos(n, g.ctrls[j]);
-        if (in_tile(p)) {
-            op.cmask_lo |= 1u << cidx(p);
-            if (g.ctrl_vals[j]) op.cval_lo |= 1u << cidx(p);
+// Op list of one tile run for the tile bit set P (bit-position mask), with
+// two peephole rewrites that keep the product unchanged:
+//  * an unconditioned one-qubit gate on a tile bit is held back and
+//    multiplied into the gates that follow on the same bit, until an op
+//    touches that bit (it commutes with every op on other bits);
+//  * diagonal phase terms (CZ, CP, diagonal gates, controlled phases) are
+//    collected into one multi-term TILE_PHASES op; a term first flushes the
+//    held gates on its bits, and a later gate on one of its bits first
+//    emits the collected terms (diagonal terms commute with each other and
+//    with every op on other bits).
+// Ops that touch held bits flush them first; reductions (TILE_GRAD) are
+// added as ops that touch their bit (the reduction is invariant under
+// unitaries on other bits applied to both vectors).
+struct TileOpBuilder {
+    int n;
+    uint64_t P;
+    std::vector<qcx::TileOp> &out;
+    cd held[qcx::kTileMaxBits][4];
+    uint32_t held_bits = 0;
+    qcx::TileOp ph{};
+    int nph = 0;
+    uint32_t ph_bits = 0;
+
+    TileOpBuilder(int n_, uint64_t P_, std::vector<qcx::TileOp> &o) : n(n_), P(P_), out(o) {}
+
+    int cidx(int p) const { return __builtin_popcountll(P & ((uint64_t(1) << p) - 1)); }
+    bool in_tile(int p) const { return (P >> p) & 1; }
+
+    void flush_bit(int b) {
+        if (!((held_bits >> b) & 1)) return;
+        const cd *m = held[b];
+        qcx::TileOp op{};
+        const bool diag = m[1] == 0.0 && m[2] == 0.0;
+        op.kind = diag ? qcx::TILE_DIAG1 : qcx::TILE_DENSE1;
+        op.b0 = b;
+        if (diag) {
+            op.u[0] = m[0].real(); op.u[1] = m[0].imag();
+            op.u[2] = m[3].real(); op.u[3] = m[3].imag();
         } else {
-            op.cmask_hi |= uint64_t(1) << p;
-            if (g.ctrl_vals[j]) op.cval_hi |= uint64_t(1) << p;
-        }
-    }
-    const double *u = g.matrix;
-    auto add_cond = [&](qcx::TileOp &o, int p, int v) {
-        if (in_tile(p)) {
-            o.cmask_lo |= 1u << cidx(p);
-            if (v) o.cval_lo |= 1u << cidx(p);
-        } else {
-            o.cmask_hi |= uint64_t(1) << p;
-            if (v) o.cval_hi |= uint64_t(1) << p;
-        }
-    };
-    if (g.n_targets == 1) {
-        const int tp = bitpos(n, g.targets[0]);
-        if (!is_diag_1q(u)) {
-            op.kind = qcx::TILE_DENSE1;
-            op.b0 = cidx(tp);
-            for (int i = 0; i < 8; ++i) op.u[i] = u[i];
-            out.push_back(op);
-        } else if (u[0] == 1.0 && u[1] == 0.0) {
-            op.kind = qcx::TILE_PHASE;
-            add_cond(op, tp, 1);
-            op.u[0] = u[6];
-            op.u[1] = u[7];
-            out.push_back(op);
-        } else if (in_tile(tp)) {
-            op.kind = qcx::TILE_DIAG1;
-            op.b0 = cidx(tp);
-            op.u[0] = u[0];
-            op.u[1] = u[1];
-            op.u[2] = u[6];
-            op.u[3] = u[7];
-            out.push_back(op);
-        } else {
-            for (int v = 0; v < 2; ++v) {
-                qcx::TileOp o = op;
-                o.kind = qcx::TILE_PHASE;
-                add_cond(o, tp, v);
-                o.u[0] = u[v ? 6 : 0];
-                o.u[1] = u[v ? 7 : 1];
-                out.push_back(o);
+            for (int i = 0; i < 4; ++i) {
+                op.u[2 * i] = m[i].real();
+                op.u[2 * i + 1] = m[i].imag();
             }
         }
-    } else {
-        op.kind = qcx::TILE_DENSE2;
-        op.b0 = cidx(bitpos(n, g.targets[0]));
-        op.b1 = cidx(bitpos(n, g.targets[1]));
-        for (int i = 0; i < 32; ++i) op.u[i] = u[i];
+        out.push_back(op);
+        held_bits &= ~(1u << b);
+    }
+    void flush_bits(uint32_t bits) {
+        for (int b = 0; bits >> b; ++b)
+            if ((bits >> b) & 1) flush_bit(b);
+    }
+    void emit_phases() {
+        if (nph == 1) {
+            qcx::TileOp op{};
+            op.kind = qcx::TILE_PHASE;
+            op.cmask_lo = ph.pm_lo[0];
+            op.cval_lo = ph.pv_lo[0];
+            op.cmask_hi = ph.pm_hi[0];
+            op.cval_hi = ph.pv_hi[0];
+            op.u[0] = ph.u[0];
+            op.u[1] = ph.u[1];
+            out.push_back(op);
+        } else if (nph > 1) {
+            ph.kind = qcx::TILE_PHASES;
+            ph.b0 = nph;
+            out.push_back(ph);
+        }
+        ph = qcx::TileOp{};
+        nph = 0;
+        ph_bits = 0;
+    }
+    // one diagonal term: multiply by `phase` where the conditions hold
+    void add_phase(uint32_t mlo, uint32_t vlo, uint64_t mhi, uint64_t vhi, cd phase) {
+        flush_bits(mlo);
+        if (nph == qcx::kTilePhaseTerms) emit_phases();
+        ph.pm_lo[nph] = mlo;
+        ph.pv_lo[nph] = vlo;
+        ph.pm_hi[nph] = mhi;
+        ph.pv_hi[nph] = vhi;
+        ph.u[2 * nph] = phase.real();
+        ph.u[2 * nph + 1] = phase.imag();
+        ++nph;
+        ph_bits |= mlo;
+    }
+    void add_op(const qcx::TileOp &op, uint32_t touched) {
+        flush_bits(touched);
+        if (ph_bits & touched) emit_phases();
         out.push_back(op);
     }
+    void add_1q(int b, const double *u) {
+        if ((ph_bits >> b) & 1) emit_phases();
+        const cd m[4] = {cd(u[0], u[1]), cd(u[2], u[3]), cd(u[4], u[5]), cd(u[6], u[7])};
+        if (!((held_bits >> b) & 1)) {
+            for (int i = 0; i < 4; ++i) held[b][i] = m[i];
+            held_bits |= 1u << b;
+            return;
+        }
+        const cd *h = held[b];   // new = m * h (m applied after h)
+        const cd r[4] = {m[0] * h[0] + m[1] * h[2], m[0] * h[1] + m[1] * h[3],
+                         m[2] * h[0] + m[3] * h[2], m[2] * h[1] + m[3] * h[3]};
+        for (int i = 0; i < 4; ++i) held[b][i] = r[i];
+    }
+    void add_gate(const qc_gate_t &g) {
+        uint32_t clo = 0, cvlo = 0;
+        uint64_t chi = 0, cvhi = 0;
+        for (int j = 0; j < g.n_ctrls; ++j) {
+            const int p = bitpos(n, g.ctrls[j]);
+            if (in_tile(p)) {
+                clo |= 1u << cidx(p);
+                if (g.ctrl_vals[j]) cvlo |= 1u << cidx(p);
+            } else {
+                chi |= uint64_t(1) << p;
+                if (g.ctrl_vals[j]) cvhi |= uint64_t(1) << p;
+            }
+        }
+        const double *u = g.matrix;
+        if (g.n_targets == 1) {
+            const int tp = bitpos(n, g.targets[0]);
+            const bool t_in = in_tile(tp);
+            const uint32_t tb = t_in ? 1u << cidx(tp) : 0u;
+            const uint64_t th = t_in ? 0 : uint64_t(1) << tp;
+            if (is_diag_1q(u)) {
+                if (g.n_ctrls == 0 && t_in) {
+                    add_1q(cidx(tp), u);
+                    return;
+                }
+                // diagonal: a term for target 1 and, unless U00 == 1, for target 0
+                add_phase(clo | tb, cvlo | tb, chi | th, cvhi | th, cd(u[6], u[7]));
+                if (!(u[0] == 1.0 && u[1] == 0.0))
+                    add_phase(clo | tb, cvlo, chi | th, cvhi, cd(u[0], u[1]));
+                return;
+            }
+            if (g.n_ctrls == 0) {
+                add_1q(cidx(tp), u);
+                return;
+            }
+            qcx::TileOp op{};
+            op.kind = qcx::TILE_DENSE1;
+            op.b0 = cidx(tp);
+            op.cmask_lo = clo;
+            op.cval_lo = cvlo;
+            op.cmask_hi = chi;
+            op.cval_hi = cvhi;
+            for (int i = 0; i < 8; ++i) op.u[i] = u[i];
+            add_op(op, clo | tb);
+        } else {
+            qcx::TileOp op{};
+            op.kind = qcx::TILE_DENSE2;
+            op.b0 = cidx(bitpos(n, g.targets[0]));
+            op.b1 = cidx(bitpos(n, g.targets[1]));
+            op.cmask_lo = clo;
+            op.cval_lo = cvlo;
+            op.cmask_hi = chi;
+            op.cval_hi = cvhi;
+            for (int i = 0; i < 32; ++i) op.u[i] = u[i];
+            add_op(op, clo | (1u << op.b0) | (1u << op.b1));
+        }
+    }
+    void finish() {
+        emit_phases();
+        flush_bits(held_bits);
+    }
+};
+
+// Convert a list of gates into the op list of one tile run.
+void tile_ops_for(int n, const qc_gate_t *gs, const std::vector<int> &idx, uint64_t P,
+                  std::vector<qcx::TileOp> &out) {
+    TileOpBuilder B(n, P, out);
+    for (int i : idx) B.add_gate(gs[i]);
+    B.finish();
 }
 
 int tile_bits_for(const qc_state_t &s) { return std::min(s.n, s.dtype == QC_C64 ? 13 : 12); }
@@ -762,7 +869,7 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
             continue;
         }
         ops.clear();
-        for (int idx : r.gates) tile_ops_for(n, gs[idx], r.P, ops);
+        tile_ops_for(n, gs, r.gates, r.P, ops);
         const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
         void *dev = nullptr;
         if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
@@ -1194,20 +1301,24 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
     };
     for (const TileRun &r : runs) {
         if (r.P == 0) return fail(QC_ERR_UNSUPPORTED, "adjoint op cannot be tiled");
+        TileOpBuilder B(n, r.P, tops);
         for (int j : r.gates) {
             if (rot_row[j] >= 0) {
-                if (int(slot_row.size()) == qcx::kAdjointMaxSlots && (rc = flush(r.P))) return rc;
-                const uint64_t Pm = r.P;
+                if (int(slot_row.size()) == qcx::kAdjointMaxSlots) {
+                    B.finish();
+                    if ((rc = flush(r.P))) return rc;
+                }
                 qcx::TileOp gop{};
                 gop.kind = qcx::TILE_GRAD;
-                gop.b0 = __builtin_popcountll(Pm & ((uint64_t(1) << bitpos(n, bwd[j].targets[0])) - 1));
+                gop.b0 = B.cidx(bitpos(n, bwd[j].targets[0]));
                 gop.b1 = gen_of[j];
                 gop.pad = int32_t(slot_row.size());
                 slot_row.push_back(rot_row[j]);
-                tops.push_back(gop);
+                B.add_op(gop, 1u << gop.b0);
             }
-            tile_ops_for(n, bwd[j], r.P, tops);
+            B.add_gate(bwd[j]);
         }
+        B.finish();
         if ((rc = flush(r.P))) return rc;
     }
     // grad[p] = sum of the rotation rows that use parameter p
@@ -1347,7 +1458,7 @@ int plan_circuit(const qc_circuit_t &c, int mmax, bool keep, std::vector<qcx::Ba
         }
         for (int p = 0; __builtin_popcountll(P) < m && p < n; ++p) P |= uint64_t(1) << p;
         const int op_begin = int(ops.size());
-        for (int idx : run) tile_ops_for(n, c.gates[idx], P, ops);
+        tile_ops_for(n, c.gates, run, P, ops);
         const int nops = int(ops.size()) - op_begin;
         phases.push_back(make_phase(n, m, P, op_begin, nops, (first ? qcx::BATCH_INIT : 0) | store));
         cost += double(uint64_t(1) << n) * (nops + 2);

@@ -107,7 +107,7 @@ __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *l
     cx<R> *state = static_cast<cx<R> *>(a.arena) + C.arena_off;
     double acc = 0.0;
     for (int p = C.phase_begin; p < C.phase_begin + C.phase_count; ++p) {
-        const BatchPhase P = a.phases[p];   // one uniform copy per phase
+        const BatchPhase &P = a.phases[p];   // read in place (pos[] is indexed at run time)
         const int T = 1 << P.m;
         // element j = threadIdx.x + 256 k: the low 8 compressed bits are this
         // thread's, the high ones come from k
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
     unsigned *bar = a.barrier + group;
     unsigned gen = 0;
     for (int jb = a.group_jobs[group]; jb < a.group_jobs[group + 1]; ++jb) {
-        const BatchJob job = a.jobs[jb];
+        const BatchJob &job = a.jobs[jb];
         if (job.kind == 0) {
             const int c = job.circ[rank];
             unsigned g0 = 0;

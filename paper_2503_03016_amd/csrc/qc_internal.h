@@ -87,8 +87,15 @@ struct Mat2d {
 // One gate of an LDS tile run (positions are compressed tile positions).
 // TILE_GRAD (adjoint kernel only): accumulate Im <lam|G|phi> for generator
 // G (b1: 1 = X, 2 = Y, 3 = Z) on compressed bit b0 into slot `pad`.
-enum TileKind { TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4 };
+// TILE_PHASES: b0 diagonal terms; amplitude i of the tile is multiplied by
+// the product of phase t (u[2t], u[2t+1]) over the terms whose conditions
+// hold: (i & pm_lo[t]) == pv_lo[t] and (tile_base & pm_hi[t]) == pv_hi[t].
+enum TileKind {
+    TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
+    TILE_PHASES = 5
+};
 constexpr int kTileMaxBits = 16;
+constexpr int kTilePhaseTerms = 16;
 struct TileOp {
     int32_t kind;
     int32_t b0, b1;            // targets (b0 = most significant bit of the local index)
@@ -96,6 +103,8 @@ struct TileOp {
     uint32_t cmask_lo, cval_lo;  // conditions on tile bits (compressed)
     uint64_t cmask_hi, cval_hi;  // conditions on bits outside the tile (global)
     double u[32];              // complex FP64 entries, interleaved
+    uint32_t pm_lo[kTilePhaseTerms], pv_lo[kTilePhaseTerms];   // TILE_PHASES terms
+    uint64_t pm_hi[kTilePhaseTerms], pv_hi[kTilePhaseTerms];
 };
 struct TileArgs {
     uint64_t n_tiles;

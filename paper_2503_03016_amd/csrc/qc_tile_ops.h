@@ -133,7 +133,45 @@ __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
             }
         }
     } break;
-    default: break;   // TILE_GRAD and unknown kinds do not change the state
+    default: break;   // TILE_GRAD, TILE_PHASES (see apply_phases) and unknown kinds
+    }
+}
+
+// TILE_PHASES: product of the diagonal terms whose conditions hold.
+template <typename R>
+__device__ inline void apply_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op) {
+    const int T = 1 << m;
+    const int nt = op.b0;
+    uint32_t live = 0;   // terms whose out-of-tile conditions hold for this tile
+    for (int t = 0; t < nt; ++t)
+        if ((tile_base & op.pm_hi[t]) == op.pv_hi[t]) live |= 1u << t;
+    if (!live) return;
+    for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
+        // terms outer, items inner: one (uniform) fetch of a term's masks and
+        // phase serves all items of the thread
+        cx<R> f[kItems];
+        uint32_t hit = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) f[k] = cx<R>{R(1), R(0)};
+#pragma unroll 4
+        for (int t = 0; t < nt; ++t) {
+            if (!((live >> t) & 1)) continue;
+            const uint32_t pm = op.pm_lo[t], pv = op.pv_lo[t];
+            const cx<R> ph = ld_u<R>(op.u, t);
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                const bool on = ((uint32_t(i0 + k * kBlock) & pm) == pv);
+                const cx<R> g = cmul(f[k], ph);
+                f[k].re = on ? g.re : f[k].re;
+                f[k].im = on ? g.im : f[k].im;
+                hit |= uint32_t(on) << k;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int i = i0 + k * kBlock;
+            if (i < T && ((hit >> k) & 1)) lds[i] = cmul(f[k], lds[i]);
+        }
     }
 }
 
@@ -144,7 +182,8 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
     for (int o = 0; o < n_ops; ++o) {
         const TileOp &op = ops[o];
         if ((tile_base & op.cmask_hi) != op.cval_hi) continue;   // uniform per tile
-        apply_one<R>(lds, m, op);
+        if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op);
+        else apply_one<R>(lds, m, op);
         __syncthreads();
     }
 }
