@@ -64,6 +64,8 @@ extern "C" {
 #define QC_MAX_FUSED 5
 /* Most control qubits on one gate. */
 #define QC_MAX_CTRLS 16
+/* Most selector qubits of a multiplexed block (qc_apply_multiplexed). */
+#define QC_MAX_SEL 2
 
 /* A borrowed view of a caller-owned state vector. */
 typedef struct {
@@ -166,25 +168,47 @@ int qc_apply_controlled(qc_state_t s, int n_ctrl, const int *ctrl, const int *ct
                         int target, const double *u, void *stream);
 
 /* Dense k-qubit gate, 1 <= k <= QC_MAX_FUSED: U (2^k x 2^k) on the listed
- * qubits (qubits[0] = most significant bit of U's index).  For QC_C64 and
- * k >= 3 the product runs on FP32 matrix cores (MFMA); FP64 on the vector
- * units otherwise. */
+ * qubits (qubits[0] = most significant bit of U's index).  For QC_C64 with
+ * k == 5 and n >= 12 the product runs on the FP32 matrix cores (MFMA); on
+ * the vector units otherwise (FP32 for QC_C64, FP64 for QC_C128). */
 int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, void *stream);
 
+/* Multiplexed k-qubit gate (a k-qubit gate whose matrix depends on the
+ * values of n_sel other qubits): psi := sum_v P_v (x) U_v psi, where P_v
+ * projects the selector qubits onto the value v (sel_qubits[0] = most
+ * significant bit of v) and U_v (2^k x 2^k) acts on `qubits` as in
+ * qc_apply_fused_k.  This is the block form of the controlled gates of
+ * section 3.2 (Pc (x) U + (I - Pc) (x) I is the case U_v = I for every v
+ * but one).  u holds the 2^n_sel matrices one after the other, each
+ * 2^k x 2^k row-major interleaved FP64 (matrix v starts at
+ * u + v * 2 * 4^k); it is consumed before the call returns.  1 <= k <=
+ * QC_MAX_FUSED, 0 <= n_sel <= QC_MAX_SEL, all k + n_sel labels distinct.
+ * Same precision and kernels as qc_apply_fused_k (matrix cores need
+ * n >= 12 + n_sel). */
+int qc_apply_multiplexed(qc_state_t s, int k, const int *qubits, int n_sel,
+                         const int *sel_qubits, const double *u, void *stream);
+
 /* Apply a gate list in order.  mode QC_EXEC_UNFUSED launches one kernel per
- * gate; QC_EXEC_FUSED first groups consecutive gates into blocks of at most
- * fuse_k qubits (host FP64 matrix products, see qc_fuse_plan) and applies
- * each block with qc_apply_fused_k; QC_EXEC_TILED applies runs of gates in
- * LDS tiles (fuse_k is ignored).  fuse_k must be 1..QC_MAX_FUSED and is
- * capped at n.  Gates may be reordered only past gates on disjoint qubits,
- * so the result is the ordered product.  stats may be NULL. */
+ * gate; QC_EXEC_FUSED first groups the gates into blocks (host FP64 matrix
+ * products, see qc_fuse_plan) and applies each block with one
+ * qc_apply_multiplexed sweep; QC_EXEC_TILED applies runs of gates in LDS
+ * tiles (fuse_k is ignored).  fuse_k must be 1..QC_MAX_FUSED and is capped
+ * at n.  A gate is moved ahead of another only when the two commute (no
+ * shared qubit, or every shared qubit is one on which both act diagonally:
+ * a control, or a target of a diagonal matrix), so the result is the
+ * ordered product.  stats may be NULL. */
 int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode,
                      int fuse_k, qc_exec_stats_t *stats, void *stream);
 
 /* Host-only planning step of QC_EXEC_FUSED (no device work): partition the
- * gate list into blocks of at most fuse_k qubits in a dependency-respecting
- * order.  block_of[g] receives the block index of gate g; *n_blocks the
- * number of blocks.  block_of must hold n_gates entries. */
+ * gate list into blocks applied in block order.  A block acts
+ * non-diagonally on at most fuse_k qubits (its block qubits) and may touch
+ * up to QC_MAX_SEL more qubits on which all its gates act diagonally (its
+ * selector qubits, making the block a multiplexed gate); a gate wider than
+ * that forms a block of its own.  Moving every gate of a block ahead of the
+ * gates of later blocks only swaps commuting gates (see qc_apply_circuit).
+ * block_of[g] receives the block index of gate g; *n_blocks the number of
+ * blocks.  block_of must hold n_gates entries. */
 int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
                  int *block_of, int *n_blocks);
 

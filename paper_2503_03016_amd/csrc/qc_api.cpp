@@ -172,9 +172,89 @@ std::vector<cd> to_cd(const double *u, int d) {
     return m;
 }
 
+// A gate as it acts inside one block: targets and controls are labels of
+// block qubits; nt == 0 is a (controlled) scalar phase u[0].
+struct LocalGate {
+    int nt = 0, nc = 0;
+    int tq[QC_MAX_FUSED];
+    int cq[QC_MAX_CTRLS];
+    int cv[QC_MAX_CTRLS];
+    std::vector<cd> u;
+};
+
+bool matrix_is_diagonal(const double *u, int nt) {
+    const int d = 1 << nt;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && (u[2 * (r * d + c)] != 0.0 || u[2 * (r * d + c) + 1] != 0.0))
+                return false;
+    return true;
+}
+
+// Qubits on which the gate acts non-diagonally: its targets unless the
+// target matrix is diagonal.  On every other qubit of the gate (controls,
+// targets of a diagonal matrix) the gate is block diagonal, so it commutes
+// with any other gate that is also diagonal on each qubit they share.
+uint64_t gate_nd_mask(const qc_gate_t &g) {
+    if (matrix_is_diagonal(g.matrix, g.n_targets)) return 0;
+    uint64_t m = 0;
+    for (int j = 0; j < g.n_targets; ++j) m |= uint64_t(1) << g.targets[j];
+    return m;
+}
+
+// The gate restricted to the selector assignment `sv` of the selector
+// qubits `sq` (sq[0] = most significant bit of sv).  Returns false when the
+// gate is the identity there (a control on a selector qubit not met).  A
+// selector qubit is never a target of a non-diagonal matrix (the fuser and
+// the multiplexed-gate path guarantee this).
+bool restrict_gate(const qc_gate_t &g, int ns, const int *sq, int sv, LocalGate &out) {
+    auto sel_bit = [&](int label) {
+        for (int j = 0; j < ns; ++j)
+            if (sq[j] == label) return (sv >> (ns - 1 - j)) & 1;
+        return -1;
+    };
+    out.nc = 0;
+    for (int j = 0; j < g.n_ctrls; ++j) {
+        const int b = sel_bit(g.ctrls[j]);
+        if (b < 0) {
+            out.cq[out.nc] = g.ctrls[j];
+            out.cv[out.nc++] = g.ctrl_vals[j];
+        } else if (b != g.ctrl_vals[j]) {
+            return false;
+        }
+    }
+    const int d = 1 << g.n_targets;
+    int fixed_idx = 0, keep = 0, kept_pos[QC_MAX_FUSED];
+    out.nt = 0;
+    for (int j = 0; j < g.n_targets; ++j) {
+        const int b = sel_bit(g.targets[j]);
+        const int shift = g.n_targets - 1 - j;
+        if (b < 0) {
+            out.tq[out.nt++] = g.targets[j];
+            kept_pos[keep++] = shift;
+        } else if (b) {
+            fixed_idx |= 1 << shift;
+        }
+    }
+    if (out.nt == g.n_targets) {
+        out.u = to_cd(g.matrix, d);
+        return true;
+    }
+    // diagonal matrix with some targets fixed by the selector
+    const int dk = 1 << out.nt;
+    out.u.assign(size_t(dk) * dk, cd(0.0, 0.0));
+    for (int r = 0; r < dk; ++r) {
+        int full = fixed_idx;
+        for (int j = 0; j < out.nt; ++j)
+            if ((r >> (out.nt - 1 - j)) & 1) full |= 1 << kept_pos[j];
+        out.u[size_t(r) * dk + r] = cd(g.matrix[2 * (full * d + full)], g.matrix[2 * (full * d + full) + 1]);
+    }
+    return true;
+}
+
 // Dense matrix (2^k, row-major) of a list of gates acting inside the block
 // whose qubits (labels, qubits[0] = MSB) are `bq`.
-std::vector<cd> block_matrix(int k, const int *bq, const std::vector<const qc_gate_t *> &gs) {
+std::vector<cd> block_matrix_local(int k, const int *bq, const std::vector<LocalGate> &gs) {
     const int dim = 1 << k;
     auto local = [&](int label) {
         for (int j = 0; j < k; ++j)
@@ -184,18 +264,39 @@ std::vector<cd> block_matrix(int k, const int *bq, const std::vector<const qc_ga
     // columns of the product, evolved as 2^k small states
     std::vector<std::vector<cd>> cols(dim, std::vector<cd>(dim, 0.0));
     for (int c = 0; c < dim; ++c) cols[c][c] = 1.0;
-    for (const qc_gate_t *g : gs) {
+    for (const LocalGate &g : gs) {
         int tb[QC_MAX_FUSED], cb[QC_MAX_CTRLS];
-        for (int j = 0; j < g->n_targets; ++j) tb[j] = local(g->targets[j]);
-        for (int j = 0; j < g->n_ctrls; ++j) cb[j] = local(g->ctrls[j]);
-        const std::vector<cd> u = to_cd(g->matrix, 1 << g->n_targets);
-        for (int c = 0; c < dim; ++c)
-            host_apply(cols[c], k, g->n_targets, tb, g->n_ctrls, cb, g->ctrl_vals, u.data());
+        for (int j = 0; j < g.nt; ++j) tb[j] = local(g.tq[j]);
+        for (int j = 0; j < g.nc; ++j) cb[j] = local(g.cq[j]);
+        for (int c = 0; c < dim; ++c) host_apply(cols[c], k, g.nt, tb, g.nc, cb, g.cv, g.u.data());
     }
     std::vector<cd> m(size_t(dim) * dim);
     for (int r = 0; r < dim; ++r)
         for (int c = 0; c < dim; ++c) m[size_t(r) * dim + c] = cols[c][r];
     return m;
+}
+
+// Matrices U_s of a multiplexed block: for every assignment s of the
+// selector qubits `sq`, the product of the gates restricted to s.  The
+// result holds the 2^ns matrices one after the other.
+std::vector<cd> block_matrices(int k, const int *bq, int ns, const int *sq,
+                               const std::vector<const qc_gate_t *> &gs) {
+    std::vector<cd> all;
+    std::vector<LocalGate> loc;
+    for (int sv = 0; sv < (1 << ns); ++sv) {
+        loc.clear();
+        for (const qc_gate_t *g : gs) {
+            LocalGate lg;
+            if (restrict_gate(*g, ns, sq, sv, lg)) loc.push_back(std::move(lg));
+        }
+        const std::vector<cd> m = block_matrix_local(k, bq, loc);
+        all.insert(all.end(), m.begin(), m.end());
+    }
+    return all;
+}
+
+std::vector<cd> block_matrix(int k, const int *bq, const std::vector<const qc_gate_t *> &gs) {
+    return block_matrices(k, bq, 0, nullptr, gs);
 }
 
 uint64_t gate_mask(const qc_gate_t &g) {
@@ -221,74 +322,100 @@ int check_gate(int n, const qc_gate_t &g) {
     return check_qubits(n, all, g.n_targets + g.n_ctrls, "gate qubit");
 }
 
-// Greedy dependency-respecting partition into blocks of <= k qubits.
-// A gate joins the block under construction when none of its qubits is
-// held by an earlier gate left out of the block and the union of qubits
-// stays within k; a gate left out blocks its qubits for later gates.
-// Members (positions in `pending`) of a block seeded by pending[seed]: the
-// pending list is scanned in order; a gate joins when none of its qubits is
-// held by an earlier pending gate left out of the block ("blocked") and it
-// fits: inside the label set `window` when one is given, else within k
-// qubits of the block grown so far.  The seed has no pending predecessor on
-// its qubits, so the block can be applied before every gate left out.
-void grow_block(const std::vector<int> &pending, const std::vector<uint64_t> &masks, int seed,
-                uint64_t window, int k, uint64_t all, std::vector<int> &members) {
+// Qubit masks of one gate for the fuser: every qubit, and the qubits it
+// acts on non-diagonally.
+struct GateMasks {
+    uint64_t all, nd;
+};
+
+// Members (positions in `pending`) of a block seeded by pending[seed].
+// The pending list is scanned in order.  A gate may move ahead of the
+// earlier pending gates left out of the block only if it commutes with
+// them: on a qubit where it acts non-diagonally no gate may have been left
+// out ("blocked_any"), and on a qubit where it acts diagonally no gate
+// acting non-diagonally there may have been left out ("blocked_nd").  It
+// must also fit: its non-diagonal qubits inside the block qubits (the label
+// set `window` when one is given, else at most k qubits grown so far); its
+// diagonal qubits either inside the block or among at most `smax` selector
+// qubits outside it.  On a selector qubit every member acts diagonally, so
+// the block is a multiplexed gate: one k-qubit matrix per selector value.
+// The seed has no pending predecessor on its qubits, so the block can be
+// applied before every gate left out.
+void grow_block(const std::vector<int> &pending, const std::vector<GateMasks> &gm, int seed,
+                uint64_t window, int k, int smax, uint64_t all, std::vector<int> &members) {
     members.clear();
-    const uint64_t sm = masks[pending[seed]];
-    uint64_t held = window ? window : sm, blocked = 0;
-    const bool oversize = __builtin_popcountll(sm) > k;
+    const GateMasks sm = gm[pending[seed]];
+    uint64_t held = window ? window : sm.all, sel = 0, blocked_any = 0, blocked_nd = 0;
+    const bool oversize = __builtin_popcountll(sm.all) > k;
     for (int i = 0; i < int(pending.size()); ++i) {
         if (i == seed) {
             members.push_back(i);
             continue;
         }
-        const uint64_t m = masks[pending[i]];
-        bool fits = !(m & blocked) && !oversize;
-        if (fits) fits = window ? (m & ~window) == 0 : __builtin_popcountll(held | m) <= k;
+        const GateMasks g = gm[pending[i]];
+        const uint64_t diag = g.all & ~g.nd;
+        bool fits = !oversize && !(g.nd & blocked_any) && !(diag & blocked_nd) && !(g.nd & sel);
+        uint64_t new_held = held, new_sel = sel;
         if (fits) {
-            held |= m;
+            if (window) {
+                fits = (g.nd & ~window) == 0;
+                new_sel = sel | (g.all & ~window);
+            } else {
+                new_held = held | g.nd;
+                const uint64_t free_diag = diag & ~new_held & ~sel;
+                if (__builtin_popcountll(new_held | free_diag) <= k) new_held |= free_diag;
+                else new_sel = sel | free_diag;
+                fits = __builtin_popcountll(new_held) <= k;
+            }
+            fits = fits && __builtin_popcountll(new_sel) <= smax;
+        }
+        if (fits) {
+            held = new_held;
+            sel = new_sel;
             members.push_back(i);
         } else {
-            blocked |= m;
-            if ((blocked & all) == all) break;   // nothing can join any more
+            blocked_any |= g.all;
+            blocked_nd |= g.nd;
+            if ((blocked_nd & all) == all) break;   // nothing can join any more
         }
     }
 }
 
-// Partition into dependency-respecting blocks of <= k qubits.  Each block is
-// chosen among candidates seeded by the first gates that have no pending
-// predecessor ("front" gates): a block grown greedily from the seed, and
-// blocks confined to each window of k consecutive qubit labels that holds
-// the seed.  The candidate absorbing the most gates wins.
-void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, std::vector<int> &block_of,
+// Partition into dependency-respecting blocks of <= k qubits (plus at most
+// smax selector qubits).  Each block is chosen among candidates seeded by
+// the first gates that have no pending predecessor ("front" gates): a
+// block grown greedily from the seed, and blocks confined to each window of
+// k consecutive qubit labels that holds the seed.  The candidate absorbing
+// the most gates wins.
+void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, int smax, std::vector<int> &block_of,
                int &n_blocks) {
     constexpr int kMaxFront = 32;
     block_of.assign(ng, -1);
     n_blocks = 0;
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
-    std::vector<uint64_t> masks(ng);
-    for (int i = 0; i < ng; ++i) masks[i] = gate_mask(gs[i]);
+    std::vector<GateMasks> gm(ng);
+    for (int i = 0; i < ng; ++i) gm[i] = {gate_mask(gs[i]), gate_nd_mask(gs[i])};
     std::vector<int> pending(ng), best, cand, front;
     for (int i = 0; i < ng; ++i) pending[i] = i;
     while (!pending.empty()) {
         front.clear();
         uint64_t seen = 0;
         for (int i = 0; i < int(pending.size()) && int(front.size()) < kMaxFront; ++i) {
-            const uint64_t m = masks[pending[i]];
+            const uint64_t m = gm[pending[i]].all;
             if (!(m & seen)) front.push_back(i);
             seen |= m;
             if ((seen & all) == all) break;
         }
         best.clear();
         for (int f : front) {
-            const uint64_t sm = masks[pending[f]];
-            grow_block(pending, masks, f, 0, k, all, cand);
+            const uint64_t sm = gm[pending[f]].all;
+            grow_block(pending, gm, f, 0, k, smax, all, cand);
             if (cand.size() > best.size()) best = cand;
             if (__builtin_popcountll(sm) > k || k >= n) continue;
             const int lo = __builtin_ctzll(sm), hi = 63 - __builtin_clzll(sm);
             for (int a = std::max(0, hi - k + 1); a <= std::min(lo, n - k); ++a) {
                 const uint64_t w = ((uint64_t(1) << k) - 1) << a;
-                grow_block(pending, masks, f, w, k, all, cand);
+                grow_block(pending, gm, f, w, k, smax, all, cand);
                 if (cand.size() > best.size()) best = cand;
             }
         }
@@ -524,8 +651,11 @@ namespace {
 // FP32 matrix-core operand layout of a 32x32 complex U (see qc_fused_mfma.hip).
 void mfma_operand_c64(const std::vector<cd> &u, std::vector<float> &out);
 
-int fused_apply(qc_state_t s, int k, const int *qubits, const std::vector<cd> &u,
-                hipStream_t stream) {
+// Apply a k-qubit block, multiplexed over `ns` selector qubits `sq` when
+// ns > 0: `u` holds the 2^ns matrices U_s one after the other (s = the
+// values of the selector qubits, sq[0] = most significant bit).
+int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
+                const std::vector<cd> &u, hipStream_t stream) {
     DevCtx *c;
     int rc = get_ctx(&c);
     if (rc) return rc;
@@ -544,12 +674,18 @@ int fused_apply(qc_state_t s, int k, const int *qubits, const std::vector<cd> &u
             if ((r >> (k - 1 - j)) & 1) o |= uint64_t(1) << pos[j];
         g.tgt_off[r] = o;
     }
+    g.n_sel = ns;
+    for (int j = 0; j < ns; ++j) g.sel_pos[j] = uint8_t(bitpos(s.n, sq[j]));
+    const size_t dd = size_t(1) << (2 * k);
     void *dev = nullptr;
     hipError_t e;
-    if (s.dtype == QC_C64 && k == 5 && s.n >= 12) {
-        std::vector<float> op;
-        mfma_operand_c64(u, op);
-        if ((rc = stage(c, op.data(), op.size() * sizeof(float), stream, &dev))) return rc;
+    if (s.dtype == QC_C64 && k == 5 && s.n >= 12 + ns) {
+        std::vector<float> op, all;
+        for (int v = 0; v < (1 << ns); ++v) {
+            mfma_operand_c64(std::vector<cd>(u.begin() + v * dd, u.begin() + (v + 1) * dd), op);
+            all.insert(all.end(), op.begin(), op.end());
+        }
+        if ((rc = stage(c, all.data(), all.size() * sizeof(float), stream, &dev))) return rc;
         e = qcx::launch_fused_mfma_c64(s.amp, s.n, g, static_cast<const float *>(dev), stream);
     } else if (s.dtype == QC_C64) {
         std::vector<float> f(u.size() * 2);
@@ -587,7 +723,7 @@ int apply_gate_unfused(qc_state_t s, const qc_gate_t &g, qc_exec_stats_t &st, vo
         for (int j = 0; j < g.n_targets; ++j) bq[j] = g.targets[j];
         for (int j = 0; j < g.n_ctrls; ++j) bq[g.n_targets + j] = g.ctrls[j];
         std::vector<const qc_gate_t *> one{&g};
-        rc = fused_apply(s, nq, bq, block_matrix(nq, bq, one), (hipStream_t)stream);
+        rc = fused_apply(s, nq, bq, 0, nullptr, block_matrix(nq, bq, one), (hipStream_t)stream);
         st.state_bytes += sweep;
     } else {
         rc = fail(QC_ERR_UNSUPPORTED, "gate with more than 5 qubits and targets > 1");
@@ -885,6 +1021,43 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
 
 }  // namespace
 
+namespace {
+
+// Block and selector qubits of a fused block.  Every qubit on which a
+// member acts non-diagonally is a block qubit; qubits where all members act
+// diagonally fill the block up to fuse_k qubits, lowest bit positions first,
+// and the rest become selector qubits (high bit positions, so the low,
+// contiguous address bits stay inside the tiles of the matrix-core kernel).
+// With `widen`, blocks narrower than fuse_k are padded with untouched
+// qubits.  Returns false when the members do not fit QC_MAX_FUSED block
+// qubits and kMaxSel selector qubits.
+bool assign_block(int n, const std::vector<const qc_gate_t *> &members, int fuse_k, bool widen,
+                  int *bq, int &k, int *sq, int &ns) {
+    uint64_t all = 0, nd = 0;
+    for (auto *g : members) {
+        all |= gate_mask(*g);
+        nd |= gate_nd_mask(*g);
+    }
+    const int width = std::max(fuse_k, __builtin_popcountll(nd));
+    if (width > QC_MAX_FUSED) return false;
+    uint64_t q = nd;
+    for (int lab = n - 1; lab >= 0 && __builtin_popcountll(q) < width; --lab)
+        if (((all & ~q) >> lab) & 1) q |= uint64_t(1) << lab;
+    const uint64_t sel = all & ~q;
+    if (__builtin_popcountll(sel) > qcx::kMaxSel) return false;
+    for (int lab = n - 1; widen && lab >= 0 && __builtin_popcountll(q) < fuse_k; --lab)
+        if (!(((q | sel) >> lab) & 1)) q |= uint64_t(1) << lab;
+    k = 0;
+    ns = 0;
+    for (int lab = 0; lab < n; ++lab) {
+        if ((q >> lab) & 1) bq[k++] = lab;
+        if ((sel >> lab) & 1) sq[ns++] = lab;
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
 
 int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, void *stream) {
@@ -894,7 +1067,27 @@ int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, vo
     if (k < 1 || k > QC_MAX_FUSED) return fail(QC_ERR_ARG, "k out of range");
     if (k > s.n) return fail(QC_ERR_QUBIT, "more gate qubits than register qubits");
     if ((rc = check_qubits(s.n, qubits, k, "target"))) return rc;
-    return fused_apply(s, k, qubits, to_cd(u, 1 << k), (hipStream_t)stream);
+    return fused_apply(s, k, qubits, 0, nullptr, to_cd(u, 1 << k), (hipStream_t)stream);
+}
+
+int qc_apply_multiplexed(qc_state_t s, int k, const int *qubits, int n_sel, const int *sel_qubits,
+                         const double *u, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!u) return fail(QC_ERR_ARG, "matrix is NULL");
+    if (k < 1 || k > QC_MAX_FUSED) return fail(QC_ERR_ARG, "k out of range");
+    if (n_sel < 0 || n_sel > QC_MAX_SEL) return fail(QC_ERR_ARG, "n_sel out of range");
+    if (k + n_sel > s.n) return fail(QC_ERR_QUBIT, "more gate qubits than register qubits");
+    if (n_sel > 0 && !sel_qubits) return fail(QC_ERR_ARG, "selector pointer is NULL");
+    if (!qubits) return fail(QC_ERR_ARG, "target pointer is NULL");
+    int all[QC_MAX_FUSED + QC_MAX_SEL];
+    for (int j = 0; j < k; ++j) all[j] = qubits[j];
+    for (int j = 0; j < n_sel; ++j) all[k + j] = sel_qubits[j];
+    if ((rc = check_qubits(s.n, all, k + n_sel, "gate qubit"))) return rc;
+    const int d = 1 << k;
+    std::vector<cd> m(size_t(d) * d << n_sel);
+    for (size_t i = 0; i < m.size(); ++i) m[i] = cd(u[2 * i], u[2 * i + 1]);
+    return fused_apply(s, k, qubits, n_sel, sel_qubits, m, (hipStream_t)stream);
 }
 
 int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *block_of,
@@ -909,7 +1102,7 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *bl
     }
     std::vector<int> bo;
     int nb = 0;
-    fuse_plan(n, n_gates, gates, fuse_k, bo, nb);
+    fuse_plan(n, n_gates, gates, fuse_k, qcx::kMaxSel, bo, nb);
     std::copy(bo.begin(), bo.end(), block_of);
     *n_blocks = nb;
     return QC_OK;
@@ -939,25 +1132,21 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     } else {
         std::vector<int> bo;
         int nb = 0;
-        fuse_plan(s.n, n_gates, gates, fuse_k, bo, nb);
+        fuse_plan(s.n, n_gates, gates, fuse_k, qcx::kMaxSel, bo, nb);
         std::vector<std::vector<const qc_gate_t *>> members(nb);
         for (int i = 0; i < n_gates; ++i) members[bo[i]].push_back(&gates[i]);
+        // complex64 blocks are widened to 5 qubits so that every block runs
+        // on the matrix-core kernel (the extra qubits carry identity)
+        const bool widen = s.dtype == QC_C64 && fuse_k == 5;
         for (int b = 0; b < nb; ++b) {
-            uint64_t m = 0;
-            for (auto *g : members[b]) m |= gate_mask(*g);
-            int bq[64], k = 0;
-            for (int q = 0; q < s.n; ++q)
-                if ((m >> q) & 1) bq[k++] = q;
-            if (k > QC_MAX_FUSED) return fail(QC_ERR_UNSUPPORTED, "gate wider than the fused path");
-            // complex64 blocks are widened to 5 qubits so that every block
-            // runs on the matrix-core kernel (the extra qubits carry identity)
-            for (int q = 0; s.dtype == QC_C64 && fuse_k == 5 && k < fuse_k && q < s.n; ++q)
-                if (!((m >> q) & 1)) {
-                    m |= uint64_t(1) << q;
-                    bq[k++] = q;
-                }
-            std::sort(bq, bq + k);
-            rc = fused_apply(s, k, bq, block_matrix(k, bq, members[b]), hs);
+            int bq[QC_MAX_FUSED], sq[qcx::kMaxSel], k = 0, ns = 0;
+            if (!assign_block(s.n, members[b], fuse_k, widen, bq, k, sq, ns)) {
+                // not expressible as one block (a gate with many controls)
+                for (auto *g : members[b])
+                    if ((rc = apply_gate_unfused(s, *g, st, stream))) return rc;
+                continue;
+            }
+            rc = fused_apply(s, k, bq, ns, sq, block_matrices(k, bq, ns, sq, members[b]), hs);
             if (rc) return rc;
             st.launches += 1;
             st.sweeps += 1;

@@ -26,6 +26,15 @@
 // U stays in VGPRs for the whole kernel; the next tile's loads are in
 // flight while the current tile is multiplied.
 //
+// Multiplexed blocks (U_v selected by up to 2 selector bits, the block
+// form of a gate controlled from outside it).  A selector bit among the 7
+// column bits of the tile is given column-index bit 5 or 6, which picks
+// the wavefront, so every wavefront still multiplies with one matrix.  A
+// selector bit above the tile is fixed per workgroup: workgroup b serves
+// the value b mod 2^c_hi of those bits only, and its tiles are enumerated
+// by inserting zeros at the tile and selector bits.  Each wavefront loads
+// its matrix once (mat_idx[workgroup value][wavefront]).
+//
 // Register layouts of v_mfma_f32_32x32x2_f32 (one block, wave64):
 //   A (32x2):  lane l holds A[l % 32][l / 32]
 //   B (2x32):  lane l holds B[l / 32][l % 32]
@@ -51,8 +60,13 @@ constexpr int kSwzBits = kTileBits - 5;
 
 struct MfmaArgs {
     cx<float> *amp;
-    const float *a_ops;         // [3][32][32]: Ur, Ui, Ur + Ui (row = output t)
-    uint64_t n_tiles;
+    const float *a_ops;         // per selector value [3][32][32]: Ur, Ui, Ur + Ui (row = output t)
+    uint64_t n_tiles;           // tiles per selector value
+    uint8_t ins_pos[kTileBits + kMaxSel];  // ascending tile + high selector bit positions
+    uint8_t sel_pos[kMaxSel];   // selector bits above the tile, most significant first
+    uint8_t mat_idx[(1 << kMaxSel) * 4];   // matrix of [workgroup selector value][wavefront]
+    int n_ins;
+    int n_sel;                  // selector bits above the tile
     uint64_t off_s[8];          // address offset of tile element 512 s
     uint8_t tile_pos[kTileBits];  // ascending bit positions of the tile bits
     uint16_t mcol[kSwzBits];    // swizzle matrix columns (bits 5..11 of j)
@@ -79,14 +93,21 @@ __global__ __launch_bounds__(kWG) void k_fused_mfma_c64(const MfmaArgs a) {
     const int h = l >> 5;
     const int nidx = l & 31;
 
+    // selector value of this workgroup and the bits it fixes
+    const unsigned sel = blockIdx.x & ((1u << a.n_sel) - 1u);
+    uint64_t sel_or = 0;
+    for (int j = 0; j < a.n_sel; ++j)
+        if ((sel >> (a.n_sel - 1 - j)) & 1u) sel_or |= uint64_t(1) << a.sel_pos[j];
+    const float *ops = a.a_ops + size_t(a.mat_idx[sel * 4 + wave]) * 3072;
+
     // U operands for the 16 K-steps: row m = l % 32, input row t = s + 16 h
     float ar[16], ai[16], as[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int idx = nidx * 32 + s + 16 * h;
-        ar[s] = a.a_ops[idx];
-        ai[s] = a.a_ops[1024 + idx];
-        as[s] = a.a_ops[2048 + idx];
+        ar[s] = ops[idx];
+        ai[s] = ops[1024 + idx];
+        as[s] = ops[2048 + idx];
     }
 
     // memory-order constants: this thread moves elements 2 tid + 512 s (+1)
@@ -104,10 +125,11 @@ __global__ __launch_bounds__(kWG) void k_fused_mfma_c64(const MfmaArgs a) {
     const uint32_t sw_rd_l = swz(cdep | (h ? a.t16 : 0u), a.mcol);
     const uint32_t sw_out_l = swz(cdep | (h ? a.t4 : 0u), a.mcol);
 
-    uint64_t tile = blockIdx.x;
+    const uint64_t tstep = gridDim.x >> a.n_sel;
+    uint64_t tile = blockIdx.x >> a.n_sel;
     if (tile >= a.n_tiles) return;
     floatx4 g[8];
-    uint64_t base = insert_zeros(tile, a.tile_pos, kTileBits);
+    uint64_t base = insert_zeros(tile, a.ins_pos, a.n_ins) | sel_or;
 #pragma unroll
     for (int s = 0; s < 8; ++s)
         g[s] = __builtin_nontemporal_load(
@@ -123,9 +145,9 @@ __global__ __launch_bounds__(kWG) void k_fused_mfma_c64(const MfmaArgs a) {
         }
         __syncthreads();
         // prefetch the next tile while this one is multiplied
-        const uint64_t next = tile + gridDim.x;
+        const uint64_t next = tile + tstep;
         const bool more = next < a.n_tiles;
-        const uint64_t nbase = more ? insert_zeros(next, a.tile_pos, kTileBits) : 0;
+        const uint64_t nbase = more ? (insert_zeros(next, a.ins_pos, a.n_ins) | sel_or) : 0;
         if (more) {
 #pragma unroll
             for (int s = 0; s < 8; ++s)
@@ -227,11 +249,12 @@ int query_grid_cap() {
 
 hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
                                  hipStream_t s) {
-    if (g.k != 5 || n < kTileBits) return hipErrorInvalidValue;
+    if (g.k != 5 || g.n_sel < 0 || g.n_sel > kMaxSel || n < kTileBits) return hipErrorInvalidValue;
     MfmaArgs a{};
     a.amp = static_cast<cx<float> *>(amp);
     a.a_ops = a_dev;
-    a.n_tiles = uint64_t(1) << (n - kTileBits);
+    uint64_t smask = 0;
+    for (int j = 0; j < g.n_sel; ++j) smask |= uint64_t(1) << g.sel_pos[j];
     // target positions, most significant local bit first
     int tpos[5];
     for (int j = 0; j < 5; ++j) {
@@ -240,9 +263,56 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
     }
     uint64_t tmask = 0;
     for (int j = 0; j < 5; ++j) tmask |= uint64_t(1) << tpos[j];
+    if (tmask & smask) return hipErrorInvalidValue;
+    // the 7 lowest other bits are the column bits; selector bits among them
+    // take column-index bits 5 and 6 (the wavefront), the rest keep
+    // ascending order
     int cpos[kColBits], nc = 0;
     for (int p = 0; p < n && nc < kColBits; ++p)
-        if (!((tmask >> p) & 1)) cpos[nc++] = p;
+        if (!((tmask >> p) & 1) && !((smask >> p) & 1)) cpos[nc++] = p;
+    int wave_bit[kMaxSel];      // per selector: wavefront bit, or -1 (above the tile)
+    int hi_rank[kMaxSel];       // per selector above the tile: rank among those bits
+    {
+        // colmask = the 7 lowest non-target bits; the n_lo selectors among
+        // them replace the highest plain entries of cpos
+        int n_lo = 0;
+        uint64_t colmask = 0;
+        int cnt = 0;
+        for (int p = 0; p < n && cnt < kColBits; ++p)
+            if (!((tmask >> p) & 1)) {
+                colmask |= uint64_t(1) << p;
+                ++cnt;
+            }
+        for (int j = 0; j < g.n_sel; ++j)
+            if ((colmask >> g.sel_pos[j]) & 1) ++n_lo;
+        nc = kColBits - n_lo;
+        int lo_seen = 0, hi_seen = 0;
+        for (int j = 0; j < g.n_sel; ++j) {
+            if ((colmask >> g.sel_pos[j]) & 1) {
+                cpos[nc + lo_seen] = g.sel_pos[j];
+                wave_bit[j] = kColBits - n_lo + lo_seen - 5;
+                hi_rank[j] = -1;
+                ++lo_seen;
+            } else {
+                wave_bit[j] = -1;
+                hi_rank[j] = hi_seen;
+                a.sel_pos[hi_seen++] = g.sel_pos[j];
+            }
+        }
+        a.n_sel = hi_seen;
+        if (n < kTileBits + a.n_sel) return hipErrorInvalidValue;
+        a.n_tiles = uint64_t(1) << (n - kTileBits - a.n_sel);
+        for (int h = 0; h < (1 << a.n_sel); ++h)
+            for (int w = 0; w < 4; ++w) {
+                int v = 0;
+                for (int j = 0; j < g.n_sel; ++j) {
+                    const int bit = wave_bit[j] >= 0 ? (w >> wave_bit[j]) & 1
+                                                     : (h >> (a.n_sel - 1 - hi_rank[j])) & 1;
+                    v = 2 * v + bit;
+                }
+                a.mat_idx[h * 4 + w] = uint8_t(v);
+            }
+    }
     int tile[kTileBits];
     for (int j = 0; j < 5; ++j) tile[j] = tpos[j];
     for (int j = 0; j < kColBits; ++j) tile[5 + j] = cpos[j];
@@ -253,6 +323,12 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
         return -1;
     };
     for (int i = 0; i < kTileBits; ++i) a.tile_pos[i] = uint8_t(tile[i]);
+    int ins[kTileBits + kMaxSel];
+    std::copy(tile, tile + kTileBits, ins);
+    for (int j = 0; j < a.n_sel; ++j) ins[kTileBits + j] = a.sel_pos[j];
+    a.n_ins = kTileBits + a.n_sel;
+    std::sort(ins, ins + a.n_ins);
+    for (int i = 0; i < a.n_ins; ++i) a.ins_pos[i] = uint8_t(ins[i]);
     for (int sidx = 0; sidx < 8; ++sidx) {
         uint64_t off = 0;
         for (int b = 0; b < 3; ++b)
@@ -274,9 +350,14 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
         a.sw_rd_s[sidx] = uint16_t(apply_m(dep_t(sidx), a.mcol));
         a.sw_out_s[sidx] = uint16_t(apply_m(dep_t(8 * (sidx / 4) + sidx % 4), a.mcol));
     }
-    uint64_t grid = a.n_tiles;
+    // a multiple of 2^n_sel workgroups, so that every value of the selector
+    // bits above the tile has the same number of workgroups
+    const uint64_t n_sets = uint64_t(1) << a.n_sel;
+    uint64_t grid = a.n_tiles << a.n_sel;
     const uint64_t cap = uint64_t(query_grid_cap());
     if (grid > cap) grid = cap;
+    grid &= ~(n_sets - 1);
+    if (grid < n_sets) grid = n_sets;
     const int tok = timer_begin("fused_mfma_c64", s);
     hipLaunchKernelGGL(k_fused_mfma_c64, dim3(unsigned(grid)), dim3(kWG), 0, s, a);
     timer_end(tok, s);

@@ -74,18 +74,25 @@ __global__ __launch_bounds__(kBlock) void k_small_gate(const SmallGateArgs<R, K>
 }
 
 // Dense k-qubit block on the vector units: one work item per column (one
-// assignment of the non-target bits).  U lives in LDS.
+// assignment of the non-target bits).  U lives in LDS; a multiplexed block
+// holds 2^n_sel matrices and each column picks the one named by its
+// selector bits.
 template <typename R, int K>
 __global__ __launch_bounds__(kBlock) void k_fused_valu(cx<R> *amp, uint64_t n_cols,
                                                        const FusedGeom g, const cx<R> *u_dev) {
     constexpr int D = 1 << K;
-    __shared__ cx<R> U[D * D];
-    for (int i = threadIdx.x; i < D * D; i += kBlock) U[i] = u_dev[i];
+    extern __shared__ unsigned char smem_u[];
+    cx<R> *U = reinterpret_cast<cx<R> *>(smem_u);
+    const int n_mat = 1 << g.n_sel;
+    for (int i = threadIdx.x; i < n_mat * D * D; i += kBlock) U[i] = u_dev[i];
     __syncthreads();
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t col = uint64_t(blockIdx.x) * kBlock + threadIdx.x; col < n_cols;
          col += stride) {
         const uint64_t base = insert_zeros(col, g.pos, g.n_pos);
+        int sel = 0;
+        for (int j = 0; j < g.n_sel; ++j) sel = (sel << 1) | int((base >> g.sel_pos[j]) & 1);
+        const cx<R> *Us = U + sel * (D * D);
         cx<R> v[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) v[c] = amp[base + g.tgt_off[c]];
@@ -93,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_valu(cx<R> *amp, uint64_t n_co
         for (int r = 0; r < D; ++r) {
             cx<R> acc{R(0), R(0)};
 #pragma unroll
-            for (int c = 0; c < D; ++c) acc = cfma(U[r * D + c], v[c], acc);
+            for (int c = 0; c < D; ++c) acc = cfma(Us[r * D + c], v[c], acc);
             amp[base + g.tgt_off[r]] = acc;
         }
     }
@@ -165,17 +172,19 @@ hipError_t small_gate_dispatch(void *amp, int n, int k, const int *tpos, int n_c
 template <typename R>
 hipError_t fused_valu_typed(void *amp, int n, const FusedGeom &g, const void *u_dev,
                             hipStream_t s) {
+    if (g.k < 1 || g.k > 5 || g.n_sel < 0 || g.n_sel > kMaxSel) return hipErrorInvalidValue;
     const uint64_t n_cols = uint64_t(1) << (n - g.k);
     const unsigned grid = grid_for(n_cols, kBlock, kStreamGridCap);
     auto *A = static_cast<cx<R> *>(amp);
     auto *U = static_cast<const cx<R> *>(u_dev);
+    const size_t lds = (size_t(1) << g.n_sel) * (size_t(1) << (2 * g.k)) * sizeof(cx<R>);
     const int tok = timer_begin(sizeof(R) == 8 ? "fused_valu_c128" : "fused_valu_c64", s);
     switch (g.k) {
-    case 1: hipLaunchKernelGGL((k_fused_valu<R, 1>), dim3(grid), dim3(kBlock), 0, s, A, n_cols, g, U); break;
-    case 2: hipLaunchKernelGGL((k_fused_valu<R, 2>), dim3(grid), dim3(kBlock), 0, s, A, n_cols, g, U); break;
-    case 3: hipLaunchKernelGGL((k_fused_valu<R, 3>), dim3(grid), dim3(kBlock), 0, s, A, n_cols, g, U); break;
-    case 4: hipLaunchKernelGGL((k_fused_valu<R, 4>), dim3(grid), dim3(kBlock), 0, s, A, n_cols, g, U); break;
-    case 5: hipLaunchKernelGGL((k_fused_valu<R, 5>), dim3(grid), dim3(kBlock), 0, s, A, n_cols, g, U); break;
+    case 1: hipLaunchKernelGGL((k_fused_valu<R, 1>), dim3(grid), dim3(kBlock), lds, s, A, n_cols, g, U); break;
+    case 2: hipLaunchKernelGGL((k_fused_valu<R, 2>), dim3(grid), dim3(kBlock), lds, s, A, n_cols, g, U); break;
+    case 3: hipLaunchKernelGGL((k_fused_valu<R, 3>), dim3(grid), dim3(kBlock), lds, s, A, n_cols, g, U); break;
+    case 4: hipLaunchKernelGGL((k_fused_valu<R, 4>), dim3(grid), dim3(kBlock), lds, s, A, n_cols, g, U); break;
+    case 5: hipLaunchKernelGGL((k_fused_valu<R, 5>), dim3(grid), dim3(kBlock), lds, s, A, n_cols, g, U); break;
     default: timer_end(tok, s); return hipErrorInvalidValue;
     }
     timer_end(tok, s);

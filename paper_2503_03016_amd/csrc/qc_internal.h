@@ -63,11 +63,18 @@ struct SmallGateArgs {
     int n_pos;
 };
 
+// k-qubit block, optionally multiplexed: with n_sel selector bits the matrix
+// applied to a group is U_s, s = the group's values at sel_pos (sel_pos[0]
+// = most significant bit of s); the 2^n_sel matrices are stored one after
+// the other.
+constexpr int kMaxSel = 2;   // U lives in LDS: 4 c128 5-qubit matrices = 64 KiB
 struct FusedGeom {
     int k;
     int n_pos;
     uint8_t pos[8];            // ascending target positions
     uint64_t tgt_off[32];      // offset of local index r
+    int n_sel;
+    uint8_t sel_pos[kMaxSel];  // selector bit positions
 };
 
 // One Pauli term of a Hamiltonian on the device: P = i^ph X^x Z^z (masks of

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqc.so")
 
 QC_C64, QC_C128 = 1, 2
 QC_EXEC_UNFUSED, QC_EXEC_FUSED, QC_EXEC_TILED = 0, 1, 2
-QC_MAX_FUSED, QC_MAX_CTRLS = 5, 16
+QC_MAX_FUSED, QC_MAX_CTRLS, QC_MAX_SEL = 5, 16, 2
 STATUS = {0: "QC_OK", -1: "QC_ERR_ARG", -2: "QC_ERR_QUBIT", -3: "QC_ERR_DTYPE",
           -4: "QC_ERR_UNSUPPORTED", -5: "QC_ERR_HIP", -6: "QC_ERR_NOMEM"}
 OP_KIND = {"RX": 1, "RY": 2, "RZ": 3, "H": 4, "X": 5, "Y": 6, "Z": 7, "CZ": 8, "CNOT": 9}
@@ -27,6 +27,7 @@ OP_KIND = {"RX": 1, "RY": 2, "RZ": 3, "H": 4, "X": 5, "Y": 6, "Z": 7, "CZ": 8, "
 EXPORTS = [
     "qc_status_string", "qc_last_error", "qc_version", "qc_state_init", "qc_state_copy",
     "qc_state_diff", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled", "qc_apply_fused_k",
+    "qc_apply_multiplexed",
     "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
@@ -101,6 +102,7 @@ def _load():
         "qc_apply_2q": ([S, i, i, dp, vp], i),
         "qc_apply_controlled": ([S, i, ip, ip, i, dp, vp], i),
         "qc_apply_fused_k": ([S, i, ip, dp, vp], i),
+        "qc_apply_multiplexed": ([S, i, ip, i, ip, dp, vp], i),
         "qc_apply_circuit": ([S, i, ctypes.POINTER(QcGate), i, i, ctypes.POINTER(QcStats), vp], i),
         "qc_fuse_plan": ([i, i, ctypes.POINTER(QcGate), i, ip, ip], i),
         "qc_probs": ([S, i, ip, vp, vp], i),
@@ -219,6 +221,17 @@ def apply_fused_k(psi: torch.Tensor, qubits: Sequence[int], u) -> torch.Tensor:
     m, p = _mat(u)
     _check(lib.qc_apply_fused_k(state_view(psi), len(qubits), _ints(qubits), p, _stream(psi)),
            "qc_apply_fused_k")
+    return psi
+
+
+def apply_multiplexed(psi: torch.Tensor, qubits: Sequence[int], sel_qubits: Sequence[int],
+                      us) -> torch.Tensor:
+    """psi := sum_v P_v (x) U_v psi; `us` holds 2^len(sel_qubits) matrices
+    (v = selector value, sel_qubits[0] = most significant bit)."""
+    arr = np.asarray(us, dtype=np.complex128)
+    m, p = _mat(arr)
+    _check(lib.qc_apply_multiplexed(state_view(psi), len(qubits), _ints(qubits), len(sel_qubits),
+                                    _ints(sel_qubits), p, _stream(psi)), "qc_apply_multiplexed")
     return psi
 
 
@@ -451,6 +464,7 @@ qc_apply_1q = apply_1q
 qc_apply_2q = apply_2q
 qc_apply_controlled = apply_controlled
 qc_apply_fused_k = apply_fused_k
+qc_apply_multiplexed = apply_multiplexed
 qc_apply_circuit = apply_circuit
 qc_fuse_plan = fuse_plan
 qc_probs = probs

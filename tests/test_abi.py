@@ -34,7 +34,7 @@ def test_package_modules_import_and_constants_match_header():
     from paper_2503_03016_amd import qc as q
     text = open(HEADER).read()
     for name in ("QC_C64", "QC_C128", "QC_EXEC_UNFUSED", "QC_EXEC_FUSED", "QC_EXEC_TILED",
-                 "QC_MAX_FUSED", "QC_MAX_CTRLS", "QC_KNOB_MFMA_WG_PER_CU",
+                 "QC_MAX_FUSED", "QC_MAX_CTRLS", "QC_MAX_SEL", "QC_KNOB_MFMA_WG_PER_CU",
                  "QC_KNOB_TILE_WG_PER_CU"):
         m = re.search(r"#define\s+%s\s+(-?\d+)" % name, text)
         assert m and getattr(q, name) == int(m.group(1)), name
@@ -100,6 +100,16 @@ def test_gate_validation(qc):
     assert lib.qc_apply_fused_k(st(qc), 6, qc._ints(range(6)), p32, None) == -1
     assert lib.qc_apply_fused_k(st(qc), 5, qc._ints(range(5)), p32, None) == -2
     assert lib.qc_apply_fused_k(st(qc, n=6), 2, qc._ints([3, 3]), p4, None) == -2
+    mux = qc.lib.qc_apply_multiplexed
+    u8, p8 = qc._mat(np.stack([np.eye(2)] * 8))
+    assert mux(st(qc, n=6), 1, qc._ints([0]), 3, qc._ints([1, 2, 3]), p8, None) == -1
+    assert mux(st(qc, n=6), 1, qc._ints([0]), -1, qc._ints([1]), p8, None) == -1
+    assert mux(st(qc, n=6), 1, qc._ints([0]), 2, qc._ints([1, 0]), p8, None) == -2
+    assert mux(st(qc, n=6), 1, qc._ints([0]), 2, qc._ints([1, 6]), p8, None) == -2
+    assert mux(st(qc, n=6), 1, qc._ints([0]), 2, None, p8, None) == -1
+    assert mux(st(qc, n=6), 1, qc._ints([0]), 2, qc._ints([1, 2]), None, None) == -1
+    assert mux(st(qc, n=2), 1, qc._ints([0]), 2, qc._ints([1, 2]), p8, None) == -2
+    assert mux(st(qc, n=6), 0, qc._ints([0]), 1, qc._ints([1]), p8, None) == -1
 
 
 def test_reduction_validation(qc):
@@ -179,17 +189,42 @@ def _gate_list(qc, ops):
     return qc.GateList(G.gate_tuples(ops))
 
 
-def _check_partition(ops, block_of, nb, k):
-    qsets = {}
-    for op, b in zip(ops, block_of):
+def _check_partition(ops, block_of, nb, k, max_sel=2):
+    """A block acts non-diagonally on <= k qubits and touches <= k + max_sel
+    qubits (or is a single gate); a gate placed in an earlier block than a
+    gate that precedes it must commute with it: every qubit they share is a
+    control or a target of a diagonal matrix for both."""
+    from paper_2503_03016_amd import gates as G
+    tuples = G.gate_tuples(ops)
+
+    def diag_qubits(t):
+        tg, cs, _, m = t
+        m = np.asarray(m)
+        is_diag = not np.any(m - np.diag(np.diag(m)))
+        return set(cs) | (set(tg) if is_diag else set())
+
+    dq = [diag_qubits(t) for t in tuples]
+    allq = [set(t[0]) | set(t[1]) for t in tuples]
+    members = {}
+    for i, b in enumerate(block_of):
         assert 0 <= b < nb
-        qsets.setdefault(b, set()).update(op.qubits)
-    assert all(len(s) <= k for s in qsets.values())
-    last = {}
-    for op, b in zip(ops, block_of):
-        for q in op.qubits:
-            assert last.get(q, -1) <= b, "a gate moved ahead of an earlier gate on its qubit"
-            last[q] = b
+        members.setdefault(b, []).append(i)
+    assert sorted(members) == list(range(nb))
+    for b, idx in members.items():
+        nd = set().union(*[allq[i] - dq[i] for i in idx])
+        touched = set().union(*[allq[i] for i in idx])
+        assert len(idx) == 1 or (len(nd) <= k and len(touched) <= k + max_sel), (b, nd, touched)
+    per_qubit = {}
+    for i, qs in enumerate(allq):
+        for q in qs:
+            per_qubit.setdefault(q, []).append(i)
+    for q, lst in per_qubit.items():
+        for a in range(len(lst)):
+            for c in range(a + 1, len(lst)):
+                i, j = lst[a], lst[c]
+                if block_of[j] < block_of[i]:
+                    shared = allq[i] & allq[j]
+                    assert shared <= (dq[i] & dq[j]), ("non-commuting gates swapped", i, j)
 
 
 @pytest.mark.parametrize("n,layers,k", [(12, 20, 5), (16, 8, 4), (32, 40, 5), (10, 6, 3)])

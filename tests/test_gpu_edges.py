@@ -28,6 +28,9 @@ def G():
     return gates
 
 
+DT = {"c128": torch.complex128, "c64": torch.complex64}
+
+
 def dev(psi, dtype):
     return torch.from_numpy(np.ascontiguousarray(psi)).to(dtype).cuda()
 
@@ -129,3 +132,38 @@ def test_unfused_c128_vs_oracle_at_22_qubits(qc, G):
     qc.state_init(t, 0)
     qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=qc.QC_EXEC_UNFUSED)
     assert np.max(np.abs(host(t) - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("dt,fuse_k", [("c128", 5), ("c64", 5), ("c128", 2), ("c64", 3)])
+def test_fused_mode_with_diagonal_and_controlled_gates_across_blocks(qc, G, dt, fuse_k):
+    """QC_EXEC_FUSED on a circuit where controls and diagonal gates reach
+    outside the blocks (multiplexed blocks), open controls, a controlled
+    gate with a non-diagonal target, and a 9-qubit MCX too wide for any
+    block (applied on its own), against the oracle."""
+    n = 14
+    rng = np.random.default_rng(31 + fuse_k)
+    ops = []
+    for layer in range(6):
+        for q in range(n):
+            ops.append(W.Op("U", (q,), matrix=random_unitary(2, rng)))
+        for q in range(layer % 2, n - 1, 2):
+            ops.append(W.Op("CZ", (q, q + 1)))
+        a, b = [int(x) for x in rng.permutation(n)[:2]]
+        ops.append(W.Op("CP", (a, b), angle=float(rng.uniform(0, 2 * np.pi))))
+        a, b = [int(x) for x in rng.permutation(n)[:2]]
+        ops.append(W.Op("CNOT", (a, b)))
+        qs = [int(x) for x in rng.permutation(n)[:3]]
+        ops.append(W.Op("MCX", tuple(qs), ctrl_val=(0, 1)))
+        ops.append(W.Op("RZ", (int(rng.integers(n)),), angle=float(rng.uniform(0, 6))))
+    ops.append(W.Op("MCX", tuple(range(9)), ctrl_val=(1, 0, 1, 1, 0, 1, 0, 1)))
+    psi0 = W.random_state(n, 77)
+    ref = oracle.run(ops, psi0)
+    t = dev(psi0, DT[dt])
+    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=qc.QC_EXEC_FUSED,
+                          fuse_k=fuse_k)
+    assert st["fused_blocks"] < len(ops) / 2
+    got = host(t)
+    if dt == "c128":
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    else:
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5

@@ -153,6 +153,40 @@ def test_fused_mfma_target_positions(qc, n):
         check(host(t), oracle.apply(psi0, qs, u), torch.complex64, ngates=8)
 
 
+def mux_oracle(psi, qs, sel, us):
+    """A multiplexed gate as 2^c controlled k-qubit gates, one per selector
+    value v, each controlled on the selector qubits reading v."""
+    c = len(sel)
+    for v in range(1 << c):
+        vals = [(v >> (c - 1 - j)) & 1 for j in range(c)]
+        psi = oracle.apply(psi, qs, us[v], ctrl=sel, ctrl_val=vals)
+    return psi
+
+
+@pytest.mark.parametrize("dt,n,k,c", [
+    ("c64", 14, 5, 2), ("c64", 16, 5, 1), ("c64", 13, 5, 2), ("c64", 11, 3, 2),
+    ("c128", 12, 5, 2), ("c128", 9, 2, 1), ("c64", 12, 5, 0)])
+def test_apply_multiplexed(qc, dt, n, k, c):
+    """qc_apply_multiplexed on the matrix-core path (complex64, k = 5,
+    n >= 12 + c) and on the vector path, with selector qubits at the lowest
+    and highest bit positions and in between."""
+    rng = np.random.default_rng(100 * n + 10 * k + c)
+    psi0 = W.random_state(n, 2000 + n)
+    layouts = [
+        (list(range(k)), list(range(n - c, n))),             # selectors at the lowest bits
+        (list(range(n - k, n)), list(range(c))),             # selectors at the highest bits
+        ([int(x) for x in rng.permutation(n)[:k + c]][:k], None),
+    ]
+    for qs, sel in layouts:
+        if sel is None:
+            rest = [q for q in rng.permutation(n) if q not in qs]
+            sel = [int(x) for x in rest[:c]]
+        us = np.stack([random_unitary(1 << k, rng) for _ in range(1 << c)])
+        t = dev(psi0, DT[dt])
+        qc.apply_multiplexed(t, qs, sel, us)
+        check(host(t), mux_oracle(psi0, qs, sel, us), DT[dt], ngates=8)
+
+
 # ---------------------------------------------------------------- circuits
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
