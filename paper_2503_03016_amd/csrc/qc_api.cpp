@@ -10,6 +10,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -107,6 +108,7 @@ std::mutex g_tmu;
 // launch-shape knobs (QC_KNOB_*)
 std::atomic<int> g_knob_mfma{4};
 std::atomic<int> g_knob_tile{8};
+std::atomic<int> g_knob_look{16};
 
 // ---------------------------------------------------------------- validation
 
@@ -381,56 +383,101 @@ void grow_block(const std::vector<int> &pending, const std::vector<GateMasks> &g
     }
 }
 
-// Partition into dependency-respecting blocks of <= k qubits (plus at most
-// smax selector qubits).  Each block is chosen among candidates seeded by
-// the first gates that have no pending predecessor ("front" gates): a
-// block grown greedily from the seed, and blocks confined to each window of
-// k consecutive qubit labels that holds the seed.  The candidate absorbing
-// the most gates wins.
-void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, int smax, std::vector<int> &block_of,
-               int &n_blocks) {
+// Candidate blocks for the current pending list: for each of the first
+// gates that have no pending predecessor ("front" gates), the block grown
+// greedily from it and the blocks confined to each window of k consecutive
+// qubit labels that holds it.
+void block_candidates(int n, const std::vector<int> &pending, const std::vector<GateMasks> &gm,
+                      int k, int smax, uint64_t all, std::vector<std::vector<int>> &out) {
     constexpr int kMaxFront = 32;
-    block_of.assign(ng, -1);
-    n_blocks = 0;
+    out.clear();
+    std::vector<int> front, cand;
+    uint64_t seen = 0;
+    for (int i = 0; i < int(pending.size()) && int(front.size()) < kMaxFront; ++i) {
+        const uint64_t m = gm[pending[i]].all;
+        if (!(m & seen)) front.push_back(i);
+        seen |= m;
+        if ((seen & all) == all) break;
+    }
+    for (int f : front) {
+        const uint64_t sm = gm[pending[f]].all;
+        grow_block(pending, gm, f, 0, k, smax, all, cand);
+        out.push_back(cand);
+        if (__builtin_popcountll(sm) > k || k >= n) continue;
+        const int lo = __builtin_ctzll(sm), hi = 63 - __builtin_clzll(sm);
+        for (int a = std::max(0, hi - k + 1); a <= std::min(lo, n - k); ++a) {
+            const uint64_t w = ((uint64_t(1) << k) - 1) << a;
+            grow_block(pending, gm, f, w, k, smax, all, cand);
+            out.push_back(cand);
+        }
+    }
+}
+
+void remove_members(const std::vector<int> &pending, const std::vector<int> &members,
+                    std::vector<int> &rest) {
+    std::vector<char> taken(pending.size(), 0);
+    for (int i : members) taken[i] = 1;
+    rest.clear();
+    for (int i = 0; i < int(pending.size()); ++i)
+        if (!taken[i]) rest.push_back(pending[i]);
+}
+
+// Partition into dependency-respecting blocks of <= k qubits (plus at most
+// smax selector qubits), handing each block to `emit` (its gate indices in
+// order) as soon as it is chosen, so a caller can launch block b while
+// block b + 1 is planned.  Each step takes the candidate block (see
+// block_candidates) that absorbs the most gates together with the best
+// candidate of the step after it, a one-step lookahead over the `look`
+// largest candidates (look <= 1: plain greedy); ties go to the larger
+// block now.
+template <typename Emit>
+void fuse_plan_each(int n, int ng, const qc_gate_t *gs, int k, int smax, int look, Emit &&emit) {
     const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     std::vector<GateMasks> gm(ng);
     for (int i = 0; i < ng; ++i) gm[i] = {gate_mask(gs[i]), gate_nd_mask(gs[i])};
-    std::vector<int> pending(ng), best, cand, front;
+    std::vector<int> pending(ng), rest, members;
     for (int i = 0; i < ng; ++i) pending[i] = i;
+    std::vector<std::vector<int>> cands, next;
     while (!pending.empty()) {
-        front.clear();
-        uint64_t seen = 0;
-        for (int i = 0; i < int(pending.size()) && int(front.size()) < kMaxFront; ++i) {
-            const uint64_t m = gm[pending[i]].all;
-            if (!(m & seen)) front.push_back(i);
-            seen |= m;
-            if ((seen & all) == all) break;
-        }
-        best.clear();
-        for (int f : front) {
-            const uint64_t sm = gm[pending[f]].all;
-            grow_block(pending, gm, f, 0, k, smax, all, cand);
-            if (cand.size() > best.size()) best = cand;
-            if (__builtin_popcountll(sm) > k || k >= n) continue;
-            const int lo = __builtin_ctzll(sm), hi = 63 - __builtin_clzll(sm);
-            for (int a = std::max(0, hi - k + 1); a <= std::min(lo, n - k); ++a) {
-                const uint64_t w = ((uint64_t(1) << k) - 1) << a;
-                grow_block(pending, gm, f, w, k, smax, all, cand);
-                if (cand.size() > best.size()) best = cand;
+        block_candidates(n, pending, gm, k, smax, all, cands);
+        std::stable_sort(cands.begin(), cands.end(),
+                         [](const std::vector<int> &a, const std::vector<int> &b) {
+                             return a.size() > b.size();
+                         });
+        int pick = 0;
+        if (look > 1) {
+            size_t best_score = 0;
+            for (int c = 0; c < std::min<int>(look, int(cands.size())); ++c) {
+                remove_members(pending, cands[c], rest);
+                size_t nx = 0;
+                if (!rest.empty()) {
+                    block_candidates(n, rest, gm, k, smax, all, next);
+                    for (auto &v : next) nx = std::max(nx, v.size());
+                }
+                const size_t score = cands[c].size() + nx;
+                if (score > best_score) {
+                    best_score = score;
+                    pick = c;
+                }
             }
         }
-        std::vector<char> taken(pending.size(), 0);
-        for (int i : best) {
-            taken[i] = 1;
-            block_of[pending[i]] = n_blocks;
-        }
-        std::vector<int> rest;
-        rest.reserve(pending.size() - best.size());
-        for (int i = 0; i < int(pending.size()); ++i)
-            if (!taken[i]) rest.push_back(pending[i]);
-        ++n_blocks;
+        members.clear();
+        for (int i : cands[pick]) members.push_back(pending[i]);
+        remove_members(pending, cands[pick], rest);
         pending.swap(rest);
+        if (!emit(members)) return;
     }
+}
+
+void fuse_plan(int n, int ng, const qc_gate_t *gs, int k, int smax, int look,
+               std::vector<int> &block_of, int &n_blocks) {
+    block_of.assign(ng, -1);
+    n_blocks = 0;
+    fuse_plan_each(n, ng, gs, k, smax, look, [&](const std::vector<int> &m) {
+        for (int i : m) block_of[i] = n_blocks;
+        ++n_blocks;
+        return true;
+    });
 }
 
 double sweep_bytes(int n, int dtype) {
@@ -445,7 +492,11 @@ double sweep_bytes(int n, int dtype) {
 namespace qcx {
 
 int knob(int which) {
-    return which == QC_KNOB_MFMA_WG_PER_CU ? g_knob_mfma.load() : g_knob_tile.load();
+    switch (which) {
+    case QC_KNOB_MFMA_WG_PER_CU: return g_knob_mfma.load();
+    case QC_KNOB_TILE_WG_PER_CU: return g_knob_tile.load();
+    default: return g_knob_look.load();
+    }
 }
 
 int timer_begin(const char *name, hipStream_t s) {
@@ -536,12 +587,18 @@ int qc_set_knob(int knob, int value) {
         g_knob_tile.store(value);
         return QC_OK;
     }
+    if (knob == QC_KNOB_FUSE_LOOKAHEAD) {
+        if (value < 0 || value > 256) return fail(QC_ERR_ARG, "fuse lookahead must be 0..256");
+        g_knob_look.store(value);
+        return QC_OK;
+    }
     return fail(QC_ERR_ARG, "unknown knob");
 }
 
 int qc_get_knob(int knob, int *value) {
     if (!value) return fail(QC_ERR_ARG, "NULL argument");
-    if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU)
+    if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU &&
+        knob != QC_KNOB_FUSE_LOOKAHEAD)
         return fail(QC_ERR_ARG, "unknown knob");
     *value = qcx::knob(knob);
     return QC_OK;
@@ -679,7 +736,9 @@ int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
     const size_t dd = size_t(1) << (2 * k);
     void *dev = nullptr;
     hipError_t e;
-    if (s.dtype == QC_C64 && k == 5 && s.n >= 12 + ns) {
+    // the matrix-core kernel moves 16-byte pairs of amplitudes
+    const bool aligned16 = (reinterpret_cast<uintptr_t>(s.amp) & 15) == 0;
+    if (s.dtype == QC_C64 && k == 5 && s.n >= 12 + ns && aligned16) {
         std::vector<float> op, all;
         for (int v = 0; v < (1 << ns); ++v) {
             mfma_operand_c64(std::vector<cd>(u.begin() + v * dd, u.begin() + (v + 1) * dd), op);
@@ -1102,7 +1161,7 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *bl
     }
     std::vector<int> bo;
     int nb = 0;
-    fuse_plan(n, n_gates, gates, fuse_k, qcx::kMaxSel, bo, nb);
+    fuse_plan(n, n_gates, gates, fuse_k, qcx::kMaxSel, g_knob_look.load(), bo, nb);
     std::copy(bo.begin(), bo.end(), block_of);
     *n_blocks = nb;
     return QC_OK;
@@ -1130,29 +1189,32 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     } else if (mode == QC_EXEC_TILED) {
         if ((rc = tiled_execute(s, n_gates, gates, st, stream))) return rc;
     } else {
-        std::vector<int> bo;
-        int nb = 0;
-        fuse_plan(s.n, n_gates, gates, fuse_k, qcx::kMaxSel, bo, nb);
-        std::vector<std::vector<const qc_gate_t *>> members(nb);
-        for (int i = 0; i < n_gates; ++i) members[bo[i]].push_back(&gates[i]);
         // complex64 blocks are widened to 5 qubits so that every block runs
-        // on the matrix-core kernel (the extra qubits carry identity)
+        // on the matrix-core kernel (the extra qubits carry identity).  Each
+        // block is launched as soon as the planner has chosen it, so the
+        // planning of the next block overlaps the device work.
         const bool widen = s.dtype == QC_C64 && fuse_k == 5;
-        for (int b = 0; b < nb; ++b) {
+        std::vector<const qc_gate_t *> members;
+        fuse_plan_each(s.n, n_gates, gates, fuse_k, qcx::kMaxSel, g_knob_look.load(),
+                       [&](const std::vector<int> &idx) {
+            members.clear();
+            for (int i : idx) members.push_back(&gates[i]);
             int bq[QC_MAX_FUSED], sq[qcx::kMaxSel], k = 0, ns = 0;
-            if (!assign_block(s.n, members[b], fuse_k, widen, bq, k, sq, ns)) {
+            if (!assign_block(s.n, members, fuse_k, widen, bq, k, sq, ns)) {
                 // not expressible as one block (a gate with many controls)
-                for (auto *g : members[b])
-                    if ((rc = apply_gate_unfused(s, *g, st, stream))) return rc;
-                continue;
+                for (auto *g : members)
+                    if ((rc = apply_gate_unfused(s, *g, st, stream))) return false;
+                return true;
             }
-            rc = fused_apply(s, k, bq, ns, sq, block_matrices(k, bq, ns, sq, members[b]), hs);
-            if (rc) return rc;
+            rc = fused_apply(s, k, bq, ns, sq, block_matrices(k, bq, ns, sq, members), hs);
+            if (rc) return false;
             st.launches += 1;
             st.sweeps += 1;
             st.fused_blocks += 1;
             st.state_bytes += sweep;
-        }
+            return true;
+        });
+        if (rc) return rc;
     }
     if (stats) *stats = st;
     return QC_OK;

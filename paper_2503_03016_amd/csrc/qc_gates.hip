@@ -44,6 +44,27 @@ __global__ __launch_bounds__(kBlock) void k_copy(cx<RD> *dst, const cx<RS> *src,
     }
 }
 
+// Same-precision copy in 16-byte units: each workgroup moves chunks of
+// kBlock * 4 units (16 KiB), loads first; the grid normally holds one chunk
+// per workgroup, which streams HBM best on MI355X.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+constexpr int kCopyUnits = 4;
+__global__ __launch_bounds__(kBlock) void k_copy_vec(floatx4_t *__restrict__ dst,
+                                                     const floatx4_t *__restrict__ src,
+                                                     uint64_t units) {
+    const uint64_t chunk = uint64_t(kBlock) * kCopyUnits;
+    for (uint64_t c = blockIdx.x; c * chunk < units; c += gridDim.x) {
+        const uint64_t b = c * chunk + threadIdx.x;
+        floatx4_t v[kCopyUnits];
+#pragma unroll
+        for (int u = 0; u < kCopyUnits; ++u)
+            if (b + u * kBlock < units) v[u] = __builtin_nontemporal_load(src + b + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < kCopyUnits; ++u)
+            if (b + u * kBlock < units) __builtin_nontemporal_store(v[u], dst + b + u * kBlock);
+    }
+}
+
 template <typename R, int K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_small_gate(const SmallGateArgs<R, K> a) {
     constexpr int D = 1 << K;
@@ -209,6 +230,18 @@ hipError_t launch_init(void *amp, int dtype, int n, uint64_t basis, hipStream_t 
 
 hipError_t launch_copy(void *dst, int dt_dst, const void *src, int dt_src, uint64_t count,
                        hipStream_t s) {
+    const size_t elem = dt_src == QC_C64 ? 8 : 16;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0;
+    if (dt_dst == dt_src && aligned && (count * elem) % 16 == 0) {
+        const uint64_t units = count * elem / 16;
+        const uint64_t chunks = (units + uint64_t(kBlock) * kCopyUnits - 1) / (uint64_t(kBlock) * kCopyUnits);
+        const unsigned grid = unsigned(chunks < (uint64_t(1) << 22) ? chunks : (uint64_t(1) << 22));
+        const int tok = timer_begin("copy", s);
+        hipLaunchKernelGGL(k_copy_vec, dim3(grid), dim3(kBlock), 0, s,
+                           static_cast<floatx4_t *>(dst), static_cast<const floatx4_t *>(src), units);
+        timer_end(tok, s);
+        return hipGetLastError();
+    }
     const unsigned grid = grid_for(count, kBlock * 4, kStreamGridCap);
     const int tok = timer_begin("copy", s);
     if (dt_dst == QC_C64 && dt_src == QC_C64)

@@ -33,7 +33,7 @@ EXPORTS = [
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
     "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune",
 ]
-QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU = 1, 2
+QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD = 1, 2, 3
 
 
 class QcError(RuntimeError):

@@ -35,7 +35,7 @@ def test_package_modules_import_and_constants_match_header():
     text = open(HEADER).read()
     for name in ("QC_C64", "QC_C128", "QC_EXEC_UNFUSED", "QC_EXEC_FUSED", "QC_EXEC_TILED",
                  "QC_MAX_FUSED", "QC_MAX_CTRLS", "QC_MAX_SEL", "QC_KNOB_MFMA_WG_PER_CU",
-                 "QC_KNOB_TILE_WG_PER_CU"):
+                 "QC_KNOB_TILE_WG_PER_CU", "QC_KNOB_FUSE_LOOKAHEAD"):
         m = re.search(r"#define\s+%s\s+(-?\d+)" % name, text)
         assert m and getattr(q, name) == int(m.group(1)), name
     for kind, code in q.OP_KIND.items():
@@ -148,6 +148,9 @@ def test_knobs(qc):
     assert qc.lib.qc_set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 0) == -1
     assert qc.lib.qc_set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 6) == -1
     assert qc.lib.qc_set_knob(qc.QC_KNOB_TILE_WG_PER_CU, 17) == -1
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_FUSE_LOOKAHEAD, -1) == -1
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_FUSE_LOOKAHEAD, 257) == -1
+    assert qc.get_knob(qc.QC_KNOB_FUSE_LOOKAHEAD) == 16
     assert qc.lib.qc_set_knob(99, 1) == -1
     qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 3)
     assert qc.get_knob(qc.QC_KNOB_MFMA_WG_PER_CU) == 3
@@ -227,11 +230,17 @@ def _check_partition(ops, block_of, nb, k, max_sel=2):
                     assert shared <= (dq[i] & dq[j]), ("non-commuting gates swapped", i, j)
 
 
+@pytest.mark.parametrize("look", [0, 16])
 @pytest.mark.parametrize("n,layers,k", [(12, 20, 5), (16, 8, 4), (32, 40, 5), (10, 6, 3)])
-def test_fuse_plan_is_a_valid_partition(qc, n, layers, k):
-    ops = W.brickwork(n, layers, seed=n, entangler="CZ")
-    gl = _gate_list(qc, ops)
-    block_of, nb = qc.fuse_plan(n, gl, k)
+def test_fuse_plan_is_a_valid_partition(qc, n, layers, k, look):
+    old = qc.get_knob(qc.QC_KNOB_FUSE_LOOKAHEAD)
+    qc.set_knob(qc.QC_KNOB_FUSE_LOOKAHEAD, look)
+    try:
+        ops = W.brickwork(n, layers, seed=n, entangler="CZ")
+        gl = _gate_list(qc, ops)
+        block_of, nb = qc.fuse_plan(n, gl, k)
+    finally:
+        qc.set_knob(qc.QC_KNOB_FUSE_LOOKAHEAD, old)
     _check_partition(ops, block_of, nb, k)
     assert nb < len(ops)
 

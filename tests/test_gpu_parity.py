@@ -75,6 +75,30 @@ def test_init_and_copy(qc, dt):
     assert np.array_equal(host(dst), want)
 
 
+def test_same_precision_copy_sizes_and_alignment(qc):
+    """The 16-byte vector copy at sizes below, at and above one 16 KiB
+    chunk, and views that start 8 bytes into an allocation (the copy and the
+    matrix-core block fall back to their 8-byte paths there)."""
+    for dtype in (torch.complex64, torch.complex128):
+        for n in (1, 2, 9, 11, 17):
+            src = dev(W.random_state(n, 40 + n), dtype)
+            dst = qc.new_state(n, dtype)
+            qc.state_copy(dst, src)
+            assert torch.equal(dst, src)
+    n = 12
+    base_src = torch.zeros((1 << n) + 1, dtype=torch.complex64, device="cuda")
+    base_dst = torch.zeros((1 << n) + 1, dtype=torch.complex64, device="cuda")
+    src, dst = base_src[1:], base_dst[1:]
+    assert src.data_ptr() % 16 == 8
+    psi0 = W.random_state(n, 41)
+    src.copy_(torch.from_numpy(psi0).to(torch.complex64).cuda())
+    qc.state_copy(dst, src)
+    assert torch.equal(dst, src)
+    u = random_unitary(32, np.random.default_rng(9))
+    qc.apply_fused_k(dst, [0, 3, 5, 8, 11], u)
+    check(host(dst), oracle.apply(host(src), [0, 3, 5, 8, 11], u), torch.complex64, ngates=8)
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n", [1, 7, 13])
 def test_apply_1q_every_target(qc, dt, n):
