@@ -41,7 +41,7 @@ def kernel_source_hash() -> str:
 def load_traffic(n: int):
     """HBM bytes per launch of the fused kernel from committed rocprofv3 PMC
     counters, if they were taken on the current kernel source and size."""
-    path = os.path.join(PROFILES, "fused_mfma_c64_traffic.json")
+    path = os.path.join(PROFILES, "fused_mfma_c64_brickwork32_traffic.json")
     if not os.path.exists(path):
         return None
     try:
