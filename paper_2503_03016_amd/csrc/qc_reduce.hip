@@ -95,7 +95,14 @@ struct MarginalArgs {
 };
 
 // Block (bin s, chunk c) sums |psi|^2 over its share of the bin's indices.
-template <typename R>
+// Each thread keeps kMargLoads independent loads in flight.  With PAIR
+// (complex64, bit 0 not a listed qubit) a load moves the two neighbouring
+// amplitudes of indices r and r + 1 (16 bytes); complex128 amplitudes are
+// 16 bytes each already.
+constexpr int kMargLoads = 4;
+typedef float floatx4_r __attribute__((ext_vector_type(4)));
+
+template <typename R, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_probs_marginal(const cx<R> *amp,
                                                            const MarginalArgs a, double *work) {
     __shared__ double lds[kWaves];
@@ -107,9 +114,34 @@ __global__ __launch_bounds__(kBlock) void k_probs_marginal(const cx<R> *amp,
     const uint64_t r0 = c * a.chunk;
     uint64_t r1 = r0 + a.chunk;
     if (r1 > a.rest) r1 = a.rest;
+    constexpr uint64_t step = PAIR ? 2 : 1;
     double acc = 0.0;
-    for (uint64_t r = r0 + threadIdx.x; r < r1; r += kBlock)
-        acc += norm2(amp[insert_zeros(r, a.pos, a.m) | binbase]);
+    for (uint64_t r = r0 + step * threadIdx.x; r < r1; r += step * kBlock * kMargLoads) {
+        if constexpr (PAIR) {
+            floatx4_r v[kMargLoads];
+#pragma unroll
+            for (int u = 0; u < kMargLoads; ++u) {
+                const uint64_t rr = r + u * step * kBlock;
+                v[u] = floatx4_r{0.f, 0.f, 0.f, 0.f};
+                if (rr < r1)
+                    v[u] = *reinterpret_cast<const floatx4_r *>(amp + (insert_zeros(rr, a.pos, a.m) | binbase));
+            }
+#pragma unroll
+            for (int u = 0; u < kMargLoads; ++u)
+                acc += (double(v[u][0]) * double(v[u][0]) + double(v[u][1]) * double(v[u][1])) +
+                       (double(v[u][2]) * double(v[u][2]) + double(v[u][3]) * double(v[u][3]));
+        } else {
+            cx<R> v[kMargLoads];
+#pragma unroll
+            for (int u = 0; u < kMargLoads; ++u) {
+                const uint64_t rr = r + u * kBlock;
+                v[u] = cx<R>{R(0), R(0)};
+                if (rr < r1) v[u] = amp[insert_zeros(rr, a.pos, a.m) | binbase];
+            }
+#pragma unroll
+            for (int u = 0; u < kMargLoads; ++u) acc += norm2(v[u]);
+        }
+    }
     const double tot = block_sum(acc, lds);
     if (threadIdx.x == 0) work[blockIdx.x] = tot;
 }
@@ -305,12 +337,19 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
     if (bins * chunks > work_elems || bins * chunks > 0x7fffffffull) return hipErrorInvalidValue;
     a.chunks = int(chunks);
     a.chunk = a.rest / chunks;
+    // pairs of neighbouring amplitudes when bit 0 is not listed, every
+    // chunk is even and the state is 16-byte aligned
+    const bool pair = dtype == QC_C64 && a.pos[0] >= 1 && (a.chunk % 2) == 0 &&
+                      (reinterpret_cast<uintptr_t>(amp) & 15) == 0;
     const int tok = timer_begin("probs_marginal", s);
-    if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_probs_marginal<float>), dim3(unsigned(bins * chunks)), dim3(kBlock),
-                           0, s, static_cast<const cx<float> *>(amp), a, work);
+    if (dtype == QC_C64 && pair)
+        hipLaunchKernelGGL((k_probs_marginal<float, true>), dim3(unsigned(bins * chunks)),
+                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, work);
+    else if (dtype == QC_C64)
+        hipLaunchKernelGGL((k_probs_marginal<float, false>), dim3(unsigned(bins * chunks)),
+                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, work);
     else
-        hipLaunchKernelGGL((k_probs_marginal<double>), dim3(unsigned(bins * chunks)),
+        hipLaunchKernelGGL((k_probs_marginal<double, false>), dim3(unsigned(bins * chunks)),
                            dim3(kBlock), 0, s, static_cast<const cx<double> *>(amp), a, work);
     hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(bins)), dim3(kBlock), 0, s, work, int(bins),
                        int(chunks), out);
