@@ -310,7 +310,7 @@ int qc_batch_destroy(qc_batch_t *b);
 /* ---- autotuning ----------------------------------------------------- */
 
 /* Launch-shape knobs (process-wide; the defaults suit MI355X). */
-#define QC_KNOB_MFMA_WG_PER_CU 1   /* persistent workgroups per CU, fused MFMA kernel (1..5) */
+#define QC_KNOB_MFMA_WG_PER_CU 1   /* fused MFMA kernel: 32 KiB tile slots per CU (1..5; a 64 KiB workgroup takes two) */
 #define QC_KNOB_TILE_WG_PER_CU 2   /* workgroups per CU, LDS tile-run kernel (1..16)        */
 #define QC_KNOB_FUSE_LOOKAHEAD 3   /* fuser: candidates scored with a one-step lookahead
                                       (0..256; 0 or 1 = plain greedy; default 16)          */
