@@ -53,6 +53,22 @@ def load_traffic(n: int):
     return d.get("hbm_bytes_per_launch")
 
 
+def load_mfma(n: int):
+    """Matrix-core utilisation of the fused kernel from committed rocprofv3
+    PMC counters, if they were taken on the current kernel source and size."""
+    path = os.path.join(PROFILES, "fused_mfma_c64_brickwork32_mfma.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash() or d.get("n_qubits") != n:
+        return None
+    return {"busy_pct": d.get("mfma_busy_pct"), "fp32_tflops": d.get("fp32_matrix_tflops"),
+            "frac_of_fp32_peak": round(d.get("fp32_matrix_tflops") / 157.3, 4)}
+
+
 def cpu_baseline(n_cpu: int, layers: int, budget_s: float):
     """The FP64 oracle on the host on a bounded sample of the same circuit
     family: the first gates of the brickwork circuit at n_cpu qubits, run
@@ -369,6 +385,7 @@ def main() -> int:
             "frac_of_copy_ceiling": (round(achieved / copy["GBps"], 4)
                                      if (achieved and copy) else None),
             "traffic": traffic,
+            "mfma": load_mfma(n),
             "launches": cnt,
             "avg_launch_ms": round(avg_launch_ms, 4),
             "algorithmic_bytes_per_launch": per_launch_bytes,
