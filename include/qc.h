@@ -314,6 +314,9 @@ int qc_batch_destroy(qc_batch_t *b);
 #define QC_KNOB_TILE_WG_PER_CU 2   /* workgroups per CU, LDS tile-run kernel (1..16)        */
 #define QC_KNOB_FUSE_LOOKAHEAD 3   /* fuser: candidates scored with a one-step lookahead
                                       (0..256; 0 or 1 = plain greedy; default 16)          */
+#define QC_KNOB_MFMA_TILE_BITS 4   /* fused MFMA kernel tile: 13 = 32 x 256 amplitudes (2 KiB
+                                      contiguous runs, used when n >= 13 + outer selector
+                                      qubits), 12 = 32 x 128 (1 KiB runs); default 13      */
 int qc_set_knob(int knob, int value);
 int qc_get_knob(int knob, int *value);
 
@@ -323,13 +326,17 @@ typedef struct {
     int32_t mfma_wg_per_cu;  /* knob value used                    */
     int32_t sweeps;          /* state sweeps of the strategy       */
     float   ms;              /* median time of one run             */
+    int32_t mfma_tile_bits;  /* QC_KNOB_MFMA_TILE_BITS value used  */
 } qc_tune_entry_t;
 
 /* Time every execution strategy for this gate list on `scratch` (its
  * contents are overwritten: each run starts from |0...0>), `reps` timed
- * runs after one warm-up each, and report them fastest first.  Writes at
- * most max_entries entries, their count to *n_entries; the knobs are left
- * at the fastest entry's values.  Host-synchronous. */
+ * runs after one warm-up each, and report them fastest first.  Strategies:
+ * unfused, LDS tile runs, fused k = 2..5, and for complex64 k = 5 every
+ * matrix-core tile shape (QC_KNOB_MFMA_TILE_BITS) with its workgroup
+ * counts (QC_KNOB_MFMA_WG_PER_CU).  Writes at most max_entries entries,
+ * their count to *n_entries; the knobs are left at the fastest entry's
+ * values.  Host-synchronous. */
 int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int reps,
                 qc_tune_entry_t *entries, int max_entries, int *n_entries, void *stream);
 

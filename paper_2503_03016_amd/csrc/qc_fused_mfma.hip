@@ -378,7 +378,8 @@ hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const flo
     // 2 KiB contiguous runs (2^13-amplitude tiles) when the register allows,
     // else 1 KiB runs (2^12-amplitude tiles)
     MfmaArgs<8> a8{};
-    if (mfma_args<8>(n, g, a8)) return launch_c<8>(amp, a_dev, a8, s);
+    if (knob(QC_KNOB_MFMA_TILE_BITS) == 13 && mfma_args<8>(n, g, a8))
+        return launch_c<8>(amp, a_dev, a8, s);
     MfmaArgs<7> a7{};
     if (mfma_args<7>(n, g, a7)) return launch_c<7>(amp, a_dev, a7, s);
     return hipErrorInvalidValue;

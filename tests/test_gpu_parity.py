@@ -162,19 +162,36 @@ def test_apply_fused_k_random_qubits(qc, dt, k):
         check(host(t), oracle.apply(psi0, qs, u), DT[dt], ngates=4)
 
 
+@pytest.mark.parametrize("tile_bits", [13, 12])
 @pytest.mark.parametrize("n", [12, 13, 16, 20])
-def test_fused_mfma_target_positions(qc, n):
+def test_fused_mfma_target_positions(qc, n, tile_bits):
     """The complex64 matrix-core path for every kind of target placement:
-    all-low bits, all-high bits, mixed, reversed order, a single tile."""
-    rng = np.random.default_rng(n)
-    psi0 = W.random_state(n, 1000 + n)
-    cases = [list(range(n - 5, n)), list(range(5)), [n - 1, 0, n // 2, 2, n - 3],
-             list(reversed(range(n - 5, n))), list(rng.permutation(n)[:5])]
-    for qs in cases:
-        u = random_unitary(32, rng)
-        t = dev(psi0, torch.complex64)
-        qc.apply_fused_k(t, qs, u)
-        check(host(t), oracle.apply(psi0, qs, u), torch.complex64, ngates=8)
+    all-low bits, all-high bits, mixed, reversed order, a single tile; both
+    tile shapes (13: 32 x 256, used from 13 qubits; 12: 32 x 128), and
+    multiplexed blocks with selectors in and above the tile."""
+    old = qc.get_knob(qc.QC_KNOB_MFMA_TILE_BITS)
+    qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, tile_bits)
+    try:
+        rng = np.random.default_rng(n)
+        psi0 = W.random_state(n, 1000 + n)
+        cases = [list(range(n - 5, n)), list(range(5)), [n - 1, 0, n // 2, 2, n - 3],
+                 list(reversed(range(n - 5, n))), list(rng.permutation(n)[:5])]
+        for qs in cases:
+            u = random_unitary(32, rng)
+            t = dev(psi0, torch.complex64)
+            qc.apply_fused_k(t, qs, u)
+            check(host(t), oracle.apply(psi0, qs, u), torch.complex64, ngates=8)
+        if n >= 14:
+            layouts = [(list(range(5)), [n - 6, n - 7]),           # selectors among the columns
+                       (list(range(n - 5, n)), [0, 1]),            # selectors above the tile
+                       ([1, 2, 3, 4, 5], [n - 6, 0])]              # one of each
+            for qs, sel in layouts:
+                us = np.stack([random_unitary(32, rng) for _ in range(1 << len(sel))])
+                t = dev(psi0, torch.complex64)
+                qc.apply_multiplexed(t, qs, sel, us)
+                check(host(t), mux_oracle(psi0, qs, sel, us), torch.complex64, ngates=8)
+    finally:
+        qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, old)
 
 
 def mux_oracle(psi, qs, sel, us):
