@@ -10,7 +10,6 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
