@@ -86,6 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
     extern __shared__ unsigned char smem[];
     __shared__ double acc[kAdjointMaxSlots];
     __shared__ double red[kWaves];
+    __shared__ TileOp op_slot[2];
+    __shared__ cx<R> ptab[1 << kPhaseTableBits];
     const int T = 1 << a.m;
     cx<R> *lp = reinterpret_cast<cx<R> *>(smem);
     cx<R> *ll = lp + T;
@@ -100,29 +102,38 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             lp[j] = phi[at];
             ll[j] = lam[at];
         }
+        // ops are staged through LDS as in tile::apply_ops
+        if (a.n_ops > 0) tile::stage_now(&op_slot[0], &ops[0]);
         __syncthreads();
         for (int o = 0; o < a.n_ops; ++o) {
-            const TileOp &op = ops[o];
-            if ((base & op.cmask_hi) != op.cval_hi) continue;   // uniform per tile
-            if (op.kind == TILE_GRAD) {
-                double v = wave_sum(grad_partial<R>(lp, ll, a.m, op.b0, op.b1));
-                if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    double s = 0.0;
-                    for (int w = 0; w < kWaves; ++w) s += red[w];
-                    acc[op.pad] += s;
+            const TileOp &op = op_slot[o & 1];
+            const bool next = o + 1 < a.n_ops;
+            tile::OpStage st;
+            if (next) tile::stage_fetch(st, &ops[o + 1]);
+            if ((base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
+                if (op.kind == TILE_GRAD) {
+                    double v = wave_sum(grad_partial<R>(lp, ll, a.m, op.b0, op.b1));
+                    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        double s = 0.0;
+                        for (int w = 0; w < kWaves; ++w) s += red[w];
+                        acc[op.pad] += s;
+                    }
+                } else if (op.kind == TILE_PHASES) {
+                    const bool any = tile::phases_table<R>(ptab, base, op);   // uniform
+                    __syncthreads();
+                    if (any) {
+                        tile::phases_apply<R>(lp, a.m, ptab, uint32_t(op.b1));
+                        tile::phases_apply<R>(ll, a.m, ptab, uint32_t(op.b1));
+                    }
+                } else {
+                    tile::apply_one<R>(lp, a.m, op);
+                    tile::apply_one<R>(ll, a.m, op);
                 }
-                __syncthreads();
-            } else if (op.kind == TILE_PHASES) {
-                tile::apply_phases<R>(lp, a.m, base, op);
-                tile::apply_phases<R>(ll, a.m, base, op);
-                __syncthreads();
-            } else {
-                tile::apply_one<R>(lp, a.m, op);
-                tile::apply_one<R>(ll, a.m, op);
-                __syncthreads();
             }
+            if (next) tile::stage_store(st, &op_slot[(o + 1) & 1]);
+            __syncthreads();
         }
         for (int j = threadIdx.x; j < T; j += kBlock) {
             const uint64_t at = base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m);

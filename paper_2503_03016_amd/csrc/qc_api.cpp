@@ -888,6 +888,7 @@ struct TileOpBuilder {
         } else if (nph > 1) {
             ph.kind = qcx::TILE_PHASES;
             ph.b0 = nph;
+            ph.b1 = int32_t(ph_bits);
             out.push_back(ph);
         }
         ph = qcx::TileOp{};
@@ -895,9 +896,13 @@ struct TileOpBuilder {
         ph_bits = 0;
     }
     // one diagonal term: multiply by `phase` where the conditions hold
+    // (a term testing more than kPhaseTableBits tile bits becomes a
+    // single-term TILE_PHASE op of its own)
     void add_phase(uint32_t mlo, uint32_t vlo, uint64_t mhi, uint64_t vhi, cd phase) {
         flush_bits(mlo);
-        if (nph == qcx::kTilePhaseTerms) emit_phases();
+        if (nph == qcx::kTilePhaseTerms ||
+            __builtin_popcount(ph_bits | mlo) > qcx::kPhaseTableBits)
+            emit_phases();
         ph.pm_lo[nph] = mlo;
         ph.pv_lo[nph] = vlo;
         ph.pm_hi[nph] = mhi;
@@ -906,6 +911,7 @@ struct TileOpBuilder {
         ph.u[2 * nph + 1] = phase.imag();
         ++nph;
         ph_bits |= mlo;
+        if (__builtin_popcount(mlo) > qcx::kPhaseTableBits) emit_phases();
     }
     void add_op(const qcx::TileOp &op, uint32_t touched) {
         flush_bits(touched);

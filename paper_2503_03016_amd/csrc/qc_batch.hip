@@ -102,7 +102,7 @@ __device__ double tile_energy(const cx<R> *lds, int m, uint64_t base, const Batc
 // Run circuit c with `G` cooperating workgroups (this one has rank `rank`).
 template <typename R>
 __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *lds, double *red,
-                            unsigned *bar, unsigned &gen) {
+                            TileOp *op_slot, unsigned *bar, unsigned &gen) {
     const BatchCircuit C = a.circ[c];
     cx<R> *state = static_cast<cx<R> *>(a.arena) + C.arena_off;
     double acc = 0.0;
@@ -130,7 +130,7 @@ __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *l
                 }
             }
             __syncthreads();
-            tile::apply_ops<R>(lds, P.m, base, a.ops + P.op_begin, P.op_count);
+            tile::apply_ops<R>(lds, P.m, base, a.ops + P.op_begin, P.op_count, op_slot);
             if (P.term_count) acc += tile_energy<R>(lds, P.m, base, a.terms + P.term_begin,
                                                     P.term_count);
             if (P.flags & BATCH_STORE)
@@ -163,6 +163,7 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
     extern __shared__ unsigned char smem[];
     __shared__ double red[kWaves];
+    __shared__ TileOp op_slot[2];
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
     // groups of G workgroups, members on one XCD under round-robin dispatch
     const unsigned G = unsigned(a.G);
@@ -177,9 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
         if (job.kind == 0) {
             const int c = job.circ[rank];
             unsigned g0 = 0;
-            if (c >= 0) run_circuit<R>(a, c, 0, 1, lds, red, bar, g0);
+            if (c >= 0) run_circuit<R>(a, c, 0, 1, lds, red, op_slot, bar, g0);
         } else {
-            run_circuit<R>(a, job.circ[0], int(rank), int(G), lds, red, bar, gen);
+            run_circuit<R>(a, job.circ[0], int(rank), int(G), lds, red, op_slot, bar, gen);
         }
         group_barrier(bar, G, gen, a.error);
     }

@@ -97,12 +97,14 @@ struct Mat2d {
 // TILE_PHASES: b0 diagonal terms; amplitude i of the tile is multiplied by
 // the product of phase t (u[2t], u[2t+1]) over the terms whose conditions
 // hold: (i & pm_lo[t]) == pv_lo[t] and (tile_base & pm_hi[t]) == pv_hi[t].
+// b1 = the union of the pm_lo masks (at most 8 tile bits).
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5
 };
 constexpr int kTileMaxBits = 16;
 constexpr int kTilePhaseTerms = 16;
+constexpr int kPhaseTableBits = 8;   // in-tile bits a TILE_PHASES op may test
 struct TileOp {
     int32_t kind;
     int32_t b0, b1;            // targets (b0 = most significant bit of the local index)

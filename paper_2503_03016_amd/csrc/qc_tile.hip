@@ -23,6 +23,7 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs a,
                                                      const TileOp *ops) {
     extern __shared__ unsigned char smem[];
+    __shared__ TileOp op_slot[2];
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
     const int T = 1 << a.m;
     // the low 8 compressed bits of this thread's elements are fixed
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
         for (int j = threadIdx.x; j < T; j += kBlock)
             lds[j] = amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)];
         __syncthreads();
-        tile::apply_ops<R>(lds, a.m, base, ops, a.n_ops);
+        tile::apply_ops<R>(lds, a.m, base, ops, a.n_ops, op_slot);
         for (int j = threadIdx.x; j < T; j += kBlock)
             amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)] = lds[j];
         __syncthreads();

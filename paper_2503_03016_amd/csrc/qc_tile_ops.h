@@ -137,53 +137,139 @@ __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
     }
 }
 
-// TILE_PHASES: product of the diagonal terms whose conditions hold.
+// TILE_PHASES: product of the diagonal terms whose conditions hold.  All
+// in-tile conditions of an op lie in the bit set U = op.b1 (at most
+// kPhaseTableBits bits, enforced when the op is built), so the phase of an
+// amplitude depends only on its bits in U: a table of 2^|U| products is
+// built once per op (one entry per thread) and every amplitude then takes
+// one table lookup and one complex product.
+// compact the bits of i that lie in mask u (ascending) into the low bits
+__device__ inline uint32_t extract_bits(uint32_t i, uint32_t u) {
+    uint32_t e = 0, k = 0;
+    while (u) {
+        const uint32_t b = uint32_t(__builtin_ctz(u));
+        e |= ((i >> b) & 1u) << k;
+        ++k;
+        u &= u - 1;
+    }
+    return e;
+}
+// inverse of extract_bits: spread the low bits of e over the positions of u
+__device__ inline uint32_t deposit_bits(uint32_t e, uint32_t u) {
+    uint32_t i = 0, k = 0;
+    while (u) {
+        const uint32_t b = uint32_t(__builtin_ctz(u));
+        i |= ((e >> k) & 1u) << b;
+        ++k;
+        u &= u - 1;
+    }
+    return i;
+}
+
+// Fill `tab` (2^|U| entries, LDS) for op; returns false when no term is
+// live for this tile (the op is the identity there).  Caller syncs before
+// using the table.
 template <typename R>
-__device__ inline void apply_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op) {
-    const int T = 1 << m;
+__device__ inline bool phases_table(cx<R> *tab, uint64_t tile_base, const TileOp &op) {
     const int nt = op.b0;
+    const uint32_t U = uint32_t(op.b1);
     uint32_t live = 0;   // terms whose out-of-tile conditions hold for this tile
     for (int t = 0; t < nt; ++t)
         if ((tile_base & op.pm_hi[t]) == op.pv_hi[t]) live |= 1u << t;
-    if (!live) return;
+    if (!live) return false;
+    const int entries = 1 << __builtin_popcount(U);
+    for (int e = threadIdx.x; e < entries; e += kBlock) {
+        const uint32_t i = deposit_bits(uint32_t(e), U);
+        cx<R> f{R(1), R(0)};
+        for (int t = 0; t < nt; ++t)
+            if (((live >> t) & 1) && (i & op.pm_lo[t]) == op.pv_lo[t]) f = cmul(f, ld_u<R>(op.u, t));
+        tab[e] = f;
+    }
+    return true;
+}
+
+// Multiply every amplitude of the tile by its table entry.
+template <typename R>
+__device__ inline void phases_apply(cx<R> *lds, int m, const cx<R> *tab, uint32_t U) {
+    const int T = 1 << m;
+    // element i = threadIdx.x + kBlock j: the low kLoBits bits are the thread's
+    const uint32_t e_lo = extract_bits(threadIdx.x & (kBlock - 1), U & (kBlock - 1));
+    const uint32_t U_hi = U >> kLoBits;
+    const int lo_count = __builtin_popcount(U & (kBlock - 1));
     for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
-        // terms outer, items inner: one (uniform) fetch of a term's masks and
-        // phase serves all items of the thread
-        cx<R> f[kItems];
-        uint32_t hit = 0;
+        cx<R> v[kItems], f[kItems];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) f[k] = cx<R>{R(1), R(0)};
-#pragma unroll 4
-        for (int t = 0; t < nt; ++t) {
-            if (!((live >> t) & 1)) continue;
-            const uint32_t pm = op.pm_lo[t], pv = op.pv_lo[t];
-            const cx<R> ph = ld_u<R>(op.u, t);
-#pragma unroll
-            for (int k = 0; k < kItems; ++k) {
-                const bool on = ((uint32_t(i0 + k * kBlock) & pm) == pv);
-                const cx<R> g = cmul(f[k], ph);
-                f[k].re = on ? g.re : f[k].re;
-                f[k].im = on ? g.im : f[k].im;
-                hit |= uint32_t(on) << k;
+        for (int k = 0; k < kItems; ++k) {
+            const int i = i0 + k * kBlock;
+            if (i < T) {
+                const uint32_t e = e_lo | (extract_bits(uint32_t(i) >> kLoBits, U_hi) << lo_count);
+                v[k] = lds[i];
+                f[k] = tab[e];
             }
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int i = i0 + k * kBlock;
-            if (i < T && ((hit >> k) & 1)) lds[i] = cmul(f[k], lds[i]);
+            if (i < T) lds[i] = cmul(f[k], v[k]);
         }
     }
 }
 
-// Apply a run of ops, one workgroup barrier per op.
+template <typename R>
+__device__ inline void apply_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op) {
+    __shared__ cx<R> tab[1 << kPhaseTableBits];
+    const bool any = phases_table<R>(tab, tile_base, op);   // uniform
+    __syncthreads();
+    if (any) phases_apply<R>(lds, m, tab, uint32_t(op.b1));
+}
+
+// Op staging: the op being applied is read from one of two LDS slots.
+// While op o runs, the first kOpWords lanes hold op o + 1 in registers
+// (a global load issued before op o starts) and write it to the other slot
+// right before op o's closing barrier, so the fetch latency of the op list
+// is hidden behind the work and every thread reads op fields (matrix
+// entries, phase terms) from LDS.
+constexpr int kOpWords = int(sizeof(TileOp) / sizeof(uint64_t));
+static_assert(sizeof(TileOp) % sizeof(uint64_t) == 0, "TileOp is copied in 8-byte words");
+static_assert(kOpWords <= kBlock, "one word per thread");
+
+struct OpStage {
+    uint64_t word = 0;
+};
+
+// Copy op `src` into `dst` (LDS) now; the caller places the barrier.
+__device__ inline void stage_now(TileOp *dst, const TileOp *src) {
+    if (threadIdx.x < kOpWords)
+        reinterpret_cast<uint64_t *>(dst)[threadIdx.x] =
+            reinterpret_cast<const uint64_t *>(src)[threadIdx.x];
+}
+// Start fetching op `src` (no wait).
+__device__ inline void stage_fetch(OpStage &st, const TileOp *src) {
+    if (threadIdx.x < kOpWords) st.word = reinterpret_cast<const uint64_t *>(src)[threadIdx.x];
+}
+// Store a fetched op into `dst` (LDS); the caller places the barrier.
+__device__ inline void stage_store(const OpStage &st, TileOp *dst) {
+    if (threadIdx.x < kOpWords) reinterpret_cast<uint64_t *>(dst)[threadIdx.x] = st.word;
+}
+
+// Apply a run of ops, one workgroup barrier per op.  `slot` is 2 TileOps of
+// LDS owned by the caller's workgroup.
 template <typename R>
 __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const TileOp *ops,
-                                 int n_ops) {
+                                 int n_ops, TileOp *slot) {
+    if (n_ops <= 0) return;
+    stage_now(&slot[0], &ops[0]);
+    __syncthreads();
     for (int o = 0; o < n_ops; ++o) {
-        const TileOp &op = ops[o];
-        if ((tile_base & op.cmask_hi) != op.cval_hi) continue;   // uniform per tile
-        if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op);
-        else apply_one<R>(lds, m, op);
+        const TileOp &op = slot[o & 1];
+        const bool next = o + 1 < n_ops;
+        OpStage st;
+        if (next) stage_fetch(st, &ops[o + 1]);
+        if ((tile_base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
+            if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op);
+            else apply_one<R>(lds, m, op);
+        }
+        if (next) stage_store(st, &slot[(o + 1) & 1]);
         __syncthreads();
     }
 }
