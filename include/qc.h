@@ -317,6 +317,8 @@ int qc_batch_destroy(qc_batch_t *b);
 #define QC_KNOB_MFMA_TILE_BITS 4   /* fused MFMA kernel tile: 13 = 32 x 256 amplitudes (2 KiB
                                       contiguous runs, used when n >= 13 + outer selector
                                       qubits), 12 = 32 x 128 (1 KiB runs); default 13      */
+#define QC_KNOB_TILE_BITS 5        /* QC_EXEC_TILED tile size cap, 2^value amplitudes (6..13;
+                                      complex128 tiles stop at 12; default 13)             */
 int qc_set_knob(int knob, int value);
 int qc_get_knob(int knob, int *value);
 
@@ -327,14 +329,16 @@ typedef struct {
     int32_t sweeps;          /* state sweeps of the strategy       */
     float   ms;              /* median time of one run             */
     int32_t mfma_tile_bits;  /* QC_KNOB_MFMA_TILE_BITS value used  */
+    int32_t tile_bits;       /* QC_KNOB_TILE_BITS value used       */
 } qc_tune_entry_t;
 
 /* Time every execution strategy for this gate list on `scratch` (its
  * contents are overwritten: each run starts from |0...0>), `reps` timed
  * runs after one warm-up each, and report them fastest first.  Strategies:
- * unfused, LDS tile runs, fused k = 2..5, and for complex64 k = 5 every
- * matrix-core tile shape (QC_KNOB_MFMA_TILE_BITS) with its workgroup
- * counts (QC_KNOB_MFMA_WG_PER_CU).  Writes at most max_entries entries,
+ * unfused, LDS tile runs at three tile sizes (QC_KNOB_TILE_BITS), fused
+ * k = 2..5, and for complex64 k = 5 every matrix-core tile shape
+ * (QC_KNOB_MFMA_TILE_BITS) with its workgroup counts
+ * (QC_KNOB_MFMA_WG_PER_CU).  Writes at most max_entries entries,
  * their count to *n_entries; the knobs are left at the fastest entry's
  * values.  Host-synchronous. */
 int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int reps,

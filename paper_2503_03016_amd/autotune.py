@@ -1,6 +1,6 @@
 """Autotuner front end: picks the execution strategy (unfused, LDS tile
-runs, fused k = 2..5), the matrix-core kernel's tile shape and its
-workgroups per CU for a circuit family by timing them with qc_autotune, and
+runs and their tile size, fused k = 2..5), the matrix-core kernel's tile
+shape and its workgroups per CU for a circuit family by timing them with qc_autotune, and
 caches the choice in a JSON file keyed by device, qubit count, element type
 and circuit signature.
 
@@ -80,5 +80,7 @@ def apply_tuned(psi: torch.Tensor, gate_tuples, family: Optional[str] = None) ->
         qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, cfg["mfma_wg_per_cu"])
     if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_tile_bits") in (12, 13):
         qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, cfg["mfma_tile_bits"])
+    if cfg["mode"] == qc.QC_EXEC_TILED and cfg.get("tile_bits"):
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, cfg["tile_bits"])
     return qc.apply_circuit(psi, qc.GateList(gate_tuples), mode=cfg["mode"],
                             fuse_k=cfg["fuse_k"] or 5)

@@ -109,6 +109,7 @@ std::atomic<int> g_knob_mfma{4};
 std::atomic<int> g_knob_tile{8};
 std::atomic<int> g_knob_look{16};
 std::atomic<int> g_knob_tbits{13};
+std::atomic<int> g_knob_tile_bits{13};
 
 // ---------------------------------------------------------------- validation
 
@@ -496,6 +497,7 @@ int knob(int which) {
     case QC_KNOB_MFMA_WG_PER_CU: return g_knob_mfma.load();
     case QC_KNOB_TILE_WG_PER_CU: return g_knob_tile.load();
     case QC_KNOB_MFMA_TILE_BITS: return g_knob_tbits.load();
+    case QC_KNOB_TILE_BITS: return g_knob_tile_bits.load();
     default: return g_knob_look.load();
     }
 }
@@ -598,13 +600,19 @@ int qc_set_knob(int knob, int value) {
         g_knob_tbits.store(value);
         return QC_OK;
     }
+    if (knob == QC_KNOB_TILE_BITS) {
+        if (value < 6 || value > 13) return fail(QC_ERR_ARG, "tile bits must be 6..13");
+        g_knob_tile_bits.store(value);
+        return QC_OK;
+    }
     return fail(QC_ERR_ARG, "unknown knob");
 }
 
 int qc_get_knob(int knob, int *value) {
     if (!value) return fail(QC_ERR_ARG, "NULL argument");
     if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU &&
-        knob != QC_KNOB_FUSE_LOOKAHEAD && knob != QC_KNOB_MFMA_TILE_BITS)
+        knob != QC_KNOB_FUSE_LOOKAHEAD && knob != QC_KNOB_MFMA_TILE_BITS &&
+        knob != QC_KNOB_TILE_BITS)
         return fail(QC_ERR_ARG, "unknown knob");
     *value = qcx::knob(knob);
     return QC_OK;
@@ -1001,7 +1009,11 @@ void tile_ops_for(int n, const qc_gate_t *gs, const std::vector<int> &idx, uint6
     B.finish();
 }
 
-int tile_bits_for(const qc_state_t &s) { return std::min(s.n, s.dtype == QC_C64 ? 13 : 12); }
+// LDS tile of the tile-run kernel: at most 64 KiB (2^13 complex64 or 2^12
+// complex128 amplitudes), capped by QC_KNOB_TILE_BITS and by n.
+int tile_bits_for(const qc_state_t &s) {
+    return std::min({s.n, s.dtype == QC_C64 ? 13 : 12, g_knob_tile_bits.load()});
+}
 
 // Greedy run formation: starting from the earliest pending gate, a gate
 // joins the run when none of its qubits is held by an earlier gate left out
@@ -1963,20 +1975,26 @@ int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int rep
     if (n_gates < 1 || !gates) return fail(QC_ERR_ARG, "empty gate list");
     for (int i = 0; i < n_gates; ++i)
         if ((rc = check_gate(scratch.n, gates[i]))) return rc;
-    struct Cand { int mode, k, wg, tbits; };
-    std::vector<Cand> cands{{QC_EXEC_UNFUSED, 0, 0, 0}, {QC_EXEC_TILED, 0, 0, 0}};
+    struct Cand { int mode, k, wg, tbits, tile_bits; };
+    std::vector<Cand> cands{{QC_EXEC_UNFUSED, 0, 0, 0, 0}};
+    {
+        const int top = scratch.dtype == QC_C64 ? 13 : 12;
+        for (int m = top; m >= top - 2; --m)
+            if (m <= scratch.n || m == top) cands.push_back({QC_EXEC_TILED, 0, 0, 0, m});
+    }
     for (int k = 2; k <= std::min(QC_MAX_FUSED, scratch.n); ++k) {
         if (scratch.dtype == QC_C64 && k == 5 && scratch.n >= 12) {
-            for (int wg = 2; wg <= 5; ++wg) cands.push_back({QC_EXEC_FUSED, 5, wg, 12});
+            for (int wg = 2; wg <= 5; ++wg) cands.push_back({QC_EXEC_FUSED, 5, wg, 12, 0});
             // 64 KiB workgroups: the knob's tile slots give 1 or 2 per CU
             if (scratch.n >= 13)
-                for (int wg = 2; wg <= 4; wg += 2) cands.push_back({QC_EXEC_FUSED, 5, wg, 13});
+                for (int wg = 2; wg <= 4; wg += 2) cands.push_back({QC_EXEC_FUSED, 5, wg, 13, 0});
         } else {
-            cands.push_back({QC_EXEC_FUSED, k, 0, 0});
+            cands.push_back({QC_EXEC_FUSED, k, 0, 0, 0});
         }
     }
     const int saved_wg = g_knob_mfma.load();
     const int saved_tbits = g_knob_tbits.load();
+    const int saved_tile_bits = g_knob_tile_bits.load();
     const hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -1985,6 +2003,7 @@ int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int rep
     for (const Cand &c : cands) {
         if (c.wg) g_knob_mfma.store(c.wg);
         if (c.tbits) g_knob_tbits.store(c.tbits);
+        g_knob_tile_bits.store(c.tile_bits ? c.tile_bits : saved_tile_bits);
         qc_exec_stats_t st{};
         std::vector<float> t;
         for (int r = 0; r <= reps && rc == QC_OK; ++r) {
@@ -2005,6 +2024,7 @@ int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int rep
         e.fuse_k = c.k;
         e.mfma_wg_per_cu = c.wg ? c.wg : saved_wg;
         e.mfma_tile_bits = c.tbits ? c.tbits : saved_tbits;
+        e.tile_bits = c.tile_bits ? c.tile_bits : saved_tile_bits;
         e.sweeps = int32_t(st.sweeps);
         e.ms = t[t.size() / 2];
         out.push_back(e);
@@ -2013,12 +2033,14 @@ int qc_autotune(qc_state_t scratch, int n_gates, const qc_gate_t *gates, int rep
     (void)hipEventDestroy(e1);
     g_knob_mfma.store(saved_wg);
     g_knob_tbits.store(saved_tbits);
+    g_knob_tile_bits.store(saved_tile_bits);
     if (rc) return rc;
     std::stable_sort(out.begin(), out.end(),
                      [](const qc_tune_entry_t &a, const qc_tune_entry_t &b) { return a.ms < b.ms; });
     if (!out.empty()) {
         g_knob_mfma.store(out[0].mfma_wg_per_cu);
         g_knob_tbits.store(out[0].mfma_tile_bits);
+        g_knob_tile_bits.store(out[0].tile_bits);
     }
     const int n = std::min<int>(int(out.size()), max_entries);
     for (int i = 0; i < n; ++i) entries[i] = out[i];

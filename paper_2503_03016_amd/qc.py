@@ -33,7 +33,8 @@ EXPORTS = [
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
     "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune",
 ]
-QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD, QC_KNOB_MFMA_TILE_BITS = 1, 2, 3, 4
+(QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD, QC_KNOB_MFMA_TILE_BITS,
+ QC_KNOB_TILE_BITS) = 1, 2, 3, 4, 5
 
 
 class QcError(RuntimeError):
@@ -72,7 +73,8 @@ class QcCircuit(ctypes.Structure):
 class QcTuneEntry(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32),
                 ("mfma_wg_per_cu", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("mfma_tile_bits", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("mfma_tile_bits", ctypes.c_int32),
+                ("tile_bits", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -230,12 +230,14 @@ def test_apply_multiplexed(qc, dt, n, k, c):
 
 # ---------------------------------------------------------------- circuits
 
+@pytest.mark.parametrize("tile_bits", [13, 10, 7])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n", [6, 13, 17])
-def test_tiled_runs_mixed_gates(qc, G, dt, n):
+def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
     """LDS tile runs: dense 1q/2q gates, diagonal gates on bits inside and
     outside the tile, controls inside and outside the tile, open controls,
-    gates that cannot join a run (3-qubit), across several tiles."""
+    gates that cannot join a run (3-qubit), across several tiles; at the
+    default tile size and two smaller ones (QC_KNOB_TILE_BITS)."""
     rng = np.random.default_rng(n)
     ops = []
     for _ in range(60):
@@ -260,7 +262,12 @@ def test_tiled_runs_mixed_gates(qc, G, dt, n):
     psi0 = W.random_state(n, 50 + n)
     ref = oracle.run(ops, psi0)
     t = dev(psi0, DT[dt])
-    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=2)
+    old = qc.get_knob(qc.QC_KNOB_TILE_BITS)
+    qc.set_knob(qc.QC_KNOB_TILE_BITS, tile_bits)
+    try:
+        st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=2)
+    finally:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
     assert st["sweeps"] < len(ops)
     check(host(t), ref, DT[dt], ngates=len(ops))
 
