@@ -78,6 +78,33 @@ __device__ inline double grad_partial(const cx<R> *f, const cx<R> *l, int m, int
     return acc;
 }
 
+// grad_partial, then (u on bit b) applied to both tiles in the same pass.
+template <typename R>
+__device__ inline double grad_partial_apply(cx<R> *f, cx<R> *l, int m, int b, int gen,
+                                            const double *u) {
+    const cx<R> u0 = tile::ld_u<R>(u, 0), u1 = tile::ld_u<R>(u, 1), u2 = tile::ld_u<R>(u, 2),
+                u3 = tile::ld_u<R>(u, 3);
+    const cx<R> z{R(0), R(0)};
+    double acc = 0.0;
+    for (int g = threadIdx.x; g < (1 << (m - 1)); g += kBlock) {
+        const uint32_t i0 = uint32_t(insert_zero(uint64_t(g), b)), i1 = i0 | (1u << b);
+        const cx<R> f0 = f[i0], f1 = f[i1], l0 = l[i0], l1 = l[i1];
+        const double f0r = f0.re, f0i = f0.im, f1r = f1.re, f1i = f1.im;
+        const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+        if (gen == 3)
+            acc += (l0r * f0i - l0i * f0r) - (l1r * f1i - l1i * f1r);
+        else if (gen == 1)
+            acc += (l0r * f1i - l0i * f1r) + (l1r * f0i - l1i * f0r);
+        else
+            acc += -(l0r * f1r + l0i * f1i) + (l1r * f0r + l1i * f0i);
+        f[i0] = cfma(u1, f1, cfma(u0, f0, z));
+        f[i1] = cfma(u3, f1, cfma(u2, f0, z));
+        l[i0] = cfma(u1, l1, cfma(u0, l0, z));
+        l[i1] = cfma(u3, l1, cfma(u2, l0, z));
+    }
+    return acc;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
                                                           const TileOp *ops,
@@ -111,8 +138,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             tile::OpStage st;
             if (next) tile::stage_fetch(st, &ops[o + 1]);
             if ((base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
-                if (op.kind == TILE_GRAD) {
-                    double v = wave_sum(grad_partial<R>(lp, ll, a.m, op.b0, op.b1));
+                if (op.kind == TILE_GRAD || op.kind == TILE_GRAD_APPLY) {
+                    double v = wave_sum(op.kind == TILE_GRAD
+                                            ? grad_partial<R>(lp, ll, a.m, op.b0, op.b1)
+                                            : grad_partial_apply<R>(lp, ll, a.m, op.b0, op.b1, op.u));
                     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
                     __syncthreads();
                     if (threadIdx.x == 0) {

@@ -1583,13 +1583,16 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
                     B.finish();
                     if ((rc = flush(r.P))) return rc;
                 }
+                // the reduction and the inverse rotation share one pass
                 qcx::TileOp gop{};
-                gop.kind = qcx::TILE_GRAD;
+                gop.kind = qcx::TILE_GRAD_APPLY;
                 gop.b0 = B.cidx(bitpos(n, bwd[j].targets[0]));
                 gop.b1 = gen_of[j];
                 gop.pad = int32_t(slot_row.size());
+                for (int i = 0; i < 8; ++i) gop.u[i] = bwd[j].matrix[i];
                 slot_row.push_back(rot_row[j]);
                 B.add_op(gop, 1u << gop.b0);
+                continue;
             }
             B.add_gate(bwd[j]);
         }

@@ -98,9 +98,12 @@ struct Mat2d {
 // the product of phase t (u[2t], u[2t+1]) over the terms whose conditions
 // hold: (i & pm_lo[t]) == pv_lo[t] and (tile_base & pm_hi[t]) == pv_hi[t].
 // b1 = the union of the pm_lo masks (at most 8 tile bits).
+// TILE_GRAD_APPLY (adjoint kernel only): TILE_GRAD on bit b0, then the
+// one-qubit matrix u[0..7] applied to both vectors on the same bit, in one
+// pass over the pairs (the partial uses the values before the update).
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
-    TILE_PHASES = 5
+    TILE_PHASES = 5, TILE_GRAD_APPLY = 6
 };
 constexpr int kTileMaxBits = 16;
 constexpr int kTilePhaseTerms = 16;
