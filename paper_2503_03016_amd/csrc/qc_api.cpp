@@ -1139,6 +1139,40 @@ bool assign_block(int n, const std::vector<const qc_gate_t *> &members, int fuse
     return true;
 }
 
+// QC_EXEC_FUSED: plan the blocks (one-step lookahead over `look`
+// candidates) and launch each block as soon as the planner has chosen it,
+// so the planning of the next block overlaps the device work.  complex64
+// blocks are widened to 5 qubits so that every block runs on the
+// matrix-core kernel (the extra qubits carry identity).
+int fused_execute(qc_state_t s, int n_gates, const qc_gate_t *gates, int fuse_k, int look,
+                  qc_exec_stats_t &st, void *stream) {
+    const hipStream_t hs = (hipStream_t)stream;
+    const double sweep = sweep_bytes(s.n, s.dtype);
+    const bool widen = s.dtype == QC_C64 && fuse_k == 5;
+    int rc = QC_OK;
+    std::vector<const qc_gate_t *> members;
+    fuse_plan_each(s.n, n_gates, gates, fuse_k, qcx::kMaxSel, look,
+                   [&](const std::vector<int> &idx) {
+        members.clear();
+        for (int i : idx) members.push_back(&gates[i]);
+        int bq[QC_MAX_FUSED], sq[qcx::kMaxSel], k = 0, ns = 0;
+        if (!assign_block(s.n, members, fuse_k, widen, bq, k, sq, ns)) {
+            // not expressible as one block (a gate with many controls)
+            for (auto *g : members)
+                if ((rc = apply_gate_unfused(s, *g, st, stream))) return false;
+            return true;
+        }
+        rc = fused_apply(s, k, bq, ns, sq, block_matrices(k, bq, ns, sq, members), hs);
+        if (rc) return false;
+        st.launches += 1;
+        st.sweeps += 1;
+        st.fused_blocks += 1;
+        st.state_bytes += sweep;
+        return true;
+    });
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1205,40 +1239,14 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
         if ((rc = check_gate(s.n, gates[i]))) return rc;
     qc_exec_stats_t st{};
     st.gates = n_gates;
-    const hipStream_t hs = (hipStream_t)stream;
-    const double sweep = sweep_bytes(s.n, s.dtype);
     if (mode == QC_EXEC_UNFUSED) {
         for (int i = 0; i < n_gates; ++i)
             if ((rc = apply_gate_unfused(s, gates[i], st, stream))) return rc;
     } else if (mode == QC_EXEC_TILED) {
         if ((rc = tiled_execute(s, n_gates, gates, st, stream))) return rc;
     } else {
-        // complex64 blocks are widened to 5 qubits so that every block runs
-        // on the matrix-core kernel (the extra qubits carry identity).  Each
-        // block is launched as soon as the planner has chosen it, so the
-        // planning of the next block overlaps the device work.
-        const bool widen = s.dtype == QC_C64 && fuse_k == 5;
-        std::vector<const qc_gate_t *> members;
-        fuse_plan_each(s.n, n_gates, gates, fuse_k, qcx::kMaxSel, g_knob_look.load(),
-                       [&](const std::vector<int> &idx) {
-            members.clear();
-            for (int i : idx) members.push_back(&gates[i]);
-            int bq[QC_MAX_FUSED], sq[qcx::kMaxSel], k = 0, ns = 0;
-            if (!assign_block(s.n, members, fuse_k, widen, bq, k, sq, ns)) {
-                // not expressible as one block (a gate with many controls)
-                for (auto *g : members)
-                    if ((rc = apply_gate_unfused(s, *g, st, stream))) return false;
-                return true;
-            }
-            rc = fused_apply(s, k, bq, ns, sq, block_matrices(k, bq, ns, sq, members), hs);
-            if (rc) return false;
-            st.launches += 1;
-            st.sweeps += 1;
-            st.fused_blocks += 1;
-            st.state_bytes += sweep;
-            return true;
-        });
-        if (rc) return rc;
+        if ((rc = fused_execute(s, n_gates, gates, fuse_k, g_knob_look.load(), st, stream)))
+            return rc;
     }
     if (stats) *stats = st;
     return QC_OK;
@@ -1540,9 +1548,15 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
             extra[n_ops - 1 - k] = uint64_t(1) << bitpos(n, o.q0);   // reduction needs the bit
         }
     }
-    // forward: phi = U_L .. U_1 psi in LDS tile runs
+    // forward: phi = U_L .. U_1 psi; complex64 registers of 12+ qubits in
+    // fused 5-qubit blocks on the matrix cores (plain greedy plan, so host
+    // planning stays short), otherwise in LDS tile runs
     qc_exec_stats_t st{};
-    if ((rc = tiled_execute(psi, n_ops, fwd.data(), st, stream))) return rc;
+    if (psi.dtype == QC_C64 && n >= 12)
+        rc = fused_execute(psi, n_ops, fwd.data(), 5, 1, st, stream);
+    else
+        rc = tiled_execute(psi, n_ops, fwd.data(), st, stream);
+    if (rc) return rc;
     // energy, then lam = H phi
     if ((rc = qc_expect_pauli(psi, n_terms, paulis, coeff, 0, energy_dev, stream))) return rc;
     void *tdev = nullptr;
