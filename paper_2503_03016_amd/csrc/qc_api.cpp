@@ -878,9 +878,37 @@ struct TileOpBuilder {
         out.push_back(op);
         held_bits &= ~(1u << b);
     }
+    // Two held gates on bits a and b: one two-qubit op with the Kronecker
+    // product U_a (x) U_b (local index 2 bit(a) + bit(b)), one pass over
+    // the tile instead of two at the same flops per amplitude.
+    void flush_pair(int a, int b) {
+        const cd *ua = held[a], *ub = held[b];
+        qcx::TileOp op{};
+        op.kind = qcx::TILE_DENSE2;
+        op.b0 = a;
+        op.b1 = b;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                const cd v = ua[2 * (r >> 1) + (c >> 1)] * ub[2 * (r & 1) + (c & 1)];
+                op.u[2 * (4 * r + c)] = v.real();
+                op.u[2 * (4 * r + c) + 1] = v.imag();
+            }
+        out.push_back(op);
+        held_bits &= ~((1u << a) | (1u << b));
+    }
     void flush_bits(uint32_t bits) {
-        for (int b = 0; bits >> b; ++b)
-            if ((bits >> b) & 1) flush_bit(b);
+        bits &= held_bits;
+        int first = -1;
+        for (int b = 0; bits >> b; ++b) {
+            if (!((bits >> b) & 1)) continue;
+            if (first < 0) {
+                first = b;
+            } else {
+                flush_pair(first, b);
+                first = -1;
+            }
+        }
+        if (first >= 0) flush_bit(first);
     }
     void emit_phases() {
         if (nph == 1) {
@@ -1548,15 +1576,10 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
             extra[n_ops - 1 - k] = uint64_t(1) << bitpos(n, o.q0);   // reduction needs the bit
         }
     }
-    // forward: phi = U_L .. U_1 psi; complex64 registers of 12+ qubits in
-    // fused 5-qubit blocks on the matrix cores (plain greedy plan, so host
-    // planning stays short), otherwise in LDS tile runs
+    // forward: phi = U_L .. U_1 psi in LDS tile runs (at these sizes a fused
+    // sweep is shorter than building its block matrices on the host)
     qc_exec_stats_t st{};
-    if (psi.dtype == QC_C64 && n >= 12)
-        rc = fused_execute(psi, n_ops, fwd.data(), 5, 1, st, stream);
-    else
-        rc = tiled_execute(psi, n_ops, fwd.data(), st, stream);
-    if (rc) return rc;
+    if ((rc = tiled_execute(psi, n_ops, fwd.data(), st, stream))) return rc;
     // energy, then lam = H phi
     if ((rc = qc_expect_pauli(psi, n_terms, paulis, coeff, 0, energy_dev, stream))) return rc;
     void *tdev = nullptr;

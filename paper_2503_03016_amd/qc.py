@@ -237,27 +237,46 @@ def apply_multiplexed(psi: torch.Tensor, qubits: Sequence[int], sel_qubits: Sequ
     return psi
 
 
+_GATE_DTYPE = np.dtype([("n_targets", "<i4"), ("n_ctrls", "<i4"),
+                        ("targets", "<i4", (QC_MAX_FUSED,)), ("ctrls", "<i4", (QC_MAX_CTRLS,)),
+                        ("ctrl_vals", "<i4", (QC_MAX_CTRLS,)), ("matrix", "<u8")], align=True)
+
+
 class GateList:
-    """qc_gate_t array built from (targets, ctrls, ctrl_vals, matrix) tuples;
-    keeps the host matrices alive while the library reads them."""
+    """qc_gate_t array built from (targets, ctrls, ctrl_vals, matrix) tuples
+    (filled in bulk through a numpy record array of the same layout); keeps
+    the host matrices alive while the library reads them."""
 
     def __init__(self, gates: Iterable[Tuple[Sequence[int], Sequence[int], Sequence[int], np.ndarray]]):
         gates = list(gates)
-        self.arr = (QcGate * max(1, len(gates)))()
-        self.keep: List[np.ndarray] = []
-        for g, (t, c, cv, u) in zip(self.arr, gates):
-            if len(t) > QC_MAX_FUSED or len(c) > QC_MAX_CTRLS:
+        assert _GATE_DTYPE.itemsize == ctypes.sizeof(QcGate)
+        count = len(gates)
+        rec = np.zeros(max(1, count), dtype=_GATE_DTYPE)
+        if count:
+            nt = np.fromiter((len(g[0]) for g in gates), dtype=np.int32, count=count)
+            nc = np.fromiter((len(g[1]) for g in gates), dtype=np.int32, count=count)
+            if nt.max() > QC_MAX_FUSED or nc.max() > QC_MAX_CTRLS:
                 raise ValueError("gate too wide for qc_gate_t")
-            g.n_targets, g.n_ctrls = len(t), len(c)
-            for j, q in enumerate(t):
-                g.targets[j] = int(q)
-            for j, (q, v) in enumerate(zip(c, cv)):
-                g.ctrls[j] = int(q)
-                g.ctrl_vals[j] = int(v)
-            m, p = _mat(u)
-            self.keep.append(m)
-            g.matrix = p
-        self.count = len(gates)
+            rec["n_targets"][:count] = nt
+            rec["n_ctrls"][:count] = nc
+            for i, (t, c, cv, _) in enumerate(gates):
+                if len(t):
+                    rec["targets"][i, :len(t)] = t
+                if len(c):
+                    rec["ctrls"][i, :len(c)] = c
+                    rec["ctrl_vals"][i, :len(c)] = cv
+            mats = [np.asarray(g[3], dtype=np.complex128).reshape(-1) for g in gates]
+            sizes = np.fromiter((m.size for m in mats), dtype=np.int64, count=count)
+            if np.any(sizes != (1 << (2 * nt.astype(np.int64)))):
+                raise ValueError("matrix size does not match the target count")
+            self._mats = np.ascontiguousarray(np.concatenate(mats))
+            offsets = np.concatenate(([0], np.cumsum(sizes)[:-1]))
+            rec["matrix"][:count] = self._mats.ctypes.data + 16 * offsets
+        else:
+            self._mats = np.zeros(1, dtype=np.complex128)
+        self._rec = rec
+        self.arr = rec.ctypes.data_as(ctypes.POINTER(QcGate))
+        self.count = count
 
 
 def apply_circuit(psi: torch.Tensor, gates: GateList, mode: int = QC_EXEC_UNFUSED,
