@@ -263,3 +263,31 @@ def test_fuse_plan_rejects_bad_gates(qc):
     gl = _gate_list(qc, [W.Op("CNOT", (0, 0))])
     with pytest.raises(qc.QcError):
         qc.fuse_plan(4, gl, 5)
+
+
+def test_gate_list_marshalling_round_trip(qc):
+    """GateList fills qc_gate_t records in bulk: every field and every matrix
+    entry reads back through the C layout."""
+    rng = np.random.default_rng(3)
+    tuples = []
+    for i in range(50):
+        k = int(rng.integers(1, 4))
+        qs = [int(x) for x in rng.permutation(10)[:k + 2]]
+        nc = int(rng.integers(0, 3))
+        u = rng.normal(size=(1 << k, 1 << k)) + 1j * rng.normal(size=(1 << k, 1 << k))
+        tuples.append((tuple(qs[:k]), tuple(qs[k:k + nc]), tuple(int(v) for v in rng.integers(0, 2, nc)), u))
+    gl = qc.GateList(tuples)
+    assert gl.count == len(tuples)
+    for i, (t, c, cv, u) in enumerate(tuples):
+        g = gl.arr[i]
+        assert g.n_targets == len(t) and g.n_ctrls == len(c)
+        assert list(g.targets[:len(t)]) == list(t)
+        assert list(g.ctrls[:len(c)]) == list(c)
+        assert list(g.ctrl_vals[:len(c)]) == list(cv)
+        d = 1 << len(t)
+        got = np.ctypeslib.as_array(g.matrix, shape=(2 * d * d,)).view(np.complex128).reshape(d, d)
+        assert np.array_equal(got, u)
+    with pytest.raises(ValueError):
+        qc.GateList([((0,), (), (), np.eye(4))])     # 4x4 matrix on one target
+    empty = qc.GateList([])
+    assert empty.count == 0
