@@ -248,8 +248,8 @@ int qc_reduced_state(qc_state_t src, int m, const int *qubits, const int *values
  * counts of section 5.2).  u_dev holds `shots` caller-supplied uniforms in
  * [0, 1) (device FP64); out_dev[k] (device int64) receives the first basis
  * index whose cumulative weight, in index order, exceeds u_dev[k] times
- * the total weight.  The cumulative weights are FP64.  Needs 12 <= n <= 33
- * (QC_ERR_UNSUPPORTED otherwise). */
+ * the total weight.  The cumulative weights are FP64 (per chunk of up to
+ * 4096 amplitudes for n <= 33, larger chunks above). */
 int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, void *stream);
 
 /* ---- differentiation ------------------------------------------------ */

@@ -1419,7 +1419,6 @@ int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, vo
     int rc = check_state(s);
     if (rc) return rc;
     if (shots < 0 || (shots > 0 && (!u_dev || !out_dev))) return fail(QC_ERR_ARG, "NULL argument");
-    if (s.n < 12 || s.n > 33) return fail(QC_ERR_UNSUPPORTED, "sampling needs 12 <= n <= 33");
     DevCtx *c;
     if ((rc = get_ctx(&c))) return rc;
     hipError_t e = qcx::launch_sample(s.amp, s.dtype, s.n, u_dev, shots, out_dev, c->work,

@@ -68,14 +68,18 @@ __global__ __launch_bounds__(kBlock) void k_reduced(const cx<R> *src, cx<R> *dst
         dst[r] = src[insert_zeros(r, a.pos, a.m) | a.fixed];
 }
 
+// Chunks of 2^cb amplitudes: cb = 12 for registers of 12..33 qubits, the
+// whole register below that, and larger chunks above, so that there are at
+// most 2^21 chunks (their sums and prefix sums live in the FP64 workspace).
 constexpr int kChunkBits = 12;
+constexpr int kMaxChunkLog = 21;
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(const cx<R> *amp, double *csum) {
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(const cx<R> *amp, int cb, double *csum) {
     __shared__ double red[kWaves];
-    const uint64_t base = uint64_t(blockIdx.x) << kChunkBits;
+    const uint64_t base = uint64_t(blockIdx.x) << cb;
     double acc = 0.0;
-    for (int j = threadIdx.x; j < (1 << kChunkBits); j += kBlock) acc += norm2(amp[base + j]);
+    for (int j = threadIdx.x; j < (1 << cb); j += kBlock) acc += norm2(amp[base + j]);
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -114,8 +118,8 @@ __global__ __launch_bounds__(1024) void k_scan(const double *csum, uint64_t nc, 
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_sample(const cx<R> *amp, const double *cpre,
-                                                   uint64_t nc, const double *u, int shots,
-                                                   int64_t *out) {
+                                                   uint64_t nc, int cb, const double *u,
+                                                   int shots, int64_t *out) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= shots) return;
     // target cumulative weight; the distribution is normalised by its total
@@ -130,10 +134,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(const cx<R> *amp, const doubl
         if (cpre[mid] <= x) lo = mid;
         else hi = mid;
     }
-    const uint64_t base = lo << kChunkBits;
+    const uint64_t base = lo << cb;
     double acc = cpre[lo];
     int64_t last_nonzero = -1;
-    for (int j = 0; j < (1 << kChunkBits); ++j) {
+    for (int j = 0; j < (1 << cb); ++j) {
         const double w = norm2(amp[base + j]);
         if (w > 0.0) last_nonzero = int64_t(base + j);
         acc += w;
@@ -199,26 +203,27 @@ hipError_t launch_reduced(const void *src, void *dst, int dtype, int n, int m, c
 
 hipError_t launch_sample(const void *amp, int dtype, int n, const double *u, int shots,
                          int64_t *out, double *work, size_t work_elems, hipStream_t s) {
-    if (n < kChunkBits) return hipErrorInvalidValue;
-    const uint64_t nc = uint64_t(1) << (n - kChunkBits);
+    int cb = n - kMaxChunkLog > kChunkBits ? n - kMaxChunkLog : kChunkBits;
+    if (cb > n) cb = n;
+    const uint64_t nc = uint64_t(1) << (n - cb);
     if (2 * nc + 1 > work_elems || nc > 0x7fffffffull) return hipErrorInvalidValue;
     double *csum = work, *cpre = work + nc;
     const int tok = timer_begin("sample", s);
     if (dtype == QC_C64)
         hipLaunchKernelGGL((k_chunk_sums<float>), dim3(unsigned(nc)), dim3(kBlock), 0, s,
-                           static_cast<const cx<float> *>(amp), csum);
+                           static_cast<const cx<float> *>(amp), cb, csum);
     else
         hipLaunchKernelGGL((k_chunk_sums<double>), dim3(unsigned(nc)), dim3(kBlock), 0, s,
-                           static_cast<const cx<double> *>(amp), csum);
+                           static_cast<const cx<double> *>(amp), cb, csum);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, csum, nc, cpre);
     const unsigned g = unsigned((shots + kBlock - 1) / kBlock);
     if (shots > 0) {
         if (dtype == QC_C64)
             hipLaunchKernelGGL((k_sample<float>), dim3(g), dim3(kBlock), 0, s,
-                               static_cast<const cx<float> *>(amp), cpre, nc, u, shots, out);
+                               static_cast<const cx<float> *>(amp), cpre, nc, cb, u, shots, out);
         else
             hipLaunchKernelGGL((k_sample<double>), dim3(g), dim3(kBlock), 0, s,
-                               static_cast<const cx<double> *>(amp), cpre, nc, u, shots, out);
+                               static_cast<const cx<double> *>(amp), cpre, nc, cb, u, shots, out);
     }
     timer_end(tok, s);
     return hipGetLastError();

@@ -59,7 +59,7 @@ def test_reduced_state_vs_oracle(qc):
         np.testing.assert_allclose(got, oracle.reduced_statevector(psi0, known, vals), atol=0)
 
 
-@pytest.mark.parametrize("n", [12, 15])
+@pytest.mark.parametrize("n", [1, 3, 7, 11, 12, 15])
 def test_sampling_vs_oracle(qc, n):
     psi0 = W.random_state(n, 44)
     t = dev(psi0, torch.complex128)
