@@ -19,6 +19,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# The fused kernel's tile counter is taken by one lane; the atomic optimizer's
+# wave-wide rewrite of it would wait on every memory operation in flight.
+EXTRA_FLAGS = {"qc_fused_mfma.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -30,7 +33,8 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
+        cmd = ([HIPCC] + FLAGS + EXTRA_FLAGS.get(src, []) +
+               ["-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj])
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         if verbose:

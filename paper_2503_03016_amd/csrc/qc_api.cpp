@@ -758,8 +758,13 @@ int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
             mfma_operand_c64(std::vector<cd>(u.begin() + v * dd, u.begin() + (v + 1) * dd), op);
             all.insert(all.end(), op.begin(), op.end());
         }
+        // the kernel's tile counters follow the operands, zeroed by the same upload
+        const size_t op_floats = all.size();
+        all.resize(op_floats + qcx::kMfmaTicketBytes / sizeof(float), 0.0f);
         if ((rc = stage(c, all.data(), all.size() * sizeof(float), stream, &dev))) return rc;
-        e = qcx::launch_fused_mfma_c64(s.amp, s.n, g, static_cast<const float *>(dev), stream);
+        e = qcx::launch_fused_mfma_c64(
+            s.amp, s.n, g, static_cast<const float *>(dev),
+            reinterpret_cast<unsigned *>(static_cast<float *>(dev) + op_floats), stream);
     } else if (s.dtype == QC_C64) {
         std::vector<float> f(u.size() * 2);
         for (size_t i = 0; i < u.size(); ++i) {

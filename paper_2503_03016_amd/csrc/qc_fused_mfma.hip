@@ -27,6 +27,13 @@
 // U stays in VGPRs for the whole kernel; the next tile's loads are in
 // flight while the current tile is multiplied.
 //
+// Tiles are handed out in ascending order from an atomic counter (one per
+// value of the selector bits above the tile, zeroed by the upload of the
+// operands), one tile ahead of its use: the tiles in flight on all CUs are
+// then always a narrow window of consecutive tiles, which streams from HBM
+// faster than a fixed tile-to-workgroup assignment whose workgroups drift
+// apart.  A workgroup stops at the first ticket past the last tile.
+//
 // Multiplexed blocks (U_v selected by up to 2 selector bits, the block
 // form of a gate controlled from outside it).  A selector bit among the C
 // column bits of the tile is given one of the column-index bits 5.. that
@@ -62,6 +69,7 @@ struct MfmaArgs {
     static constexpr int kTileBits = 5 + C;
     cx<float> *amp;
     const float *a_ops;         // per selector value [3][32][32]: Ur, Ui, Ur + Ui (row = output t)
+    unsigned *tickets;          // zeroed tile counters, one per selector value, 64 B apart
     uint64_t n_tiles;           // tiles per value of the selector bits above the tile
     uint64_t off_s[8];          // address offset of tile element 2 W 64 s
     uint8_t tile_pos[kTileBits];             // ascending bit positions of the tile bits
@@ -131,18 +139,45 @@ __global__ __launch_bounds__(64 << (C - 5)) void k_fused_mfma_c64(const MfmaArgs
     const uint32_t sw_rd_l = swz<C>(cdep | (h ? a.t16 : 0u), a.mcol);
     const uint32_t sw_out_l = swz<C>(cdep | (h ? a.t4 : 0u), a.mcol);
 
-    const uint64_t tstep = gridDim.x >> a.n_sel;
-    uint64_t tile = blockIdx.x >> a.n_sel;
+    // Tile base address: the tile index with zeros inserted at the tile and
+    // high selector positions, held in registers.  (Reading the positions
+    // from the argument block inside the loop would be a vector memory load,
+    // and waiting for it would also wait for every store still in flight.)
+    constexpr int kIns = kTileBits + kMaxSel;
+    uint32_t ins[kIns];
+#pragma unroll
+    for (int j = 0; j < kIns; ++j) ins[j] = a.ins_pos[j];
+    const int n_ins = a.n_ins;
+    auto tile_base = [&](uint64_t t) {
+#pragma unroll
+        for (int j = 0; j < kIns; ++j)
+            if (j < n_ins) {
+                const uint32_t p = ins[j];
+                t = ((t >> p) << (p + 1)) | (t & ((uint64_t(1) << p) - 1));
+            }
+        return t | sel_or;
+    };
+
+    // tile tickets: thread 0 takes them, LDS broadcasts them
+    __shared__ unsigned ticket_lds;
+    unsigned *const counter = a.tickets + 16 * sel;
+    unsigned pending = 0;
+    if (tid == 0) ticket_lds = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint64_t tile = ticket_lds;
+    __syncthreads();   // every thread has read it before thread 0 writes the next
     if (tile >= a.n_tiles) return;
     floatx4 g[8];
-    uint64_t base = insert_zeros(tile, a.ins_pos, a.n_ins) | sel_or;
+    uint64_t base = tile_base(tile);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
         g[s] = __builtin_nontemporal_load(
             reinterpret_cast<const floatx4 *>(&a.amp[base + off_thr + a.off_s[s]]));
+    if (tid == 0) pending = atomicAdd(counter, 1u);
 
     for (;;) {
-        // 2. stage the tile in LDS
+        // 2. stage the tile in LDS; publish the ticket taken one tile ago
+        if (tid == 0) ticket_lds = pending;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const uint32_t slot = sw_thr ^ a.sw_mem_s[s];
@@ -150,15 +185,17 @@ __global__ __launch_bounds__(64 << (C - 5)) void k_fused_mfma_c64(const MfmaArgs
             lds[slot ^ 1u] = make_float2(g[s][2], g[s][3]);
         }
         __syncthreads();
-        // prefetch the next tile while this one is multiplied
-        const uint64_t next = tile + tstep;
+        // prefetch the next tile while this one is multiplied, and take the
+        // ticket of the one after it
+        const uint64_t next = ticket_lds;
         const bool more = next < a.n_tiles;
-        const uint64_t nbase = more ? (insert_zeros(next, a.ins_pos, a.n_ins) | sel_or) : 0;
+        const uint64_t nbase = more ? tile_base(next) : 0;
         if (more) {
 #pragma unroll
             for (int s = 0; s < 8; ++s)
                 g[s] = __builtin_nontemporal_load(
                     reinterpret_cast<const floatx4 *>(&a.amp[nbase + off_thr + a.off_s[s]]));
+            if (tid == 0) pending = atomicAdd(counter, 1u);
         }
         // 3. operands and 3M products
         floatx16 p1 = {0}, p2 = {0}, p3 = {0};
@@ -349,10 +386,12 @@ bool mfma_args(int n, const FusedGeom &g, MfmaArgs<C> &a) {
 }
 
 template <int C>
-hipError_t launch_c(void *amp, const float *a_dev, MfmaArgs<C> &a, hipStream_t s) {
+hipError_t launch_c(void *amp, const float *a_dev, unsigned *tickets, MfmaArgs<C> &a,
+                    hipStream_t s) {
     constexpr int kWaves = 1 << (C - 5);
     a.amp = static_cast<cx<float> *>(amp);
     a.a_ops = a_dev;
+    a.tickets = tickets;
     // the knob counts resident 32 KiB tiles per CU: a 64 KiB workgroup takes two
     int per_cu = knob(QC_KNOB_MFMA_WG_PER_CU) / (kWaves / 4);
     if (per_cu < 1) per_cu = 1;
@@ -373,15 +412,15 @@ hipError_t launch_c(void *amp, const float *a_dev, MfmaArgs<C> &a, hipStream_t s
 }  // namespace
 
 hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
-                                 hipStream_t s) {
+                                 unsigned *tickets, hipStream_t s) {
     if (g.k != 5 || g.n_sel < 0 || g.n_sel > kMaxSel) return hipErrorInvalidValue;
     // 2 KiB contiguous runs (2^13-amplitude tiles) when the register allows,
     // else 1 KiB runs (2^12-amplitude tiles)
     MfmaArgs<8> a8{};
     if (knob(QC_KNOB_MFMA_TILE_BITS) == 13 && mfma_args<8>(n, g, a8))
-        return launch_c<8>(amp, a_dev, a8, s);
+        return launch_c<8>(amp, a_dev, tickets, a8, s);
     MfmaArgs<7> a7{};
-    if (mfma_args<7>(n, g, a7)) return launch_c<7>(amp, a_dev, a7, s);
+    if (mfma_args<7>(n, g, a7)) return launch_c<7>(amp, a_dev, tickets, a7, s);
     return hipErrorInvalidValue;
 }
 

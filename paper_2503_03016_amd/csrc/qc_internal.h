@@ -175,8 +175,10 @@ hipError_t launch_phase(void *amp, int dtype, int n, int m, const int *pos, cons
                         double phase_re, double phase_im, hipStream_t s);
 hipError_t launch_fused_valu(void *amp, int dtype, int n, const FusedGeom &g,
                              const void *u_dev, hipStream_t s);
+// tickets: kMfmaTicketBytes of zeroed device memory private to this launch
+constexpr size_t kMfmaTicketBytes = 64 * (1 << kMaxSel);
 hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
-                                 hipStream_t s);
+                                 unsigned *tickets, hipStream_t s);
 hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_pos,
                              bool identity, double *out, hipStream_t s);
 hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const int *pos,
