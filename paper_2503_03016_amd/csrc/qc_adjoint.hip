@@ -122,13 +122,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
     __syncthreads();
     const uint64_t off_lo =
         tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
+    const uint64_t mask = tile::hi_mask(a.pos, a.m);
     for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
-        for (int j = threadIdx.x; j < T; j += kBlock) {
-            const uint64_t at = base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m);
-            lp[j] = phi[at];
-            ll[j] = lam[at];
-        }
+        tile::tile_load<R>(lp, phi, base, off_lo, mask, T);
+        tile::tile_load<R>(ll, lam, base, off_lo, mask, T);
         // ops are staged through LDS as in tile::apply_ops
         if (a.n_ops > 0) tile::stage_now(&op_slot[0], &ops[0]);
         __syncthreads();
@@ -164,11 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             if (next) tile::stage_store(st, &op_slot[(o + 1) & 1]);
             __syncthreads();
         }
-        for (int j = threadIdx.x; j < T; j += kBlock) {
-            const uint64_t at = base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m);
-            phi[at] = lp[j];
-            lam[at] = ll[j];
-        }
+        tile::tile_store<R>(phi, lp, base, off_lo, mask, T);
+        tile::tile_store<R>(lam, ll, base, off_lo, mask, T);
         __syncthreads();
     }
     for (int s = threadIdx.x; s < n_slots; s += kBlock)

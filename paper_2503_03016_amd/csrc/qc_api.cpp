@@ -738,7 +738,7 @@ int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
     std::copy(pos, pos + k, srt);
     std::sort(srt, srt + k);
     g.n_pos = k;
-    for (int j = 0; j < k; ++j) g.pos[j] = uint8_t(srt[j]);
+    for (int j = 0; j < k; ++j) g.pos[j] = uint32_t(srt[j]);
     for (int r = 0; r < (1 << k); ++r) {
         uint64_t o = 0;
         for (int j = 0; j < k; ++j)
@@ -746,7 +746,7 @@ int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
         g.tgt_off[r] = o;
     }
     g.n_sel = ns;
-    for (int j = 0; j < ns; ++j) g.sel_pos[j] = uint8_t(bitpos(s.n, sq[j]));
+    for (int j = 0; j < ns; ++j) g.sel_pos[j] = uint32_t(bitpos(s.n, sq[j]));
     const size_t dd = size_t(1) << (2 * k);
     void *dev = nullptr;
     hipError_t e;
@@ -1100,7 +1100,7 @@ qcx::TileArgs tile_args(int n, int m, uint64_t P, int n_ops) {
     a.n_ops = n_ops;
     a.n_tiles = uint64_t(1) << (n - m);
     for (int p = 0, j = 0; p < n; ++p)
-        if ((P >> p) & 1) a.pos[j++] = uint8_t(p);
+        if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
     return a;
 }
 
@@ -1719,7 +1719,7 @@ qcx::BatchPhase make_phase(int n, int m, uint64_t P, int op_begin, int op_count,
     ph.op_count = op_count;
     ph.flags = flags;
     for (int p = 0, j = 0; p < n; ++p)
-        if ((P >> p) & 1) ph.pos[j++] = uint8_t(p);
+        if ((P >> p) & 1) ph.pos[j++] = uint32_t(p);
     return ph;
 }
 

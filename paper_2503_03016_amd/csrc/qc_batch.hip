@@ -106,40 +106,37 @@ __device__ void run_circuit(const BatchArgs &a, int c, int rank, int G, cx<R> *l
     const BatchCircuit C = a.circ[c];
     cx<R> *state = static_cast<cx<R> *>(a.arena) + C.arena_off;
     double acc = 0.0;
+    // the phase's tile positions, copied to LDS once per phase: the phase
+    // table is in global memory, and vector loads of it inside the tile loop
+    // would wait for the stores in flight
+    __shared__ uint32_t pos[kTileMaxBits];
     for (int p = C.phase_begin; p < C.phase_begin + C.phase_count; ++p) {
-        const BatchPhase &P = a.phases[p];   // read in place (pos[] is indexed at run time)
-        const int T = 1 << P.m;
-        // element j = threadIdx.x + 256 k: the low 8 compressed bits are this
-        // thread's, the high ones come from k
-        const int lo_bits = P.m < tile::kLoBits ? P.m : tile::kLoBits;
-        const uint64_t off_lo = tile::deposit(uint32_t(threadIdx.x) & uint32_t(T - 1), P.pos, lo_bits);
-        for (uint64_t t = rank; t < P.n_tiles; t += G) {
-            const uint64_t base = insert_zeros(t, P.pos, P.m);
-            if (P.flags & BATCH_INIT) {
+        const BatchPhase &P = a.phases[p];
+        if (threadIdx.x < kTileMaxBits) pos[threadIdx.x] = P.pos[threadIdx.x];
+        const int m = P.m, flags = P.flags;
+        const int op_begin = P.op_begin, op_count = P.op_count;
+        const int term_begin = P.term_begin, term_count = P.term_count;
+        const uint64_t n_tiles = P.n_tiles;
+        __syncthreads();
+        const int T = 1 << m;
+        const uint64_t off_lo = tile::deposit(uint32_t(threadIdx.x) & uint32_t(T - 1), pos,
+                                              m < tile::kLoBits ? m : tile::kLoBits);
+        const uint64_t mask = tile::hi_mask(pos, m);
+        for (uint64_t t = rank; t < n_tiles; t += G) {
+            const uint64_t base = insert_zeros(t, pos, m);
+            if (flags & BATCH_INIT) {
                 for (int j = threadIdx.x; j < T; j += kBlock) {
                     cx<R> v{R(0), R(0)};
                     if (base == 0 && j == 0) v.re = R(1);
                     lds[j] = v;
                 }
             } else {
-                for (int j = threadIdx.x; j < T; j += kBlock) {
-                    uint64_t off = off_lo;
-                    for (int b = tile::kLoBits; b < P.m; ++b)
-                        if ((j >> b) & 1) off |= uint64_t(1) << P.pos[b];
-                    lds[j] = state[base + off];
-                }
+                tile::tile_load<R>(lds, state, base, off_lo, mask, T);
             }
             __syncthreads();
-            tile::apply_ops<R>(lds, P.m, base, a.ops + P.op_begin, P.op_count, op_slot);
-            if (P.term_count) acc += tile_energy<R>(lds, P.m, base, a.terms + P.term_begin,
-                                                    P.term_count);
-            if (P.flags & BATCH_STORE)
-                for (int j = threadIdx.x; j < T; j += kBlock) {
-                    uint64_t off = off_lo;
-                    for (int b = tile::kLoBits; b < P.m; ++b)
-                        if ((j >> b) & 1) off |= uint64_t(1) << P.pos[b];
-                    state[base + off] = lds[j];
-                }
+            tile::apply_ops<R>(lds, m, base, a.ops + op_begin, op_count, op_slot);
+            if (term_count) acc += tile_energy<R>(lds, m, base, a.terms + term_begin, term_count);
+            if (flags & BATCH_STORE) tile::tile_store<R>(state, lds, base, off_lo, mask, T);
             __syncthreads();
         }
         if (G > 1) group_barrier(bar, G, gen, a.error);

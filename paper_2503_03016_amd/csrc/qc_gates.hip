@@ -153,7 +153,7 @@ hipError_t small_gate_typed(void *amp, int n, const int *tpos, int n_ctrl, const
             all[j] = all[j - 1];
             all[j - 1] = t;
         }
-    for (int j = 0; j < nfix; ++j) a.pos[j] = uint8_t(all[j]);
+    for (int j = 0; j < nfix; ++j) a.pos[j] = uint32_t(all[j]);
     a.n_pos = nfix;
     a.or_bits = 0;
     for (int j = 0; j < n_ctrl; ++j)

@@ -31,7 +31,12 @@ __host__ __device__ inline cx<R> cfma(cx<R> a, cx<R> b, cx<R> acc) {
 
 // Index of group g once zero bits are inserted at the ascending bit
 // positions pos[0..m-1] (positions refer to the final index).
-__host__ __device__ inline uint64_t insert_zeros(uint64_t g, const uint8_t *pos, int m) {
+//
+// Bit-position tables in kernel arguments are 32-bit words: gfx9 has no
+// scalar byte load, so a byte table indexed in a loop is read with vector
+// loads, and waiting for one of those also waits for every store in flight.
+// 32-bit entries at a uniform index are read with scalar loads instead.
+__host__ __device__ inline uint64_t insert_zeros(uint64_t g, const uint32_t *pos, int m) {
     for (int j = 0; j < m; ++j) {
         const int p = pos[j];
         const uint64_t lo = g & ((uint64_t(1) << p) - 1);
@@ -59,7 +64,7 @@ struct SmallGateArgs {
     uint64_t or_bits;          // control values placed at their bit positions
     uint64_t tgt_off[1 << K];  // offset of local index r (bit deposit)
     cx<R> u[(1 << K) * (1 << K)];
-    uint8_t pos[kMaxPos];      // ascending positions of targets + controls
+    uint32_t pos[kMaxPos];     // ascending positions of targets + controls
     int n_pos;
 };
 
@@ -71,10 +76,10 @@ constexpr int kMaxSel = 2;   // U lives in LDS: 4 c128 5-qubit matrices = 64 KiB
 struct FusedGeom {
     int k;
     int n_pos;
-    uint8_t pos[8];            // ascending target positions
+    uint32_t pos[8];           // ascending target positions
     uint64_t tgt_off[32];      // offset of local index r
     int n_sel;
-    uint8_t sel_pos[kMaxSel];  // selector bit positions
+    uint32_t sel_pos[kMaxSel];  // selector bit positions
 };
 
 // One Pauli term of a Hamiltonian on the device: P = i^ph X^x Z^z (masks of
@@ -122,7 +127,7 @@ struct TileArgs {
     uint64_t n_tiles;
     int m;                     // tile bits
     int n_ops;
-    uint8_t pos[kTileMaxBits];  // ascending global bit positions of the tile bits
+    uint32_t pos[kTileMaxBits];  // ascending global bit positions of the tile bits
 };
 
 // ---- batched persistent launch: device program ---------------------------
@@ -130,7 +135,7 @@ enum BatchFlags { BATCH_INIT = 1, BATCH_STORE = 2 };
 struct BatchPhase {
     uint64_t n_tiles;
     int32_t m, op_begin, op_count, term_begin, term_count, flags;
-    uint8_t pos[kTileMaxBits];     // ascending global bit positions of the tile bits
+    uint32_t pos[kTileMaxBits];    // ascending global bit positions of the tile bits
 };
 struct BatchTerm {
     uint64_t z_hi;     // z bits outside the tile (global positions)

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_collapse(cx<R> *amp, uint64_t count,
 }
 
 struct ReduceArgs {
-    uint8_t pos[QC_MAX_QUBITS];   // ascending positions of the known qubits
+    uint32_t pos[QC_MAX_QUBITS];  // ascending positions of the known qubits
     int m;
     uint64_t fixed;               // known values at their positions
     uint64_t count;               // 2^(n-m) output amplitudes
@@ -188,7 +188,7 @@ hipError_t launch_reduced(const void *src, void *dst, int dtype, int n, int m, c
             srt[j] = srt[j - 1];
             srt[j - 1] = t;
         }
-    for (int j = 0; j < m; ++j) a.pos[j] = uint8_t(srt[j]);
+    for (int j = 0; j < m; ++j) a.pos[j] = uint32_t(srt[j]);
     a.m = m;
     a.count = uint64_t(1) << (n - m);
     const unsigned g = grid_for(a.count);

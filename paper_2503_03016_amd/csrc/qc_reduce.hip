@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_probs_full(const cx<R> *amp, uint64_
 }
 
 struct PermArgs {
-    uint8_t src_pos[QC_MAX_QUBITS];   // bit position of the qubit that becomes
+    uint32_t src_pos[QC_MAX_QUBITS];  // bit position of the qubit that becomes
                                       // outcome bit (m-1-j), j = list index
     int m;
 };
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_probs_perm(const cx<R> *amp, uint64_
 
 struct MarginalArgs {
     uint64_t bin_off[24];      // offset of outcome bit (m-1-j) = listed qubit j
-    uint8_t pos[QC_MAX_QUBITS];  // ascending positions of the listed qubits
+    uint32_t pos[QC_MAX_QUBITS];  // ascending positions of the listed qubits
     int m;
     uint64_t rest;             // 2^(n-m) indices per bin
     uint64_t chunk;            // indices of one bin summed by one block
@@ -303,7 +303,7 @@ hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_
     } else {
         PermArgs p{};
         p.m = n;
-        for (int j = 0; j < n; ++j) p.src_pos[j] = uint8_t(perm_pos[j]);
+        for (int j = 0; j < n; ++j) p.src_pos[j] = uint32_t(perm_pos[j]);
         if (dtype == QC_C64)
             hipLaunchKernelGGL((k_probs_perm<float>), dim3(unsigned(g)), dim3(kBlock), 0, s,
                                static_cast<const cx<float> *>(amp), count, p, out);
@@ -328,7 +328,7 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
             sorted[j] = sorted[j - 1];
             sorted[j - 1] = t;
         }
-    for (int j = 0; j < m; ++j) a.pos[j] = uint8_t(sorted[j]);
+    for (int j = 0; j < m; ++j) a.pos[j] = uint32_t(sorted[j]);
     a.rest = uint64_t(1) << (n - m);
     const uint64_t bins = uint64_t(1) << m;
     // enough blocks to fill the chip, at least 4096 indices per block

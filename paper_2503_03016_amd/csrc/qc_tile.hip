@@ -29,14 +29,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
     // the low 8 compressed bits of this thread's elements are fixed
     const uint64_t off_lo =
         tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
+    const uint64_t mask = tile::hi_mask(a.pos, a.m);
     for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
-        for (int j = threadIdx.x; j < T; j += kBlock)
-            lds[j] = amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)];
+        tile::tile_load<R>(lds, amp, base, off_lo, mask, T);
         __syncthreads();
         tile::apply_ops<R>(lds, a.m, base, ops, a.n_ops, op_slot);
-        for (int j = threadIdx.x; j < T; j += kBlock)
-            amp[base + off_lo + tile::deposit_hi(uint32_t(j), a.pos, a.m)] = lds[j];
+        tile::tile_store<R>(amp, lds, base, off_lo, mask, T);
         __syncthreads();
     }
 }

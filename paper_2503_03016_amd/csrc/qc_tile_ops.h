@@ -18,6 +18,7 @@ namespace tile {
 
 constexpr int kBlock = 512;     // threads per workgroup of the tile kernels
 constexpr int kLoBits = 9;      // log2(kBlock)
+constexpr int kLoadBatch = 8;   // tile elements a thread loads before waiting for them
 constexpr int kItems = 4;       // independent groups per thread per step
 
 template <typename R>
@@ -275,19 +276,61 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
 }
 
 // address offset of compressed tile index j
-__device__ inline uint64_t deposit(uint32_t j, const uint8_t *pos, int m) {
+__device__ inline uint64_t deposit(uint32_t j, const uint32_t *pos, int m) {
     uint64_t off = 0;
     for (int b = 0; b < m; ++b)
         if ((j >> b) & 1) off |= uint64_t(1) << pos[b];
     return off;
 }
 
-// address offset of the bits >= kLoBits of compressed tile index j
-__device__ inline uint64_t deposit_hi(uint32_t j, const uint8_t *pos, int m) {
-    uint64_t off = 0;
-    for (int b = kLoBits; b < m; ++b)
-        if ((j >> b) & 1) off |= uint64_t(1) << pos[b];
-    return off;
+// Offsets of the elements j = threadIdx.x + kBlock k of a tile: the low
+// kLoBits compressed bits are the thread's (deposit once), the bits above
+// come from k.  D(k), the deposit of k at the tile positions kLoBits .. m-1,
+// runs through the submasks of hi_mask(pos, m) in ascending order, so
+// D(k + 1) = next_submask(D(k), mask): no table lookups per element.
+__device__ inline uint64_t hi_mask(const uint32_t *pos, int m) {
+    uint64_t mask = 0;
+    for (int b = kLoBits; b < m; ++b) mask |= uint64_t(1) << pos[b];
+    return mask;
+}
+__device__ inline uint64_t next_submask(uint64_t d, uint64_t mask) { return (d - mask) & mask; }
+
+// Move the tile at `base` between HBM and LDS (T = 2^m elements): kLoadBatch
+// loads in flight per thread before the first of them is waited for.  Every
+// address formed here lies in the tile (off_lo takes the thread index modulo
+// T, and the submasks stay inside the mask), so the loads are guarded only
+// by the uniform k < K; the LDS writes also need j < T.
+template <typename R>
+__device__ inline void tile_load(cx<R> *lds, const cx<R> *amp, uint64_t base, uint64_t off_lo,
+                                 uint64_t mask, int T) {
+    const int K = T > kBlock ? T >> kLoBits : 1;
+    uint64_t d = 0;
+    for (int k0 = 0; k0 < K; k0 += kLoadBatch) {
+        cx<R> v[kLoadBatch];
+        uint64_t dk = d;
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            v[u] = k0 + u < K ? amp[base + off_lo + dk] : cx<R>{R(0), R(0)};
+            dk = next_submask(dk, mask);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int j = int(threadIdx.x) + (k0 + u) * kBlock;
+            if (k0 + u < K && j < T) lds[j] = v[u];
+        }
+        d = dk;
+    }
+}
+template <typename R>
+__device__ inline void tile_store(cx<R> *amp, const cx<R> *lds, uint64_t base, uint64_t off_lo,
+                                  uint64_t mask, int T) {
+    const int K = T > kBlock ? T >> kLoBits : 1;
+    uint64_t d = 0;
+    for (int k = 0; k < K; ++k) {
+        const int j = int(threadIdx.x) + k * kBlock;
+        if (j < T) amp[base + off_lo + d] = lds[j];
+        d = next_submask(d, mask);
+    }
 }
 
 }  // namespace tile
