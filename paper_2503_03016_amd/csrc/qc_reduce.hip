@@ -175,19 +175,22 @@ struct ExpectArgs {
     int n_terms;
 };
 
-template <typename R>
+// NT = the group's term count rounded up to 1, 4, 8, 16 or 32: the
+// accumulators and the term tables are indexed with constants only, so they
+// stay in registers.
+template <typename R, int NT>
 __global__ __launch_bounds__(kBlock) void k_expect_group(const cx<R> *amp, const ExpectArgs a,
                                                          double *work) {
     __shared__ double lds[kWaves];
-    double acc[kExpectMaxTerms];
+    double acc[NT];
 #pragma unroll
-    for (int t = 0; t < kExpectMaxTerms; ++t) acc[t] = 0.0;
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < a.n_items; g += stride) {
         if (a.hpos < 0) {
             const double w = norm2(amp[g]);
 #pragma unroll
-            for (int t = 0; t < kExpectMaxTerms; ++t)
+            for (int t = 0; t < NT; ++t)
                 if (t < a.n_terms) acc[t] += (__popcll(g & a.zmask[t]) & 1) ? -w : w;
         } else {
             const uint64_t j = insert_zero(g, a.hpos);
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_expect_group(const cx<R> *amp, const
             const double c1 = br * ar + bi * ai;
             const double c2 = br * ai - bi * ar;
 #pragma unroll
-            for (int t = 0; t < kExpectMaxTerms; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 if (t < a.n_terms) {
                     const double sj = (__popcll(j & a.zmask[t]) & 1) ? -1.0 : 1.0;
                     const double sx = (__popcll(jx & a.zmask[t]) & 1) ? -1.0 : 1.0;
@@ -215,10 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_expect_group(const cx<R> *amp, const
             }
         }
     }
-    for (int t = 0; t < a.n_terms; ++t) {
-        const double tot = block_sum(acc[t], lds);
-        if (threadIdx.x == 0) work[size_t(t) * gridDim.x + blockIdx.x] = tot;
-    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        if (t < a.n_terms) {   // uniform
+            const double tot = block_sum(acc[t], lds);
+            if (threadIdx.x == 0) work[size_t(t) * gridDim.x + blockIdx.x] = tot;
+        }
 }
 
 // tab[t] = coefficient of term t, tab[n_terms + t] = slot of term t in vals
@@ -357,6 +362,22 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
     return hipGetLastError();
 }
 
+template <typename R>
+void launch_expect_nt(const cx<R> *amp, const ExpectArgs &a, double *work, unsigned grid,
+                      hipStream_t s) {
+    static_assert(kExpectMaxTerms == 32, "term-count buckets assume at most 32 terms");
+    if (a.n_terms <= 1)
+        hipLaunchKernelGGL((k_expect_group<R, 1>), dim3(grid), dim3(kBlock), 0, s, amp, a, work);
+    else if (a.n_terms <= 4)
+        hipLaunchKernelGGL((k_expect_group<R, 4>), dim3(grid), dim3(kBlock), 0, s, amp, a, work);
+    else if (a.n_terms <= 8)
+        hipLaunchKernelGGL((k_expect_group<R, 8>), dim3(grid), dim3(kBlock), 0, s, amp, a, work);
+    else if (a.n_terms <= 16)
+        hipLaunchKernelGGL((k_expect_group<R, 16>), dim3(grid), dim3(kBlock), 0, s, amp, a, work);
+    else
+        hipLaunchKernelGGL((k_expect_group<R, 32>), dim3(grid), dim3(kBlock), 0, s, amp, a, work);
+}
+
 hipError_t launch_expect_group(const void *amp, int dtype, int n, uint64_t xmask, int hpos,
                                int n_terms, const uint64_t *zmask, const int *phase,
                                double *term_vals, double *work, hipStream_t s) {
@@ -373,11 +394,9 @@ hipError_t launch_expect_group(const void *amp, int dtype, int n, uint64_t xmask
     const unsigned grid = reduce_grid(a.n_items);
     const int tok = timer_begin("expect", s);
     if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_expect_group<float>), dim3(grid), dim3(kBlock), 0, s,
-                           static_cast<const cx<float> *>(amp), a, work);
+        launch_expect_nt<float>(static_cast<const cx<float> *>(amp), a, work, grid, s);
     else
-        hipLaunchKernelGGL((k_expect_group<double>), dim3(grid), dim3(kBlock), 0, s,
-                           static_cast<const cx<double> *>(amp), a, work);
+        launch_expect_nt<double>(static_cast<const cx<double> *>(amp), a, work, grid, s);
     hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(n_terms)), dim3(kBlock), 0, s, work, n_terms,
                        int(grid), term_vals);
     timer_end(tok, s);
