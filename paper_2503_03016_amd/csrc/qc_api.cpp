@@ -1342,13 +1342,86 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
     const hipStream_t hs = (hipStream_t)stream;
     double *vals = c->work;                         // n_terms values
     double *part = c->work + ((n_terms + 255) & ~255);  // per-block partials
-    // group terms by x mask, preserving first-seen order
-    std::vector<int> order(n_terms);
-    for (int t = 0; t < n_terms; ++t) order[t] = t;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xm[a] < xm[b]; });
-    // term values are written in grouped order, then permuted by combine
+    // Tile passes: the tile is the kExpectLowBits lowest bits plus up to
+    // m - kExpectLowBits more; a term whose X bits all lie in a pass's tile
+    // bits is evaluated in that pass (the pair j, j ^ x is in one tile), and
+    // every diagonal term rides in the first pass.  Terms that fit no tile
+    // (more X bits above the low ones than a tile has room for) are
+    // evaluated one X mask at a time with the pair kernel.
+    const int m = std::min(n, s.dtype == QC_C64 ? 12 : 11);
+    const int L = std::min(qcx::kExpectLowBits, m);
+    const uint64_t low = (uint64_t(1) << L) - 1;
+    std::vector<int> rest, diag, order;
+    for (int t = 0; t < n_terms; ++t) {
+        if (xm[t] == 0) diag.push_back(t);
+        else if (__builtin_popcountll(xm[t] & ~low) <= m - L) rest.push_back(t);
+        else order.push_back(t);   // pair kernel
+    }
+    struct ExpPass {
+        uint64_t P;
+        std::vector<int> terms;
+    };
+    std::vector<ExpPass> passes;
+    while (!rest.empty()) {
+        uint64_t S = 0;
+        for (int t : rest) {
+            const uint64_t hb = xm[t] & ~low;
+            if (__builtin_popcountll(S | hb) <= m - L) S |= hb;
+        }
+        for (int p = L; __builtin_popcountll(S) < m - L && p < n; ++p) S |= uint64_t(1) << p;
+        ExpPass ps{low | S, {}};
+        std::vector<int> left;
+        for (int t : rest) ((xm[t] & ~ps.P) == 0 ? ps.terms : left).push_back(t);
+        passes.push_back(std::move(ps));
+        rest.swap(left);
+    }
+    if (!diag.empty()) {
+        if (passes.empty()) {
+            uint64_t P = 0;
+            for (int p = 0; p < m; ++p) P |= uint64_t(1) << p;
+            passes.push_back({P, {}});
+        }
+        passes[0].terms.insert(passes[0].terms.begin(), diag.begin(), diag.end());
+    }
+    // term values: tile-pass terms first (pass order), then the pair
+    // kernel's terms grouped by x mask; combine permutes them back
     std::vector<int> where(n_terms);
-    for (int i = 0; i < n_terms; ++i) where[order[i]] = i;
+    int slot = 0;
+    for (const ExpPass &ps : passes) {
+        for (size_t k0 = 0; k0 < ps.terms.size(); k0 += qcx::kExpectTileMaxTerms) {
+            const size_t k1 = std::min(ps.terms.size(), k0 + qcx::kExpectTileMaxTerms);
+            std::vector<qcx::ExpectTerm> et(k1 - k0);
+            for (size_t k = k0; k < k1; ++k) {
+                const int t = ps.terms[k];
+                uint32_t xc = 0, zc = 0;
+                for (int p = 0, j = 0; p < n; ++p) {
+                    if (!((ps.P >> p) & 1)) continue;
+                    if ((xm[t] >> p) & 1) xc |= 1u << j;
+                    if ((zm[t] >> p) & 1) zc |= 1u << j;
+                    ++j;
+                }
+                qcx::ExpectTerm &e = et[k - k0];
+                e.z_hi = zm[t] & ~ps.P;
+                e.xc = xc;
+                e.zc = zc;
+                e.ph = ph[t];
+                e.xtop = xc ? 31 - __builtin_clz(xc) : -1;
+                where[t] = slot + int(k - k0);
+            }
+            void *tdev = nullptr;
+            if ((rc = stage(c, et.data(), et.size() * sizeof(qcx::ExpectTerm), hs, &tdev))) return rc;
+            const qcx::TileArgs a = tile_args(n, m, ps.P, 0);
+            hipError_t e = qcx::launch_expect_tiles(s.amp, s.dtype, a,
+                                                    static_cast<const qcx::ExpectTerm *>(tdev),
+                                                    int(k1 - k0), vals + slot, part, hs);
+            if (e != hipSuccess) return hip_fail(e, "expect_tiles");
+            slot += int(k1 - k0);
+        }
+    }
+    // pair kernel: group the remaining terms by x mask, preserving first-seen order
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xm[a] < xm[b]; });
+    for (size_t i = 0; i < order.size(); ++i) where[order[i]] = slot + int(i);
+    vals += slot;
     size_t i0 = 0;
     while (i0 < order.size()) {
         size_t i1 = i0;
@@ -1368,6 +1441,7 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
         if (e != hipSuccess) return hip_fail(e, "expect");
         i0 = i1;
     }
+    vals = c->work;
     // combine in the caller's term order: out[0] = sum_t c_t v_t, out[1+t] = v_t
     std::vector<double> tab(size_t(2) * n_terms);
     for (int t = 0; t < n_terms; ++t) {

@@ -130,6 +130,17 @@ struct TileArgs {
     uint32_t pos[kTileMaxBits];  // ascending global bit positions of the tile bits
 };
 
+// One Pauli term of a tile pass of the expectation: X bits xc and Z bits zc
+// inside the tile (compressed positions), Z bits z_hi outside it (global
+// positions), ph = number of Y factors mod 4, xtop = top bit of xc.
+struct ExpectTerm {
+    uint64_t z_hi;
+    uint32_t xc, zc;
+    int32_t ph, xtop;
+};
+constexpr int kExpectTileMaxTerms = 512;   // terms per tile-pass launch
+constexpr int kExpectLowBits = 6;          // lowest bits, always tile bits (runs of 64)
+
 // ---- batched persistent launch: device program ---------------------------
 enum BatchFlags { BATCH_INIT = 1, BATCH_STORE = 2 };
 struct BatchPhase {
@@ -198,6 +209,11 @@ hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_
 
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s);
+// vals[k] = <psi|P_k|psi> for the nt terms of one tile pass; part holds
+// nt x grid partials
+hipError_t launch_expect_tiles(const void *amp, int dtype, const TileArgs &a,
+                               const ExpectTerm *terms_dev, int nt, double *vals, double *part,
+                               hipStream_t s);
 
 hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const double *prob,
                            double *prob_out, hipStream_t s);

@@ -387,6 +387,39 @@ def test_expect_pauli_random_terms(qc, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [16, 19])
+def test_expect_pauli_tile_passes(qc, dt, n):
+    """Registers larger than one expectation tile: Ising terms spread over
+    several tile passes, X bits straddling low and high positions, Z bits
+    outside the tile, Y-heavy strings, and strings with more high X bits
+    than a tile holds (evaluated by the pair kernel)."""
+    rng = np.random.default_rng(100 + n)
+    psi0 = W.random_state(n, 22)
+    t = dev(psi0, DT[dt])
+    st = host(t)
+    terms = list(W.tfim_terms(n))
+    def one(spec):
+        s = ["I"] * n
+        for q, c in spec.items():
+            s[q] = c
+        return "".join(s)
+    terms += [(one({0: "X", n - 1: "X"}), 0.7), (one({0: "Y", 1: "Y"}), -0.4),
+              (one({n - 1: "Y", n - 2: "X", 0: "Z"}), 0.25), ("Z" * n, 1.5),
+              (one({q: "X" for q in range(0, n, 2)}), 0.3),            # many high X bits
+              (one({q: "Y" for q in range(n - 6, n)}), -0.6),          # low bits only
+              (one({q: "X" for q in range(6)}), 0.9)]                  # high bits only
+    for _ in range(24):
+        terms.append(("".join(rng.choice(list("IIIXYZ"), n)), float(rng.normal())))
+    out = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    ref_terms = np.array([oracle.expect_pauli(st, p).real for p, _ in terms])
+    np.testing.assert_allclose(out[1:], ref_terms, atol=1e-12)
+    assert abs(out[0] - sum(c * r for (_, c), r in zip(terms, ref_terms))) < 1e-11
+    # identical on a second call (fixed-order reductions)
+    out2 = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    assert np.array_equal(out, out2)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_tfim_energy_after_hea(qc, G, dt):
     n = 14
     theta = np.random.default_rng(5).uniform(0, 2 * math.pi, 4 * n * 2)
