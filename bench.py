@@ -7,10 +7,12 @@ apply the 1900 gates as fused blocks, and take the measurement
 probabilities of qubit 0.  The reference is the plain unfused complex128
 run of the same circuit on the same GPU (one kernel sweep per gate); the
 bench reports the speedup over it and the error of the complex64 state
-against it.  Prints one JSON line.
+against it, and (unless --no-split) the unfused complex64 and fused
+complex128 runs that separate the precision gain from the fusion gain.
+Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 32] [--layers 40]
-                    [--no-ref] [--no-cpu]
+                    [--no-ref] [--no-split] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -216,6 +218,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-ref", action="store_true", help="skip the unfused complex128 run")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the unfused complex64 and fused complex128 runs that separate the "
+                         "precision gain from the fusion gain")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=24)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -338,6 +343,39 @@ def main() -> int:
         }
         log("c128 unfused: %.2f s, speedup %.2fx, rel err %.2e"
             % (t128, t128 / t_fused, math.sqrt(d[0] / d[1])))
+        if not args.no_split:
+            # separate the precision gain from the fusion gain: unfused
+            # complex64 and fused complex128 on the same circuit
+            def timed(state, mode):
+                qc.state_init(state, 0)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                stx = qc.apply_circuit(state, gl, mode=mode, fuse_k=5)
+                b.record(stream)
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / 1e3, stx
+            t64u, st64u = timed(psi, qc.QC_EXEC_UNFUSED)
+            d64u = qc.state_diff(psi, ref_psi).cpu().tolist()
+            f128 = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+            t128f, st128f = timed(f128, qc.QC_EXEC_FUSED)
+            d128f = qc.state_diff(f128, ref_psi).cpu().tolist()
+            del f128
+            ref.update({
+                "c64_unfused_s": round(t64u, 4),
+                "c64_unfused_GBps": round(st64u["state_bytes"] / t64u / 1e9, 1),
+                "err_rel_c64_unfused_vs_c128": float("%.3e" % math.sqrt(d64u[0] / d64u[1])),
+                "c128_fused_s": round(t128f, 4),
+                "c128_fused_sweeps": st128f["sweeps"],
+                "c128_fused_GBps": round(st128f["state_bytes"] / t128f / 1e9, 1),
+                "err_rel_c128_fused_vs_c128": float("%.3e" % math.sqrt(d128f[0] / d128f[1])),
+                "speedup_precision_unfused": round(t128 / t64u, 2),
+                "speedup_fusion_c128": round(t128 / t128f, 2),
+                "speedup_fusion_c64": round(t64u / t_fused, 2),
+            })
+            log("c64 unfused: %.2f s; c128 fused: %.2f s (%d sweeps)"
+                % (t64u, t128f, st128f["sweeps"]))
         del ref_psi
         torch.cuda.empty_cache()
 

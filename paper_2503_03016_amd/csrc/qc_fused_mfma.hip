@@ -327,7 +327,7 @@ bool mfma_args(int n, const FusedGeom &g, MfmaArgs<C> &a) {
         } else {
             wave_bit[j] = -1;
             hi_rank[j] = hi_seen;
-            a.sel_pos[hi_seen++] = uint8_t(g.sel_pos[j]);
+            a.sel_pos[hi_seen++] = g.sel_pos[j];
         }
     }
     a.n_sel = hi_seen;
