@@ -58,49 +58,81 @@ __global__ __launch_bounds__(kBlock) void k_pauli_apply(const cx<R> *psi, cx<R> 
     }
 }
 
-// Im <lam|G|phi> over the pairs of compressed bit b of one tile (partial of
-// this thread); G: 1 = X, 2 = Y, 3 = Z.
+// Im <lam|G|phi> over one pair (i0, i1 = i0 with bit b set) for generator
+// G (1 = X, 2 = Y, 3 = Z), in the state's precision; the caller accumulates
+// in FP64.  conj(a) b = (ar br + ai bi) + i (ar bi - ai br).
 template <typename R>
-__device__ inline double grad_partial(const cx<R> *f, const cx<R> *l, int m, int b, int gen) {
-    double acc = 0.0;
-    for (int g = threadIdx.x; g < (1 << (m - 1)); g += kBlock) {
-        const uint32_t i0 = uint32_t(insert_zero(uint64_t(g), b)), i1 = i0 | (1u << b);
-        const double f0r = f[i0].re, f0i = f[i0].im, f1r = f[i1].re, f1i = f[i1].im;
-        const double l0r = l[i0].re, l0i = l[i0].im, l1r = l[i1].re, l1i = l[i1].im;
-        // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-        if (gen == 3)
-            acc += (l0r * f0i - l0i * f0r) - (l1r * f1i - l1i * f1r);
-        else if (gen == 1)
-            acc += (l0r * f1i - l0i * f1r) + (l1r * f0i - l1i * f0r);
-        else
-            acc += -(l0r * f1r + l0i * f1i) + (l1r * f0r + l1i * f0i);
-    }
-    return acc;
+__device__ inline R grad_pair(cx<R> f0, cx<R> f1, cx<R> l0, cx<R> l1, int gen) {
+    if (gen == 3) return (l0.re * f0.im - l0.im * f0.re) - (l1.re * f1.im - l1.im * f1.re);
+    if (gen == 1) return (l0.re * f1.im - l0.im * f1.re) + (l1.re * f0.im - l1.im * f0.re);
+    return -(l0.re * f1.re + l0.im * f1.im) + (l1.re * f0.re + l1.im * f0.im);
 }
 
-// grad_partial, then (u on bit b) applied to both tiles in the same pass.
-template <typename R>
-__device__ inline double grad_partial_apply(cx<R> *f, cx<R> *l, int m, int b, int gen,
-                                            const double *u) {
-    const cx<R> u0 = tile::ld_u<R>(u, 0), u1 = tile::ld_u<R>(u, 1), u2 = tile::ld_u<R>(u, 2),
-                u3 = tile::ld_u<R>(u, 3);
-    const cx<R> z{R(0), R(0)};
+// The one-qubit matrix u = [u0 u1; u2 u3] on the pair (a0, a1): general
+// complex, real (imaginary parts zero) or diagonal.
+enum { APPLY_NONE = 0, APPLY_GENERAL = 1, APPLY_REAL = 2, APPLY_DIAG = 3 };
+template <typename R, int A>
+__device__ inline void apply_pair(cx<R> &a0, cx<R> &a1, cx<R> u0, cx<R> u1, cx<R> u2, cx<R> u3) {
+    if (A == APPLY_GENERAL) {
+        const cx<R> z{R(0), R(0)};
+        const cx<R> b0 = cfma(u1, a1, cfma(u0, a0, z));
+        a1 = cfma(u3, a1, cfma(u2, a0, z));
+        a0 = b0;
+    } else if (A == APPLY_REAL) {
+        const cx<R> b0{u0.re * a0.re + u1.re * a1.re, u0.re * a0.im + u1.re * a1.im};
+        a1 = cx<R>{u2.re * a0.re + u3.re * a1.re, u2.re * a0.im + u3.re * a1.im};
+        a0 = b0;
+    } else if (A == APPLY_DIAG) {
+        a0 = cmul(u0, a0);
+        a1 = cmul(u3, a1);
+    }
+}
+
+// Im <lam|G|phi> over the pairs of compressed bit b of one tile (partial of
+// this thread).  Unless A == APPLY_NONE, the one-qubit matrix u on bit b is
+// then applied to both tiles in the same pass (the partial uses the values
+// before the update).  tile::kItems independent pairs per thread per step.
+template <typename R, int A>
+__device__ inline double grad_pairs(cx<R> *f, cx<R> *l, int m, int b, int gen, const double *u) {
+    cx<R> u0{}, u1{}, u2{}, u3{};
+    if (A != APPLY_NONE) {
+        u0 = tile::ld_u<R>(u, 0);
+        u1 = tile::ld_u<R>(u, 1);
+        u2 = tile::ld_u<R>(u, 2);
+        u3 = tile::ld_u<R>(u, 3);
+    }
+    const int npairs = 1 << (m - 1);
+    const uint32_t bit = 1u << b;
     double acc = 0.0;
-    for (int g = threadIdx.x; g < (1 << (m - 1)); g += kBlock) {
-        const uint32_t i0 = uint32_t(insert_zero(uint64_t(g), b)), i1 = i0 | (1u << b);
-        const cx<R> f0 = f[i0], f1 = f[i1], l0 = l[i0], l1 = l[i1];
-        const double f0r = f0.re, f0i = f0.im, f1r = f1.re, f1i = f1.im;
-        const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
-        if (gen == 3)
-            acc += (l0r * f0i - l0i * f0r) - (l1r * f1i - l1i * f1r);
-        else if (gen == 1)
-            acc += (l0r * f1i - l0i * f1r) + (l1r * f0i - l1i * f0r);
-        else
-            acc += -(l0r * f1r + l0i * f1i) + (l1r * f0r + l1i * f0i);
-        f[i0] = cfma(u1, f1, cfma(u0, f0, z));
-        f[i1] = cfma(u3, f1, cfma(u2, f0, z));
-        l[i0] = cfma(u1, l1, cfma(u0, l0, z));
-        l[i1] = cfma(u3, l1, cfma(u2, l0, z));
+    for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * tile::kItems) {
+        uint32_t i0[tile::kItems];
+        bool ok[tile::kItems];
+        cx<R> f0[tile::kItems], f1[tile::kItems], l0[tile::kItems], l1[tile::kItems];
+#pragma unroll
+        for (int k = 0; k < tile::kItems; ++k) {
+            const int g = g0 + k * kBlock;
+            ok[k] = g < npairs;
+            i0[k] = tile::ins0(uint32_t(g), b);
+            if (ok[k]) {
+                f0[k] = f[i0[k]];
+                f1[k] = f[i0[k] | bit];
+                l0[k] = l[i0[k]];
+                l1[k] = l[i0[k] | bit];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < tile::kItems; ++k) {
+            if (!ok[k]) continue;
+            acc += double(grad_pair<R>(f0[k], f1[k], l0[k], l1[k], gen));
+            if (A != APPLY_NONE) {
+                apply_pair<R, A>(f0[k], f1[k], u0, u1, u2, u3);
+                apply_pair<R, A>(l0[k], l1[k], u0, u1, u2, u3);
+                f[i0[k]] = f0[k];
+                f[i0[k] | bit] = f1[k];
+                l[i0[k]] = l0[k];
+                l[i0[k] | bit] = l1[k];
+            }
+        }
     }
     return acc;
 }
@@ -112,7 +144,20 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
                                                           double *partial, int cols) {
     extern __shared__ unsigned char smem[];
     __shared__ double acc[kAdjointMaxSlots];
-    __shared__ double red[kWaves];
+    // per-wavefront partials of a gradient op, double-buffered: thread 0
+    // adds them into acc at the start of the next op, after the op's own
+    // closing barrier, so a gradient costs no barrier of its own (the
+    // additions keep their order: one slot at a time, wavefronts in order)
+    __shared__ double red[2][kWaves];
+    int pend_slot = -1, pend_buf = 0;
+    auto fold = [&]() {
+        if (pend_slot >= 0 && threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kWaves; ++w) s += red[pend_buf][w];
+            acc[pend_slot] += s;
+        }
+        pend_slot = -1;
+    };
     __shared__ TileOp op_slot[2];
     __shared__ cx<R> ptab[1 << kPhaseTableBits];
     const int T = 1 << a.m;
@@ -135,18 +180,21 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             const bool next = o + 1 < a.n_ops;
             tile::OpStage st;
             if (next) tile::stage_fetch(st, &ops[o + 1]);
+            fold();
             if ((base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
-                if (op.kind == TILE_GRAD || op.kind == TILE_GRAD_APPLY) {
-                    double v = wave_sum(op.kind == TILE_GRAD
-                                            ? grad_partial<R>(lp, ll, a.m, op.b0, op.b1)
-                                            : grad_partial_apply<R>(lp, ll, a.m, op.b0, op.b1, op.u));
-                    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-                    __syncthreads();
-                    if (threadIdx.x == 0) {
-                        double s = 0.0;
-                        for (int w = 0; w < kWaves; ++w) s += red[w];
-                        acc[op.pad] += s;
+                if (op.kind == TILE_GRAD || op.kind == TILE_GRAD_APPLY ||
+                    op.kind == TILE_GRAD_APPLY_REAL || op.kind == TILE_GRAD_APPLY_DIAG) {
+                    double v;
+                    switch (op.kind) {   // uniform
+                    case TILE_GRAD: v = grad_pairs<R, APPLY_NONE>(lp, ll, a.m, op.b0, op.b1, nullptr); break;
+                    case TILE_GRAD_APPLY_REAL: v = grad_pairs<R, APPLY_REAL>(lp, ll, a.m, op.b0, op.b1, op.u); break;
+                    case TILE_GRAD_APPLY_DIAG: v = grad_pairs<R, APPLY_DIAG>(lp, ll, a.m, op.b0, op.b1, op.u); break;
+                    default: v = grad_pairs<R, APPLY_GENERAL>(lp, ll, a.m, op.b0, op.b1, op.u); break;
                     }
+                    v = wave_sum(v);
+                    if ((threadIdx.x & 63) == 0) red[o & 1][threadIdx.x >> 6] = v;
+                    pend_slot = op.pad;
+                    pend_buf = o & 1;
                 } else if (op.kind == TILE_PHASES) {
                     const bool any = tile::phases_table<R>(ptab, base, op);   // uniform
                     __syncthreads();
@@ -162,6 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
             if (next) tile::stage_store(st, &op_slot[(o + 1) & 1]);
             __syncthreads();
         }
+        fold();
         tile::tile_store<R>(phi, lp, base, off_lo, mask, T);
         tile::tile_store<R>(lam, ll, base, off_lo, mask, T);
         __syncthreads();

@@ -1700,11 +1700,15 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
                 }
                 // the reduction and the inverse rotation share one pass
                 qcx::TileOp gop{};
-                gop.kind = qcx::TILE_GRAD_APPLY;
+                const double *mu = bwd[j].matrix;
+                const bool real = mu[1] == 0 && mu[3] == 0 && mu[5] == 0 && mu[7] == 0;
+                const bool diag = mu[2] == 0 && mu[3] == 0 && mu[4] == 0 && mu[5] == 0;
+                gop.kind = real ? qcx::TILE_GRAD_APPLY_REAL
+                                : diag ? qcx::TILE_GRAD_APPLY_DIAG : qcx::TILE_GRAD_APPLY;
                 gop.b0 = B.cidx(bitpos(n, bwd[j].targets[0]));
                 gop.b1 = gen_of[j];
                 gop.pad = int32_t(slot_row.size());
-                for (int i = 0; i < 8; ++i) gop.u[i] = bwd[j].matrix[i];
+                for (int i = 0; i < 8; ++i) gop.u[i] = mu[i];
                 slot_row.push_back(rot_row[j]);
                 B.add_op(gop, 1u << gop.b0);
                 continue;

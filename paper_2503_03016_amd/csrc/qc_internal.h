@@ -106,9 +106,11 @@ struct Mat2d {
 // TILE_GRAD_APPLY (adjoint kernel only): TILE_GRAD on bit b0, then the
 // one-qubit matrix u[0..7] applied to both vectors on the same bit, in one
 // pass over the pairs (the partial uses the values before the update).
+// TILE_GRAD_APPLY_REAL / _DIAG: the same for a matrix whose imaginary parts
+// (inverse RY) or off-diagonal entries (inverse RZ) are all zero.
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
-    TILE_PHASES = 5, TILE_GRAD_APPLY = 6
+    TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8
 };
 constexpr int kTileMaxBits = 16;
 constexpr int kTilePhaseTerms = 16;
