@@ -203,8 +203,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
                         tile::phases_apply<R>(ll, a.m, ptab, uint32_t(op.b1));
                     }
                 } else {
-                    tile::apply_one<R>(lp, a.m, op);
-                    tile::apply_one<R>(ll, a.m, op);
+                    // the backward op lists hold no TILE_KRON (built with kron_max 1)
+                    tile::apply_one<R, false>(lp, a.m, op);
+                    tile::apply_one<R, false>(ll, a.m, op);
                 }
             }
             if (next) tile::stage_store(st, &op_slot[(o + 1) & 1]);

@@ -855,6 +855,7 @@ struct TileOpBuilder {
     std::vector<qcx::TileOp> &out;
     cd held[qcx::kTileMaxBits][4];
     uint32_t held_bits = 0;
+    int kron_max = qcx::kKronMax;   // 1: held bits are flushed one op per bit
     qcx::TileOp ph{};
     int nph = 0;
     uint32_t ph_bits = 0;
@@ -886,34 +887,41 @@ struct TileOpBuilder {
     // Two held gates on bits a and b: one two-qubit op with the Kronecker
     // product U_a (x) U_b (local index 2 bit(a) + bit(b)), one pass over
     // the tile instead of two at the same flops per amplitude.
-    void flush_pair(int a, int b) {
-        const cd *ua = held[a], *ub = held[b];
+    // one-qubit matrices held on 2..kKronMax bits: one op, applied to each
+    // group of amplitudes in registers
+    void flush_group(const int *bits, int g) {
+        if (g < 2) {   // a single bit is a plain one-qubit op
+            for (int j = 0; j < g; ++j) flush_bit(bits[j]);
+            return;
+        }
         qcx::TileOp op{};
-        op.kind = qcx::TILE_DENSE2;
-        op.b0 = a;
-        op.b1 = b;
-        for (int r = 0; r < 4; ++r)
-            for (int c = 0; c < 4; ++c) {
-                const cd v = ua[2 * (r >> 1) + (c >> 1)] * ub[2 * (r & 1) + (c & 1)];
-                op.u[2 * (4 * r + c)] = v.real();
-                op.u[2 * (4 * r + c) + 1] = v.imag();
+        op.kind = qcx::TILE_KRON;
+        op.b0 = g;
+        op.b1 = 0;
+        for (int j = 0; j < g; ++j) {
+            op.b1 |= bits[j] << (5 * j);
+            for (int e = 0; e < 4; ++e) {
+                op.u[8 * j + 2 * e] = held[bits[j]][e].real();
+                op.u[8 * j + 2 * e + 1] = held[bits[j]][e].imag();
             }
+            held_bits &= ~(1u << bits[j]);
+        }
         out.push_back(op);
-        held_bits &= ~((1u << a) | (1u << b));
     }
     void flush_bits(uint32_t bits) {
         bits &= held_bits;
-        int first = -1;
+        int group[qcx::kKronMax], g = 0;
         for (int b = 0; bits >> b; ++b) {
             if (!((bits >> b) & 1)) continue;
-            if (first < 0) {
-                first = b;
-            } else {
-                flush_pair(first, b);
-                first = -1;
+            group[g++] = b;
+            if (g == kron_max) {
+                if (g == 1) flush_bit(group[0]);
+                else flush_group(group, g);
+                g = 0;
             }
         }
-        if (first >= 0) flush_bit(first);
+        if (g == 1) flush_bit(group[0]);
+        else if (g > 1) flush_group(group, g);
     }
     void emit_phases() {
         if (nph == 1) {
@@ -1692,6 +1700,7 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
     for (const TileRun &r : runs) {
         if (r.P == 0) return fail(QC_ERR_UNSUPPORTED, "adjoint op cannot be tiled");
         TileOpBuilder B(n, r.P, tops);
+        B.kron_max = 1;   // k_adjoint_tiles is compiled without TILE_KRON
         for (int j : r.gates) {
             if (rot_row[j] >= 0) {
                 if (int(slot_row.size()) == qcx::kAdjointMaxSlots) {

@@ -108,10 +108,16 @@ struct Mat2d {
 // pass over the pairs (the partial uses the values before the update).
 // TILE_GRAD_APPLY_REAL / _DIAG: the same for a matrix whose imaginary parts
 // (inverse RY) or off-diagonal entries (inverse RZ) are all zero.
+// TILE_KRON: b0 = g (2..kKronMax) one-qubit matrices on the distinct
+// compressed bits (b1 >> 5j) & 31, j < g, ascending; matrix j is u[8j ..
+// 8j + 7].  They commute, so each group of 2^g amplitudes is loaded once and
+// the matrices are applied one after another in registers.  No conditions.
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
-    TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8
+    TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
+    TILE_KRON = 9
 };
+constexpr int kKronMax = 3;
 constexpr int kTileMaxBits = 16;
 constexpr int kTilePhaseTerms = 16;
 constexpr int kPhaseTableBits = 8;   // in-tile bits a TILE_PHASES op may test

@@ -30,9 +30,71 @@ __device__ inline uint32_t ins0(uint32_t g, int p) {
     return ((g >> p) << (p + 1)) | (g & ((1u << p) - 1u));
 }
 
+// Values every lane holds the same (op fields read from LDS), moved to
+// scalar registers so that they take no vector registers.
+__device__ inline uint32_t uniform(uint32_t x) { return uint32_t(__builtin_amdgcn_readfirstlane(int(x))); }
+__device__ inline float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ inline double uniform(double x) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// TILE_KRON with G matrices: one group of 2^G amplitudes per thread per
+// step, loaded once; matrix j acts on the pairs that differ in bit j of the
+// local index.  Bit positions and matrix entries are kept in scalar
+// registers.
+template <typename R, int G>
+__device__ inline void apply_kron(cx<R> *lds, int m, const TileOp &op) {
+    constexpr int D = 1 << G;
+    const uint32_t bits = uniform(uint32_t(op.b1));
+    int bit[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) bit[j] = (bits >> (5 * j)) & 31;
+    uint32_t off[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        off[r] = 0;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if ((r >> j) & 1) off[r] |= 1u << bit[j];
+    }
+    cx<R> um[G][4];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            um[j][e] = cx<R>{uniform(R(op.u[8 * j + 2 * e])), uniform(R(op.u[8 * j + 2 * e + 1]))};
+    const cx<R> z{R(0), R(0)};
+    const int ngroups = (1 << m) >> G;
+    for (int grp = threadIdx.x; grp < ngroups; grp += kBlock) {
+        uint32_t base = uint32_t(grp);
+#pragma unroll
+        for (int j = 0; j < G; ++j) base = ins0(base, bit[j]);   // ascending positions
+        cx<R> a[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) a[r] = lds[base | off[r]];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+                if (!((r >> j) & 1)) {
+                    const cx<R> a0 = a[r], a1 = a[r | (1 << j)];
+                    a[r] = cfma(um[j][1], a1, cfma(um[j][0], a0, z));
+                    a[r | (1 << j)] = cfma(um[j][3], a1, cfma(um[j][2], a0, z));
+                }
+#pragma unroll
+        for (int r = 0; r < D; ++r) lds[base | off[r]] = a[r];
+    }
+}
+
 // Apply one op to the tile in `lds` (no barrier).  Ops whose conditions on
-// bits outside the tile fail are skipped by the caller.
-template <typename R>
+// bits outside the tile fail are skipped by the caller.  KRON = false
+// compiles TILE_KRON out (for kernels whose op lists are built without it,
+// where its registers would lower occupancy).
+template <typename R, bool KRON = true>
 __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
     const int T = 1 << m;
     const uint32_t cm = op.cmask_lo, cv = op.cval_lo;
@@ -134,6 +196,12 @@ __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
             }
         }
     } break;
+    case TILE_KRON:
+        if constexpr (KRON) {
+            if (op.b0 == 2) apply_kron<R, 2>(lds, m, op);
+            else if (op.b0 == 3) apply_kron<R, 3>(lds, m, op);
+        }
+        break;
     default: break;   // TILE_GRAD, TILE_PHASES (see apply_phases) and unknown kinds
     }
 }
