@@ -79,25 +79,39 @@ def cpu_baseline(n_cpu: int, layers: int, budget_s: float):
     import workloads as W
 
     ops = W.brickwork(n_cpu, layers, seed=32, entangler="CZ")
-    psi = oracle.basis_state(n_cpu, 0)
     sweep = 2.0 * (1 << n_cpu) * 16.0
-    done = 0
-    t0 = time.perf_counter()
-    for op in ops:
-        psi = oracle.run([op], psi)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+
+    def run(limit_s):
+        psi = oracle.basis_state(n_cpu, 0)
+        done = 0
+        t0 = time.perf_counter()
+        for op in ops:
+            psi = oracle.run([op], psi)
+            done += 1
+            if time.perf_counter() - t0 > limit_s:
+                break
+        return done, time.perf_counter() - t0
+
+    cores = oracle.threads()
+    done, dt = run(budget_s)
+    # the same sample on one thread (a third of the budget)
+    oracle.set_threads(1)
+    try:
+        done1, dt1 = run(budget_s / 3.0)
+    finally:
+        oracle.set_threads(cores)
     return {
         "value": round(done * sweep / dt / 1e9, 3),
         "unit": "GB/s",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": "FP64 oracle, brickwork %d qubits (Haar U(2) + CZ, seed 32), first %d of %d "
                   "gates, complex128, one state pass per gate; %.1f s wall, %.2f gates/s"
                   % (n_cpu, done, len(ops), dt, done / dt),
         "gates_per_s": round(done / dt, 4),
+        "one_thread": {"value": round(done1 * sweep / dt1 / 1e9, 3), "unit": "GB/s",
+                       "gates_per_s": round(done1 / dt1, 4), "gates": done1,
+                       "seconds": round(dt1, 2)},
     }
 
 
