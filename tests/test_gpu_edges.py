@@ -203,3 +203,28 @@ def test_fused_launches_on_two_streams(qc, G):
     ref = oracle.run(ops_a, oracle.basis_state(n, 0))
     err = np.linalg.norm(seq[0] - ref) / np.linalg.norm(ref)
     assert err < 1e-5, err
+
+
+def test_fused_c64_32_qubit_circuit_then_inverse(qc, G):
+    """The 32-qubit, depth-40 brickwork at full size, in the launch
+    configuration bench.py times (fused 5-qubit blocks, complex64, default
+    knobs): after the circuit the norm is 1 within the FP32 bound, and the
+    circuit followed by its inverse (reversed gates, adjoint matrices, also
+    fused) returns |0...0>.  The unfused complex128 comparison at this size
+    is bench.py's err_rel_vs_c128; at 30 qubits it is a test above."""
+    n, ops = W.config_brickwork32()
+    gts = G.gate_tuples(ops)
+    inv = [(tg, cs, cv, np.conj(np.asarray(m)).T.copy()) for tg, cs, cv, m in reversed(gts)]
+    t = qc.new_state(n, torch.complex64)
+    qc.state_init(t, 0)
+    st = qc.apply_circuit(t, qc.GateList(gts), mode=qc.QC_EXEC_FUSED, fuse_k=5)
+    assert st["fused_blocks"] < 70
+    p = qc.probs(t, [0]).cpu().numpy()
+    assert abs(p.sum() - 1.0) < 1e-5
+    qc.apply_circuit(t, qc.GateList(inv), mode=qc.QC_EXEC_FUSED, fuse_k=5)
+    p0 = qc.probs(t, list(range(8))).cpu().numpy()     # outcome 0 of the first 8 qubits
+    amp0 = t[0].item()
+    assert abs(abs(amp0) ** 2 - 1.0) < 1e-4, amp0
+    assert abs(p0[0] - 1.0) < 1e-4
+    del t
+    torch.cuda.empty_cache()
