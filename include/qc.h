@@ -32,9 +32,20 @@
  *   that fails validation enqueues nothing and leaves the state untouched.
  *   qc_last_error() gives a human-readable reason (per host thread).
  *   No C++ exception crosses this interface.
- * - The library owns a small per-device workspace (reduction partials and a
- *   staging ring for matrices), allocated on first use.  Calls that use it
- *   must not run concurrently on different streams of the same device.
+ * - The library owns a small per-device workspace (reduction partials) and a
+ *   64 MiB staging ring (pinned host memory copied to device memory on the
+ *   call's stream) for matrices and op lists, both allocated on first use.
+ *   Every call takes its own ring slot, so gate and circuit calls issued
+ *   from one host thread may run on different streams at once.  Calls that
+ *   use the reduction workspace (qc_probs, qc_expect_pauli, qc_state_diff,
+ *   qc_sample, qc_collapse, qc_adjoint_grad) must not run concurrently on
+ *   different streams of the same device.  Concurrent calls from several
+ *   host threads are not supported.
+ * - A HIP graph that captures a gate or circuit call re-reads its staged
+ *   matrices from the ring's host memory at every replay: replay it only
+ *   while later calls have not reused those ring slots (a wrap of the ring
+ *   also synchronises the device, which a capture does not allow).
+ *   qc_run_batch is the entry point meant for capture.
  */
 #ifndef QC_H_
 #define QC_H_
