@@ -595,3 +595,24 @@ def test_autograd_energy_function(qc):
     e_ref = oracle.energy(oracle.run(ops, oracle.basis_state(n, 0), th0), terms)
     assert abs(e.item() - e_ref) < 1e-12
     np.testing.assert_allclose(theta.grad.numpy(), 3.0 * g_ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_expect_pauli_many_terms_in_one_pass(qc, dt):
+    """More terms than one tile-pass launch takes (512): 560 diagonal and
+    60 low-X terms all fit the first pass's tile bits, so that pass is
+    split over several launches."""
+    n = 14
+    rng = np.random.default_rng(314)
+    psi0 = W.random_state(n, 23)
+    t = dev(psi0, DT[dt])
+    st = host(t)
+    terms = [("".join(rng.choice(list("IZ"), n)), float(rng.normal())) for _ in range(560)]
+    for _ in range(60):
+        s = list(rng.choice(list("IZ"), n))
+        s[n - 1 - int(rng.integers(0, 6))] = str(rng.choice(list("XY")))   # X/Y on one of the 6 lowest bits
+        terms.append(("".join(s), float(rng.normal())))
+    out = qc.expect_pauli(t, terms, per_term=True).cpu().numpy()
+    ref_terms = np.array([oracle.expect_pauli(st, p).real for p, _ in terms])
+    np.testing.assert_allclose(out[1:], ref_terms, atol=1e-12)
+    assert abs(out[0] - sum(c * r for (_, c), r in zip(terms, ref_terms))) < 1e-10
