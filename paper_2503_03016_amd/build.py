@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqc.so")
 SOURCES = ["qc_api.cpp", "qc_gates.hip", "qc_reduce.hip", "qc_fused_mfma.hip", "qc_tile.hip",
-           "qc_adjoint.hip", "qc_batch.hip", "qc_measure.hip", "qc_expect_tiles.hip"]
+           "qc_adjoint.hip", "qc_batch.hip", "qc_measure.hip", "qc_expect_tiles.hip",
+           "qc_fused_mfma_c128.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -19,9 +20,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-# The fused kernel's tile counter is taken by one lane; the atomic optimizer's
+# The fused kernels' tile counter is taken by one lane; the atomic optimizer's
 # wave-wide rewrite of it would wait on every memory operation in flight.
-EXTRA_FLAGS = {"qc_fused_mfma.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+EXTRA_FLAGS = {"qc_fused_mfma.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+               "qc_fused_mfma_c128.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def build(verbose: bool = False) -> str:

@@ -765,6 +765,25 @@ int fused_apply(qc_state_t s, int k, const int *qubits, int ns, const int *sq,
         e = qcx::launch_fused_mfma_c64(
             s.amp, s.n, g, static_cast<const float *>(dev),
             reinterpret_cast<unsigned *>(static_cast<float *>(dev) + op_floats), stream);
+    } else if (s.dtype == QC_C128 && k == 5 && aligned16 && qcx::fused_mfma_c128_fits(s.n, g)) {
+        // FP64 matrix cores: per selector value Ur, Ui, Ur + Ui, then the
+        // kernel's tile counters, zeroed by the same upload
+        std::vector<double> all(size_t(3 * 1024) << ns);
+        for (int v = 0; v < (1 << ns); ++v)
+            for (int r = 0; r < 32; ++r)
+                for (int c = 0; c < 32; ++c) {
+                    const cd x = u[size_t(v) * dd + size_t(r) * 32 + c];
+                    double *m = all.data() + size_t(v) * 3072;
+                    m[r * 32 + c] = x.real();
+                    m[1024 + r * 32 + c] = x.imag();
+                    m[2048 + r * 32 + c] = x.real() + x.imag();
+                }
+        const size_t op_doubles = all.size();
+        all.resize(op_doubles + qcx::kMfmaTicketBytes / sizeof(double), 0.0);
+        if ((rc = stage(c, all.data(), all.size() * sizeof(double), stream, &dev))) return rc;
+        e = qcx::launch_fused_mfma_c128(
+            s.amp, s.n, g, static_cast<const double *>(dev),
+            reinterpret_cast<unsigned *>(static_cast<double *>(dev) + op_doubles), stream);
     } else if (s.dtype == QC_C64) {
         std::vector<float> f(u.size() * 2);
         for (size_t i = 0; i < u.size(); ++i) {

@@ -203,6 +203,11 @@ hipError_t launch_fused_valu(void *amp, int dtype, int n, const FusedGeom &g,
 constexpr size_t kMfmaTicketBytes = 64 * (1 << kMaxSel);
 hipError_t launch_fused_mfma_c64(void *amp, int n, const FusedGeom &g, const float *a_dev,
                                  unsigned *tickets, hipStream_t s);
+// complex128 on the FP64 matrix cores: a_dev per matrix [3][32][32] doubles
+// (Ur, Ui, Ur + Ui); fused_mfma_c128_fits tells whether a geometry fits
+bool fused_mfma_c128_fits(int n, const FusedGeom &g);
+hipError_t launch_fused_mfma_c128(void *amp, int n, const FusedGeom &g, const double *a_dev,
+                                  unsigned *tickets, hipStream_t s);
 hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_pos,
                              bool identity, double *out, hipStream_t s);
 hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const int *pos,

@@ -194,6 +194,31 @@ def test_fused_mfma_target_positions(qc, n, tile_bits):
         qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, old)
 
 
+@pytest.mark.parametrize("n", [12, 13, 16, 20])
+def test_fused_mfma_c128_target_positions(qc, n):
+    """The complex128 FP64 matrix-core path (32 x 128 tiles) for every kind
+    of target placement, and multiplexed blocks with selectors in and above
+    the tile, against the oracle at the complex128 tolerance."""
+    rng = np.random.default_rng(500 + n)
+    psi0 = W.random_state(n, 3000 + n)
+    cases = [list(range(n - 5, n)), list(range(5)), [n - 1, 0, n // 2, 2, n - 3],
+             list(reversed(range(n - 5, n))), list(rng.permutation(n)[:5])]
+    for qs in cases:
+        u = random_unitary(32, rng)
+        t = dev(psi0, torch.complex128)
+        qc.apply_fused_k(t, qs, u)
+        check(host(t), oracle.apply(psi0, qs, u), torch.complex128, ngates=8)
+    if n >= 14:
+        layouts = [(list(range(5)), [n - 6, n - 7]),           # selectors among the columns
+                   (list(range(n - 5, n)), [0, 1]),            # selectors above the tile
+                   ([1, 2, 3, 4, 5], [n - 6, 0])]              # one of each
+        for qs, sel in layouts:
+            us = np.stack([random_unitary(32, rng) for _ in range(1 << len(sel))])
+            t = dev(psi0, torch.complex128)
+            qc.apply_multiplexed(t, qs, sel, us)
+            check(host(t), mux_oracle(psi0, qs, sel, us), torch.complex128, ngates=8)
+
+
 def mux_oracle(psi, qs, sel, us):
     """A multiplexed gate as 2^c controlled k-qubit gates, one per selector
     value v, each controlled on the selector qubits reading v."""
