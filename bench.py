@@ -232,6 +232,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-ref", action="store_true", help="skip the unfused complex128 run")
+    ap.add_argument("--c128-fused-only", action="store_true",
+                    help="run only the circuit fused on a complex128 state (--steps runs), "
+                         "each followed by one state copy; for profiling that kernel")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the unfused complex64 and fused complex128 runs that separate the "
                          "precision gain from the fusion gain")
@@ -266,6 +269,27 @@ def main() -> int:
     plan_ms = (time.perf_counter() - t0) * 1e3
     log("workload: %d qubits, %d gates, %d fused blocks (plan %.1f ms)"
         % (n, len(ops), nblocks, plan_ms))
+
+    if args.c128_fused_only:
+        # the same circuit fused on a complex128 state, --steps times, each
+        # run followed by one plain copy of the state (the scale of HBM byte
+        # counters); for profiling the complex128 matrix-core kernel alone
+        psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(psi)
+        times = []
+        for _ in range(max(1, args.steps)):
+            qc.state_init(psi, 0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = qc.apply_circuit(psi, gl, mode=qc.QC_EXEC_FUSED, fuse_k=5)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            qc.state_copy(dst, psi)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "brickwork %d qubits, depth %d, complex128, fused 5-qubit blocks"
+                          % (n, layers), "runs": len(times), "sweeps": st["sweeps"],
+                          "s_per_run": [round(t, 4) for t in times]}), flush=True)
+        return 0
 
     psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
