@@ -137,8 +137,11 @@ __device__ inline double grad_pairs(cx<R> *f, cx<R> *l, int m, int b, int gen, c
     return acc;
 }
 
+// At most 128 VGPRs (4 wavefronts per SIMD): two workgroups per CU, which
+// their LDS (two tiles of at most 32 KiB) allows.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
                                                           const TileOp *ops,
                                                           const int32_t *slot_row, int n_slots,
                                                           double *partial, int cols) {
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
         pend_slot = -1;
     };
     __shared__ TileOp op_slot[2];
-    __shared__ cx<R> ptab[1 << kPhaseTableBits];
+    __shared__ tile::PhaseTables<R> pt;
     const int T = 1 << a.m;
     cx<R> *lp = reinterpret_cast<cx<R> *>(smem);
     cx<R> *ll = lp + T;
@@ -196,11 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiles(cx<R> *phi, cx<R> *lam
                     pend_slot = op.pad;
                     pend_buf = o & 1;
                 } else if (op.kind == TILE_PHASES) {
-                    const bool any = tile::phases_table<R>(ptab, base, op);   // uniform
+                    const bool any = tile::phases_table<R>(pt.tab, pt.hix, a.m, base, op, op.b0,
+                                                           uint32_t(op.b1));   // uniform
                     __syncthreads();
                     if (any) {
-                        tile::phases_apply<R>(lp, a.m, ptab, uint32_t(op.b1));
-                        tile::phases_apply<R>(ll, a.m, ptab, uint32_t(op.b1));
+                        tile::phases_apply<R>(lp, a.m, pt.tab, pt.hix, uint32_t(op.b1));
+                        tile::phases_apply<R>(ll, a.m, pt.tab, pt.hix, uint32_t(op.b1));
                     }
                 } else {
                     // the backward op lists hold no TILE_KRON (built with kron_max 1)

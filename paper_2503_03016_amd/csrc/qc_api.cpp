@@ -1061,12 +1061,58 @@ struct TileOpBuilder {
     }
 };
 
+// An unconditioned one-qubit op followed by a phase op becomes one
+// TILE_DENSE1_PHASES op: one pass over the tile instead of two.  Only the
+// ops from index `begin` on (one run's list) are merged.
+void merge_dense_phases(std::vector<qcx::TileOp> &ops, size_t begin) {
+    std::vector<qcx::TileOp> out(ops.begin(), ops.begin() + begin);
+    out.reserve(ops.size());
+    for (size_t k = begin; k < ops.size(); ++k) {
+        const qcx::TileOp &d = ops[k];
+        if (k + 1 < ops.size() && d.kind == qcx::TILE_DENSE1 && d.cmask_lo == 0 && d.cmask_hi == 0) {
+            const qcx::TileOp &p = ops[k + 1];
+            qcx::TileOp mo{};
+            bool ok = false;
+            if (p.kind == qcx::TILE_PHASES && p.cmask_lo == 0 && p.cmask_hi == 0) {
+                mo = p;          // terms and their bit set b1
+                mo.pad = p.b0;   // term count
+                ok = true;
+            } else if (p.kind == qcx::TILE_PHASE &&
+                       __builtin_popcount(p.cmask_lo) <= qcx::kPhaseTableBits) {
+                mo.pm_lo[0] = p.cmask_lo;   // the op's conditions become the term's
+                mo.pv_lo[0] = p.cval_lo;
+                mo.pm_hi[0] = p.cmask_hi;
+                mo.pv_hi[0] = p.cval_hi;
+                mo.u[0] = p.u[0];
+                mo.u[1] = p.u[1];
+                mo.pad = 1;
+                mo.b1 = int32_t(p.cmask_lo);
+                ok = true;
+            }
+            if (ok) {
+                mo.kind = qcx::TILE_DENSE1_PHASES;
+                mo.b0 = d.b0;
+                mo.cmask_lo = mo.cval_lo = 0;
+                mo.cmask_hi = mo.cval_hi = 0;
+                for (int i = 0; i < 8; ++i) mo.u1[i] = d.u[i];
+                out.push_back(mo);
+                ++k;
+                continue;
+            }
+        }
+        out.push_back(d);
+    }
+    ops.swap(out);
+}
+
 // Convert a list of gates into the op list of one tile run.
 void tile_ops_for(int n, const qc_gate_t *gs, const std::vector<int> &idx, uint64_t P,
                   std::vector<qcx::TileOp> &out) {
+    const size_t begin = out.size();
     TileOpBuilder B(n, P, out);
     for (int i : idx) B.add_gate(gs[i]);
     B.finish();
+    merge_dense_phases(out, begin);
 }
 
 // LDS tile of the tile-run kernel: at most 64 KiB (2^13 complex64 or 2^12

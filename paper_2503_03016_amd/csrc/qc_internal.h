@@ -108,6 +108,9 @@ struct Mat2d {
 // pass over the pairs (the partial uses the values before the update).
 // TILE_GRAD_APPLY_REAL / _DIAG: the same for a matrix whose imaginary parts
 // (inverse RY) or off-diagonal entries (inverse RZ) are all zero.
+// TILE_DENSE1_PHASES: the one-qubit matrix u1 on bit b0 (no conditions),
+// then the pad diagonal terms of a TILE_PHASES op over the bits b1, in one
+// pass over the pairs.
 // TILE_KRON: b0 = g (2..kKronMax) one-qubit matrices on the distinct
 // compressed bits (b1 >> 5j) & 31, j < g, ascending; matrix j is u[8j ..
 // 8j + 7].  They commute, so each group of 2^g amplitudes is loaded once and
@@ -115,7 +118,7 @@ struct Mat2d {
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
-    TILE_KRON = 9
+    TILE_KRON = 9, TILE_DENSE1_PHASES = 10
 };
 constexpr int kKronMax = 3;
 constexpr int kTileMaxBits = 16;
@@ -130,6 +133,7 @@ struct TileOp {
     double u[32];              // complex FP64 entries, interleaved
     uint32_t pm_lo[kTilePhaseTerms], pv_lo[kTilePhaseTerms];   // TILE_PHASES terms
     uint64_t pm_hi[kTilePhaseTerms], pv_hi[kTilePhaseTerms];
+    double u1[8];              // TILE_DENSE1_PHASES: the one-qubit matrix
 };
 struct TileArgs {
     uint64_t n_tiles;

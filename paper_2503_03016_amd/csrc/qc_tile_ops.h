@@ -202,7 +202,7 @@ __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
             else if (op.b0 == 3) apply_kron<R, 3>(lds, m, op);
         }
         break;
-    default: break;   // TILE_GRAD, TILE_PHASES (see apply_phases) and unknown kinds
+    default: break;   // TILE_GRAD, TILE_PHASES, TILE_DENSE1_PHASES (see apply_ops) and unknown kinds
     }
 }
 
@@ -235,45 +235,88 @@ __device__ inline uint32_t deposit_bits(uint32_t e, uint32_t u) {
     return i;
 }
 
-// Fill `tab` (2^|U| entries, LDS) for op; returns false when no term is
-// live for this tile (the op is the identity there).  Caller syncs before
-// using the table.
+// Element i = threadIdx.x + kBlock g of a tile has table index
+// e_lo | hix[g]: e_lo from the thread's low kLoBits bits (fixed per thread),
+// hix[g] from the group number g (the same for every lane), so that no lane
+// compacts bits per element.
+constexpr int kPhaseGroups = 1 << (kTileMaxBits - kLoBits);
+static_assert((1 << kPhaseTableBits) <= kBlock / 2 && (1 << kPhaseTableBits) % 64 == 0,
+              "table entries and group indices use disjoint wavefronts");
+static_assert(kPhaseGroups <= kBlock / 2, "one group index per thread");
+
+// Fill `tab` (2^|U| entries, LDS) and `hix` (one entry per element group)
+// for the first n_terms terms of op, which test the tile bits U; returns
+// false when no term is live for this tile (the op is the identity there).
+// Caller syncs before using the tables.
 template <typename R>
-__device__ inline bool phases_table(cx<R> *tab, uint64_t tile_base, const TileOp &op) {
-    const int nt = op.b0;
-    const uint32_t U = uint32_t(op.b1);
-    uint32_t live = 0;   // terms whose out-of-tile conditions hold for this tile
-    for (int t = 0; t < nt; ++t)
-        if ((tile_base & op.pm_hi[t]) == op.pv_hi[t]) live |= 1u << t;
+__device__ inline R lane_value(R x, int lane);
+template <>
+__device__ inline float lane_value(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+template <>
+__device__ inline double lane_value(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename R>
+__device__ inline bool phases_table(cx<R> *tab, uint32_t *hix, int m, uint64_t tile_base,
+                                    const TileOp &op, int n_terms, uint32_t U_in) {
+    static_assert(kTilePhaseTerms <= 64, "one term per lane");
+    const int nt = int(uniform(uint32_t(n_terms)));
+    const uint32_t U = uniform(U_in);
+    // lane t of every wavefront loads term t (all terms at once, no chain
+    // of dependent LDS reads); the term's fields then reach the other lanes
+    // through readlane
+    const int lane = int(threadIdx.x & 63);
+    const int tl = lane < kTilePhaseTerms ? lane : 0;
+    const uint32_t ml = op.pm_lo[tl], vl = op.pv_lo[tl];
+    const R pr = R(op.u[2 * tl]), pi = R(op.u[2 * tl + 1]);
+    const bool ok = lane < nt && (tile_base & op.pm_hi[tl]) == op.pv_hi[tl];
+    // terms whose out-of-tile conditions hold for this tile
+    const uint32_t live = uniform(uint32_t(__ballot(ok)));
     if (!live) return false;
-    const int entries = 1 << __builtin_popcount(U);
-    for (int e = threadIdx.x; e < entries; e += kBlock) {
-        const uint32_t i = deposit_bits(uint32_t(e), U);
+    const uint32_t entries = 1u << __builtin_popcount(U);
+    const uint32_t e = threadIdx.x;
+    // whole wavefronts enter (the condition is the same for its 64 lanes):
+    // readlane takes the term from a lane that must have computed it, so no
+    // lane may be switched off here; lanes past the table build a dummy entry
+    if ((e & ~63u) < entries) {
+        const uint32_t i = deposit_bits(e < entries ? e : 0u, U);
         cx<R> f{R(1), R(0)};
-        for (int t = 0; t < nt; ++t)
-            if (((live >> t) & 1) && (i & op.pm_lo[t]) == op.pv_lo[t]) f = cmul(f, ld_u<R>(op.u, t));
-        tab[e] = f;
+#pragma unroll
+        for (int t = 0; t < kTilePhaseTerms; ++t) {
+            if (!((live >> t) & 1u)) continue;   // uniform
+            const uint32_t mt = uint32_t(__builtin_amdgcn_readlane(int(ml), t));
+            const uint32_t vt = uint32_t(__builtin_amdgcn_readlane(int(vl), t));
+            const cx<R> p{lane_value(pr, t), lane_value(pi, t)};
+            if ((i & mt) == vt) f = cmul(f, p);
+        }
+        if (e < entries) tab[e] = f;
+    } else if (e >= uint32_t(kBlock / 2)) {
+        const uint32_t g = e - uint32_t(kBlock / 2);
+        const uint32_t groups = m > kLoBits ? 1u << (m - kLoBits) : 1u;
+        if (g < groups) hix[g] = extract_bits(g, U >> kLoBits) << __builtin_popcount(U & (kBlock - 1));
     }
     return true;
 }
 
 // Multiply every amplitude of the tile by its table entry.
 template <typename R>
-__device__ inline void phases_apply(cx<R> *lds, int m, const cx<R> *tab, uint32_t U) {
+__device__ inline void phases_apply(cx<R> *lds, int m, const cx<R> *tab, const uint32_t *hix,
+                                    uint32_t U) {
     const int T = 1 << m;
-    // element i = threadIdx.x + kBlock j: the low kLoBits bits are the thread's
     const uint32_t e_lo = extract_bits(threadIdx.x & (kBlock - 1), U & (kBlock - 1));
-    const uint32_t U_hi = U >> kLoBits;
-    const int lo_count = __builtin_popcount(U & (kBlock - 1));
-    for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
+    for (int i0 = threadIdx.x, g0 = 0; i0 < T; i0 += kBlock * kItems, g0 += kItems) {
         cx<R> v[kItems], f[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int i = i0 + k * kBlock;
-            if (i < T) {
-                const uint32_t e = e_lo | (extract_bits(uint32_t(i) >> kLoBits, U_hi) << lo_count);
+            if (i < T) {   // then g0 + k < max(T / kBlock, 1)
                 v[k] = lds[i];
-                f[k] = tab[e];
+                f[k] = tab[e_lo | hix[g0 + k]];
             }
         }
 #pragma unroll
@@ -284,12 +327,67 @@ __device__ inline void phases_apply(cx<R> *lds, int m, const cx<R> *tab, uint32_
     }
 }
 
+// LDS of a TILE_PHASES op: the product table and the group indices
 template <typename R>
-__device__ inline void apply_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op) {
-    __shared__ cx<R> tab[1 << kPhaseTableBits];
-    const bool any = phases_table<R>(tab, tile_base, op);   // uniform
+struct PhaseTables {
+    cx<R> tab[1 << kPhaseTableBits];
+    uint32_t hix[kPhaseGroups];
+};
+
+template <typename R>
+__device__ inline void apply_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op,
+                                    PhaseTables<R> &pt) {
+    const bool any = phases_table<R>(pt.tab, pt.hix, m, tile_base, op, op.b0, uint32_t(op.b1));
     __syncthreads();
-    if (any) phases_apply<R>(lds, m, tab, uint32_t(op.b1));
+    if (any) phases_apply<R>(lds, m, pt.tab, pt.hix, uint32_t(op.b1));
+}
+
+// TILE_DENSE1_PHASES: pair (i0, i1 = i0 | 2^b) gets the matrix, then each
+// element its table entry.  Thread t takes the pairs g = t + kBlock k; the
+// low kLoBits bits of i0 = ins0(g, b) and of i1 depend on t only, so their
+// part of the table index is found once per thread, and the rest is the
+// group entry hix[i >> kLoBits].
+template <typename R>
+__device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op,
+                                           PhaseTables<R> &pt) {
+    const uint32_t U = uint32_t(op.b1);
+    const bool any = phases_table<R>(pt.tab, pt.hix, m, tile_base, op, op.pad, U);   // uniform
+    __syncthreads();
+    const int T = 1 << m;
+    const int b = op.b0;
+    const uint32_t bit = 1u << b;
+    const cx<R> u0 = ld_u<R>(op.u1, 0), u1 = ld_u<R>(op.u1, 1), u2 = ld_u<R>(op.u1, 2),
+                u3 = ld_u<R>(op.u1, 3);
+    const uint32_t lo = ins0(threadIdx.x, b) & (kBlock - 1);
+    const uint32_t e0_lo = extract_bits(lo, U & (kBlock - 1));
+    const uint32_t e1_lo = extract_bits((lo | bit) & (kBlock - 1), U & (kBlock - 1));
+    const int npairs = T >> 1;
+    for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
+        uint32_t i0[kItems];
+        cx<R> a0[kItems], a1[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int g = g0 + k * kBlock;
+            i0[k] = ins0(uint32_t(g), b);
+            if (g < npairs) {
+                a0[k] = lds[i0[k]];
+                a1[k] = lds[i0[k] | bit];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (g0 + k * kBlock >= npairs) continue;
+            const cx<R> z{R(0), R(0)};
+            cx<R> v0 = cfma(u1, a1[k], cfma(u0, a0[k], z));
+            cx<R> v1 = cfma(u3, a1[k], cfma(u2, a0[k], z));
+            if (any) {
+                v0 = cmul(pt.tab[e0_lo | pt.hix[i0[k] >> kLoBits]], v0);
+                v1 = cmul(pt.tab[e1_lo | pt.hix[(i0[k] | bit) >> kLoBits]], v1);
+            }
+            lds[i0[k]] = v0;
+            lds[i0[k] | bit] = v1;
+        }
+    }
 }
 
 // Op staging: the op being applied is read from one of two LDS slots.
@@ -327,6 +425,7 @@ template <typename R>
 __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const TileOp *ops,
                                  int n_ops, TileOp *slot) {
     if (n_ops <= 0) return;
+    __shared__ PhaseTables<R> pt;
     stage_now(&slot[0], &ops[0]);
     __syncthreads();
     for (int o = 0; o < n_ops; ++o) {
@@ -335,7 +434,8 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
         OpStage st;
         if (next) stage_fetch(st, &ops[o + 1]);
         if ((tile_base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
-            if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op);
+            if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op, pt);
+            else if (op.kind == TILE_DENSE1_PHASES) apply_dense1_phases<R>(lds, m, tile_base, op, pt);
             else apply_one<R>(lds, m, op);
         }
         if (next) stage_store(st, &slot[(o + 1) & 1]);

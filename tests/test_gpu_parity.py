@@ -297,6 +297,39 @@ def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
     check(host(t), ref, DT[dt], ngates=len(ops))
 
 
+@pytest.mark.parametrize("tile_bits", [13, 10, 7])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [8, 16])
+def test_tiled_dense_then_phases(qc, G, dt, n, tile_bits):
+    """Tile runs where a one-qubit gate is followed by diagonal terms (the
+    pattern a tile run applies in one pass): QFT, and random one-qubit gates
+    each followed by 1-4 controlled phases and CZs whose qubits lie inside
+    and outside the tile, including single terms with a control outside."""
+    rng = np.random.default_rng(7 * n + tile_bits)
+    rand_ops = []
+    for _ in range(40):
+        q = int(rng.integers(0, n))
+        rand_ops.append(W.Op("U", (q,), matrix=random_unitary(2, rng)))
+        for _ in range(int(rng.integers(1, 5))):
+            a, b = [int(x) for x in rng.permutation(n)[:2]]
+            if rng.integers(0, 3) == 0:
+                rand_ops.append(W.Op("CZ", (a, b)))
+            else:
+                rand_ops.append(W.Op("CP", (a, b), angle=float(rng.uniform(0, 6))))
+    old = qc.get_knob(qc.QC_KNOB_TILE_BITS)
+    try:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, tile_bits)
+        for ops in (W.qft(n), rand_ops):
+            psi0 = W.random_state(n, 90 + n)
+            ref = oracle.run(ops, psi0)
+            t = dev(psi0, DT[dt])
+            st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=2)
+            assert st["sweeps"] < len(ops)
+            check(host(t), ref, DT[dt], ngates=len(ops))
+    finally:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_brickwork12_config(qc, G, dt, mode):
