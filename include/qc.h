@@ -199,6 +199,15 @@ int qc_apply_fused_k(qc_state_t s, int k, const int *qubits, const double *u, vo
 int qc_apply_multiplexed(qc_state_t s, int k, const int *qubits, int n_sel,
                          const int *sel_qubits, const double *u, void *stream);
 
+/* Relabel the qubits (the permutation gates of section 5.4 taken
+ * together): qubit q of the register becomes qubit perm[q], i.e. the
+ * amplitude at basis state x moves to the basis state whose bit for label
+ * perm[q] is x's bit for label q.  perm must hold a permutation of 0..n-1
+ * (QC_ERR_QUBIT otherwise, QC_ERR_ARG if NULL).  One sweep over the state when the relabelling is
+ * its own inverse (any set of disjoint SWAPs), two otherwise; none for the
+ * identity.  In place; the state's size and precision are unchanged. */
+int qc_permute_qubits(qc_state_t s, const int *perm, void *stream);
+
 /* Apply a gate list in order.  mode QC_EXEC_UNFUSED launches one kernel per
  * gate; QC_EXEC_FUSED first groups the gates into blocks (host FP64 matrix
  * products, see qc_fuse_plan) and applies each block with one
@@ -207,7 +216,11 @@ int qc_apply_multiplexed(qc_state_t s, int k, const int *qubits, int n_sel,
  * at n.  A gate is moved ahead of another only when the two commute (no
  * shared qubit, or every shared qubit is one on which both act diagonally:
  * a control, or a target of a diagonal matrix), so the result is the
- * ordered product.  stats may be NULL. */
+ * ordered product.  In the fused and tiled modes a SWAP gate (two targets,
+ * no controls, exactly the 4 x 4 permutation matrix of section 5.4) moves
+ * no data: the later gates are applied with its two qubits exchanged, and
+ * the relabelling of all such SWAPs is applied at the end with
+ * qc_permute_qubits (counted in stats).  stats may be NULL. */
 int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode,
                      int fuse_k, qc_exec_stats_t *stats, void *stream);
 

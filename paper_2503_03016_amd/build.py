@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqc.so")
 SOURCES = ["qc_api.cpp", "qc_gates.hip", "qc_reduce.hip", "qc_fused_mfma.hip", "qc_tile.hip",
            "qc_adjoint.hip", "qc_batch.hip", "qc_measure.hip", "qc_expect_tiles.hip",
-           "qc_fused_mfma_c128.hip"]
+           "qc_fused_mfma_c128.hip", "qc_permute.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1331,6 +1331,70 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *bl
     return QC_OK;
 }
 
+namespace {
+
+// Move the bit of label from[q] to label to[q] for every qubit q.
+int relabel(qc_state_t s, const int *from, const int *to, qc_exec_stats_t &st, void *stream) {
+    uint32_t sigma[QC_MAX_QUBITS];
+    for (int q = 0; q < s.n; ++q) sigma[bitpos(s.n, from[q])] = uint32_t(bitpos(s.n, to[q]));
+    int sweeps = 0;
+    const hipError_t e = qcx::launch_permute_bits(s.amp, s.dtype, s.n, sigma, &sweeps,
+                                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "permute");
+    st.launches += sweeps;
+    st.sweeps += sweeps;
+    st.state_bytes += sweeps * sweep_bytes(s.n, s.dtype);
+    return QC_OK;
+}
+
+bool is_swap_gate(const qc_gate_t &g) {
+    if (g.n_targets != 2 || g.n_ctrls != 0) return false;
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            const bool one = (r == c && (r == 0 || r == 3)) || (r == 1 && c == 2) || (r == 2 && c == 1);
+            if (g.matrix[2 * (4 * r + c)] != (one ? 1.0 : 0.0) || g.matrix[2 * (4 * r + c) + 1] != 0.0)
+                return false;
+        }
+    return true;
+}
+
+// SWAP gates leave the list: the gates after one are rewritten with its two
+// qubits exchanged.  phys[q] receives the label that holds qubit q's bit
+// once `out` has been applied.  Returns false (out untouched) if the list
+// holds no SWAP.
+bool defer_swaps(int n, int ng, const qc_gate_t *gs, std::vector<qc_gate_t> &out, int *phys) {
+    int i0 = 0;
+    while (i0 < ng && !is_swap_gate(gs[i0])) ++i0;
+    if (i0 == ng) return false;
+    for (int q = 0; q < n; ++q) phys[q] = q;
+    out.assign(gs, gs + i0);
+    for (int i = i0; i < ng; ++i) {
+        const qc_gate_t &g = gs[i];
+        if (is_swap_gate(g)) {
+            std::swap(phys[g.targets[0]], phys[g.targets[1]]);
+            continue;
+        }
+        qc_gate_t h = g;
+        for (int j = 0; j < h.n_targets; ++j) h.targets[j] = phys[g.targets[j]];
+        for (int j = 0; j < h.n_ctrls; ++j) h.ctrls[j] = phys[g.ctrls[j]];
+        out.push_back(h);
+    }
+    return true;
+}
+
+}  // namespace
+
+int qc_permute_qubits(qc_state_t s, const int *perm, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!perm) return fail(QC_ERR_ARG, "perm is NULL");
+    if ((rc = check_qubits(s.n, perm, s.n, "perm entry"))) return rc;
+    int id[QC_MAX_QUBITS];
+    for (int q = 0; q < s.n; ++q) id[q] = q;
+    qc_exec_stats_t st{};
+    return relabel(s, id, perm, st, stream);
+}
+
 int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode, int fuse_k,
                      qc_exec_stats_t *stats, void *stream) {
     int rc = check_state(s);
@@ -1348,11 +1412,23 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
     if (mode == QC_EXEC_UNFUSED) {
         for (int i = 0; i < n_gates; ++i)
             if ((rc = apply_gate_unfused(s, gates[i], st, stream))) return rc;
-    } else if (mode == QC_EXEC_TILED) {
-        if ((rc = tiled_execute(s, n_gates, gates, st, stream))) return rc;
     } else {
-        if ((rc = fused_execute(s, n_gates, gates, fuse_k, g_knob_look.load(), st, stream)))
-            return rc;
+        std::vector<qc_gate_t> rel;
+        int phys[QC_MAX_QUBITS];
+        const bool deferred = defer_swaps(s.n, n_gates, gates, rel, phys);
+        const qc_gate_t *gl = deferred ? rel.data() : gates;
+        const int ng = deferred ? int(rel.size()) : n_gates;
+        if (ng > 0) {
+            rc = mode == QC_EXEC_TILED
+                     ? tiled_execute(s, ng, gl, st, stream)
+                     : fused_execute(s, ng, gl, fuse_k, g_knob_look.load(), st, stream);
+            if (rc) return rc;
+        }
+        if (deferred) {
+            int id[QC_MAX_QUBITS];
+            for (int q = 0; q < s.n; ++q) id[q] = q;
+            if ((rc = relabel(s, phys, id, st, stream))) return rc;
+        }
     }
     if (stats) *stats = st;
     return QC_OK;

@@ -226,6 +226,10 @@ hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_
 
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s);
+// new[sigma(i)] = old[i], sigma moving bit position p to sigma[p] (a
+// permutation of 0..n-1, host array); *sweeps receives 0, 1 or 2
+hipError_t launch_permute_bits(void *amp, int dtype, int n, const uint32_t *sigma, int *sweeps,
+                               hipStream_t s);
 // vals[k] = <psi|P_k|psi> for the nt terms of one tile pass; part holds
 // nt x grid partials
 hipError_t launch_expect_tiles(const void *amp, int dtype, const TileArgs &a,

@@ -27,7 +27,7 @@ OP_KIND = {"RX": 1, "RY": 2, "RZ": 3, "H": 4, "X": 5, "Y": 6, "Z": 7, "CZ": 8, "
 EXPORTS = [
     "qc_status_string", "qc_last_error", "qc_version", "qc_state_init", "qc_state_copy",
     "qc_state_diff", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled", "qc_apply_fused_k",
-    "qc_apply_multiplexed",
+    "qc_apply_multiplexed", "qc_permute_qubits",
     "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
@@ -105,6 +105,7 @@ def _load():
         "qc_apply_controlled": ([S, i, ip, ip, i, dp, vp], i),
         "qc_apply_fused_k": ([S, i, ip, dp, vp], i),
         "qc_apply_multiplexed": ([S, i, ip, i, ip, dp, vp], i),
+        "qc_permute_qubits": ([S, ip, vp], i),
         "qc_apply_circuit": ([S, i, ctypes.POINTER(QcGate), i, i, ctypes.POINTER(QcStats), vp], i),
         "qc_fuse_plan": ([i, i, ctypes.POINTER(QcGate), i, ip, ip], i),
         "qc_probs": ([S, i, ip, vp, vp], i),
@@ -234,6 +235,12 @@ def apply_multiplexed(psi: torch.Tensor, qubits: Sequence[int], sel_qubits: Sequ
     m, p = _mat(arr)
     _check(lib.qc_apply_multiplexed(state_view(psi), len(qubits), _ints(qubits), len(sel_qubits),
                                     _ints(sel_qubits), p, _stream(psi)), "qc_apply_multiplexed")
+    return psi
+
+
+def permute_qubits(psi: torch.Tensor, perm: Sequence[int]) -> torch.Tensor:
+    """Qubit q of the register becomes qubit perm[q] (in place)."""
+    _check(lib.qc_permute_qubits(state_view(psi), _ints(perm), _stream(psi)), "qc_permute_qubits")
     return psi
 
 
@@ -486,6 +493,7 @@ qc_apply_2q = apply_2q
 qc_apply_controlled = apply_controlled
 qc_apply_fused_k = apply_fused_k
 qc_apply_multiplexed = apply_multiplexed
+qc_permute_qubits = permute_qubits
 qc_apply_circuit = apply_circuit
 qc_fuse_plan = fuse_plan
 qc_probs = probs

@@ -110,6 +110,12 @@ def test_gate_validation(qc):
     assert mux(st(qc, n=6), 1, qc._ints([0]), 2, qc._ints([1, 2]), None, None) == -1
     assert mux(st(qc, n=2), 1, qc._ints([0]), 2, qc._ints([1, 2]), p8, None) == -2
     assert mux(st(qc, n=6), 0, qc._ints([0]), 1, qc._ints([1]), p8, None) == -1
+    perm = qc.lib.qc_permute_qubits
+    assert perm(st(qc), None, None) == -1
+    assert perm(st(qc), qc._ints([0, 1, 1, 3]), None) == -2
+    assert perm(st(qc), qc._ints([0, 1, 2, 4]), None) == -2
+    assert perm(st(qc), qc._ints([3, 2, 1, -1]), None) == -2
+    assert perm(st(qc), qc._ints([0, 1, 2, 3]), None) == 0   # identity: no device work
 
 
 def test_reduction_validation(qc):

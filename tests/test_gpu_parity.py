@@ -330,6 +330,94 @@ def test_tiled_dense_then_phases(qc, G, dt, n, tile_bits):
         qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
 
 
+def swap_ops_for(perm):
+    """SWAP gates after which qubit q of the register sits at label perm[q]."""
+    n = len(perm)
+    at = list(range(n))      # at[label] = original qubit held there
+    where = list(range(n))   # where[q] = label holding original qubit q
+    ops = []
+    for label in range(n):
+        q = perm.index(label)
+        if where[q] != label:
+            other = at[label]
+            ops.append(W.Op("SWAP", (label, where[q])))
+            at[where[q]], at[label] = other, q
+            where[other], where[q] = where[q], label
+    return ops
+
+
+PERMS = {
+    "reverse": lambda n, rng: list(range(n))[::-1],
+    "random": lambda n, rng: [int(x) for x in rng.permutation(n)],
+    "cycle3": lambda n, rng: [1, 2, 0] + list(range(3, n)) if n >= 3 else list(range(n))[::-1],
+    "hi_lo": lambda n, rng: [n - 1] + list(range(1, n - 1)) + [0] if n >= 2 else [0],
+}
+
+
+@pytest.mark.parametrize("kind", sorted(PERMS))
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 7, 12, 17])
+def test_permute_qubits(qc, dt, n, kind):
+    """qc_permute_qubits against the oracle's SWAP gates (and the relabelling
+    written as a transpose of the 2 x ... x 2 tensor): amplitudes move
+    unchanged, so the match is exact."""
+    rng = np.random.default_rng(31 * n + len(kind))
+    perm = PERMS[kind](n, rng)
+    psi0 = W.random_state(n, 300 + n)
+    ref = oracle.run(swap_ops_for(perm), psi0)
+    inv = [perm.index(axis) for axis in range(n)]
+    assert np.array_equal(ref, psi0.reshape([2] * n).transpose(inv).reshape(-1))
+    t = dev(psi0, DT[dt])
+    qc.permute_qubits(t, perm)
+    want = ref.astype(np.complex64) if dt == "c64" else ref
+    assert np.array_equal(host(t), want)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("n", [10, 15])
+def test_circuit_with_swaps(qc, G, dt, mode, n):
+    """SWAP gates between other gates (fused and tiled modes leave them out
+    and relabel the later gates): the result against the oracle."""
+    rng = np.random.default_rng(n + 10 * mode)
+    ops = []
+    for _ in range(80):
+        kind = rng.integers(0, 5)
+        q = [int(x) for x in rng.permutation(n)[:2]]
+        if kind == 0:
+            ops.append(W.Op("SWAP", (q[0], q[1])))
+        elif kind == 1:
+            ops.append(W.Op("U", (q[0],), matrix=random_unitary(2, rng)))
+        elif kind == 2:
+            ops.append(W.Op("CP", (q[0], q[1]), angle=float(rng.uniform(0, 6))))
+        elif kind == 3:
+            ops.append(W.Op("CNOT", (q[0], q[1])))
+        else:
+            ops.append(W.Op("U", (q[0], q[1]), matrix=random_unitary(4, rng)))
+    psi0 = W.random_state(n, 400 + n)
+    ref = oracle.run(ops, psi0)
+    t = dev(psi0, DT[dt])
+    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=mode, fuse_k=4)
+    assert st["gates"] == len(ops)
+    check(host(t), ref, DT[dt], ngates=len(ops))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_qft_final_swaps_take_one_sweep(qc, G, mode):
+    """The QFT's closing SWAP network relabels no gate (nothing follows it),
+    and together it is its own inverse: one extra sweep over the state."""
+    n = 16
+    ops = W.qft(n)
+    core = [op for op in ops if op.kind != "SWAP"]
+    psi0 = W.random_state(n, 28)
+    sweeps = []
+    for lst in (ops, core):
+        t = dev(psi0, torch.complex64)
+        sweeps.append(qc.apply_circuit(t, qc.GateList(G.gate_tuples(lst)), mode=mode, fuse_k=5)["sweeps"])
+    assert sweeps[0] == sweeps[1] + 1
+    check(host(t), oracle.run(core, psi0), torch.complex64, ngates=len(core))   # t: the core run
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_brickwork12_config(qc, G, dt, mode):
