@@ -1065,8 +1065,8 @@ struct TileOpBuilder {
 // TILE_DENSE1_PHASES op: one pass over the tile instead of two.  Only the
 // ops from index `begin` on (one run's list) are merged.
 void merge_dense_phases(std::vector<qcx::TileOp> &ops, size_t begin) {
-    std::vector<qcx::TileOp> out(ops.begin(), ops.begin() + begin);
-    out.reserve(ops.size());
+    std::vector<qcx::TileOp> out;   // the run's merged list (the ops before begin stay put)
+    out.reserve(ops.size() - begin);
     for (size_t k = begin; k < ops.size(); ++k) {
         const qcx::TileOp &d = ops[k];
         if (k + 1 < ops.size() && d.kind == qcx::TILE_DENSE1 && d.cmask_lo == 0 && d.cmask_hi == 0) {
@@ -1102,7 +1102,8 @@ void merge_dense_phases(std::vector<qcx::TileOp> &ops, size_t begin) {
         }
         out.push_back(d);
     }
-    ops.swap(out);
+    ops.resize(begin);
+    ops.insert(ops.end(), out.begin(), out.end());
 }
 
 // Convert a list of gates into the op list of one tile run.
