@@ -232,7 +232,9 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
  * that forms a block of its own.  Moving every gate of a block ahead of the
  * gates of later blocks only swaps commuting gates (see qc_apply_circuit).
  * block_of[g] receives the block index of gate g; *n_blocks the number of
- * blocks.  block_of must hold n_gates entries. */
+ * blocks.  block_of must hold n_gates entries.  SWAP gates are planned here
+ * like any other gate; qc_apply_circuit first takes them out of the list
+ * and relabels the gates after them (see there), and plans that list. */
 int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
                  int *block_of, int *n_blocks);
 
