@@ -875,9 +875,14 @@ struct TileOpBuilder {
     cd held[qcx::kTileMaxBits][4];
     uint32_t held_bits = 0;
     int kron_max = qcx::kKronMax;   // 1: held bits are flushed one op per bit
-    qcx::TileOp ph{};
-    int nph = 0;
-    uint32_t ph_bits = 0;
+    bool fans = true;                // false: no TILE_FAN ops (kernels without them)
+    struct Term {
+        uint32_t mlo, vlo;
+        uint64_t mhi, vhi;
+        cd phase;
+    };
+    std::vector<Term> terms;   // diagonal terms collected since the last emission
+    uint32_t ph_bits = 0;      // the tile bits they test
 
     TileOpBuilder(int n_, uint64_t P_, std::vector<qcx::TileOp> &o) : n(n_), P(P_), out(o) {}
 
@@ -942,44 +947,116 @@ struct TileOpBuilder {
         if (g == 1) flush_bit(group[0]);
         else if (g > 1) flush_group(group, g);
     }
+    // The collected terms as ops: one TILE_FAN op when they are the phases
+    // of controlled-phase gates sharing an in-tile target (conditions all
+    // "= 1", each term testing the target and at most one other bit), else
+    // TILE_PHASES ops of at most kTilePhaseTerms terms testing at most
+    // kPhaseTableBits tile bits, in order (the terms commute), a lone term
+    // or one testing more bits as a TILE_PHASE op.
     void emit_phases() {
-        if (nph == 1) {
+        if (!terms.empty() && !(fans && terms.size() > 1 && emit_fan())) {
             qcx::TileOp op{};
-            op.kind = qcx::TILE_PHASE;
-            op.cmask_lo = ph.pm_lo[0];
-            op.cval_lo = ph.pv_lo[0];
-            op.cmask_hi = ph.pm_hi[0];
-            op.cval_hi = ph.pv_hi[0];
-            op.u[0] = ph.u[0];
-            op.u[1] = ph.u[1];
-            out.push_back(op);
-        } else if (nph > 1) {
-            ph.kind = qcx::TILE_PHASES;
-            ph.b0 = nph;
-            ph.b1 = int32_t(ph_bits);
-            out.push_back(ph);
+            int nt = 0;
+            uint32_t bits = 0;
+            auto flush = [&]() {
+                if (nt == 1) {
+                    qcx::TileOp one{};
+                    one.kind = qcx::TILE_PHASE;
+                    one.cmask_lo = op.pm_lo[0];
+                    one.cval_lo = op.pv_lo[0];
+                    one.cmask_hi = op.pm_hi[0];
+                    one.cval_hi = op.pv_hi[0];
+                    one.u[0] = op.u[0];
+                    one.u[1] = op.u[1];
+                    out.push_back(one);
+                } else if (nt > 1) {
+                    op.kind = qcx::TILE_PHASES;
+                    op.b0 = nt;
+                    op.b1 = int32_t(bits);
+                    out.push_back(op);
+                }
+                op = qcx::TileOp{};
+                nt = 0;
+                bits = 0;
+            };
+            for (const Term &tm : terms) {
+                if (nt == qcx::kTilePhaseTerms ||
+                    __builtin_popcount(bits | tm.mlo) > qcx::kPhaseTableBits)
+                    flush();
+                op.pm_lo[nt] = tm.mlo;
+                op.pv_lo[nt] = tm.vlo;
+                op.pm_hi[nt] = tm.mhi;
+                op.pv_hi[nt] = tm.vhi;
+                op.u[2 * nt] = tm.phase.real();
+                op.u[2 * nt + 1] = tm.phase.imag();
+                ++nt;
+                bits |= tm.mlo;
+                if (__builtin_popcount(tm.mlo) > qcx::kPhaseTableBits) flush();
+            }
+            flush();
         }
-        ph = qcx::TileOp{};
-        nph = 0;
+        terms.clear();
         ph_bits = 0;
     }
+    // TILE_FAN op(s) for the collected terms if they have the fan form;
+    // false (nothing emitted) otherwise.  Out-of-tile controls beyond
+    // kTilePhaseTerms go to further TILE_FAN ops on the same target.
+    bool emit_fan() {
+        uint32_t common = ~0u;
+        for (const Term &tm : terms) {
+            const int lo = __builtin_popcount(tm.mlo), hi = __builtin_popcountll(tm.mhi);
+            if (tm.vlo != tm.mlo || tm.vhi != tm.mhi || lo < 1 || hi > 1 || lo + hi > 2) return false;
+            common &= tm.mlo;
+        }
+        if (!common) return false;
+        const int t = __builtin_ctz(common);
+        cd bitph[qcx::kTileMaxBits];
+        for (auto &v : bitph) v = 1.0;
+        uint32_t ctl = 0;
+        std::vector<std::pair<uint64_t, cd>> hi;   // out-of-tile control bit, phase
+        for (const Term &tm : terms) {
+            if (tm.mhi) {
+                auto it = std::find_if(hi.begin(), hi.end(),
+                                       [&](const std::pair<uint64_t, cd> &h) { return h.first == tm.mhi; });
+                if (it == hi.end()) hi.push_back({tm.mhi, tm.phase});
+                else it->second *= tm.phase;
+                continue;
+            }
+            const uint32_t c = tm.mlo & ~(1u << t);   // the control bit, or none
+            const int b = c ? __builtin_ctz(c) : t;
+            bitph[b] *= tm.phase;
+            ctl |= c;
+        }
+        size_t h0 = 0;
+        do {
+            qcx::TileOp op{};
+            op.kind = qcx::TILE_FAN;
+            op.b0 = t;
+            if (h0 == 0) {   // the in-tile controls and target-only terms go with the first op
+                op.b1 = int32_t(ctl);
+                for (int b = 0; b < qcx::kTileMaxBits; ++b) {
+                    op.u[2 * b] = (b == t || ((ctl >> b) & 1)) ? bitph[b].real() : 1.0;
+                    op.u[2 * b + 1] = (b == t || ((ctl >> b) & 1)) ? bitph[b].imag() : 0.0;
+                }
+            } else {
+                op.u[2 * t] = 1.0;
+            }
+            int k = 0;
+            for (; h0 < hi.size() && k < qcx::kTilePhaseTerms; ++h0, ++k) {
+                op.fan_mask[k] = hi[h0].first;
+                op.fan_ph[2 * k] = hi[h0].second.real();
+                op.fan_ph[2 * k + 1] = hi[h0].second.imag();
+            }
+            op.pad = k;
+            out.push_back(op);
+        } while (h0 < hi.size());
+        return true;
+    }
     // one diagonal term: multiply by `phase` where the conditions hold
-    // (a term testing more than kPhaseTableBits tile bits becomes a
-    // single-term TILE_PHASE op of its own)
     void add_phase(uint32_t mlo, uint32_t vlo, uint64_t mhi, uint64_t vhi, cd phase) {
         flush_bits(mlo);
-        if (nph == qcx::kTilePhaseTerms ||
-            __builtin_popcount(ph_bits | mlo) > qcx::kPhaseTableBits)
-            emit_phases();
-        ph.pm_lo[nph] = mlo;
-        ph.pv_lo[nph] = vlo;
-        ph.pm_hi[nph] = mhi;
-        ph.pv_hi[nph] = vhi;
-        ph.u[2 * nph] = phase.real();
-        ph.u[2 * nph + 1] = phase.imag();
-        ++nph;
+        terms.push_back({mlo, vlo, mhi, vhi, phase});
         ph_bits |= mlo;
-        if (__builtin_popcount(mlo) > qcx::kPhaseTableBits) emit_phases();
     }
     void add_op(const qcx::TileOp &op, uint32_t touched) {
         flush_bits(touched);
@@ -1088,6 +1165,14 @@ void merge_dense_phases(std::vector<qcx::TileOp> &ops, size_t begin) {
                 mo.pad = 1;
                 mo.b1 = int32_t(p.cmask_lo);
                 ok = true;
+            }
+            if (!ok && p.kind == qcx::TILE_FAN && p.b0 == d.b0) {
+                mo = p;
+                mo.kind = qcx::TILE_DENSE1_FAN;
+                for (int i = 0; i < 8; ++i) mo.u1[i] = d.u[i];
+                out.push_back(mo);
+                ++k;
+                continue;
             }
             if (ok) {
                 mo.kind = qcx::TILE_DENSE1_PHASES;
@@ -1843,6 +1928,7 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
         if (r.P == 0) return fail(QC_ERR_UNSUPPORTED, "adjoint op cannot be tiled");
         TileOpBuilder B(n, r.P, tops);
         B.kron_max = 1;   // k_adjoint_tiles is compiled without TILE_KRON
+        B.fans = false;   // nor with the fan ops
         for (int j : r.gates) {
             if (rot_row[j] >= 0) {
                 if (int(slot_row.size()) == qcx::kAdjointMaxSlots) {

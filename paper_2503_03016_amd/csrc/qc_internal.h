@@ -111,6 +111,13 @@ struct Mat2d {
 // TILE_DENSE1_PHASES: the one-qubit matrix u1 on bit b0 (no conditions),
 // then the pad diagonal terms of a TILE_PHASES op over the bits b1, in one
 // pass over the pairs.
+// TILE_FAN: the phases of controlled-phase gates sharing the target bit b0
+// (all conditions "= 1"): an amplitude with bit b0 set is multiplied by
+// u[2 b0] + i u[2 b0 + 1] (terms on the target alone), by u[2c] + i
+// u[2c + 1] for every control bit c of the mask b1 that it has set, and by
+// fan_ph[2k] + i fan_ph[2k + 1] for every out-of-tile control k < pad whose
+// bit fan_mask[k] the tile has set.  TILE_DENSE1_FAN: the one-qubit matrix
+// u1 on bit b0 first, in the same pass over the pairs.
 // TILE_KRON: b0 = g (2..kKronMax) one-qubit matrices on the distinct
 // compressed bits (b1 >> 5j) & 31, j < g, ascending; matrix j is u[8j ..
 // 8j + 7].  They commute, so each group of 2^g amplitudes is loaded once and
@@ -118,7 +125,7 @@ struct Mat2d {
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
-    TILE_KRON = 9, TILE_DENSE1_PHASES = 10
+    TILE_KRON = 9, TILE_DENSE1_PHASES = 10, TILE_FAN = 11, TILE_DENSE1_FAN = 12
 };
 constexpr int kKronMax = 3;
 constexpr int kTileMaxBits = 16;
@@ -131,10 +138,19 @@ struct TileOp {
     uint32_t cmask_lo, cval_lo;  // conditions on tile bits (compressed)
     uint64_t cmask_hi, cval_hi;  // conditions on bits outside the tile (global)
     double u[32];              // complex FP64 entries, interleaved
-    uint32_t pm_lo[kTilePhaseTerms], pv_lo[kTilePhaseTerms];   // TILE_PHASES terms
-    uint64_t pm_hi[kTilePhaseTerms], pv_hi[kTilePhaseTerms];
-    double u1[8];              // TILE_DENSE1_PHASES: the one-qubit matrix
+    union {
+        struct {               // TILE_PHASES terms
+            uint32_t pm_lo[kTilePhaseTerms], pv_lo[kTilePhaseTerms];
+            uint64_t pm_hi[kTilePhaseTerms], pv_hi[kTilePhaseTerms];
+        };
+        struct {               // TILE_FAN out-of-tile controls
+            uint64_t fan_mask[kTilePhaseTerms];
+            double fan_ph[2 * kTilePhaseTerms];
+        };
+    };
+    double u1[8];              // TILE_DENSE1_PHASES / TILE_DENSE1_FAN: the one-qubit matrix
 };
+static_assert(kTileMaxBits <= 16, "TILE_FAN keeps one phase per tile bit in u");
 struct TileArgs {
     uint64_t n_tiles;
     int m;                     // tile bits

@@ -202,7 +202,7 @@ __device__ inline void apply_one(cx<R> *lds, int m, const TileOp &op) {
             else if (op.b0 == 3) apply_kron<R, 3>(lds, m, op);
         }
         break;
-    default: break;   // TILE_GRAD, TILE_PHASES, TILE_DENSE1_PHASES (see apply_ops) and unknown kinds
+    default: break;   // TILE_GRAD, TILE_PHASES, TILE_DENSE1_PHASES, the fan ops (see apply_ops), unknown kinds
     }
 }
 
@@ -390,6 +390,91 @@ __device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base
     }
 }
 
+// TILE_FAN / TILE_DENSE1_FAN.  The phase of an amplitude with the target
+// bit set factorizes: K (terms on the target alone, and the out-of-tile
+// controls the tile has set) times the phases of its set control bits
+// below kLoBits (fixed per thread: the pairs a thread takes share their low
+// bits) times those of its set control bits above (fixed per group of
+// kBlock elements: fan_h, one entry per group, built by the first threads).
+// No table over the control bits and no limit on their number.
+constexpr int kFanGroups = 1 << (13 - kLoBits);   // tiles hold at most 2^13 amplitudes
+
+template <typename R, bool DENSE>
+__device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op,
+                                 cx<R> *fan_h) {
+    const int T = 1 << m;
+    const int t = op.b0;
+    const uint32_t bit = 1u << t;
+    const uint32_t cm = uniform(uint32_t(op.b1));
+    // K: lane k of each wavefront takes out-of-tile control k, then a
+    // butterfly over 16 lanes multiplies them; lane 0's product is used
+    const int nh = int(uniform(uint32_t(op.pad)));
+    const int lane = int(threadIdx.x & 63);
+    const int kl = lane < kTilePhaseTerms ? lane : 0;
+    const uint64_t fm = op.fan_mask[kl];
+    cx<R> f{R(1), R(0)};
+    if (lane < nh && (tile_base & fm) == fm) f = cx<R>{R(op.fan_ph[2 * kl]), R(op.fan_ph[2 * kl + 1])};
+    static_assert(kTilePhaseTerms == 16, "one butterfly over 16 lanes");
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+        const cx<R> o{__shfl_xor(f.re, off, 64), __shfl_xor(f.im, off, 64)};
+        f = cmul(f, o);
+    }
+    cx<R> K{lane_value(f.re, 0), lane_value(f.im, 0)};
+    K = cmul(K, ld_u<R>(op.u, t));
+    const int groups = m > kLoBits ? 1 << (m - kLoBits) : 1;
+    if (int(threadIdx.x) < groups) {
+        cx<R> h = K;
+        for (int c = kLoBits; c < m; ++c)
+            if (((cm >> c) & 1u) && ((threadIdx.x >> (c - kLoBits)) & 1u)) h = cmul(h, ld_u<R>(op.u, c));
+        fan_h[threadIdx.x] = h;
+    }
+    // the thread's factor from the control bits below kLoBits of its
+    // elements with the target set (the same for every pair it takes)
+    const uint32_t lo1 = (ins0(threadIdx.x, t) | bit) & (kBlock - 1);
+    cx<R> flo{R(1), R(0)};
+#pragma unroll
+    for (int c = 0; c < kLoBits; ++c)
+        if ((cm >> c) & 1u) {   // uniform
+            const cx<R> p = ld_u<R>(op.u, c);
+            if ((lo1 >> c) & 1u) flo = cmul(flo, p);
+        }
+    cx<R> u0, u1, u2, u3;
+    if (DENSE) {
+        u0 = ld_u<R>(op.u1, 0);
+        u1 = ld_u<R>(op.u1, 1);
+        u2 = ld_u<R>(op.u1, 2);
+        u3 = ld_u<R>(op.u1, 3);
+    }
+    __syncthreads();   // fan_h
+    const int npairs = T >> 1;
+    for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
+        uint32_t i1[kItems];
+        cx<R> a0[kItems], a1[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int g = g0 + k * kBlock;
+            i1[k] = ins0(uint32_t(g), t) | bit;
+            if (g < npairs) {
+                if (DENSE) a0[k] = lds[i1[k] ^ bit];
+                a1[k] = lds[i1[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (g0 + k * kBlock >= npairs) continue;
+            const cx<R> ph = cmul(flo, fan_h[i1[k] >> kLoBits]);
+            if (DENSE) {
+                const cx<R> z{R(0), R(0)};
+                lds[i1[k] ^ bit] = cfma(u1, a1[k], cfma(u0, a0[k], z));
+                lds[i1[k]] = cmul(ph, cfma(u3, a1[k], cfma(u2, a0[k], z)));
+            } else {
+                lds[i1[k]] = cmul(ph, a1[k]);
+            }
+        }
+    }
+}
+
 // Op staging: the op being applied is read from one of two LDS slots.
 // While op o runs, the first kOpWords lanes hold op o + 1 in registers
 // (a global load issued before op o starts) and write it to the other slot
@@ -426,6 +511,7 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
                                  int n_ops, TileOp *slot) {
     if (n_ops <= 0) return;
     __shared__ PhaseTables<R> pt;
+    __shared__ cx<R> fan_h[kFanGroups];
     stage_now(&slot[0], &ops[0]);
     __syncthreads();
     for (int o = 0; o < n_ops; ++o) {
@@ -436,6 +522,8 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
         if ((tile_base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
             if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op, pt);
             else if (op.kind == TILE_DENSE1_PHASES) apply_dense1_phases<R>(lds, m, tile_base, op, pt);
+            else if (op.kind == TILE_FAN) apply_fan<R, false>(lds, m, tile_base, op, fan_h);
+            else if (op.kind == TILE_DENSE1_FAN) apply_fan<R, true>(lds, m, tile_base, op, fan_h);
             else apply_one<R>(lds, m, op);
         }
         if (next) stage_store(st, &slot[(o + 1) & 1]);

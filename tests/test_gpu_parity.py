@@ -447,6 +447,36 @@ def test_qft_random_state(qc, G, dt, mode):
     check(host(t), ref, DT[dt], ngates=len(ops))
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_qft24_small_tiles(qc, G, dt):
+    """24-qubit QFT in tile runs of 7-bit tiles: a controlled-phase fan then
+    has more than 16 controls outside the tile, so its phases span two fan
+    ops.  Against the unfused complex128 run (whole state) and the oracle's
+    Fourier sums (sampled amplitudes)."""
+    n = 24
+    ops = W.qft(n)
+    psi0 = W.random_state(n, 24)
+    gl = qc.GateList(G.gate_tuples(ops))
+    ref = dev(psi0, torch.complex128)
+    qc.apply_circuit(ref, gl, mode=0)
+    t = dev(psi0, DT[dt])
+    old = qc.get_knob(qc.QC_KNOB_TILE_BITS)
+    try:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, 7)
+        qc.apply_circuit(t, gl, mode=2)
+    finally:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
+    torch.cuda.synchronize()
+    for y in (0, 1, 987654 % (1 << n), (1 << n) - 1):
+        want = oracle.qft_amplitude(psi0, y)
+        assert abs(complex(ref[y].item()) - want) < 1e-12, y
+    d = qc.state_diff(t, ref).cpu().numpy()
+    if dt == "c128":
+        assert np.max(np.abs(host(t) - host(ref))) < 1e-12
+    else:
+        assert math.sqrt(d[0] / d[1]) < 1e-5
+
+
 def test_qft28_sampled_amplitudes(qc, G):
     """28-qubit QFT on the seeded Gaussian state (4 GiB complex128): sampled
     output amplitudes against the oracle's discrete Fourier sum, and the
