@@ -363,8 +363,13 @@ __device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base
     const uint32_t e1_lo = extract_bits((lo | bit) & (kBlock - 1), U & (kBlock - 1));
     const int npairs = T >> 1;
     for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
+        // complex64: every LDS read of the step (amplitudes and table
+        // entries) is issued before any is used; complex128 reads the table
+        // entries where they are used (holding them too would take the
+        // batch kernel past 128 registers)
+        constexpr bool kEarly = sizeof(R) == sizeof(float);
         uint32_t i0[kItems];
-        cx<R> a0[kItems], a1[kItems];
+        cx<R> a0[kItems], a1[kItems], f0[kItems], f1[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int g = g0 + k * kBlock;
@@ -372,6 +377,10 @@ __device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base
             if (g < npairs) {
                 a0[k] = lds[i0[k]];
                 a1[k] = lds[i0[k] | bit];
+                if (kEarly && any) {
+                    f0[k] = pt.tab[e0_lo | pt.hix[i0[k] >> kLoBits]];
+                    f1[k] = pt.tab[e1_lo | pt.hix[(i0[k] | bit) >> kLoBits]];
+                }
             }
         }
 #pragma unroll
@@ -381,8 +390,12 @@ __device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base
             cx<R> v0 = cfma(u1, a1[k], cfma(u0, a0[k], z));
             cx<R> v1 = cfma(u3, a1[k], cfma(u2, a0[k], z));
             if (any) {
-                v0 = cmul(pt.tab[e0_lo | pt.hix[i0[k] >> kLoBits]], v0);
-                v1 = cmul(pt.tab[e1_lo | pt.hix[(i0[k] | bit) >> kLoBits]], v1);
+                if (!kEarly) {
+                    f0[k] = pt.tab[e0_lo | pt.hix[i0[k] >> kLoBits]];
+                    f1[k] = pt.tab[e1_lo | pt.hix[(i0[k] | bit) >> kLoBits]];
+                }
+                v0 = cmul(f0[k], v0);
+                v1 = cmul(f1[k], v1);
             }
             lds[i0[k]] = v0;
             lds[i0[k] | bit] = v1;
@@ -450,7 +463,9 @@ __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const Ti
     const int npairs = T >> 1;
     for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
         uint32_t i1[kItems];
-        cx<R> a0[kItems], a1[kItems];
+        cx<R> a0[kItems], a1[kItems], h[kItems];
+        // every LDS read of the step (amplitudes and group factors) is
+        // issued before any is used
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int g = g0 + k * kBlock;
@@ -458,12 +473,13 @@ __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const Ti
             if (g < npairs) {
                 if (DENSE) a0[k] = lds[i1[k] ^ bit];
                 a1[k] = lds[i1[k]];
+                h[k] = fan_h[i1[k] >> kLoBits];
             }
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             if (g0 + k * kBlock >= npairs) continue;
-            const cx<R> ph = cmul(flo, fan_h[i1[k] >> kLoBits]);
+            const cx<R> ph = cmul(flo, h[k]);
             if (DENSE) {
                 const cx<R> z{R(0), R(0)};
                 lds[i1[k] ^ bit] = cfma(u1, a1[k], cfma(u0, a0[k], z));
