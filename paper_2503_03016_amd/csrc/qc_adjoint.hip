@@ -137,6 +137,55 @@ __device__ inline double grad_pairs(cx<R> *f, cx<R> *l, int m, int b, int gen, c
     return acc;
 }
 
+// TILE_GRAD_APPLY2: two gradient-and-apply steps on bit b in one pass over
+// the pairs: partial 1 (generator gen1), matrix u on both tiles, partial 2
+// (generator gen2) on the updated values, matrix w on both tiles.
+template <typename R, int A1, int A2>
+__device__ inline void grad_pairs2(cx<R> *f, cx<R> *l, int m, int b, int gen1, int gen2,
+                                   const double *u, const double *w, double &acc1, double &acc2) {
+    const cx<R> u0 = tile::ld_u<R>(u, 0), u1 = tile::ld_u<R>(u, 1), u2 = tile::ld_u<R>(u, 2),
+                u3 = tile::ld_u<R>(u, 3);
+    const cx<R> w0 = tile::ld_u<R>(w, 0), w1 = tile::ld_u<R>(w, 1), w2 = tile::ld_u<R>(w, 2),
+                w3 = tile::ld_u<R>(w, 3);
+    // complex128: two pairs per thread per step (four would pass 128 registers)
+    constexpr int kI = sizeof(R) == sizeof(float) ? tile::kItems : 2;
+    const int npairs = 1 << (m - 1);
+    const uint32_t bit = 1u << b;
+    acc1 = 0.0;
+    acc2 = 0.0;
+    for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kI) {
+        uint32_t i0[kI];
+        bool ok[kI];
+        cx<R> f0[kI], f1[kI], l0[kI], l1[kI];
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            const int g = g0 + k * kBlock;
+            ok[k] = g < npairs;
+            i0[k] = tile::ins0(uint32_t(g), b);
+            if (ok[k]) {
+                f0[k] = f[i0[k]];
+                f1[k] = f[i0[k] | bit];
+                l0[k] = l[i0[k]];
+                l1[k] = l[i0[k] | bit];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            if (!ok[k]) continue;
+            acc1 += double(grad_pair<R>(f0[k], f1[k], l0[k], l1[k], gen1));
+            apply_pair<R, A1>(f0[k], f1[k], u0, u1, u2, u3);
+            apply_pair<R, A1>(l0[k], l1[k], u0, u1, u2, u3);
+            acc2 += double(grad_pair<R>(f0[k], f1[k], l0[k], l1[k], gen2));
+            apply_pair<R, A2>(f0[k], f1[k], w0, w1, w2, w3);
+            apply_pair<R, A2>(l0[k], l1[k], w0, w1, w2, w3);
+            f[i0[k]] = f0[k];
+            f[i0[k] | bit] = f1[k];
+            l[i0[k]] = l0[k];
+            l[i0[k] | bit] = l1[k];
+        }
+    }
+}
+
 // At most 128 VGPRs (4 wavefronts per SIMD): two workgroups per CU, which
 // their LDS (two tiles of at most 32 KiB) allows.
 template <typename R>
@@ -151,15 +200,22 @@ void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
     // adds them into acc at the start of the next op, after the op's own
     // closing barrier, so a gradient costs no barrier of its own (the
     // additions keep their order: one slot at a time, wavefronts in order)
-    __shared__ double red[2][kWaves];
-    int pend_slot = -1, pend_buf = 0;
+    // (a paired op leaves a second partial in red2 for slot pend_slot2)
+    __shared__ double red[2][kWaves], red2[2][kWaves];
+    int pend_slot = -1, pend_slot2 = -1, pend_buf = 0;
     auto fold = [&]() {
         if (pend_slot >= 0 && threadIdx.x == 0) {
             double s = 0.0;
             for (int w = 0; w < kWaves; ++w) s += red[pend_buf][w];
             acc[pend_slot] += s;
+            if (pend_slot2 >= 0) {
+                s = 0.0;
+                for (int w = 0; w < kWaves; ++w) s += red2[pend_buf][w];
+                acc[pend_slot2] += s;
+            }
         }
         pend_slot = -1;
+        pend_slot2 = -1;
     };
     __shared__ TileOp op_slot[2];
     __shared__ tile::PhaseTables<R> pt;
@@ -197,6 +253,20 @@ void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
                     v = wave_sum(v);
                     if ((threadIdx.x & 63) == 0) red[o & 1][threadIdx.x >> 6] = v;
                     pend_slot = op.pad;
+                    pend_buf = o & 1;
+                } else if (op.kind == TILE_GRAD_APPLY2_DIAG_REAL) {
+                    double v1, v2;
+                    const int gens = op.b1;
+                    grad_pairs2<R, APPLY_DIAG, APPLY_REAL>(lp, ll, a.m, op.b0, gens & 15, gens >> 4,
+                                                           op.u, op.u1, v1, v2);
+                    v1 = wave_sum(v1);
+                    v2 = wave_sum(v2);
+                    if ((threadIdx.x & 63) == 0) {
+                        red[o & 1][threadIdx.x >> 6] = v1;
+                        red2[o & 1][threadIdx.x >> 6] = v2;
+                    }
+                    pend_slot = op.pad & 0xffff;
+                    pend_slot2 = op.pad >> 16;
                     pend_buf = o & 1;
                 } else if (op.kind == TILE_PHASES) {
                     const bool any = tile::phases_table<R>(pt.tab, pt.hix, a.m, base, op, op.b0,

@@ -1788,7 +1788,43 @@ bool is_rotation(int kind) { return kind == QC_OP_RX || kind == QC_OP_RY || kind
 
 }  // namespace
 
-extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
+extern "C" namespace {
+
+// A diagonal gradient-and-apply op followed by a real one on the same bit
+// (an inverse RZ and an inverse RY on one qubit in the backward pass)
+// becomes one TILE_GRAD_APPLY2_DIAG_REAL op: one pass over both tiles'
+// pairs instead of two.
+void merge_grad_pairs(std::vector<qcx::TileOp> &ops) {
+    auto plain = [](const qcx::TileOp &o) { return o.cmask_lo == 0 && o.cmask_hi == 0; };
+    std::vector<qcx::TileOp> out;
+    out.reserve(ops.size());
+    for (size_t k = 0; k < ops.size(); ++k) {
+        const qcx::TileOp &a = ops[k];
+        if (k + 1 < ops.size() && a.kind == qcx::TILE_GRAD_APPLY_DIAG &&
+            ops[k + 1].kind == qcx::TILE_GRAD_APPLY_REAL && ops[k + 1].b0 == a.b0 && plain(a) &&
+            plain(ops[k + 1])) {
+            const qcx::TileOp &b = ops[k + 1];
+            qcx::TileOp mo{};
+            mo.kind = qcx::TILE_GRAD_APPLY2_DIAG_REAL;
+            mo.b0 = a.b0;
+            mo.b1 = a.b1 | (b.b1 << 4);
+            mo.pad = a.pad | (b.pad << 16);
+            for (int i = 0; i < 8; ++i) {
+                mo.u[i] = a.u[i];
+                mo.u1[i] = b.u[i];
+            }
+            out.push_back(mo);
+            ++k;
+            continue;
+        }
+        out.push_back(a);
+    }
+    ops.swap(out);
+}
+
+}  // namespace
+
+int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
                                const double *theta, int n_params, int n_terms,
                                const char *paulis, const double *coeff, double *energy_dev,
                                double *grad_dev, void *stream) {
@@ -1910,6 +1946,7 @@ extern "C" int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *op
     std::vector<int32_t> slot_row;
     auto flush = [&](uint64_t P) -> int {
         if (tops.empty()) return QC_OK;
+        merge_grad_pairs(tops);
         const qcx::TileArgs a = tile_args(n, mb, P, int(tops.size()));
         void *odev = nullptr, *sdev = nullptr;
         int r2 = stage(c, tops.data(), tops.size() * sizeof(qcx::TileOp), hs, &odev);

@@ -118,6 +118,11 @@ struct Mat2d {
 // fan_ph[2k] + i fan_ph[2k + 1] for every out-of-tile control k < pad whose
 // bit fan_mask[k] the tile has set.  TILE_DENSE1_FAN: the one-qubit matrix
 // u1 on bit b0 first, in the same pass over the pairs.
+// TILE_GRAD_APPLY2_DIAG_REAL (adjoint kernel only): a TILE_GRAD_APPLY_DIAG
+// and a TILE_GRAD_APPLY_REAL op on bit b0 (inverse RZ, then inverse RY) in
+// one pass: generator b1 & 15, slot pad & 0xffff, matrix u[0..7] first,
+// then generator b1 >> 4, slot pad >> 16, matrix u1.  Each partial uses the
+// values before its own matrix.
 // TILE_KRON: b0 = g (2..kKronMax) one-qubit matrices on the distinct
 // compressed bits (b1 >> 5j) & 31, j < g, ascending; matrix j is u[8j ..
 // 8j + 7].  They commute, so each group of 2^g amplitudes is loaded once and
@@ -125,7 +130,8 @@ struct Mat2d {
 enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
-    TILE_KRON = 9, TILE_DENSE1_PHASES = 10, TILE_FAN = 11, TILE_DENSE1_FAN = 12
+    TILE_KRON = 9, TILE_DENSE1_PHASES = 10, TILE_FAN = 11, TILE_DENSE1_FAN = 12,
+    TILE_GRAD_APPLY2_DIAG_REAL = 13
 };
 constexpr int kKronMax = 3;
 constexpr int kTileMaxBits = 16;
@@ -264,6 +270,7 @@ hipError_t launch_batch(const BatchArgs &a, int dtype, unsigned grid, size_t lds
                         hipStream_t s);
 
 constexpr int kAdjointMaxSlots = 512;   // rotations per adjoint tile run
+static_assert(kAdjointMaxSlots <= 65536, "TILE_GRAD_APPLY2 packs two slots in 16 bits each");
 unsigned adjoint_tile_grid(uint64_t n_tiles);
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
                               const PauliTermDev *terms, int nt, hipStream_t s);
