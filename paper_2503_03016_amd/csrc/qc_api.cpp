@@ -841,6 +841,10 @@ struct TileClass {
 };
 
 bool is_diag_1q(const double *u) { return u[2] == 0 && u[3] == 0 && u[4] == 0 && u[5] == 0; }
+bool is_x_1q(const double *u) {
+    return u[0] == 0 && u[1] == 0 && u[2] == 1 && u[3] == 0 && u[4] == 1 && u[5] == 0 && u[6] == 0 &&
+           u[7] == 0;
+}
 
 TileClass tile_class(int n, const qc_gate_t &g) {
     TileClass c{};
@@ -883,6 +887,14 @@ struct TileOpBuilder {
     };
     std::vector<Term> terms;   // diagonal terms collected since the last emission
     uint32_t ph_bits = 0;      // the tile bits they test
+    // controlled-X gates collected for one TILE_XPERM op: no target is
+    // another's target or control, so they commute and their product is
+    // its own inverse.  (Pending phase terms never test a collected target,
+    // and collected gates never target a bit a pending term tests: the two
+    // collections commute.)
+    qcx::TileOp xp{};
+    uint32_t xp_bits = 0, xp_tgt = 0;   // the tile bits the gates touch / target
+    bool xperms = true;                 // false: no TILE_XPERM ops (kernels without them)
 
     TileOpBuilder(int n_, uint64_t P_, std::vector<qcx::TileOp> &o) : n(n_), P(P_), out(o) {}
 
@@ -1055,16 +1067,43 @@ struct TileOpBuilder {
     // one diagonal term: multiply by `phase` where the conditions hold
     void add_phase(uint32_t mlo, uint32_t vlo, uint64_t mhi, uint64_t vhi, cd phase) {
         flush_bits(mlo);
+        if (mlo & xp_tgt) emit_xperm();
         terms.push_back({mlo, vlo, mhi, vhi, phase});
         ph_bits |= mlo;
+    }
+    void emit_xperm() {
+        if (xp.b0 > 0) {
+            xp.kind = qcx::TILE_XPERM;
+            out.push_back(xp);
+        }
+        xp = qcx::TileOp{};
+        xp_bits = xp_tgt = 0;
+    }
+    // X on tile bit t where the controls hold (clo/cvlo in the tile, chi/cvhi
+    // outside)
+    void add_xgate(int t, uint32_t clo, uint32_t cvlo, uint64_t chi, uint64_t cvhi) {
+        const uint32_t tb = 1u << t;
+        flush_bits(clo | tb);
+        if (ph_bits & tb) emit_phases();
+        if ((xp_bits & tb) || (clo & xp_tgt) || xp.b0 == qcx::kXpermTerms) emit_xperm();
+        const int k = xp.b0++;
+        xp.x_cm[k] = clo;
+        xp.x_cv[k] = cvlo;
+        xp.x_t[k] = uint32_t(t);
+        xp.x_hm[k] = chi;
+        xp.x_hv[k] = cvhi;
+        xp_bits |= clo | tb;
+        xp_tgt |= tb;
     }
     void add_op(const qcx::TileOp &op, uint32_t touched) {
         flush_bits(touched);
         if (ph_bits & touched) emit_phases();
+        if (xp_bits & touched) emit_xperm();
         out.push_back(op);
     }
     void add_1q(int b, const double *u) {
         if ((ph_bits >> b) & 1) emit_phases();
+        if ((xp_bits >> b) & 1) emit_xperm();
         const cd m[4] = {cd(u[0], u[1]), cd(u[2], u[3]), cd(u[4], u[5]), cd(u[6], u[7])};
         if (!((held_bits >> b) & 1)) {
             for (int i = 0; i < 4; ++i) held[b][i] = m[i];
@@ -1110,6 +1149,10 @@ struct TileOpBuilder {
                 add_1q(cidx(tp), u);
                 return;
             }
+            if (xperms && t_in && is_x_1q(u)) {
+                add_xgate(cidx(tp), clo, cvlo, chi, cvhi);
+                return;
+            }
             qcx::TileOp op{};
             op.kind = qcx::TILE_DENSE1;
             op.b0 = cidx(tp);
@@ -1134,6 +1177,7 @@ struct TileOpBuilder {
     }
     void finish() {
         emit_phases();
+        emit_xperm();
         flush_bits(held_bits);
     }
 };
@@ -1966,6 +2010,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         TileOpBuilder B(n, r.P, tops);
         B.kron_max = 1;   // k_adjoint_tiles is compiled without TILE_KRON
         B.fans = false;   // nor with the fan ops
+        B.xperms = false;   // nor with the X permutations
         for (int j : r.gates) {
             if (rot_row[j] >= 0) {
                 if (int(slot_row.size()) == qcx::kAdjointMaxSlots) {

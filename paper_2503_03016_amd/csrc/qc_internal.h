@@ -123,6 +123,11 @@ struct Mat2d {
 // one pass: generator b1 & 15, slot pad & 0xffff, matrix u[0..7] first,
 // then generator b1 >> 4, slot pad >> 16, matrix u1.  Each partial uses the
 // values before its own matrix.
+// TILE_XPERM: b0 controlled-X gates that commute (no target is another's
+// target or control) as one permutation of the tile: amplitude i trades
+// places with i ^ f(i), f(i) = the OR of 2^x_t[k] over the gates k whose
+// controls hold: (i & x_cm[k]) == x_cv[k] and (tile_base & x_hm[k]) ==
+// x_hv[k].  The permutation is its own inverse, so one pass of swaps.
 // TILE_KRON: b0 = g (2..kKronMax) one-qubit matrices on the distinct
 // compressed bits (b1 >> 5j) & 31, j < g, ascending; matrix j is u[8j ..
 // 8j + 7].  They commute, so each group of 2^g amplitudes is loaded once and
@@ -131,8 +136,9 @@ enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
     TILE_KRON = 9, TILE_DENSE1_PHASES = 10, TILE_FAN = 11, TILE_DENSE1_FAN = 12,
-    TILE_GRAD_APPLY2_DIAG_REAL = 13
+    TILE_GRAD_APPLY2_DIAG_REAL = 13, TILE_XPERM = 14
 };
+constexpr int kXpermTerms = 12;
 constexpr int kKronMax = 3;
 constexpr int kTileMaxBits = 16;
 constexpr int kTilePhaseTerms = 16;
@@ -152,6 +158,10 @@ struct TileOp {
         struct {               // TILE_FAN out-of-tile controls
             uint64_t fan_mask[kTilePhaseTerms];
             double fan_ph[2 * kTilePhaseTerms];
+        };
+        struct {               // TILE_XPERM gates
+            uint32_t x_cm[kXpermTerms], x_cv[kXpermTerms], x_t[kXpermTerms];
+            uint64_t x_hm[kXpermTerms], x_hv[kXpermTerms];
         };
     };
     double u1[8];              // TILE_DENSE1_PHASES / TILE_DENSE1_FAN: the one-qubit matrix

@@ -491,6 +491,52 @@ __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const Ti
     }
 }
 
+// TILE_XPERM: each thread takes its elements i (threadIdx.x + kBlock k),
+// finds its partner j = i ^ f(i) and swaps the two when j > i, so every
+// pair is moved by exactly one thread and no barrier is needed inside the
+// op.  The gates' fields are moved to scalar registers; lane k of every
+// wavefront checks the out-of-tile controls of gate k.
+template <typename R>
+__device__ inline void apply_xperm(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op) {
+    const int T = 1 << m;
+    const int nt = int(uniform(uint32_t(op.b0)));
+    const int lane = int(threadIdx.x & 63);
+    const int kl = lane < kXpermTerms ? lane : 0;
+    const bool ok = lane < nt && (tile_base & op.x_hm[kl]) == op.x_hv[kl];
+    const uint32_t live = uniform(uint32_t(__ballot(ok)));
+    uint32_t cm[kXpermTerms], cv[kXpermTerms], fb[kXpermTerms];
+#pragma unroll
+    for (int t = 0; t < kXpermTerms; ++t) {
+        cm[t] = uniform(op.x_cm[t]);
+        cv[t] = uniform(op.x_cv[t]);
+        fb[t] = ((live >> t) & 1u) ? 1u << uniform(op.x_t[t]) : 0u;
+    }
+    for (int i0 = threadIdx.x; i0 < T; i0 += kBlock * kItems) {
+        uint32_t j[kItems];
+        cx<R> a[kItems], b[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t i = uint32_t(i0 + k * kBlock);
+            uint32_t f = 0;
+#pragma unroll
+            for (int t = 0; t < kXpermTerms; ++t)
+                if ((i & cm[t]) == cv[t]) f |= fb[t];
+            j[k] = i ^ f;
+            const bool mine = i < uint32_t(T) && j[k] > i;
+            a[k] = mine ? lds[i] : cx<R>{R(0), R(0)};
+            b[k] = mine ? lds[j[k]] : cx<R>{R(0), R(0)};
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint32_t i = uint32_t(i0 + k * kBlock);
+            if (i < uint32_t(T) && j[k] > i) {
+                lds[i] = b[k];
+                lds[j[k]] = a[k];
+            }
+        }
+    }
+}
+
 // Op staging: the op being applied is read from one of two LDS slots.
 // While op o runs, the first kOpWords lanes hold op o + 1 in registers
 // (a global load issued before op o starts) and write it to the other slot
@@ -540,6 +586,7 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
             else if (op.kind == TILE_DENSE1_PHASES) apply_dense1_phases<R>(lds, m, tile_base, op, pt);
             else if (op.kind == TILE_FAN) apply_fan<R, false>(lds, m, tile_base, op, fan_h);
             else if (op.kind == TILE_DENSE1_FAN) apply_fan<R, true>(lds, m, tile_base, op, fan_h);
+            else if (op.kind == TILE_XPERM) apply_xperm<R>(lds, m, tile_base, op);
             else apply_one<R>(lds, m, op);
         }
         if (next) stage_store(st, &slot[(o + 1) & 1]);
