@@ -1066,7 +1066,9 @@ struct TileOpBuilder {
     }
     // one diagonal term: multiply by `phase` where the conditions hold
     void add_phase(uint32_t mlo, uint32_t vlo, uint64_t mhi, uint64_t vhi, cd phase) {
-        flush_bits(mlo);
+        // all held gates go out now, in groups of kron_max bits (a ladder of
+        // diagonal gates would otherwise flush them one bit at a time)
+        if (mlo & held_bits) flush_bits(held_bits);
         if (mlo & xp_tgt) emit_xperm();
         terms.push_back({mlo, vlo, mhi, vhi, phase});
         ph_bits |= mlo;
