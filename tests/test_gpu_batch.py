@@ -61,7 +61,8 @@ def test_batch_mixed_sizes_states_and_energies(qc, G, dtype):
 
 
 def test_batch_general_gates_and_terms(qc, G):
-    """Dense 1q/2q gates, controls (open and closed), phases, Y terms."""
+    """Dense 1q/2q gates, controls (open and closed), phases, Y terms, and
+    QFT circuits (controlled-phase fans, SWAPs)."""
     rng = np.random.default_rng(3)
     from dense_ref import random_unitary
     circuits, refs = [], []
@@ -82,6 +83,12 @@ def test_batch_general_gates_and_terms(qc, G):
         circuits.append((n, G.gate_tuples(ops), terms))
         psi = oracle.run(ops, oracle.basis_state(n, 0))
         refs.append(oracle.energy(psi, terms))
+        # a QFT after a layer of random one-qubit gates: controlled-phase
+        # fans and SWAPs inside the batch kernel
+        rq = np.random.default_rng(30 + n)   # its own stream: the draws above stay as they were
+        qops = [W.Op("U", (q,), matrix=random_unitary(2, rq)) for q in range(n)] + W.qft(n)
+        circuits.append((n, G.gate_tuples(qops), W.tfim_terms(n)))
+        refs.append(oracle.energy(oracle.run(qops, oracle.basis_state(n, 0)), W.tfim_terms(n)))
     b = qc.Batch(circuits, dtype=torch.complex128)
     e = b.run().cpu().numpy()
     assert b.status() == 0
