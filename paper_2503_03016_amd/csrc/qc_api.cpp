@@ -1014,6 +1014,9 @@ struct TileOpBuilder {
     // false (nothing emitted) otherwise.  Out-of-tile controls beyond
     // kTilePhaseTerms go to further TILE_FAN ops on the same target.
     bool emit_fan() {
+        // the kernels keep one group entry per kBlock amplitudes for at most
+        // 2^13-amplitude tiles (64 KiB of complex64, the LDS tile limit)
+        if (__builtin_popcountll(P) > 13) return false;
         uint32_t common = ~0u;
         for (const Term &tm : terms) {
             const int lo = __builtin_popcount(tm.mlo), hi = __builtin_popcountll(tm.mhi);
