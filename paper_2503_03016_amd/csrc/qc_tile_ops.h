@@ -407,51 +407,67 @@ __device__ inline void apply_dense1_phases(cx<R> *lds, int m, uint64_t tile_base
 // bit set factorizes: K (terms on the target alone, and the out-of-tile
 // controls the tile has set) times the phases of its set control bits
 // below kLoBits (fixed per thread: the pairs a thread takes share their low
-// bits) times those of its set control bits above (fixed per group of
-// kBlock elements: fan_h, one entry per group, built by the first threads).
-// No table over the control bits and no limit on their number.
+// bits; from two small tables, over bits 0..5 and 6..8) times those of its
+// set control bits above (fixed per group of kBlock elements: one entry per
+// group, K included).  The tables are built by the first two wavefronts.
+// No table over all the control bits and no limit on their number.
 constexpr int kFanGroups = 1 << (13 - kLoBits);   // tiles hold at most 2^13 amplitudes
+
+// LDS of a fan op: the group factors (K included) and two tables of the
+// low-bit factor: lo6[e] over control bits 0..5, lo3[e] over bits 6..8
+template <typename R>
+struct FanTables {
+    cx<R> h[kFanGroups];
+    cx<R> lo6[64], lo3[8];
+};
 
 template <typename R, bool DENSE>
 __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const TileOp &op,
-                                 cx<R> *fan_h) {
+                                 FanTables<R> &ft) {
+    static_assert(kLoBits == 9, "the low-bit factor tables cover 6 + 3 bits");
     const int T = 1 << m;
     const int t = op.b0;
     const uint32_t bit = 1u << t;
     const uint32_t cm = uniform(uint32_t(op.b1));
-    // K: lane k of each wavefront takes out-of-tile control k, then a
-    // butterfly over 16 lanes multiplies them; lane 0's product is used
-    const int nh = int(uniform(uint32_t(op.pad)));
-    const int lane = int(threadIdx.x & 63);
-    const int kl = lane < kTilePhaseTerms ? lane : 0;
-    const uint64_t fm = op.fan_mask[kl];
-    cx<R> f{R(1), R(0)};
-    if (lane < nh && (tile_base & fm) == fm) f = cx<R>{R(op.fan_ph[2 * kl]), R(op.fan_ph[2 * kl + 1])};
-    static_assert(kTilePhaseTerms == 16, "one butterfly over 16 lanes");
+    if (threadIdx.x < 64) {   // wavefront 0: K, the group factors, lo6
+        // K: lane k takes out-of-tile control k, then a butterfly over 16
+        // lanes multiplies them; lane 0's product is used
+        const int nh = int(uniform(uint32_t(op.pad)));
+        const int lane = int(threadIdx.x);
+        const int kl = lane < kTilePhaseTerms ? lane : 0;
+        const uint64_t fm = op.fan_mask[kl];
+        cx<R> f{R(1), R(0)};
+        if (lane < nh && (tile_base & fm) == fm) f = cx<R>{R(op.fan_ph[2 * kl]), R(op.fan_ph[2 * kl + 1])};
+        static_assert(kTilePhaseTerms == 16, "one butterfly over 16 lanes");
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-        const cx<R> o{__shfl_xor(f.re, off, 64), __shfl_xor(f.im, off, 64)};
-        f = cmul(f, o);
-    }
-    cx<R> K{lane_value(f.re, 0), lane_value(f.im, 0)};
-    K = cmul(K, ld_u<R>(op.u, t));
-    const int groups = m > kLoBits ? 1 << (m - kLoBits) : 1;
-    if (int(threadIdx.x) < groups) {
-        cx<R> h = K;
-        for (int c = kLoBits; c < m; ++c)
-            if (((cm >> c) & 1u) && ((threadIdx.x >> (c - kLoBits)) & 1u)) h = cmul(h, ld_u<R>(op.u, c));
-        fan_h[threadIdx.x] = h;
-    }
-    // the thread's factor from the control bits below kLoBits of its
-    // elements with the target set (the same for every pair it takes)
-    const uint32_t lo1 = (ins0(threadIdx.x, t) | bit) & (kBlock - 1);
-    cx<R> flo{R(1), R(0)};
-#pragma unroll
-    for (int c = 0; c < kLoBits; ++c)
-        if ((cm >> c) & 1u) {   // uniform
-            const cx<R> p = ld_u<R>(op.u, c);
-            if ((lo1 >> c) & 1u) flo = cmul(flo, p);
+        for (int off = 1; off < 16; off <<= 1) {
+            const cx<R> o{__shfl_xor(f.re, off, 64), __shfl_xor(f.im, off, 64)};
+            f = cmul(f, o);
         }
+        cx<R> K{lane_value(f.re, 0), lane_value(f.im, 0)};
+        K = cmul(K, ld_u<R>(op.u, t));
+        const int groups = m > kLoBits ? 1 << (m - kLoBits) : 1;
+        if (lane < groups) {
+            cx<R> h = K;
+            for (int c = kLoBits; c < m; ++c)
+                if (((cm >> c) & 1u) && ((lane >> (c - kLoBits)) & 1)) h = cmul(h, ld_u<R>(op.u, c));
+            ft.h[lane] = h;
+        }
+        cx<R> p{R(1), R(0)};
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (((cm >> c) & 1u) && ((lane >> c) & 1)) p = cmul(p, ld_u<R>(op.u, c));
+        ft.lo6[lane] = p;
+    } else if (threadIdx.x < 72) {   // lo3
+        const int e = int(threadIdx.x) - 64;
+        cx<R> p{R(1), R(0)};
+#pragma unroll
+        for (int c = 6; c < kLoBits; ++c)
+            if (((cm >> c) & 1u) && ((e >> (c - 6)) & 1)) p = cmul(p, ld_u<R>(op.u, c));
+        ft.lo3[e] = p;
+    }
+    // the thread's elements with the target set share their low kLoBits bits
+    const uint32_t lo1 = (ins0(threadIdx.x, t) | bit) & (kBlock - 1);
     cx<R> u0, u1, u2, u3;
     if (DENSE) {
         u0 = ld_u<R>(op.u1, 0);
@@ -459,7 +475,8 @@ __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const Ti
         u2 = ld_u<R>(op.u1, 2);
         u3 = ld_u<R>(op.u1, 3);
     }
-    __syncthreads();   // fan_h
+    __syncthreads();   // the fan tables
+    const cx<R> flo = cmul(ft.lo6[lo1 & 63], ft.lo3[lo1 >> 6]);
     const int npairs = T >> 1;
     for (int g0 = threadIdx.x; g0 < npairs; g0 += kBlock * kItems) {
         uint32_t i1[kItems];
@@ -473,7 +490,7 @@ __device__ inline void apply_fan(cx<R> *lds, int m, uint64_t tile_base, const Ti
             if (g < npairs) {
                 if (DENSE) a0[k] = lds[i1[k] ^ bit];
                 a1[k] = lds[i1[k]];
-                h[k] = fan_h[i1[k] >> kLoBits];
+                h[k] = ft.h[i1[k] >> kLoBits];
             }
         }
 #pragma unroll
@@ -573,7 +590,7 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
                                  int n_ops, TileOp *slot) {
     if (n_ops <= 0) return;
     __shared__ PhaseTables<R> pt;
-    __shared__ cx<R> fan_h[kFanGroups];
+    __shared__ FanTables<R> ft;
     stage_now(&slot[0], &ops[0]);
     __syncthreads();
     for (int o = 0; o < n_ops; ++o) {
@@ -584,8 +601,8 @@ __device__ inline void apply_ops(cx<R> *lds, int m, uint64_t tile_base, const Ti
         if ((tile_base & op.cmask_hi) == op.cval_hi) {   // uniform per tile
             if (op.kind == TILE_PHASES) apply_phases<R>(lds, m, tile_base, op, pt);
             else if (op.kind == TILE_DENSE1_PHASES) apply_dense1_phases<R>(lds, m, tile_base, op, pt);
-            else if (op.kind == TILE_FAN) apply_fan<R, false>(lds, m, tile_base, op, fan_h);
-            else if (op.kind == TILE_DENSE1_FAN) apply_fan<R, true>(lds, m, tile_base, op, fan_h);
+            else if (op.kind == TILE_FAN) apply_fan<R, false>(lds, m, tile_base, op, ft);
+            else if (op.kind == TILE_DENSE1_FAN) apply_fan<R, true>(lds, m, tile_base, op, ft);
             else if (op.kind == TILE_XPERM) apply_xperm<R>(lds, m, tile_base, op);
             else apply_one<R>(lds, m, op);
         }
