@@ -18,8 +18,12 @@
 // Diagonal terms: thread t owns the elements i = t + kBlock k, k < K, so
 // (-1)^popc(i & z) = (-1)^popc(t & z_lo) (-1)^popc(k & z_k) with z_lo, z_k
 // the parts of z below and above bit kLoBits.  The thread takes |psi_i|^2
-// once per tile and their K Walsh sums W[h] = sum_k (-1)^popc(k & h) w_k;
-// a diagonal term is then one W entry and one sign.
+// once per tile and their K Walsh sums W[h] = sum_k (-1)^popc(k & h) w_k.
+// The leading diagonal terms of a launch then take the transform further,
+// over the six lane bits (butterflies between lanes), and each one reads
+// its coefficient from the eight wavefronts (through LDS) with their signs:
+// one thread per term, no reduction per term.  Diagonal terms after the
+// first X term take one W entry and one sign and a wavefront sum.
 #include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
@@ -38,21 +42,35 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Bytes before the term slots: the tile, or the diagonal terms'
+// coefficients (kBlock doubles per element a thread holds) if larger.
+__host__ __device__ inline size_t diag_region(int T, size_t elem) {
+    const size_t tile = size_t(T) * elem;
+    const size_t co = size_t(T > kBlock ? T : kBlock) * sizeof(double);
+    return tile > co ? tile : co;
+}
+static_assert(kWaves == 8, "frequency bits 6..8 are the wavefront index");
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const TileArgs a,
                                                          const ExpectTerm *terms, int nt,
                                                          double *part) {
     extern __shared__ unsigned char smem[];
     const int T = 1 << a.m;
+    const int K = T > kBlock ? T >> tile::kLoBits : 1;   // elements per thread
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
-    double *wacc = reinterpret_cast<double *>(lds + T);   // [term][wave]
+    double *coef = reinterpret_cast<double *>(smem);   // reuses the tile (see diag_region)
+    double *wacc = reinterpret_cast<double *>(smem + diag_region(T, sizeof(cx<R>)));   // [term][wave]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < nt * kWaves; i += kBlock) wacc[i] = 0.0;
+    // the leading diagonal terms (thread d keeps the sum of term d)
+    int nd = 0;
+    while (nd < nt && nd < kBlock && terms[nd].xc == 0) ++nd;
+    double dacc = 0.0;
     const uint64_t off_lo =
         tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
     const uint64_t mask = tile::hi_mask(a.pos, a.m);
     const int half = T >> 1;
-    const int K = T > kBlock ? T >> tile::kLoBits : 1;   // elements per thread
     for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
         tile::tile_load<R>(lds, amp, base, off_lo, mask, T);
@@ -76,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
                     W[k] = u + v;
                     W[k | h] = u - v;
                 }
-        for (int k = 0; k < nt; ++k) {
+        for (int k = nd; k < nt; ++k) {
             const ExpectTerm tm = terms[k];
             double acc = 0.0;
             if (tm.xc == 0) {
@@ -113,13 +131,42 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
             if (__popcll(base & tm.z_hi) & 1) acc = -acc;
             if (lane == 0) wacc[k * kWaves + wave] += acc;
         }
+        if (nd > 0) {   // uniform
+            // the Walsh transform of |psi|^2 continued over the six lane
+            // bits: W[h] of lane l becomes the coefficient of frequency
+            // (l, h) summed over this wavefront's elements
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+#pragma unroll
+                for (int h = 0; h < kMaxK; ++h) {
+                    const double p = __shfl_xor(W[h], 1 << b, 64);
+                    W[h] = ((lane >> b) & 1) ? p - W[h] : W[h] + p;
+                }
+            __syncthreads();   // every read of the tile is done: its LDS now holds the coefficients
+            for (int h = 0; h < K; ++h) coef[h * kBlock + int(threadIdx.x)] = W[h];
+            __syncthreads();
+            // term d: frequency zc = (wavefront bits, lane bits, h); the
+            // eight wavefronts' coefficients combine with their signs
+            if (int(threadIdx.x) < nd) {
+                const ExpectTerm tm = terms[threadIdx.x];
+                const uint32_t lu = tm.zc & 63u, wu = (tm.zc >> 6) & 7u, hu = tm.zc >> tile::kLoBits;
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    const double c = coef[hu * kBlock + uint32_t(w) * 64 + lu];
+                    v += (__popc(uint32_t(w) & wu) & 1) ? -c : c;
+                }
+                // the Z bits outside the tile give every amplitude of it one sign
+                dacc += (__popcll(base & tm.z_hi) & 1) ? -v : v;
+            }
+        }
         __syncthreads();
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nt; k += kBlock) {
         double s = 0.0;
         for (int w = 0; w < kWaves; ++w) s += wacc[k * kWaves + w];
-        part[size_t(k) * gridDim.x + blockIdx.x] = s;
+        part[size_t(k) * gridDim.x + blockIdx.x] = k < nd ? dacc : s;   // thread k < nd owns term k
     }
 }
 
@@ -157,7 +204,7 @@ hipError_t launch_expect_tiles(const void *amp, int dtype, const TileArgs &a,
     if (nt < 1 || nt > kExpectTileMaxTerms || a.m < 1 || (1 << a.m) > kBlock * kMaxK)
         return hipErrorInvalidValue;
     const size_t elem = dtype == QC_C64 ? 8 : 16;
-    const size_t lds = (size_t(1) << a.m) * elem + size_t(nt) * kWaves * sizeof(double);
+    const size_t lds = diag_region(1 << a.m, elem) + size_t(nt) * kWaves * sizeof(double);
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned grid = expect_tiles_grid(a.n_tiles);
     const int tok = timer_begin("expect_tiles", s);
