@@ -104,6 +104,17 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
                 for (int h = 1; h < kMaxK; ++h)
                     if (zk == uint32_t(h)) w = W[h];
                 acc = (__popc(threadIdx.x & tm.zc) & 1) ? -w : w;
+            } else if (tm.zc == 0 && tm.ph == 0) {   // uniform: X factors only
+                // both signs +1: the pair gives 2 Re(conj(b) a)
+                const uint32_t hb = tm.xtop;
+                for (int g = threadIdx.x; g < half; g += kBlock) {
+                    const uint32_t i = ((uint32_t(g) >> hb) << (hb + 1)) | (uint32_t(g) & ((1u << hb) - 1));
+                    const uint32_t ix = i ^ tm.xc;
+                    const double ar = double(lds[i].re), ai = double(lds[i].im);
+                    const double br = double(lds[ix].re), bi = double(lds[ix].im);
+                    acc += br * ar + bi * ai;
+                }
+                acc *= 2.0;
             } else {
                 // pairs (i, i ^ xc), i with a zero at the top bit of xc
                 const uint32_t hb = tm.xtop;
