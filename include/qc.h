@@ -65,7 +65,7 @@ extern "C" {
 #define QC_ERR_ARG         -1   /* malformed argument (null pointer, size) */
 #define QC_ERR_QUBIT       -2   /* qubit label out of range or repeated    */
 #define QC_ERR_DTYPE       -3   /* unknown or mismatched element type      */
-#define QC_ERR_UNSUPPORTED -4   /* valid request this build does not serve */
+#define QC_ERR_UNSUPPORTED -4   /* valid request the library does not serve */
 #define QC_ERR_HIP         -5   /* HIP runtime error (see qc_last_error)   */
 #define QC_ERR_NOMEM       -6   /* workspace allocation failed             */
 
