@@ -76,6 +76,15 @@ __device__ double tile_energy(const cx<R> *lds, int m, uint64_t base, const Batc
                 const double w = double(a.re) * double(a.re) + double(a.im) * double(a.im);
                 acc += ((sbase + __popc(uint32_t(j) & tm.zc)) & 1) ? -tm.c * w : tm.c * w;
             }
+        } else if (tm.zc == 0 && tm.ph == 0 && sbase == 0) {   // uniform: X factors only
+            // both signs +1: the pair gives 2 Re(conj(b) a)
+            double v = 0.0;
+            for (int g = threadIdx.x; g < (T >> 1); g += kBlock) {
+                const uint32_t j = uint32_t(insert_zero(uint64_t(g), tm.xtop));
+                const cx<R> pa = lds[j], pb = lds[j ^ tm.xc];
+                v += double(pb.re) * double(pa.re) + double(pb.im) * double(pa.im);
+            }
+            acc += 2.0 * tm.c * v;
         } else {
             for (int g = threadIdx.x; g < (T >> 1); g += kBlock) {
                 const uint32_t j = uint32_t(insert_zero(uint64_t(g), tm.xtop));
