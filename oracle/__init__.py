@@ -17,7 +17,17 @@ Van Beeumen, 2025):
 * ``collapse`` / ``simulate``  collapse and renormalisation, section 3.3;
                                one branch per outcome with non-zero
                                probability (mid-circuit measurements,
-                               section 3.3 and the examples of section 5).
+                               section 3.3 and the examples of section 5),
+                               measurements in the Z, X, Y or a custom basis
+                               (basis change V before, V^dagger after,
+                               sections 2 and 3.3) and qubit resets
+                               (section 3.3).
+* ``reset``                    one branch of a qubit reset: the outcome-b
+                               collapse of section 3.3 followed, for b = 1,
+                               by X on the qubit.
+* ``counts``                   shot counts over the measured qubits (the
+                               ``counts`` of section 5.2) from caller-given
+                               uniforms.
 * ``reduced_statevector``      state of the unmeasured qubits once the
                                measured ones are known (section 5.1).
 * ``expect_pauli`` / ``energy``  <psi|P|psi> for Pauli strings, the quantity
@@ -52,6 +62,7 @@ __all__ = [
     "build", "gate_matrix", "apply", "run", "probs", "collapse", "simulate",
     "reduced_statevector", "expect_pauli", "energy", "param_shift_grad",
     "fd_grad", "qft_amplitude", "basis_state", "set_threads", "threads",
+    "reset", "sample", "counts",
 ]
 
 
@@ -270,30 +281,62 @@ _BASIS_CHANGE = {
 }
 
 
+def basis_change(basis) -> Optional[np.ndarray]:
+    """The matrix V applied before a measurement in ``basis`` (None for the
+    computational basis): "x", "y", or a caller-given 2 x 2 unitary (a
+    custom basis, section 2).  V^dagger is applied after the measurement
+    (section 3.3)."""
+    if isinstance(basis, str):
+        seq = _BASIS_CHANGE[basis]
+        if seq is None:
+            return None
+        v = np.eye(2, dtype=np.complex128)
+        for g in seq:          # applied in this order: V = last @ ... @ first
+            v = gate_matrix(g) @ v
+        return v
+    v = np.asarray(basis, dtype=np.complex128)
+    if v.shape != (2, 2):
+        raise ValueError("a custom measurement basis is a 2 x 2 matrix")
+    return v
+
+
+def reset(psi: np.ndarray, q: int, outcome: int) -> Tuple[np.ndarray, float]:
+    """One branch of a reset of qubit q (section 3.3): collapse onto
+    ``outcome`` (renormalised), then, if the outcome is 1, flip the qubit
+    back to |0> with X.  Returns the branch state and its probability."""
+    post, pb = collapse(psi, q, outcome)
+    if outcome == 1 and pb > 0.0:
+        post = apply(post, (q,), gate_matrix("X"))
+    return post, pb
+
+
 def simulate(n: int, items, init) -> List[Tuple[str, float, np.ndarray]]:
     """Branching simulation as in section 3.3: ``items`` is a list of
-    workloads.Op gates and ``("M", qubit[, basis])`` measurements.  Returns
-    one (outcome string, probability, final state) per branch with non-zero
-    probability, outcomes ordered lexicographically, one character per
-    measurement in the order performed."""
+    workloads.Op gates, ``("M", qubit[, basis])`` measurements (basis "z",
+    "x", "y" or a 2 x 2 basis-change matrix V) and ``("R", qubit)`` resets.
+    Returns one (outcome string, probability, final state) per branch with
+    non-zero probability, outcomes ordered lexicographically, one character
+    per measurement or reset in the order performed (a reset records the
+    outcome of its measurement: its two branches are different states)."""
     psi0 = basis_state(n, init) if isinstance(init, (str, int)) else _cvec(init)
     branches = [("", 1.0, psi0.copy())]
     for it in items:
-        if isinstance(it, tuple) and it and it[0] == "M":
+        if isinstance(it, tuple) and it and it[0] in ("M", "R"):
             q = it[1]
-            basis = it[2] if len(it) > 2 else "z"
-            pre = _BASIS_CHANGE[basis]
+            is_reset = it[0] == "R"
+            v = None if is_reset else basis_change(it[2] if len(it) > 2 else "z")
             new = []
             for res, p, psi in branches:
-                if pre:
-                    for g in pre:
-                        psi = apply(psi, (q,), gate_matrix(g))
+                if v is not None:
+                    psi = apply(psi, (q,), v)
                 for b in (0, 1):
-                    post, pb = collapse(psi, q, b)
+                    if is_reset:
+                        post, pb = reset(psi, q, b)
+                    else:
+                        post, pb = collapse(psi, q, b)
                     if pb > 1e-14:
-                        if pre:
-                            for g in reversed(pre):
-                                post = apply(post, (q,), gate_matrix(g).conj().T)
+                        if v is not None:
+                            post = apply(post, (q,), v.conj().T)
                         new.append((res + str(b), p * pb, post))
             branches = new
         else:
@@ -370,6 +413,19 @@ def sample(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
     cdf = np.cumsum(p)
     x = np.asarray(u, dtype=np.float64) * cdf[-1]
     return np.searchsorted(cdf, x, side="right").astype(np.int64)
+
+
+def counts(psi: np.ndarray, qubits: Sequence[int], u: np.ndarray) -> np.ndarray:
+    """Shot counts over the measured qubits (``counts`` of section 5.2): each
+    uniform draws one basis index with ``sample``; the shot is recorded
+    under the values of the listed qubits (first listed = most significant
+    bit of the outcome).  Returns 2^len(qubits) integer counts."""
+    n = nqubits(_cvec(psi))
+    idx = sample(psi, u)
+    out = np.zeros(idx.shape, dtype=np.int64)
+    for q in qubits:
+        out = 2 * out + ((idx >> (n - 1 - q)) & 1)
+    return np.bincount(out, minlength=1 << len(qubits)).astype(np.int64)
 
 
 # ------------------------------------------------------------------- QFT

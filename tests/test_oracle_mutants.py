@@ -10,6 +10,7 @@ import ctypes
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -75,3 +76,58 @@ def test_pins_catch_planted_mistake(name, tmp_path, monkeypatch):
         except (AssertionError, ValueError):
             failures += 1
     assert failures > 0, "no pin caught the planted mistake %s" % name
+
+
+# ---- mistakes in the oracle's gate library (oracle/__init__.py) -------------
+
+def _mutated_gate_matrix(real, kind_hit, change):
+    def gm(kind, angle=None):
+        m = real(kind, angle)
+        return change(m) if kind == kind_hit else m
+    return gm
+
+
+GATE_MUTANTS = {
+    # RX with the sign of its off-diagonal entries flipped: exp(+i t X/2)
+    "rx_offdiag_sign": ("RX", lambda m: np.array([[m[0, 0], -m[0, 1]], [-m[1, 0], m[1, 1]]])),
+    # RY transposed
+    "ry_transposed": ("RY", lambda m: m.T.copy()),
+    # RZ conjugated
+    "rz_conjugated": ("RZ", lambda m: m.conj()),
+    # Y with the wrong sign
+    "y_sign": ("Y", lambda m: -m),
+    # S and its adjoint swapped
+    "s_conjugated": ("S", lambda m: m.conj()),
+    "sdg_conjugated": ("SDG", lambda m: m.conj()),
+    # phase gate conjugated
+    "p_conjugated": ("P", lambda m: m.conj()),
+    # H with its rows swapped
+    "h_rows_swapped": ("H", lambda m: m[::-1].copy()),
+    # X replaced by the identity
+    "x_identity": ("X", lambda m: np.eye(2, dtype=complex)),
+    # Z replaced by X
+    "z_as_x": ("Z", lambda m: np.array([[0, 1], [1, 0]], dtype=complex)),
+}
+
+GATE_PIN_TESTS = [
+    pins.test_gate_library_vs_definitions,
+    pins.test_every_gate_kind_through_run_vs_dense,
+    pins.test_named_gates_vs_dense,
+    pins.test_paper_tomography_exact_part,
+    pins.test_paper_grover,
+    pins.test_paper_qec,
+    pins.test_qft_basis_state_closed_form,
+]
+
+
+@pytest.mark.parametrize("name", sorted(GATE_MUTANTS))
+def test_pins_catch_gate_library_mistake(name, monkeypatch):
+    kind, change = GATE_MUTANTS[name]
+    monkeypatch.setattr(oracle, "gate_matrix", _mutated_gate_matrix(oracle.gate_matrix, kind, change))
+    failures = 0
+    for t in GATE_PIN_TESTS:
+        try:
+            t()
+        except (AssertionError, ValueError):
+            failures += 1
+    assert failures > 0, "no pin caught the planted gate-library mistake %s" % name

@@ -51,9 +51,7 @@ def _teleport_init():
 
 def test_paper_teleportation():
     ex = GOLD["teleportation"]
-    items = [W.Op("CNOT", (0, 1)), W.Op("H", (0,)), ("M", 0), ("M", 1),
-             W.Op("CNOT", (1, 2)), W.Op("CZ", (0, 2))]
-    br = oracle.simulate(3, items, _teleport_init())
+    br = oracle.simulate(3, W.teleportation(), _teleport_init())
     assert [b[0] for b in br] == ex["results"]
     np.testing.assert_allclose([b[1] for b in br], ex["probabilities"], atol=tol(ex))
     np.testing.assert_allclose(br[0][2], cplx(ex["state_00"]), atol=tol(ex))
@@ -91,24 +89,20 @@ def test_paper_tomography_exact_part():
 
 def test_paper_grover():
     ex = GOLD["grover"]
-    H0, H1 = W.Op("H", (0,)), W.Op("H", (1,))
-    items = [H0, H1, W.Op("CZ", (0, 1)), H0, H1, W.Op("Z", (0,)), W.Op("Z", (1,)),
-             W.Op("CZ", (0, 1)), H0, H1, ("M", 0), ("M", 1)]
-    br = oracle.simulate(2, items, ex["init"])
+    br = oracle.simulate(2, W.grover2("11"), ex["init"])
     assert [b[0] for b in br] == ex["results"]
     np.testing.assert_allclose([b[1] for b in br], ex["probabilities"], atol=1e-14)
+    # one Grover iteration finds any marked state of N = 4 with certainty
+    for marked in ("00", "01", "10", "11"):
+        br = oracle.simulate(2, W.grover2(marked), "00")
+        assert [b[0] for b in br] == [marked] and abs(br[0][1] - 1.0) < 1e-14
 
 
 def test_paper_qec():
     ex = GOLD["qec"]
     v = np.array([1.0, 1j]) / math.sqrt(2.0)
     init = np.kron(v, np.eye(16)[:, 0])
-    items = [W.Op("CNOT", (0, 1)), W.Op("CNOT", (0, 2)), W.Op("X", (0,)),
-             W.Op("CNOT", (0, 3)), W.Op("CNOT", (1, 3)), W.Op("CNOT", (0, 4)),
-             W.Op("CNOT", (2, 4)), ("M", 3), ("M", 4),
-             W.Op("MCX", (3, 4, 2), ctrl_val=(0, 1)), W.Op("MCX", (3, 4, 1), ctrl_val=(1, 0)),
-             W.Op("MCX", (3, 4, 0), ctrl_val=(1, 1))]
-    br = oracle.simulate(5, items, init)
+    br = oracle.simulate(5, W.bitflip_code(error_qubit=0), init)
     assert [b[0] for b in br] == ex["results"]
     np.testing.assert_allclose([b[1] for b in br], ex["probabilities"], atol=1e-14)
     # closed form of this circuit: the error on q0 is undone, leaving
@@ -117,6 +111,99 @@ def test_paper_qec():
     ref[0b00011] = 1 / math.sqrt(2)
     ref[0b11111] = 1j / math.sqrt(2)
     np.testing.assert_allclose(br[0][2], ref, atol=1e-14)
+
+
+def test_bitflip_code_corrects_every_single_error():
+    # syndrome (parity q0q1, parity q0q2) names the flipped qubit; after the
+    # correction the encoded state is (|000> + i|111>)/sqrt2 whatever the error
+    v = np.array([1.0, 1j]) / math.sqrt(2.0)
+    init = np.kron(v, np.eye(16)[:, 0])
+    syndromes = {None: "00", 0: "11", 1: "10", 2: "01"}
+    for err, syn in syndromes.items():
+        br = oracle.simulate(5, W.bitflip_code(error_qubit=err), init)
+        assert [b[0] for b in br] == [syn] and abs(br[0][1] - 1.0) < 1e-14
+        anc = int(syn, 2)
+        ref = np.zeros(32, dtype=complex)
+        ref[anc] = 1 / math.sqrt(2)
+        ref[0b11100 | anc] = 1j / math.sqrt(2)
+        np.testing.assert_allclose(br[0][2], ref, atol=1e-14)
+
+
+# ------------------------------------------------ measurement bases and reset
+
+def test_custom_basis_h_is_the_x_basis():
+    # sections 2 and 3.3: a custom basis change V = H is the preconfigured
+    # X-basis measurement: same outcomes, probabilities and post-states
+    rng = np.random.default_rng(41)
+    psi = random_state(3, rng)
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2.0)
+    for q in range(3):
+        a = oracle.simulate(3, [("M", q, "x")], psi)
+        b = oracle.simulate(3, [("M", q, H)], psi)
+        assert [r for r, _, _ in a] == [r for r, _, _ in b]
+        for (_, pa, sa), (_, pb, sb) in zip(a, b):
+            assert abs(pa - pb) < 1e-15
+            np.testing.assert_allclose(sa, sb, atol=1e-15)
+        # X-basis probabilities are the |+>/|-> projections, from dense algebra
+        plus = np.array([1, 1]) / math.sqrt(2.0)
+        proj = dense_gate(3, [q], np.outer(plus, plus))
+        assert abs(a[0][1] - np.vdot(psi, proj @ psi).real) < 1e-14
+
+
+def test_custom_basis_hsdg_gives_tomography_s2():
+    # section 5.2: v = (1, i)/sqrt2 measured in the Y basis gives 0 with
+    # certainty, so S_2 = P(0) - P(1) = 1; a custom V = H S^dagger (the
+    # matrix product, built here from its factors) reproduces it
+    v = np.array([1.0, 1j]) / math.sqrt(2.0)
+    Hm = np.array([[1, 1], [1, -1]]) / math.sqrt(2.0)
+    Sdg = np.diag([1, -1j])
+    br = oracle.simulate(1, [("M", 0, Hm @ Sdg)], v)
+    p = {r: pr for r, pr, _ in br}
+    assert abs(p.get("0", 0.0) - p.get("1", 0.0) - 1.0) < 1e-14
+    # the basis change is reverted after the measurement: the branch state
+    # is the Y eigenvector again
+    np.testing.assert_allclose(br[0][2], v, atol=1e-15)
+    # a basis V whose rows are arbitrary orthonormal vectors: P(b) = |<row_b|v>|^2
+    rng = np.random.default_rng(43)
+    V = random_unitary(2, rng)
+    br = oracle.simulate(1, [("M", 0, V)], v)
+    for r, pr, _ in br:
+        assert abs(pr - abs(V[int(r)] @ v) ** 2) < 1e-14
+
+
+def test_reset_bell_branches():
+    # section 3.3 resets: reset q0 of (|00> + |11>)/sqrt2.  Outcome 0 (p 1/2)
+    # leaves |00>; outcome 1 (p 1/2) collapses to |11> and flips q0 back: |01>
+    bell = np.array([1, 0, 0, 1]) / math.sqrt(2.0)
+    br = oracle.simulate(2, [("R", 0)], bell)
+    assert [r for r, _, _ in br] == ["0", "1"]
+    np.testing.assert_allclose([p for _, p, _ in br], [0.5, 0.5], atol=1e-15)
+    np.testing.assert_allclose(br[0][2], [1, 0, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(br[1][2], [0, 1, 0, 0], atol=1e-15)
+    # a reset qubit reads 0 with certainty in every branch, for any state
+    psi = random_state(4, np.random.default_rng(44))
+    for q in range(4):
+        for _, _, s in oracle.simulate(4, [("R", q)], psi):
+            assert abs(oracle.probs(s, [q])[0] - 1.0) < 1e-14
+    # reset of a qubit already in |0> is one branch with the state unchanged
+    prod = np.kron([1, 0], random_state(2, np.random.default_rng(45)))
+    br = oracle.simulate(3, [("R", 0)], prod)
+    assert len(br) == 1 and abs(br[0][1] - 1.0) < 1e-14
+    np.testing.assert_allclose(br[0][2], prod, atol=1e-15)
+
+
+def test_counts_over_measured_qubits():
+    # section 5.2 counts: shots recorded under the values of the listed
+    # qubits; a product state |1>|+>|0> gives "10"/"11" half each on (0, 1)
+    n = 3
+    plus = np.array([1, 1]) / math.sqrt(2.0)
+    psi = np.kron(np.kron([0, 1], plus), [1, 0]).astype(complex)
+    u = (np.arange(1000) + 0.5) / 1000
+    c = oracle.counts(psi, [0, 1], u)
+    assert list(c) == [0, 0, 500, 500]
+    # listing order sets the bit order of the outcome
+    assert list(oracle.counts(psi, [1, 0], u)) == [0, 500, 0, 500]
+    assert int(oracle.counts(psi, [2], u)[0]) == 1000 and n == 3
 
 
 def test_open_control_only_fires_on_zero():
@@ -182,6 +269,59 @@ def test_controlled_all_values_vs_dense():
     u = random_unitary(4, rng)
     np.testing.assert_allclose(oracle.apply(psi, [4, 1], u, [2], [1]),
                                dense_gate(n, [4, 1], u, [2], [1]) @ psi, atol=1e-13)
+
+
+def test_gate_library_vs_definitions():
+    """Every named one-qubit matrix of the oracle's gate library against its
+    definition from the Pauli matrices: R_P(t) = exp(-i t P / 2) by scipy's
+    matrix exponential, H = (X + Z)/sqrt2, S = exp(i pi/4 (I - Z)),
+    P(phi) = exp(i phi (I - Z)/2), SWAP = (I I + X X + Y Y + Z Z)/2."""
+    from scipy.linalg import expm
+    from dense_ref import PAULI
+    I, X, Y, Z = (PAULI[c] for c in "IXYZ")
+    for k in "IXYZ":
+        np.testing.assert_allclose(oracle.gate_matrix(k), PAULI[k], atol=0)
+    np.testing.assert_allclose(oracle.gate_matrix("H"), (X + Z) / math.sqrt(2.0), atol=1e-16)
+    S = expm(0.25j * math.pi * (I - Z))
+    np.testing.assert_allclose(oracle.gate_matrix("S"), S, atol=1e-15)
+    np.testing.assert_allclose(oracle.gate_matrix("SDG"), S.conj().T, atol=1e-15)
+    for t in (0.0, 0.37, -1.2, 2.9, 5.5, 2 * math.pi):
+        for k, P in (("RX", X), ("RY", Y), ("RZ", Z)):
+            np.testing.assert_allclose(oracle.gate_matrix(k, t), expm(-0.5j * t * P), atol=1e-15)
+        np.testing.assert_allclose(oracle.gate_matrix("P", t), expm(0.5j * t * (I - Z)),
+                                   atol=1e-15)
+    swap = 0.5 * sum(np.kron(PAULI[c], PAULI[c]) for c in "IXYZ")
+    np.testing.assert_allclose(oracle.gate_matrix("SWAP"), swap, atol=1e-16)
+
+
+def test_every_gate_kind_through_run_vs_dense():
+    """run() on each kind it accepts, against the dense register operator of
+    the gate's definition (controls as projectors, section 3.2)."""
+    from scipy.linalg import expm
+    from dense_ref import PAULI
+    I, X, Y, Z = (PAULI[c] for c in "IXYZ")
+    n = 4
+    psi = random_state(n, np.random.default_rng(6))
+    u = random_unitary(4, np.random.default_rng(7))
+    t = 0.83
+    cases = [
+        (W.Op("I", (1,)), dense_gate(n, [1], I)),
+        (W.Op("X", (2,)), dense_gate(n, [2], X)),
+        (W.Op("Y", (0,)), dense_gate(n, [0], Y)),
+        (W.Op("Z", (3,)), dense_gate(n, [3], Z)),
+        (W.Op("H", (1,)), dense_gate(n, [1], (X + Z) / math.sqrt(2.0))),
+        (W.Op("S", (2,)), dense_gate(n, [2], expm(0.25j * math.pi * (I - Z)))),
+        (W.Op("SDG", (0,)), dense_gate(n, [0], expm(-0.25j * math.pi * (I - Z)))),
+        (W.Op("RX", (3,), angle=t), dense_gate(n, [3], expm(-0.5j * t * X))),
+        (W.Op("RY", (1,), pidx=0), dense_gate(n, [1], expm(-0.5j * t * Y))),
+        (W.Op("RZ", (2,), pidx=0), dense_gate(n, [2], expm(-0.5j * t * Z))),
+        (W.Op("P", (0,), angle=t), dense_gate(n, [0], expm(0.5j * t * (I - Z)))),
+        (W.Op("CP", (3, 0), angle=t), dense_gate(n, [0], expm(0.5j * t * (I - Z)), [3], [1])),
+        (W.Op("MCX", (0, 2, 1), ctrl_val=(1, 0)), dense_gate(n, [1], X, [0, 2], [1, 0])),
+        (W.Op("U", (2, 0), matrix=u), dense_gate(n, [2, 0], u)),
+    ]
+    for op, mat in cases:
+        np.testing.assert_allclose(oracle.run([op], psi, np.array([t])), mat @ psi, atol=1e-13)
 
 
 def test_named_gates_vs_dense():

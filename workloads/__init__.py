@@ -36,7 +36,8 @@ import numpy as np
 __all__ = [
     "Op", "haar_u2", "brickwork", "qft", "hea", "tfim_terms", "random_state",
     "batch_config", "adjoint_config", "config_brickwork12",
-    "config_qft28", "config_brickwork32", "ghz",
+    "config_qft28", "config_brickwork32", "ghz", "teleportation", "grover2",
+    "bitflip_code",
 ]
 
 
@@ -124,6 +125,57 @@ def ghz(n: int) -> List[Op]:
     for q in range(n - 1):
         ops.append(Op("CNOT", (q, q + 1)))
     return ops
+
+
+def teleportation(src: int = 0, a: int = 1, b: int = 2) -> list:
+    """Quantum teleportation of the state of qubit ``src`` onto qubit ``b``
+    (section 5.1): qubits a and b share a Bell pair.  Bell-basis measurement
+    of (src, a) = CNOT(src, a), H(src), measure both; then the corrections
+    X^m_a and Z^m_src on b, written as gates controlled by the measured
+    qubits (they hold their collapsed values)."""
+    return [Op("CNOT", (src, a)), Op("H", (src,)), ("M", src), ("M", a),
+            Op("CNOT", (a, b)), Op("CZ", (src, b))]
+
+
+def _flip_phase_of(bits: str) -> List[Op]:
+    """-1 on the two-qubit basis state |bits> only: X on the qubits that read
+    0 in ``bits`` turns it into |11>, CZ flips |11>, the X gates go back."""
+    xs = [Op("X", (q,)) for q, c in enumerate(bits) if c == "0"]
+    return xs + [Op("CZ", (0, 1))] + xs
+
+
+def grover2(marked: str) -> list:
+    """Grover search on two qubits for the basis state ``marked`` (section
+    5.3): uniform superposition, the phase oracle of the marked state, the
+    diffusion operator H^2 (2|00><00| - I) H^2 (up to a global phase:
+    -1 on every basis state but |00>, i.e. Z on both qubits then CZ), and a
+    measurement of both qubits.  One iteration finds the marked state with
+    probability 1 for N = 4."""
+    if len(marked) != 2 or any(c not in "01" for c in marked):
+        raise ValueError("marked must be a two-character bitstring")
+    h = [Op("H", (0,)), Op("H", (1,))]
+    diffuse = h + [Op("Z", (0,)), Op("Z", (1,)), Op("CZ", (0, 1))] + h
+    return h + _flip_phase_of(marked) + diffuse + [("M", 0), ("M", 1)]
+
+
+def bitflip_code(error_qubit: Optional[int] = None) -> list:
+    """Three-qubit bit-flip code with syndrome measurement (section 5.4):
+    qubit 0 is encoded onto qubits 0..2 with two CNOTs; an X error hits
+    ``error_qubit`` (none if None); ancilla 3 records the parity of qubits
+    0 and 1, ancilla 4 that of qubits 0 and 2; both ancillas are measured
+    and the qubit whose flip explains the syndrome is flipped back by an X
+    controlled by the ancillas' values (open control = 0)."""
+    items: list = [Op("CNOT", (0, 1)), Op("CNOT", (0, 2))]
+    if error_qubit is not None:
+        items.append(Op("X", (error_qubit,)))
+    for anc, pair in ((3, (0, 1)), (4, (0, 2))):
+        for q in pair:
+            items.append(Op("CNOT", (q, anc)))
+    items += [("M", 3), ("M", 4)]
+    for q in (2, 1, 0):
+        syndrome = (int(q in (0, 1)), int(q in (0, 2)))
+        items.append(Op("MCX", (3, 4, q), ctrl_val=syndrome))
+    return items
 
 
 def tfim_terms(n: int, j: float = 1.0, h: float = 1.0) -> List[Tuple[str, float]]:
