@@ -12,7 +12,14 @@ complex128 runs that separate the precision gain from the fusion gain.
 Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 32] [--layers 40]
-                    [--no-ref] [--no-split] [--no-cpu]
+                    [--no-ref] [--no-split] [--no-cpu] [--no-secondary]
+                    [--only brickwork12|qft28|tfim28|batch512|adjoint24]
+
+Every reported figure comes with its check: the headline state against the
+unfused complex128 run (relative error <= 1e-5), the batch energies against
+the oracle's stored values, the batch status flags, the QFT modes against
+the unfused complex128 run; if a check fails, "value" is null and the exit
+status is 1.
 """
 from __future__ import annotations
 
@@ -134,19 +141,36 @@ def _time(fn, reps: int = 3, warm: int = 1) -> float:
     return out[len(out) // 2]
 
 
-def secondary_workloads() -> dict:
-    """The other four synthetic configurations, timed on the GPU (state
-    contents do not change the work, so QFT starts from |0...0>)."""
-    import numpy as np
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    """Stored FP64 oracle values (written by tests/golden/make_golden.py,
+    which calls only the oracle); None when the file is absent."""
+    path = os.path.join(GOLDEN, name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def _diff(qc, a, ref):
+    """relative 2-norm and max-abs error of state a against ref (FP64)."""
+    d = qc.state_diff(a, ref).cpu().tolist()
+    return {"rel": float("%.3e" % math.sqrt(d[0] / d[1])), "maxabs": float("%.3e" % d[2])}
+
+
+def wl_brickwork12() -> dict:
+    """12-qubit brickwork, 20 layers, complex128: unfused, one LDS tile run,
+    and one workgroup of the batch kernel; states against the unfused run."""
     import torch
     import workloads as W
     from paper_2503_03016_amd import gates as G
     from paper_2503_03016_amd import qc
 
-    res = {}
-    # 12-qubit brickwork, 20 layers, complex128: whole circuit in one LDS tile
     n, ops = W.config_brickwork12()
-    gl = qc.GateList(G.gate_tuples(ops))
+    gts = G.gate_tuples(ops)
+    gl = qc.GateList(gts)
+    ref = qc.new_state(n, torch.complex128)
+    qc.state_init(ref, 0)
+    qc.apply_circuit(ref, gl, mode=qc.QC_EXEC_UNFUSED)
     psi = qc.new_state(n, torch.complex128)
     r = {}
     for name, mode in (("unfused", qc.QC_EXEC_UNFUSED), ("tiled", qc.QC_EXEC_TILED)):
@@ -158,69 +182,212 @@ def secondary_workloads() -> dict:
             qc.probs(psi)
         ms = _time(run, reps=5)
         r[name] = {"us": round(ms * 1e3, 1), "sweeps": st["sweeps"],
-                   "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
-    b = qc.Batch([(n, G.gate_tuples(ops), W.tfim_terms(n))], dtype=torch.complex128)
+                   "gates_per_s": round(len(ops) / (ms / 1e3), 1),
+                   "err_vs_unfused_c128": _diff(qc, psi, ref)}
+    b = qc.Batch([(n, gts, W.tfim_terms(n))], dtype=torch.complex128, keep_states=True)
     ms = _time(lambda: b.run(), reps=5)
     r["one_workgroup_batch"] = {"us": round(ms * 1e3, 1),
-                                "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
-    res["brickwork12_c128"] = r
-    del psi, b
-    log("secondary: brickwork12 done")
+                                "gates_per_s": round(len(ops) / (ms / 1e3), 1),
+                                "err_vs_unfused_c128": _diff(qc, b.state(0), ref)}
+    return r
 
-    # 28-qubit QFT, complex128 and complex64
-    n = 28
-    ops = W.qft(n)
+
+def wl_qft28() -> dict:
+    """28-qubit QFT of the seeded Gaussian state (seed 28), complex128 and
+    complex64, every execution mode; states against the unfused complex128
+    run, whose sampled amplitudes are checked against the oracle's stored
+    discrete Fourier sums."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2503_03016_amd import gates as G
+    from paper_2503_03016_amd import qc
+
+    n, ops, psi0 = W.config_qft28()
     gl = qc.GateList(G.gate_tuples(ops))
+    host = torch.from_numpy(psi0)
+    ref = host.cuda()
+    del psi0
     r = {}
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st = qc.apply_circuit(ref, gl, mode=qc.QC_EXEC_UNFUSED)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    r["c128_unfused"] = {"ms": round(ms, 2), "sweeps": st["sweeps"],
+                         "GBps": round(st["state_bytes"] / (ms / 1e3) / 1e9, 1),
+                         "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
+    gold = _golden("qft28_amplitudes.json")
+    if gold:
+        idx = torch.tensor(gold["indices"], dtype=torch.int64, device="cuda")
+        want = np.array([complex(a, b) for a, b in gold["amplitudes"]])
+        got = ref[idx].cpu().numpy()
+        r["c128_unfused"]["err_vs_oracle_sampled_maxabs"] = float(
+            "%.3e" % np.max(np.abs(got - want)))
     for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
-        psi = qc.new_state(n, dt)
-        for name, mode in (("unfused", qc.QC_EXEC_UNFUSED), ("tiled", qc.QC_EXEC_TILED),
-                           ("fused", qc.QC_EXEC_FUSED)):
+        src = host.to(dt).cuda()
+        psi = torch.empty_like(src)
+        for name, mode in (("tiled", qc.QC_EXEC_TILED), ("fused", qc.QC_EXEC_FUSED)):
             st = {}
 
             def run():
                 st.update(qc.apply_circuit(psi, gl, mode=mode, fuse_k=5))
-            qc.state_init(psi, 0)
-            ms = _time(run, reps=1)
+            qc.state_copy(psi, src)
+            run()                            # warm-up (and the checked run)
+            err = _diff(qc, psi, ref)
+            qc.state_copy(psi, src)
+            ms = _time(run, reps=1, warm=0)
             r["%s_%s" % (dname, name)] = {
                 "ms": round(ms, 2), "sweeps": st["sweeps"],
                 "GBps": round(st["state_bytes"] / (ms / 1e3) / 1e9, 1),
-                "gates_per_s": round(len(ops) / (ms / 1e3), 1)}
+                "gates_per_s": round(len(ops) / (ms / 1e3), 1),
+                "err_vs_unfused_c128": err}
+        if dname == "c64":
+            qc.state_copy(psi, src)
+            st = qc.apply_circuit(psi, gl, mode=qc.QC_EXEC_UNFUSED)
+            err = _diff(qc, psi, ref)
+            qc.state_copy(psi, src)
+            ms = _time(lambda: qc.apply_circuit(psi, gl, mode=qc.QC_EXEC_UNFUSED), reps=1, warm=0)
+            r["c64_unfused"] = {"ms": round(ms, 2), "sweeps": st["sweeps"],
+                                "GBps": round(st["state_bytes"] / (ms / 1e3) / 1e9, 1),
+                                "gates_per_s": round(len(ops) / (ms / 1e3), 1),
+                                "err_vs_unfused_c128": err}
+        del src, psi
+        torch.cuda.empty_cache()
+    return r
+
+
+def wl_tfim28() -> dict:
+    """<H> of the 28-qubit open-chain transverse-field Ising model (55 Pauli
+    terms) on the seeded Gaussian state, complex128 and complex64; per-term
+    values of the complex64 run against the complex128 run."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2503_03016_amd import qc
+
+    n = 28
+    terms = W.tfim_terms(n)
+    host = torch.from_numpy(W.random_state(n, seed=28))
+    r = {}
+    vals = {}
+    S = float(1 << n)
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        psi = host.to(dt).cuda()
+        v = qc.expect_pauli(psi, terms, per_term=True)
+        vals[dname] = v.cpu().numpy()
+        ms = _time(lambda: qc.expect_pauli(psi, terms), reps=5)
+        elem = 16 if dt == torch.complex128 else 8
+        r[dname] = {"ms": round(ms, 3), "terms": len(terms),
+                    "state_reads_GB": round(S * elem / 1e9, 3),
+                    "energy": float(vals[dname][0])}
         del psi
         torch.cuda.empty_cache()
-    res["qft28"] = r
-    log("secondary: qft28 done")
+    r["c64"]["err_vs_c128_energy"] = float("%.3e" % abs(vals["c64"][0] - vals["c128"][0]))
+    r["c64"]["err_vs_c128_max_term"] = float(
+        "%.3e" % np.max(np.abs(vals["c64"][1:] - vals["c128"][1:])))
+    return r
 
-    # batch of 512 circuits, one persistent launch, complex64
+
+def wl_batch512() -> dict:
+    """512 circuits (n uniform in [10, 20], 8-layer ansatz, TFIM energy) in
+    one persistent launch, complex64, eager and as a replayed HIP graph;
+    every energy against the oracle's stored energies."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2503_03016_amd import gates as G
+    from paper_2503_03016_amd import qc
+
     cfg = W.batch_config()
     t0 = time.perf_counter()
     circuits = [(cn, G.gate_tuples(W.hea(cn, 8), th), W.tfim_terms(cn)) for cn, th in cfg]
     b = qc.Batch(circuits, dtype=torch.complex64)
     create_s = time.perf_counter() - t0
-    ms = _time(lambda: b.run(), reps=3)
+    energy = torch.empty(len(cfg), dtype=torch.float64, device="cuda")
+    ms = _time(lambda: b.run(energy), reps=5)
+    status = b.status()
+    e = energy.cpu().numpy()
     gates = sum(8 * (3 * cn - 1) for cn, _ in cfg)
-    res["batch512_c64"] = {"ms": round(ms, 3), "circuits_per_s": round(512 / (ms / 1e3), 1),
-                           "gates_per_s": round(gates / (ms / 1e3), 1), "gates": gates,
-                           "grid": b.grid, "phases": b.phases,
-                           "host_plan_and_upload_s": round(create_s, 2)}
-    del b
-    log("secondary: batch512 done")
+    r = {"ms": round(ms, 3), "circuits_per_s": round(512 / (ms / 1e3), 1),
+         "gates_per_s": round(gates / (ms / 1e3), 1), "gates": gates,
+         "grid": b.grid, "phases": b.phases, "status_flags": status,
+         "host_plan_and_upload_s": round(create_s, 2)}
+    # the same launch captured in a HIP graph and replayed
+    out = torch.empty_like(energy)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run(out)
+    r["graph_replay_ms"] = round(_time(lambda: g.replay(), reps=5), 3)
+    r["graph_replay_bitwise_equal"] = bool(torch.equal(out, energy))
+    gold = _golden("batch512_energies.json")
+    if gold:
+        ref = np.array(gold["energies"])
+        ns = np.array([cn for cn, _ in cfg])
+        err = np.abs(e - ref)
+        r["err_vs_oracle_max_abs_dE"] = float("%.3e" % err.max())
+        r["err_within_bound"] = bool(np.all(err < 2 * (2 * ns - 1) * 1e-5))
+    del g, b
+    return r
 
-    # adjoint gradient, 24 qubits, 16 layers, 768 parameters
+
+def wl_adjoint24() -> dict:
+    """Adjoint gradient of the 24-qubit 16-layer ansatz (768 parameters),
+    complex128 and complex64: energy and six gradients against the oracle's
+    stored values, the complex64 gradient against the complex128 one."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2503_03016_amd import qc
+
     n, ops, theta, terms = W.adjoint_config()
     r = {}
+    grads = {}
+    gold = _golden("adjoint24.json")
     for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
         psi = qc.new_state(n, dt)
         lam = qc.new_state(n, dt)
+        res = {}
 
         def run():
             qc.state_init(psi, 0)
-            qc.adjoint_grad(psi, lam, ops, theta, terms)
+            res["eg"] = qc.adjoint_grad(psi, lam, ops, theta, terms)
         ms = _time(run, reps=3)
-        r[dname] = {"ms": round(ms, 2), "ops": len(ops), "params": int(len(theta))}
+        e, g = res["eg"]
+        grads[dname] = g.cpu().numpy()
+        r[dname] = {"ms": round(ms, 2), "ops": len(ops), "params": int(len(theta)),
+                    "energy": float(e.item())}
+        if gold:
+            r[dname]["err_vs_oracle_energy"] = float("%.3e" % abs(e.item() - gold["energy"]))
+            r[dname]["err_vs_oracle_param_shift_max"] = float(
+                "%.3e" % np.max(np.abs(grads[dname][gold["params"]] - np.array(gold["grad"]))))
         del psi, lam
-    res["adjoint24"] = r
-    log("secondary: adjoint24 done")
+        torch.cuda.empty_cache()
+    r["c64"]["err_vs_c128_max_abs_dg"] = float(
+        "%.3e" % np.max(np.abs(grads["c64"] - grads["c128"])))
+    return r
+
+
+WORKLOADS = {"brickwork12": wl_brickwork12, "qft28": wl_qft28, "tfim28": wl_tfim28,
+             "batch512": wl_batch512, "adjoint24": wl_adjoint24}
+
+
+def secondary_workloads() -> dict:
+    """The other synthetic configurations, timed on the GPU, each with its
+    error against the oracle or against the unfused complex128 run."""
+    res = {}
+    for name, fn in WORKLOADS.items():
+        res[name] = fn()
+        log("secondary: %s done" % name)
     return res
 
 
@@ -244,7 +411,10 @@ def main() -> int:
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the plain-copy calibration run (bandwidth ceiling)")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the other four workloads")
+                    help="skip the other workloads")
+    ap.add_argument("--only", choices=sorted(WORKLOADS),
+                    help="run just this one secondary workload and print its JSON line "
+                         "(for profiling one kernel family)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -261,6 +431,11 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only:
+        log("workload %s only" % args.only)
+        res = WORKLOADS[args.only]()
+        print(json.dumps({"workload": args.only, "result": res}), flush=True)
+        return 0
     n, layers = args.n, args.layers
     _, ops = W.config_brickwork32(n, layers)
     gl = qc.GateList(G.gate_tuples(ops))
@@ -470,8 +645,33 @@ def main() -> int:
     }
     out.update(ref)
     out["secondary_workloads"] = secondary
+    # correctness gates: a number is reported only for a correct result
+    checks = {}
+    if "err_rel_vs_c128" in ref:
+        checks["headline_rel_err_le_1e-5"] = ref["err_rel_vs_c128"] <= 1e-5
+    checks["headline_prob_sums_to_1"] = abs(sum(p0h) - 1.0) < 1e-5
+    if secondary:
+        b5 = secondary.get("batch512", {})
+        checks["batch512_status_ok"] = b5.get("status_flags") == 0
+        if "err_within_bound" in b5:
+            checks["batch512_energies_vs_oracle"] = b5["err_within_bound"]
+        checks["batch512_graph_replay_equal"] = b5.get("graph_replay_bitwise_equal", False)
+        q = secondary.get("qft28", {})
+        for k, v in q.items():
+            e = v.get("err_vs_unfused_c128")
+            if e:
+                checks["qft28_%s" % k] = (e["maxabs"] <= 1e-12 if k.startswith("c128")
+                                          else e["rel"] <= 1e-5)
+        a = secondary.get("adjoint24", {})
+        if "c128" in a and "err_vs_oracle_param_shift_max" in a["c128"]:
+            checks["adjoint24_c128_vs_oracle"] = a["c128"]["err_vs_oracle_param_shift_max"] <= 1e-9
+    out["checks"] = checks
+    ok = all(checks.values())
+    if not ok:
+        out["value"] = None
+        log("CHECK FAILED: %s" % [k for k, v in checks.items() if not v])
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

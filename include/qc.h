@@ -41,11 +41,17 @@
  *   qc_sample, qc_collapse, qc_adjoint_grad) must not run concurrently on
  *   different streams of the same device.  Concurrent calls from several
  *   host threads are not supported.
- * - A HIP graph that captures a gate or circuit call re-reads its staged
- *   matrices from the ring's host memory at every replay: replay it only
- *   while later calls have not reused those ring slots (a wrap of the ring
- *   also synchronises the device, which a capture does not allow).
- *   qc_run_batch is the entry point meant for capture.
+ * - HIP graph capture.  Gate, circuit, reduction and measurement calls
+ *   may be captured into a HIP graph: they enqueue no allocation, memset
+ *   or host synchronisation while their stream is capturing.  Call
+ *   qc_reserve before the capture (it allocates the workspace and empties
+ *   the staging ring).  The ring slots a capture takes (its matrices and op
+ *   lists, copied again by every replay) are protected: later calls skip
+ *   them, until the next qc_reserve, after which graphs captured earlier
+ *   must not be replayed.  A call whose staging would not fit in the rest
+ *   of the ring during a capture fails with QC_ERR_UNSUPPORTED and
+ *   enqueues nothing.  Kernel timing (qc_timing_enable) records nothing for
+ *   launches made while their stream is capturing.
  */
 #ifndef QC_H_
 #define QC_H_
@@ -143,6 +149,12 @@ const char *qc_status_string(int status);
 const char *qc_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int qc_version(void);
+
+/* Allocate the device's workspace and staging ring if needed, wait for
+ * the device, and empty the ring (releasing the slots of graphs captured
+ * earlier).  Host-synchronous; call it before capturing a HIP graph.
+ * QC_ERR_UNSUPPORTED when `stream` is itself being captured. */
+int qc_reserve(void *stream);
 
 /* ---- state preparation (section 3.1 "Initialization") --------------- */
 
@@ -246,7 +258,9 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
  * m == n this is the full distribution.  m in [1, n]; m <= 24 unless m == n. */
 int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream);
 
-/* Pauli-string expectation values.  paulis holds n_terms strings of n
+/* Pauli-string expectation values <psi|P|psi>, the coefficients
+ * S_i = <sigma_i> of the tomography example (section 5.2), for tensor
+ * products of I, X, Y, Z.  paulis holds n_terms strings of n
  * characters from {I,X,Y,Z} back to back (character q acts on qubit q);
  * coeff holds n_terms FP64 coefficients (host).
  * out_dev[0] = sum_t coeff[t] * Re <psi|P_t|psi>; if per_term != 0,
@@ -261,6 +275,16 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
  * other amplitude is set to 0.  prob_dev[0] receives P (device FP64; may be
  * NULL).  If P == 0 the state is left unchanged (an impossible outcome). */
 int qc_collapse(qc_state_t s, int q, int outcome, double *prob_dev, void *stream);
+
+/* One branch of a qubit reset (the "qubit resets" of section 3.3): qubit q
+ * is measured and set back to |0>.  With P = sum over indices whose qubit q
+ * reads `outcome` of |psi_i|^2 (FP64), the amplitude pair (psi_i0, psi_i1),
+ * i1 = i0 with qubit q set, becomes (psi_i_outcome / sqrt(P), 0): the
+ * outcome's collapse of qc_collapse followed, for outcome 1, by X on q.
+ * prob_dev[0] receives P (device FP64; may be NULL).  If P == 0 the state
+ * is left unchanged (an impossible outcome).  A full reset splits a state
+ * into the branches of both outcomes, as a measurement does. */
+int qc_reset(qc_state_t s, int q, int outcome, double *prob_dev, void *stream);
 
 /* State of the unlisted qubits when the m listed qubits hold `values`
  * (0/1 each), the reducedStatevector of section 5.1: dst (n - m qubits, the
@@ -277,6 +301,17 @@ int qc_reduced_state(qc_state_t src, int m, const int *qubits, const int *values
  * the total weight.  The cumulative weights are FP64 (per chunk of up to
  * 4096 amplitudes for n <= 33, larger chunks above). */
 int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, void *stream);
+
+/* Shot counts over the m listed qubits (the counts of section 5.2): each
+ * of the `shots` uniforms u_dev[k] in [0, 1) (device FP64) draws one basis
+ * index as qc_sample does, and counts_dev[s] (device int64, 2^m entries,
+ * overwritten) receives the number of shots whose listed qubits read s
+ * (qubits[0] = most significant bit of s).  1 <= m <= min(n,
+ * QC_MAX_COUNT_QUBITS); 0 <= shots <= QC_MAX_COUNT_SHOTS. */
+#define QC_MAX_COUNT_QUBITS 24
+#define QC_MAX_COUNT_SHOTS (1 << 21)
+int qc_counts(qc_state_t s, int m, const int *qubits, int shots, const double *u_dev,
+              int64_t *counts_dev, void *stream);
 
 /* ---- differentiation ------------------------------------------------ */
 

@@ -1,14 +1,18 @@
 """torch.autograd.Function around qc_adjoint_grad.
 
 Energy.apply(theta, circuit) returns E(theta) = <phi|H|phi> with
-phi = U(theta)|0...0>; its backward multiplies the adjoint-method gradient
-dE/dtheta (computed by the same C-ABI call as the forward, so the backward
-pass launches nothing) by the incoming gradient.
+phi = U(theta)|0...0>.  When theta needs a gradient, the forward is one
+qc_adjoint_grad call (forward, energy and the adjoint backward sweep
+together) and the backward only scales the saved dE/dtheta by the incoming
+gradient.  When it does not (torch.no_grad, or theta without
+requires_grad), the forward runs the circuit and the energy alone
+(qc_apply_circuit + qc_expect_pauli): no adjoint sweep is spent.
 """
 from __future__ import annotations
 
 import torch
 
+from . import gates as G
 from . import qc
 
 
@@ -29,8 +33,13 @@ class Energy(torch.autograd.Function):
     def forward(ctx, theta: torch.Tensor, circ: AdjointCircuit):
         th = theta.detach().to("cpu", torch.float64).numpy()
         qc.state_init(circ.psi, 0)
-        energy, grad = qc.adjoint_grad(circ.psi, circ.lam, circ.ops, th, circ.terms)
-        ctx.save_for_backward(grad.to(theta.device, theta.dtype))
+        if ctx.needs_input_grad[0]:
+            energy, grad = qc.adjoint_grad(circ.psi, circ.lam, circ.ops, th, circ.terms)
+            ctx.save_for_backward(grad.to(theta.device, theta.dtype))
+        else:
+            qc.apply_circuit(circ.psi, qc.GateList(G.gate_tuples(circ.ops, th)),
+                             mode=qc.QC_EXEC_TILED)
+            energy = qc.expect_pauli(circ.psi, circ.terms)[:1]
         return energy.reshape(()).to(theta.device, theta.dtype)
 
     @staticmethod

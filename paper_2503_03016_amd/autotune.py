@@ -62,7 +62,14 @@ def tune(n: int, dtype: torch.dtype, gate_tuples, family: Optional[str] = None,
     if key in cache and not force:
         return cache[key]
     scratch = qc.new_state(n, dtype)
-    table = qc.autotune(scratch, qc.GateList(gate_tuples), reps=reps)
+    saved = {k: qc.get_knob(k) for k in _KNOBS}
+    try:
+        table = qc.autotune(scratch, qc.GateList(gate_tuples), reps=reps)
+    finally:
+        # qc_autotune leaves the knobs at the winner's values; apply_tuned
+        # sets them per call instead
+        for k, v in saved.items():
+            qc.set_knob(k, v)
     del scratch
     best = dict(table[0])
     best["mode_name"] = MODE_NAMES.get(best["mode"], str(best["mode"]))
@@ -72,15 +79,25 @@ def tune(n: int, dtype: torch.dtype, gate_tuples, family: Optional[str] = None,
     return best
 
 
+_KNOBS = (qc.QC_KNOB_MFMA_WG_PER_CU, qc.QC_KNOB_MFMA_TILE_BITS, qc.QC_KNOB_TILE_BITS)
+
+
 def apply_tuned(psi: torch.Tensor, gate_tuples, family: Optional[str] = None) -> dict:
-    """Apply a circuit with its tuned configuration."""
+    """Apply a circuit with its tuned configuration.  The launch-shape knobs
+    are process-wide: they are set for this call only and restored after
+    it, so later calls on other circuit families keep their own shapes."""
     n = qc.state_view(psi).n
     cfg = tune(n, psi.dtype, gate_tuples, family)
-    if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_wg_per_cu"):
-        qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, cfg["mfma_wg_per_cu"])
-    if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_tile_bits") in (12, 13):
-        qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, cfg["mfma_tile_bits"])
-    if cfg["mode"] == qc.QC_EXEC_TILED and cfg.get("tile_bits"):
-        qc.set_knob(qc.QC_KNOB_TILE_BITS, cfg["tile_bits"])
-    return qc.apply_circuit(psi, qc.GateList(gate_tuples), mode=cfg["mode"],
-                            fuse_k=cfg["fuse_k"] or 5)
+    saved = {k: qc.get_knob(k) for k in _KNOBS}
+    try:
+        if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_wg_per_cu"):
+            qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, cfg["mfma_wg_per_cu"])
+        if cfg["mode"] == qc.QC_EXEC_FUSED and cfg.get("mfma_tile_bits") in (12, 13):
+            qc.set_knob(qc.QC_KNOB_MFMA_TILE_BITS, cfg["mfma_tile_bits"])
+        if cfg["mode"] == qc.QC_EXEC_TILED and cfg.get("tile_bits"):
+            qc.set_knob(qc.QC_KNOB_TILE_BITS, cfg["tile_bits"])
+        return qc.apply_circuit(psi, qc.GateList(gate_tuples), mode=cfg["mode"],
+                                fuse_k=cfg["fuse_k"] or 5)
+    finally:
+        for k, v in saved.items():
+            qc.set_knob(k, v)

@@ -46,10 +46,21 @@ struct DevCtx {
     char *ring_dev = nullptr;
     char *ring_host = nullptr;
     size_t ring_head = 0;
+    // ring bytes [prot_lo, prot_hi) hold slots staged while a stream was
+    // being captured into a HIP graph: every replay copies them again, so
+    // later calls skip them until the next qc_reserve
+    size_t prot_lo = 0, prot_hi = 0;
 };
 
 DevCtx g_dev[kMaxDevices];
 std::mutex g_mu;
+
+// true while `s` is being captured into a HIP graph
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
 
 int get_ctx(DevCtx **out) {
     int d = 0;
@@ -59,6 +70,7 @@ int get_ctx(DevCtx **out) {
     std::lock_guard<std::mutex> lk(g_mu);
     DevCtx &c = g_dev[d];
     if (!c.ready) {
+        // first use on this device (qc_reserve does it before a graph capture)
         if (hipMalloc(&c.work, kWorkElems * sizeof(double)) != hipSuccess)
             return fail(QC_ERR_NOMEM, "workspace allocation failed");
         if (hipMalloc(&c.ring_dev, kRingBytes) != hipSuccess)
@@ -75,14 +87,33 @@ int get_ctx(DevCtx **out) {
 // Copy a small host array into device memory owned by the ring.  The copy
 // is ordered on `s` before any kernel the caller enqueues afterwards.  When
 // the ring wraps, the device is drained first so no slot still in use by an
-// earlier copy or kernel is overwritten.
+// earlier copy or kernel is overwritten.  While `s` is being captured into
+// a HIP graph there is no drain: a slot that does not fit before the end of
+// the ring is refused (QC_ERR_UNSUPPORTED; qc_reserve makes room before a
+// capture), and the slots taken are protected from later calls.
 int stage(DevCtx *c, const void *src, size_t bytes, hipStream_t s, void **dev) {
     const size_t need = (bytes + 255) & ~size_t(255);
     if (need > kRingBytes) return fail(QC_ERR_ARG, "staged array too large");
+    const bool cap = capturing(s);
+    auto overlaps_prot = [&](size_t h) {
+        return c->prot_hi > c->prot_lo && h < c->prot_hi && h + need > c->prot_lo;
+    };
+    if (!cap && overlaps_prot(c->ring_head)) c->ring_head = c->prot_hi;
     if (c->ring_head + need > kRingBytes) {
+        if (cap)
+            return fail(QC_ERR_UNSUPPORTED,
+                        "staging ring full during graph capture (call qc_reserve before capturing)");
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
         c->ring_head = 0;
+        if (overlaps_prot(c->ring_head)) c->ring_head = c->prot_hi;
+        if (c->ring_head + need > kRingBytes)
+            return fail(QC_ERR_NOMEM, "staging ring held by captured graphs (call qc_reserve)");
+    }
+    if (cap) {
+        if (c->prot_hi <= c->prot_lo) c->prot_lo = c->ring_head;
+        if (c->ring_head < c->prot_lo) c->prot_lo = c->ring_head;
+        c->prot_hi = std::max(c->prot_hi, c->ring_head + need);
     }
     std::memcpy(c->ring_host + c->ring_head, src, bytes);
     hipError_t e = hipMemcpyAsync(c->ring_dev + c->ring_head, c->ring_host + c->ring_head, bytes,
@@ -503,7 +534,7 @@ int knob(int which) {
 }
 
 int timer_begin(const char *name, hipStream_t s) {
-    if (!g_timing.load(std::memory_order_relaxed)) return -1;
+    if (!g_timing.load(std::memory_order_relaxed) || capturing(s)) return -1;
     TimerRec r;
     r.name = name;
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
@@ -541,7 +572,20 @@ const char *qc_status_string(int status) {
 
 const char *qc_last_error(void) { return t_err.c_str(); }
 
-int qc_version(void) { return 10000; }
+int qc_version(void) { return 10100; }
+
+int qc_reserve(void *stream) {
+    const hipStream_t hs = (hipStream_t)stream;
+    if (capturing(hs)) return fail(QC_ERR_UNSUPPORTED, "qc_reserve inside a graph capture");
+    DevCtx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    c->ring_head = 0;
+    c->prot_lo = c->prot_hi = 0;
+    return QC_OK;
+}
 
 int qc_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);
@@ -1757,6 +1801,22 @@ int qc_collapse(qc_state_t s, int q, int outcome, double *prob_dev, void *stream
     return e == hipSuccess ? QC_OK : hip_fail(e, "collapse");
 }
 
+int qc_reset(qc_state_t s, int q, int outcome, double *prob_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (outcome != 0 && outcome != 1) return fail(QC_ERR_ARG, "outcome must be 0 or 1");
+    if ((rc = check_qubits(s.n, &q, 1, "qubit"))) return rc;
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    const hipStream_t hs = (hipStream_t)stream;
+    const int p = bitpos(s.n, q);
+    double *pr = c->work + kWorkElems - 2;
+    hipError_t e = qcx::launch_probs_marginal(s.amp, s.dtype, s.n, 1, &p, pr, c->work,
+                                              kWorkElems - 2, hs);
+    if (e == hipSuccess) e = qcx::launch_reset(s.amp, s.dtype, s.n, p, outcome, pr, prob_dev, hs);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "reset");
+}
+
 int qc_reduced_state(qc_state_t src, int m, const int *qubits, const int *values, qc_state_t dst,
                      void *stream) {
     int rc = check_state(src);
@@ -1787,6 +1847,32 @@ int qc_sample(qc_state_t s, int shots, const double *u_dev, int64_t *out_dev, vo
     hipError_t e = qcx::launch_sample(s.amp, s.dtype, s.n, u_dev, shots, out_dev, c->work,
                                       kWorkElems, (hipStream_t)stream);
     return e == hipSuccess ? QC_OK : hip_fail(e, "sample");
+}
+
+int qc_counts(qc_state_t s, int m, const int *qubits, int shots, const double *u_dev,
+              int64_t *counts_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (m < 1 || m > s.n || m > QC_MAX_COUNT_QUBITS)
+        return fail(QC_ERR_ARG, "m must be in [1, min(n, QC_MAX_COUNT_QUBITS)]");
+    if (shots < 0 || shots > QC_MAX_COUNT_SHOTS)
+        return fail(QC_ERR_ARG, "shots must be in [0, QC_MAX_COUNT_SHOTS]");
+    if (!counts_dev || (shots > 0 && !u_dev)) return fail(QC_ERR_ARG, "NULL argument");
+    if ((rc = check_qubits(s.n, qubits, m, "qubit"))) return rc;
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    int pos[QC_MAX_QUBITS];
+    for (int j = 0; j < m; ++j) pos[j] = bitpos(s.n, qubits[j]);
+    // the sampled indices sit at the top of the workspace; the sampler's
+    // chunk sums use at most 2^22 + 1 entries below them
+    constexpr size_t kIdx = size_t(QC_MAX_COUNT_SHOTS);
+    static_assert(kWorkElems - kIdx >= (size_t(2) << 21) + 1, "chunk-sum area");
+    int64_t *idx = reinterpret_cast<int64_t *>(c->work + (kWorkElems - kIdx));
+    const hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = qcx::launch_sample(s.amp, s.dtype, s.n, u_dev, shots, idx, c->work,
+                                      kWorkElems - kIdx, hs);
+    if (e == hipSuccess) e = qcx::launch_count(idx, shots, m, pos, counts_dev, hs);
+    return e == hipSuccess ? QC_OK : hip_fail(e, "counts");
 }
 
 }  // extern "C"

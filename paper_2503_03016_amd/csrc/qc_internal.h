@@ -246,6 +246,9 @@ hipError_t launch_fused_mfma_c128(void *amp, int n, const FusedGeom &g, const do
                                   unsigned *tickets, hipStream_t s);
 hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_pos,
                              bool identity, double *out, hipStream_t s);
+// FP64 workspace entries launch_probs_marginal needs for (n, m): 0 when
+// every bin is one block that writes its sum straight to the output
+size_t probs_marginal_work(int n, int m);
 hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const int *pos,
                                  double *out, double *work, size_t work_elems, hipStream_t s);
 hipError_t launch_expect_group(const void *amp, int dtype, int n, uint64_t xmask, int hpos,
@@ -270,6 +273,11 @@ hipError_t launch_expect_tiles(const void *amp, int dtype, const TileArgs &a,
 
 hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const double *prob,
                            double *prob_out, hipStream_t s);
+hipError_t launch_reset(void *amp, int dtype, int n, int p, int b, const double *prob,
+                        double *prob_out, hipStream_t s);
+// counts[s] (2^m int64, zeroed here) = shots whose index reads s at pos[]
+hipError_t launch_count(const int64_t *idx, int shots, int m, const int *pos, int64_t *counts,
+                        hipStream_t s);
 hipError_t launch_reduced(const void *src, void *dst, int dtype, int n, int m, const int *pos,
                           const int *val, hipStream_t s);
 hipError_t launch_sample(const void *amp, int dtype, int n, const double *u, int shots,

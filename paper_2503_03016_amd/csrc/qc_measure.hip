@@ -53,6 +53,47 @@ __global__ __launch_bounds__(kBlock) void k_collapse(cx<R> *amp, uint64_t count,
     }
 }
 
+// Reset of bit p, branch b (section 3.3 resets): with P = prob[b], the
+// pair (i0, i1 = i0 | 2^p) becomes (a_b / sqrt(P), 0): the outcome-b
+// collapse followed, for b = 1, by X on the bit.  One pass over the pairs.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_reset(cx<R> *amp, uint64_t pairs, int p, int b,
+                                                  const double *prob, double *prob_out) {
+    const double P = prob[b];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && prob_out) prob_out[0] = P;
+    if (!(P > 0.0)) return;                 // impossible outcome: state unchanged
+    const R scale = R(1.0 / sqrt(P));
+    const uint64_t bit = uint64_t(1) << p;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t g = uint64_t(blockIdx.x) * kBlock + threadIdx.x; g < pairs; g += stride) {
+        const uint64_t i0 = insert_zero(g, p);
+        const cx<R> v = amp[b ? (i0 | bit) : i0];
+        amp[i0] = cx<R>{v.re * scale, v.im * scale};
+        amp[i0 | bit] = cx<R>{R(0), R(0)};
+    }
+}
+
+// Shot counts over m listed bits: counts[s] = number of shots whose index
+// reads s at the listed positions (pos[0] = most significant bit of s).
+// Integer atomics: the result does not depend on the order of the adds.
+struct CountArgs {
+    uint32_t pos[QC_MAX_QUBITS];
+    int m;
+};
+__global__ __launch_bounds__(kBlock) void k_zero_i64(int64_t *p, uint64_t count) {
+    const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+__global__ __launch_bounds__(kBlock) void k_count(const int64_t *idx, int shots, const CountArgs a,
+                                                  unsigned long long *counts) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= shots) return;
+    const uint64_t i = uint64_t(idx[k]);
+    uint64_t s = 0;
+    for (int j = 0; j < a.m; ++j) s = (s << 1) | ((i >> a.pos[j]) & 1);
+    atomicAdd(counts + s, 1ull);
+}
+
 struct ReduceArgs {
     uint32_t pos[QC_MAX_QUBITS];  // ascending positions of the known qubits
     int m;
@@ -171,6 +212,35 @@ hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const doub
         hipLaunchKernelGGL((k_collapse<double>), dim3(g), dim3(kBlock), 0, s,
                            static_cast<cx<double> *>(amp), count, p, b, prob, prob_out);
     timer_end(tok, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(void *amp, int dtype, int n, int p, int b, const double *prob,
+                        double *prob_out, hipStream_t s) {
+    const uint64_t pairs = uint64_t(1) << (n - 1);
+    const unsigned g = grid_for(pairs);
+    const int tok = timer_begin("reset", s);
+    if (dtype == QC_C64)
+        hipLaunchKernelGGL((k_reset<float>), dim3(g), dim3(kBlock), 0, s,
+                           static_cast<cx<float> *>(amp), pairs, p, b, prob, prob_out);
+    else
+        hipLaunchKernelGGL((k_reset<double>), dim3(g), dim3(kBlock), 0, s,
+                           static_cast<cx<double> *>(amp), pairs, p, b, prob, prob_out);
+    timer_end(tok, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const int64_t *idx, int shots, int m, const int *pos, int64_t *counts,
+                        hipStream_t s) {
+    CountArgs a{};
+    a.m = m;
+    for (int j = 0; j < m; ++j) a.pos[j] = uint32_t(pos[j]);
+    const uint64_t bins = uint64_t(1) << m;
+    hipLaunchKernelGGL(k_zero_i64, dim3(unsigned((bins + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, counts, bins);
+    if (shots > 0)
+        hipLaunchKernelGGL(k_count, dim3(unsigned((shots + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, idx, shots, a, reinterpret_cast<unsigned long long *>(counts));
     return hipGetLastError();
 }
 

@@ -320,6 +320,20 @@ hipError_t launch_probs_full(const void *amp, int dtype, int n, const int *perm_
     return hipGetLastError();
 }
 
+// Blocks per bin of the marginal kernel: enough blocks to fill the chip,
+// at least 4096 indices per block.
+static uint64_t marginal_chunks(int n, int m) {
+    const uint64_t rest = uint64_t(1) << (n - m), bins = uint64_t(1) << m;
+    uint64_t chunks = 1;
+    while (bins * chunks < 4096 && rest / (chunks * 2) >= 4096) chunks *= 2;
+    return chunks;
+}
+
+size_t probs_marginal_work(int n, int m) {
+    const uint64_t chunks = marginal_chunks(n, m);
+    return chunks == 1 ? 0 : size_t((uint64_t(1) << m) * chunks);
+}
+
 hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const int *pos,
                                  double *out, double *work, size_t work_elems, hipStream_t s) {
     MarginalArgs a{};
@@ -336,10 +350,13 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
     for (int j = 0; j < m; ++j) a.pos[j] = uint32_t(sorted[j]);
     a.rest = uint64_t(1) << (n - m);
     const uint64_t bins = uint64_t(1) << m;
-    // enough blocks to fill the chip, at least 4096 indices per block
-    uint64_t chunks = 1;
-    while (bins * chunks < 4096 && a.rest / (chunks * 2) >= 4096) chunks *= 2;
-    if (bins * chunks > work_elems || bins * chunks > 0x7fffffffull) return hipErrorInvalidValue;
+    const uint64_t chunks = marginal_chunks(n, m);
+    // one chunk per bin: every block writes its bin's sum straight into out
+    // (no partials, so no workspace bound: a 24-qubit marginal has 2^24 bins)
+    const bool direct = chunks == 1;
+    if ((!direct && bins * chunks > work_elems) || bins * chunks > 0x7fffffffull)
+        return hipErrorInvalidValue;
+    double *dst = direct ? out : work;
     a.chunks = int(chunks);
     a.chunk = a.rest / chunks;
     // pairs of neighbouring amplitudes when bit 0 is not listed, every
@@ -349,15 +366,16 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
     const int tok = timer_begin("probs_marginal", s);
     if (dtype == QC_C64 && pair)
         hipLaunchKernelGGL((k_probs_marginal<float, true>), dim3(unsigned(bins * chunks)),
-                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, work);
+                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, dst);
     else if (dtype == QC_C64)
         hipLaunchKernelGGL((k_probs_marginal<float, false>), dim3(unsigned(bins * chunks)),
-                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, work);
+                           dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, dst);
     else
         hipLaunchKernelGGL((k_probs_marginal<double, false>), dim3(unsigned(bins * chunks)),
-                           dim3(kBlock), 0, s, static_cast<const cx<double> *>(amp), a, work);
-    hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(bins)), dim3(kBlock), 0, s, work, int(bins),
-                       int(chunks), out);
+                           dim3(kBlock), 0, s, static_cast<const cx<double> *>(amp), a, dst);
+    if (!direct)
+        hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(bins)), dim3(kBlock), 0, s, work, int(bins),
+                           int(chunks), out);
     timer_end(tok, s);
     return hipGetLastError();
 }

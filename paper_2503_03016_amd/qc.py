@@ -31,8 +31,10 @@ EXPORTS = [
     "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
-    "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune",
+    "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune", "qc_reset", "qc_counts",
+    "qc_reserve",
 ]
+QC_MAX_COUNT_QUBITS, QC_MAX_COUNT_SHOTS = 24, 1 << 21
 (QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD, QC_KNOB_MFMA_TILE_BITS,
  QC_KNOB_TILE_BITS) = 1, 2, 3, 4, 5
 
@@ -123,6 +125,9 @@ def _load():
         "qc_collapse": ([S, i, i, vp, vp], i),
         "qc_reduced_state": ([S, i, ip, ip, S, vp], i),
         "qc_sample": ([S, i, vp, vp, vp], i),
+        "qc_reset": ([S, i, i, vp, vp], i),
+        "qc_counts": ([S, i, ip, i, vp, vp, vp], i),
+        "qc_reserve": ([vp], i),
         "qc_set_knob": ([i, i], i),
         "qc_get_knob": ([i, ip], i),
         "qc_autotune": ([S, i, ctypes.POINTER(QcGate), i, ctypes.POINTER(QcTuneEntry), i, ip, vp],
@@ -340,6 +345,37 @@ def collapse(psi: torch.Tensor, q: int, outcome: int) -> torch.Tensor:
     return p
 
 
+def reset(psi: torch.Tensor, q: int, outcome: int) -> torch.Tensor:
+    """One branch of a reset of qubit q in place (collapse onto `outcome`,
+    renormalise, then X on q for outcome 1); returns P(outcome) as a device
+    FP64 tensor of one element."""
+    p = torch.empty(1, dtype=torch.float64, device=psi.device)
+    _check(lib.qc_reset(state_view(psi), int(q), int(outcome), ctypes.c_void_p(p.data_ptr()),
+                        _stream(psi)), "qc_reset")
+    return p
+
+
+def counts(psi: torch.Tensor, qubits: Sequence[int], u: torch.Tensor) -> torch.Tensor:
+    """Shot counts over the listed qubits for the uniforms u (device FP64):
+    a device int64 tensor of 2^len(qubits) counts (qubits[0] = most
+    significant bit of the outcome)."""
+    if u.dtype != torch.float64 or u.device != psi.device or not u.is_contiguous():
+        raise TypeError("u must be a contiguous FP64 tensor on the state's device")
+    out = torch.empty(1 << len(qubits), dtype=torch.int64, device=psi.device)
+    _check(lib.qc_counts(state_view(psi), len(qubits), _ints(qubits), int(u.numel()),
+                         ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                         _stream(psi)), "qc_counts")
+    return out
+
+
+def reserve(device=None) -> None:
+    """qc_reserve: allocate the workspace and empty the staging ring before a
+    HIP graph capture (host-synchronous)."""
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    _check(lib.qc_reserve(ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)),
+           "qc_reserve")
+
+
 def reduced_state(psi: torch.Tensor, qubits: Sequence[int], values) -> torch.Tensor:
     """Amplitudes of the other qubits when `qubits` hold `values`."""
     sv = state_view(psi)
@@ -504,3 +540,6 @@ qc_timing_query = timing_query
 qc_collapse = collapse
 qc_reduced_state = reduced_state
 qc_sample = sample
+qc_reset = reset
+qc_counts = counts
+qc_reserve = reserve

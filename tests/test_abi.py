@@ -132,6 +132,30 @@ def test_reduction_validation(qc):
     assert lib.qc_expect_pauli(st(qc), 0, b"", cp, 0, out, None) == -1
 
 
+def test_measurement_validation(qc):
+    lib = qc.lib
+    out = ctypes.c_void_p(FAKE)
+    for fn in (lib.qc_collapse, lib.qc_reset):
+        assert fn(st(qc), 4, 0, out, None) == -2
+        assert fn(st(qc), -1, 1, out, None) == -2
+        assert fn(st(qc), 0, 2, out, None) == -1
+        assert fn(st(qc, amp=None), 0, 0, out, None) == -1
+    cnt = lib.qc_counts
+    u = ctypes.c_void_p(FAKE)
+    assert cnt(st(qc), 0, qc._ints([0]), 10, u, out, None) == -1
+    assert cnt(st(qc), 5, qc._ints(range(5)), 10, u, out, None) == -1
+    assert cnt(st(qc), 2, qc._ints([1, 1]), 10, u, out, None) == -2
+    assert cnt(st(qc), 1, qc._ints([0]), -1, u, out, None) == -1
+    assert cnt(st(qc), 1, qc._ints([0]), qc.QC_MAX_COUNT_SHOTS + 1, u, out, None) == -1
+    assert cnt(st(qc), 1, qc._ints([0]), 10, None, out, None) == -1
+    assert cnt(st(qc), 1, qc._ints([0]), 10, u, None, None) == -1
+    assert cnt(st(qc, n=30), 25, qc._ints(range(25)), 10, u, out, None) == -1
+    text = open(HEADER).read()
+    for name in ("QC_MAX_COUNT_QUBITS", "QC_MAX_COUNT_SHOTS"):
+        m = re.search(r"#define\s+%s\s+(\(?[-\d <]+\)?)" % name, text)
+        assert m and eval(m.group(1)) == getattr(qc, name), name
+
+
 def test_adjoint_validation(qc):
     lib = qc.lib
     ops, nops = qc.make_ops([W.Op("RY", (0,), pidx=3)])

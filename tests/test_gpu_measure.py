@@ -104,9 +104,7 @@ def test_simulate_paper_examples_on_gpu(qc):
     ex = GOLD["teleportation"]
     v = np.array([1.0, 1j]) / math.sqrt(2)
     init = np.kron(v, np.array([1.0, 0, 0, 1.0]) / math.sqrt(2))
-    items = [W.Op("CNOT", (0, 1)), W.Op("H", (0,)), ("M", 0), ("M", 1), W.Op("CNOT", (1, 2)),
-             W.Op("CZ", (0, 2))]
-    br = simulate(3, items, init)
+    br = simulate(3, W.teleportation(), init)
     assert [b[0] for b in br] == ex["results"]
     np.testing.assert_allclose([b[1] for b in br], ex["probabilities"], atol=1e-14)
     ref = np.array([complex(a, b) for a, b in ex["state_00"]])
@@ -121,13 +119,105 @@ def test_simulate_paper_examples_on_gpu(qc):
     assert [b[0] for b in by] == ["0"] and abs(by[0][1] - 1) < 1e-14
     # error correction: syndrome '11' with probability 1
     init = np.kron(v, np.eye(16)[:, 0])
-    items = [W.Op("CNOT", (0, 1)), W.Op("CNOT", (0, 2)), W.Op("X", (0,)), W.Op("CNOT", (0, 3)),
-             W.Op("CNOT", (1, 3)), W.Op("CNOT", (0, 4)), W.Op("CNOT", (2, 4)), ("M", 3), ("M", 4),
-             W.Op("MCX", (3, 4, 2), ctrl_val=(0, 1)), W.Op("MCX", (3, 4, 1), ctrl_val=(1, 0)),
-             W.Op("MCX", (3, 4, 0), ctrl_val=(1, 1))]
+    items = W.bitflip_code(error_qubit=0)
     br = simulate(5, items, init)
     assert [b[0] for b in br] == GOLD["qec"]["results"]
     assert abs(br[0][1] - 1.0) < 1e-14
     # agreement with the oracle's own branching simulation
     ob = oracle.simulate(5, items, init)
     np.testing.assert_allclose(host(br[0][2]), ob[0][2], atol=1e-14)
+
+    # Grover: every marked state of N = 4 found with probability 1
+    for marked in ("00", "01", "10", "11"):
+        br = simulate(2, W.grover2(marked), "00")
+        assert [b[0] for b in br] == [marked] and abs(br[0][1] - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_reset_vs_oracle(qc, dtype):
+    n = 13
+    psi0 = W.random_state(n, 37)
+    tol = 1e-13 if dtype == torch.complex128 else 1e-6
+    for q in (0, 5, 12):
+        for b in (0, 1):
+            t = dev(psi0, dtype)
+            held = host(t)
+            p = qc.reset(t, q, b).item()
+            ref, pref = oracle.reset(held, q, b)
+            assert abs(p - pref) < 1e-13
+            assert np.max(np.abs(host(t) - ref)) < tol
+            # the qubit reads 0 with certainty afterwards
+            assert abs(qc.probs(t, [q])[0].item() - 1.0) < (1e-13 if tol < 1e-10 else 1e-6)
+    # an impossible outcome leaves the state unchanged and reports 0
+    t = dev(oracle.basis_state(n, 0), dtype)
+    assert qc.reset(t, 3, 1).item() == 0.0
+    assert np.array_equal(host(t), oracle.basis_state(n, 0))
+
+
+def test_simulate_reset_and_custom_basis_vs_oracle(qc):
+    from paper_2503_03016_amd.simulate import simulate
+    # reset of a Bell pair's first qubit: |00> and |01>, half each
+    bell = np.array([1, 0, 0, 1]) / math.sqrt(2.0)
+    br = simulate(2, [("R", 0)], bell)
+    assert [b[0] for b in br] == ["0", "1"]
+    np.testing.assert_allclose([b[1] for b in br], [0.5, 0.5], atol=1e-14)
+    np.testing.assert_allclose(host(br[0][2]), [1, 0, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(host(br[1][2]), [0, 1, 0, 0], atol=1e-15)
+    # custom bases: V = H is the X basis; V = H S^dagger gives S_2 = 1 (5.2)
+    v = np.array([1.0, 1j]) / math.sqrt(2)
+    Hm = np.array([[1, 1], [1, -1]]) / math.sqrt(2.0)
+    bx = simulate(1, [("M", 0, Hm)], v)
+    np.testing.assert_allclose([b[1] for b in bx], [0.5, 0.5], atol=1e-14)
+    by = simulate(1, [("M", 0, Hm @ np.diag([1, -1j]))], v)
+    assert [b[0] for b in by] == ["0"] and abs(by[0][1] - 1) < 1e-14
+    np.testing.assert_allclose(host(by[0][2]), v, atol=1e-15)
+    # a mixed program of gates, custom-basis measurements and resets on 6
+    # qubits, branch by branch against the oracle
+    n = 6
+    rng = np.random.default_rng(61)
+    V = W.haar_u2(rng)
+    items = (W.brickwork(n, 2, seed=62, entangler="CNOT") + [("M", 2, V), ("R", 4)] +
+             W.brickwork(n, 1, seed=63, entangler="CZ") + [("M", 0, "y"), ("R", 2), ("M", 5, "x")])
+    gb = simulate(n, items, 0)
+    ob = oracle.simulate(n, items, 0)
+    assert [b[0] for b in gb] == [b[0] for b in ob]
+    for (_, pg, sg), (_, po, so) in zip(gb, ob):
+        assert abs(pg - po) < 1e-13
+        np.testing.assert_allclose(host(sg), so, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,qubits", [(7, [0]), (12, [3, 11, 0]), (15, [14, 2, 7, 9])])
+def test_counts_vs_oracle(qc, n, qubits):
+    psi0 = W.random_state(n, 70 + n)
+    t = dev(psi0, torch.complex128)
+    u = np.random.default_rng(n).uniform(size=50000)
+    got = qc.counts(t, qubits, torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = oracle.counts(psi0, qubits, u)
+    assert got.sum() == len(u)
+    # shots may differ only where u sits on a CDF boundary (see sampling)
+    assert np.abs(got - ref).sum() <= 4
+    # and the per-shot indices agree with qc_sample, bit for bit, otherwise
+    idx = qc.sample(t, torch.from_numpy(u).cuda()).cpu().numpy()
+    out = np.zeros_like(idx)
+    for q in qubits:
+        out = 2 * out + ((idx >> (n - 1 - q)) & 1)
+    assert np.array_equal(np.bincount(out, minlength=1 << len(qubits)), got)
+
+
+def test_marginal_over_24_qubits(qc):
+    # 26-qubit register, marginal over 24 listed qubits (2^24 bins)
+    n = 26
+    t = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+    rng = np.random.default_rng(26)
+    idx = rng.choice(1 << n, size=4096, replace=False)
+    vals = rng.standard_normal(4096) + 1j * rng.standard_normal(4096)
+    vals /= np.linalg.norm(vals)
+    t[torch.from_numpy(idx).cuda()] = torch.from_numpy(vals.astype(np.complex64)).cuda()
+    qubits = [int(q) for q in rng.permutation(n)[:24]]
+    got = qc.probs(t, qubits).cpu().numpy()
+    full = np.zeros(1 << n, dtype=np.complex128)
+    full[idx] = vals.astype(np.complex64)
+    ref = oracle.probs(full, qubits)
+    del full
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+    assert abs(got.sum() - 1.0) < 1e-6

@@ -751,10 +751,13 @@ def test_autotune_picks_a_correct_fast_strategy(qc, G, tmp_path, monkeypatch):
     assert again["ms"] == best["ms"]          # served from the cache
     psi = qc.new_state(n, torch.complex64)
     qc.state_init(psi, 0)
+    knobs = [qc.QC_KNOB_MFMA_WG_PER_CU, qc.QC_KNOB_MFMA_TILE_BITS, qc.QC_KNOB_TILE_BITS]
+    before = [qc.get_knob(k) for k in knobs]
     autotune.apply_tuned(psi, gts, family="brickwork16x6")
+    # the tuned launch shape is used for that call only
+    assert [qc.get_knob(k) for k in knobs] == before
     ref = oracle.run(ops, oracle.basis_state(n, 0))
     check(host(psi), ref, torch.complex64, ngates=len(ops))
-    qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 4)
 
 
 def test_autograd_energy_function(qc):
@@ -771,6 +774,13 @@ def test_autograd_energy_function(qc):
     e_ref = oracle.energy(oracle.run(ops, oracle.basis_state(n, 0), th0), terms)
     assert abs(e.item() - e_ref) < 1e-12
     np.testing.assert_allclose(theta.grad.numpy(), 3.0 * g_ref, atol=1e-11)
+    # energy only (no gradient wanted): the forward runs without the
+    # adjoint sweep and gives the same energy
+    with torch.no_grad():
+        e2 = energy(theta, circ)
+    assert abs(e2.item() - e_ref) < 1e-12
+    e3 = energy(torch.tensor(th0, dtype=torch.float64), circ)
+    assert abs(e3.item() - e_ref) < 1e-12 and not e3.requires_grad
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
