@@ -92,6 +92,7 @@ struct MarginalArgs {
     uint64_t rest;             // 2^(n-m) indices per bin
     uint64_t chunk;            // indices of one bin summed by one block
     int chunks;                // blocks per bin
+    uint64_t items;            // bins * chunks
 };
 
 // Block (bin s, chunk c) sums |psi|^2 over its share of the bin's indices.
@@ -103,11 +104,10 @@ constexpr int kMargLoads = 4;
 typedef float floatx4_r __attribute__((ext_vector_type(4)));
 
 template <typename R, bool PAIR>
-__global__ __launch_bounds__(kBlock) void k_probs_marginal(const cx<R> *amp,
-                                                           const MarginalArgs a, double *work) {
-    __shared__ double lds[kWaves];
-    const uint64_t s = blockIdx.x / unsigned(a.chunks);
-    const uint64_t c = blockIdx.x % unsigned(a.chunks);
+__device__ inline void marginal_item(const cx<R> *amp, const MarginalArgs &a, uint64_t b,
+                                     double *work, double *lds) {
+    const uint64_t s = b / unsigned(a.chunks);
+    const uint64_t c = b % unsigned(a.chunks);
     uint64_t binbase = 0;
     for (int j = 0; j < a.m; ++j)
         if ((s >> (a.m - 1 - j)) & 1) binbase |= a.bin_off[j];
@@ -143,7 +143,18 @@ __global__ __launch_bounds__(kBlock) void k_probs_marginal(const cx<R> *amp,
         }
     }
     const double tot = block_sum(acc, lds);
-    if (threadIdx.x == 0) work[blockIdx.x] = tot;
+    if (threadIdx.x == 0) work[b] = tot;
+}
+
+// Work item b = (bin s, chunk c) = (b / chunks, b % chunks), b < items;
+// blocks step through the items with a stride of the grid size (a launch
+// may not hold more than 2^32 threads: 2^24 one-block bins exceed it).
+template <typename R, bool PAIR>
+__global__ __launch_bounds__(kBlock) void k_probs_marginal(const cx<R> *amp,
+                                                           const MarginalArgs a, double *work) {
+    __shared__ double lds[kWaves];
+    for (uint64_t b = blockIdx.x; b < a.items; b += gridDim.x)
+        marginal_item<R, PAIR>(amp, a, b, work, lds);
 }
 
 // out[s] = sum over the chunks of bin s, in chunk order.
@@ -359,19 +370,21 @@ hipError_t launch_probs_marginal(const void *amp, int dtype, int n, int m, const
     double *dst = direct ? out : work;
     a.chunks = int(chunks);
     a.chunk = a.rest / chunks;
+    a.items = bins * chunks;
+    const unsigned grid = unsigned(a.items < (uint64_t(1) << 20) ? a.items : (uint64_t(1) << 20));
     // pairs of neighbouring amplitudes when bit 0 is not listed, every
     // chunk is even and the state is 16-byte aligned
     const bool pair = dtype == QC_C64 && a.pos[0] >= 1 && (a.chunk % 2) == 0 &&
                       (reinterpret_cast<uintptr_t>(amp) & 15) == 0;
     const int tok = timer_begin("probs_marginal", s);
     if (dtype == QC_C64 && pair)
-        hipLaunchKernelGGL((k_probs_marginal<float, true>), dim3(unsigned(bins * chunks)),
+        hipLaunchKernelGGL((k_probs_marginal<float, true>), dim3(grid),
                            dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, dst);
     else if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_probs_marginal<float, false>), dim3(unsigned(bins * chunks)),
+        hipLaunchKernelGGL((k_probs_marginal<float, false>), dim3(grid),
                            dim3(kBlock), 0, s, static_cast<const cx<float> *>(amp), a, dst);
     else
-        hipLaunchKernelGGL((k_probs_marginal<double, false>), dim3(unsigned(bins * chunks)),
+        hipLaunchKernelGGL((k_probs_marginal<double, false>), dim3(grid),
                            dim3(kBlock), 0, s, static_cast<const cx<double> *>(amp), a, dst);
     if (!direct)
         hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(bins)), dim3(kBlock), 0, s, work, int(bins),
