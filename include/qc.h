@@ -258,6 +258,21 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
  * m == n this is the full distribution.  m in [1, n]; m <= 24 unless m == n. */
 int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream);
 
+/* qc_probs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, result and kernels, but no allocation of any kind -
+ * no workspace, no staging ring, no hipMalloc/hipFree, and no qc_reserve
+ * needed.  Its partial sums live in a static device array of
+ * QC_PROBS_NOALLOC_SCRATCH doubles (64 KiB) that each GPU holds until the
+ * process ends; every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU (concurrent streams or host threads) race.  The array
+ * needs no clearing: each call writes every partial it reads.  A marginal
+ * whose partial sums would not fit returns QC_ERR_UNSUPPORTED (none does
+ * with the current launch shapes: fewer than 8192 partials, or none when
+ * every bin is one block). */
+#define QC_PROBS_NOALLOC_SCRATCH 8192
+int qc_probs_noalloc(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream);
+
 /* Pauli-string expectation values <psi|P|psi>, the coefficients
  * S_i = <sigma_i> of the tomography example (section 5.2), for tensor
  * products of I, X, Y, Z.  paulis holds n_terms strings of n

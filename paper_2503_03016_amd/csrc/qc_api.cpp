@@ -1638,6 +1638,76 @@ int qc_probs(qc_state_t s, int m, const int *qubits, double *out_dev, void *stre
     return e == hipSuccess ? QC_OK : hip_fail(e, "probs");
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------- allocation-free probs
+
+// Partial sums of qc_probs_noalloc: a fixed device array instead of the
+// allocated workspace.  Every GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it only names the symbol): the device address comes
+// from hipGetSymbolAddress, once per device, kept in g_scratch_dev.
+static __device__ __align__(256) double scratch[QC_PROBS_NOALLOC_SCRATCH];
+
+namespace {
+
+constexpr size_t kScratchElems = QC_PROBS_NOALLOC_SCRATCH;
+double *g_scratch_dev[kMaxDevices];
+std::mutex g_scratch_mu;
+
+int scratch_address(double **out) {
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (d < 0 || d >= kMaxDevices) return fail(QC_ERR_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[d]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(QC_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[d] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[d];
+    return QC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qc_probs_noalloc(qc_state_t s, int m, const int *qubits, double *out_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (!out_dev) return fail(QC_ERR_ARG, "output pointer is NULL");
+    if (m < 1 || m > s.n) return fail(QC_ERR_ARG, "m out of range");
+    if (m != s.n && m > 24) return fail(QC_ERR_UNSUPPORTED, "marginal over more than 24 qubits");
+    if ((rc = check_qubits(s.n, qubits, m, "qubit"))) return rc;
+    int pos[QC_MAX_QUBITS];
+    bool identity = (m == s.n);
+    for (int j = 0; j < m; ++j) {
+        pos[j] = bitpos(s.n, qubits[j]);
+        if (qubits[j] != j) identity = false;
+    }
+    const hipStream_t hs = (hipStream_t)stream;
+    hipError_t e;
+    if (m == s.n) {   // one output per amplitude: no partial sums at all
+        e = qcx::launch_probs_full(s.amp, s.dtype, s.n, pos, identity, out_dev, hs);
+    } else {
+        const size_t need = qcx::probs_marginal_work(s.n, m);
+        if (need > kScratchElems)
+            return fail(QC_ERR_UNSUPPORTED, "marginal needs " + std::to_string(need) +
+                                                " partial sums, more than the " +
+                                                std::to_string(kScratchElems) +
+                                                " of the static scratch array");
+        double *work = nullptr;
+        if ((rc = scratch_address(&work))) return rc;
+        e = qcx::launch_probs_marginal(s.amp, s.dtype, s.n, m, pos, out_dev, work, kScratchElems,
+                                       hs);
+    }
+    return e == hipSuccess ? QC_OK : hip_fail(e, "probs_noalloc");
+}
+
 int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
                     int per_term, double *out_dev, void *stream) {
     int rc = check_state(s);

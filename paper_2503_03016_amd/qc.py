@@ -32,7 +32,7 @@ EXPORTS = [
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
     "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune", "qc_reset", "qc_counts",
-    "qc_reserve",
+    "qc_reserve", "qc_probs_noalloc",
 ]
 QC_MAX_COUNT_QUBITS, QC_MAX_COUNT_SHOTS = 24, 1 << 21
 (QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD, QC_KNOB_MFMA_TILE_BITS,
@@ -128,6 +128,7 @@ def _load():
         "qc_reset": ([S, i, i, vp, vp], i),
         "qc_counts": ([S, i, ip, i, vp, vp, vp], i),
         "qc_reserve": ([vp], i),
+        "qc_probs_noalloc": ([S, i, ip, vp, vp], i),
         "qc_set_knob": ([i, i], i),
         "qc_get_knob": ([i, ip], i),
         "qc_autotune": ([S, i, ctypes.POINTER(QcGate), i, ctypes.POINTER(QcTuneEntry), i, ip, vp],
@@ -313,6 +314,19 @@ def probs(psi: torch.Tensor, qubits: Optional[Sequence[int]] = None) -> torch.Te
     out = torch.empty(1 << len(qs), dtype=torch.float64, device=psi.device)
     _check(lib.qc_probs(sv, len(qs), _ints(qs), ctypes.c_void_p(out.data_ptr()), _stream(psi)),
            "qc_probs")
+    return out
+
+
+def probs_noalloc(psi: torch.Tensor, out: torch.Tensor,
+                  qubits: Optional[Sequence[int]] = None) -> torch.Tensor:
+    """qc_probs_noalloc into a caller-given FP64 device tensor `out` of
+    2^len(qubits) entries (the library allocates nothing)."""
+    sv = state_view(psi)
+    qs = list(range(sv.n)) if qubits is None else list(qubits)
+    if out.dtype != torch.float64 or out.numel() != (1 << len(qs)) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous FP64 tensor of 2^len(qubits) entries")
+    _check(lib.qc_probs_noalloc(sv, len(qs), _ints(qs), ctypes.c_void_p(out.data_ptr()),
+                                _stream(psi)), "qc_probs_noalloc")
     return out
 
 
@@ -543,3 +557,4 @@ qc_sample = sample
 qc_reset = reset
 qc_counts = counts
 qc_reserve = reserve
+qc_probs_noalloc = probs_noalloc
