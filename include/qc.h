@@ -395,6 +395,9 @@ int qc_batch_destroy(qc_batch_t *b);
                                       qubits), 12 = 32 x 128 (1 KiB runs); default 13      */
 #define QC_KNOB_TILE_BITS 5        /* QC_EXEC_TILED tile size cap, 2^value amplitudes (6..13;
                                       complex128 tiles stop at 12; default 13)             */
+#define QC_KNOB_TILE_ENGINE 6      /* QC_EXEC_TILED engine: 1 = register-resident tiles
+                                      (amplitudes in registers, LDS only to exchange index
+                                      bits; default), 0 = LDS-resident tiles               */
 int qc_set_knob(int knob, int value);
 int qc_get_knob(int knob, int *value);
 

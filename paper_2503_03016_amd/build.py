@@ -22,8 +22,13 @@ FLAGS = [
 ]
 # The fused kernels' tile counter is taken by one lane; the atomic optimizer's
 # wave-wide rewrite of it would wait on every memory operation in flight.
+# The register-resident tile interpreter keeps each thread's amplitudes in
+# an array indexed by compile-time element numbers only; merging the
+# identical tails of its per-slot switch cases would index that array with a
+# run-time value and move it to scratch memory, so common-code sinking is off.
 EXTRA_FLAGS = {"qc_fused_mfma.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
-               "qc_fused_mfma_c128.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+               "qc_fused_mfma_c128.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+               "qc_tile.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
 
 
 def build(verbose: bool = False) -> str:

@@ -141,6 +141,7 @@ std::atomic<int> g_knob_tile{8};
 std::atomic<int> g_knob_look{16};
 std::atomic<int> g_knob_tbits{13};
 std::atomic<int> g_knob_tile_bits{13};
+std::atomic<int> g_knob_tile_engine{1};
 
 // ---------------------------------------------------------------- validation
 
@@ -529,6 +530,7 @@ int knob(int which) {
     case QC_KNOB_TILE_WG_PER_CU: return g_knob_tile.load();
     case QC_KNOB_MFMA_TILE_BITS: return g_knob_tbits.load();
     case QC_KNOB_TILE_BITS: return g_knob_tile_bits.load();
+    case QC_KNOB_TILE_ENGINE: return g_knob_tile_engine.load();
     default: return g_knob_look.load();
     }
 }
@@ -649,6 +651,11 @@ int qc_set_knob(int knob, int value) {
         g_knob_tile_bits.store(value);
         return QC_OK;
     }
+    if (knob == QC_KNOB_TILE_ENGINE) {
+        if (value != 0 && value != 1) return fail(QC_ERR_ARG, "tile engine must be 0 or 1");
+        g_knob_tile_engine.store(value);
+        return QC_OK;
+    }
     return fail(QC_ERR_ARG, "unknown knob");
 }
 
@@ -656,7 +663,7 @@ int qc_get_knob(int knob, int *value) {
     if (!value) return fail(QC_ERR_ARG, "NULL argument");
     if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU &&
         knob != QC_KNOB_FUSE_LOOKAHEAD && knob != QC_KNOB_MFMA_TILE_BITS &&
-        knob != QC_KNOB_TILE_BITS)
+        knob != QC_KNOB_TILE_BITS && knob != QC_KNOB_TILE_ENGINE)
         return fail(QC_ERR_ARG, "unknown knob");
     *value = qcx::knob(knob);
     return QC_OK;
@@ -1356,6 +1363,526 @@ qcx::TileArgs tile_args(int n, int m, uint64_t P, int n_ops) {
     return a;
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident tile programs: the op list of a run (TileOpBuilder) is
+// lowered to RtOps for a layout that changes as the run proceeds (see RtOp
+// in qc_internal.h).  Slots 0..rb-1 are the register (element index) bits,
+// slot rb + k is bit k of the thread index.  Before an op whose
+// non-diagonal targets are not all register slots, an RT_REMAP brings them
+// in; the register set chosen then holds the targets plus the bits whose
+// next use comes soonest (farthest next use leaves first), so one exchange
+// serves as many later ops as possible.
+constexpr uint32_t kRtLdsTabMax = 16384;   // LDS bytes for the lane tables of one program
+struct RtLayout {
+    int m = 0, rb = 0;
+    int bit_of[32];    // slot -> compressed tile bit
+    int slot_of[32];   // compressed tile bit -> slot
+};
+
+struct RtLowering {
+    int n, m, rb, dtype;
+    uint64_t P;
+    const qcx::TileOp *ops;
+    int n_ops;
+    std::vector<uint32_t> need;   // per op: compressed bits that must be register slots
+    RtLayout L;
+    std::vector<qcx::RtOp> out;
+    double scale = 1.0;           // deferred factor of the unscaled Hadamards
+    // table blob: lane tables (copied to LDS) and wave / window tables
+    std::vector<unsigned char> lblob, gblob;
+    std::vector<size_t> gpatch;   // (op index) whose w[1], w[2..] are gblob offsets
+
+    static uint32_t add_tab(std::vector<unsigned char> &b, const void *p, size_t bytes) {
+        while (b.size() % 16) b.push_back(0);
+        const uint32_t off = uint32_t(b.size());
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        b.insert(b.end(), c, c + bytes);
+        return off;
+    }
+    // complex table in the program's precision
+    uint32_t add_ctab(std::vector<unsigned char> &b, const std::vector<cd> &t) {
+        if (is64()) {
+            std::vector<float> f(2 * t.size());
+            for (size_t i = 0; i < t.size(); ++i) {
+                f[2 * i] = float(t[i].real());
+                f[2 * i + 1] = float(t[i].imag());
+            }
+            return add_tab(b, f.data(), f.size() * sizeof(float));
+        }
+        std::vector<double> d(2 * t.size());
+        for (size_t i = 0; i < t.size(); ++i) {
+            d[2 * i] = t[i].real();
+            d[2 * i + 1] = t[i].imag();
+        }
+        return add_tab(b, d.data(), d.size() * sizeof(double));
+    }
+    // windows of 6 consecutive global positions covering the bits of `hi`
+    static std::vector<int> windows_of(uint64_t hi) {
+        std::vector<int> lo;
+        for (int p = 0; p < 64; ++p)
+            if ((hi >> p) & 1) {
+                lo.push_back(p);
+                p += 5;
+            }
+        return lo;
+    }
+
+    int E() const { return 1 << rb; }
+    bool is64() const { return dtype == QC_C64; }
+    void put(double *arr, int i, double v) {
+        if (is64()) qcx::rt_vals<float>(arr)[i] = float(v);
+        else arr[i] = v;
+    }
+    void put_c(double *arr, int i, cd v) {
+        put(arr, 2 * i, v.real());
+        put(arr, 2 * i + 1, v.imag());
+    }
+    uint32_t swz(uint32_t j) const {
+        return is64() ? qcx::rt_swizzle<4>(j) : qcx::rt_swizzle<3>(j);
+    }
+    // element part of the tile index of element e under layout l
+    uint32_t dep_reg(const RtLayout &l, int e) const {
+        uint32_t j = 0;
+        for (int i = 0; i < rb; ++i)
+            if ((e >> i) & 1) j |= 1u << l.bit_of[i];
+        return j;
+    }
+
+    // ops here are the expanded ones of rt_expand (at most two targets)
+    static uint32_t need_of(const qcx::TileOp &op) {
+        switch (op.kind) {
+        case qcx::TILE_DENSE1: return 1u << op.b0;
+        case qcx::TILE_DENSE2: return (1u << op.b0) | (1u << op.b1);
+        case qcx::TILE_XPERM: {
+            uint32_t b = 0;
+            for (int k = 0; k < op.b0; ++k) b |= 1u << op.x_t[k];
+            return b;
+        }
+        default: return 0;   // diagonal ops: any slot
+        }
+    }
+
+    // initial layout: lanes on the lowest compressed bits (coalesced loads),
+    // registers on the earliest-needed other bits, wavefronts on the rest
+    void initial_layout() {
+        L.m = m;
+        L.rb = rb;
+        const int tb = m - rb;
+        const int lanes = std::min(tb, 6);
+        std::vector<int> order;   // candidate register bits by first use
+        std::vector<int> first(m, INT32_MAX);
+        for (int i = n_ops - 1; i >= 0; --i)
+            for (int b = 0; b < m; ++b)
+                if ((need[i] >> b) & 1) first[b] = i;
+        std::vector<int> rest;
+        for (int b = lanes; b < m; ++b) rest.push_back(b);
+        std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return first[a] < first[b]; });
+        int slot = 0;
+        std::vector<bool> used(m, false);
+        for (int k = 0; k < rb; ++k) {   // register slots
+            L.bit_of[slot++] = rest[k];
+            used[rest[k]] = true;
+        }
+        for (int b = 0; b < lanes; ++b) {   // lane slots
+            L.bit_of[slot++] = b;
+            used[b] = true;
+        }
+        for (int b = 0; b < m; ++b)          // wavefront slots
+            if (!used[b]) L.bit_of[slot++] = b;
+        for (int sl = 0; sl < m; ++sl) L.slot_of[L.bit_of[sl]] = sl;
+    }
+
+    int next_use(int b, int from) const {
+        for (int i = from; i < n_ops; ++i)
+            if ((need[i] >> b) & 1) return i;
+        return INT32_MAX;
+    }
+
+    void emit_remap(const RtLayout &nl) {
+        qcx::RtOp r{};
+        r.kind = qcx::RT_REMAP;
+        for (int e = 0; e < E(); ++e) {
+            r.w[e] = swz(dep_reg(nl, e));
+            r.w[16 + e] = swz(dep_reg(L, e));
+        }
+        for (int k = 0; k < m - rb; ++k) {
+            r.w[32 + k] = uint32_t(L.bit_of[rb + k]);
+            r.w[48 + k] = uint32_t(nl.bit_of[rb + k]);
+        }
+        out.push_back(r);
+        L = nl;
+    }
+
+    // make every bit of `req` a register slot (op index i for the lookahead)
+    void ensure(uint32_t req, int i) {
+        uint32_t missing = 0;
+        for (int b = 0; b < m; ++b)
+            if (((req >> b) & 1) && L.slot_of[b] >= rb) missing |= 1u << b;
+        if (!missing) return;
+        // the new register set: req plus the soonest-needed other bits
+        std::vector<int> cand;
+        for (int b = 0; b < m; ++b)
+            if (!((req >> b) & 1)) cand.push_back(b);
+        std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+            const int na = next_use(a, i), nb = next_use(b, i);
+            if (na != nb) return na < nb;
+            return L.slot_of[a] < rb && L.slot_of[b] >= rb;   // ties: keep residents
+        });
+        uint32_t keep = req;
+        for (size_t k = 0; __builtin_popcount(keep) < rb && k < cand.size(); ++k) {
+            const int b = cand[k];
+            if (next_use(b, i) == INT32_MAX && L.slot_of[b] >= rb) continue;   // no gain
+            keep |= 1u << b;
+        }
+        // bits already in registers stay in their slots; the others swap with
+        // register bits that leave
+        RtLayout nl = L;
+        std::vector<int> leaving, arriving;
+        for (int sl = 0; sl < rb; ++sl)
+            if (!((keep >> L.bit_of[sl]) & 1)) leaving.push_back(sl);
+        for (int b = 0; b < m; ++b)
+            if (((keep >> b) & 1) && L.slot_of[b] >= rb) arriving.push_back(b);
+        // fewer arrivals than free slots: keep the rest of the leavers
+        for (size_t k = 0; k < arriving.size(); ++k) {
+            const int rs = leaving[k], ts = L.slot_of[arriving[k]];
+            nl.bit_of[rs] = arriving[k];
+            nl.bit_of[ts] = L.bit_of[rs];
+        }
+        for (int sl = 0; sl < m; ++sl) nl.slot_of[nl.bit_of[sl]] = sl;
+        emit_remap(nl);
+    }
+
+    // conditions on compressed tile bits -> thread (tm/tv) and element (rm/rv) parts
+    void split(uint32_t cm, uint32_t cv, uint32_t &tm, uint32_t &tv, uint32_t &rm, uint32_t &rv) const {
+        tm = tv = rm = rv = 0;
+        for (int b = 0; b < m; ++b) {
+            if (!((cm >> b) & 1)) continue;
+            const int sl = L.slot_of[b];
+            const uint32_t v = (cv >> b) & 1;
+            if (sl < rb) {
+                rm |= 1u << sl;
+                rv |= v << sl;
+            } else {
+                tm |= 1u << (sl - rb);
+                tv |= v << (sl - rb);
+            }
+        }
+    }
+
+    static bool is_hadamard(const double *u) {
+        const double s = 0.70710678118654752440;
+        auto near = [](double a, double b) { return std::fabs(a - b) < 1e-15; };
+        return near(u[0], s) && near(u[2], s) && near(u[4], s) && near(u[6], -s) && u[1] == 0 &&
+               u[3] == 0 && u[5] == 0 && u[7] == 0;
+    }
+
+    void u1(int b, const double *u, uint32_t cm, uint32_t cv, uint64_t hm, uint64_t hv) {
+        qcx::RtOp r{};
+        r.a = L.slot_of[b];
+        r.hm = hm;
+        r.hv = hv;
+        split(cm, cv, r.tm, r.tv, r.rm, r.rv);
+        const bool uncond = cm == 0 && hm == 0;
+        if (uncond && is_hadamard(u)) {
+            r.kind = qcx::RT_H;
+            scale *= 0.70710678118654752440;
+            out.push_back(r);
+            return;
+        }
+        const bool real = u[1] == 0 && u[3] == 0 && u[5] == 0 && u[7] == 0;
+        r.kind = real ? qcx::RT_U1R : qcx::RT_U1;
+        for (int i = 0; i < 8; ++i) put(r.u, i, u[i]);
+        out.push_back(r);
+    }
+
+    // diagonal terms (the TILE_PHASES term arrays, or one TILE_PHASE term):
+    // the terms whose thread and tile conditions hold come from a lane table,
+    // a wave table and window tables of bit masks
+    void diag_terms(int nt, const uint32_t *pm, const uint32_t *pv, const uint64_t *hm,
+                    const uint64_t *hv, const double *ph) {
+        bool all_neg = true;
+        for (int k = 0; k < nt; ++k)
+            if (!(ph[2 * k] == -1.0 && ph[2 * k + 1] == 0.0)) all_neg = false;
+        qcx::RtOp r{};
+        r.kind = all_neg ? qcx::RT_SIGN : qcx::RT_TERMS;
+        r.nt = nt;
+        uint32_t lane[64], wave[8];
+        for (auto &x : lane) x = 0;
+        for (auto &x : wave) x = 0;
+        uint64_t hi_all = 0;
+        for (int k = 0; k < nt; ++k) hi_all |= hm[k];
+        const std::vector<int> win = windows_of(hi_all);
+        std::vector<std::vector<uint32_t>> wt(win.size(), std::vector<uint32_t>(64, 0));
+        for (int k = 0; k < nt; ++k) {
+            uint32_t tm, tv, rm, rv;
+            split(pm[k], pv[k], tm, tv, rm, rv);
+            for (uint32_t l = 0; l < 64; ++l)
+                if ((l & tm & 63u) == (tv & 63u)) lane[l] |= 1u << k;
+            for (uint32_t w8 = 0; w8 < 8; ++w8)
+                if ((w8 & (tm >> 6)) == (tv >> 6)) wave[w8] |= 1u << k;
+            for (size_t j = 0; j < win.size(); ++j) {
+                const uint64_t wm = uint64_t(63) << win[j];
+                for (uint64_t x = 0; x < 64; ++x)
+                    if (((x << win[j]) & hm[k] & wm) == (hv[k] & wm)) wt[j][x] |= 1u << k;
+            }
+            for (int e = 0; e < E(); ++e)
+                if ((uint32_t(e) & rm) == rv) r.w[32 + e] |= 1u << k;
+            if (!all_neg) put_c(r.u, k, cd(ph[2 * k], ph[2 * k + 1]));
+        }
+        r.w[0] = add_tab(lblob, lane, sizeof(lane));
+        r.w[1] = add_tab(gblob, wave, sizeof(wave));
+        r.b = int(win.size());
+        for (size_t j = 0; j < win.size(); ++j) {
+            r.w[2 + j] = add_tab(gblob, wt[j].data(), 64 * sizeof(uint32_t));
+            r.hw[j] = uint64_t(win[j]);
+        }
+        gpatch.push_back(out.size());
+        out.push_back(r);
+    }
+
+    void fan(const qcx::TileOp &op) {
+        const int t = op.b0;
+        const uint32_t ctl = uint32_t(op.b1);
+        qcx::RtOp r{};
+        r.kind = qcx::RT_FAN;
+        r.a = L.slot_of[t];
+        const cd tphase(op.u[2 * t], op.u[2 * t + 1]);
+        for (int e = 0; e < E(); ++e) {
+            cd g = tphase;
+            for (int c = 0; c < m; ++c)
+                if (((ctl >> c) & 1) && L.slot_of[c] < rb && ((e >> L.slot_of[c]) & 1))
+                    g *= cd(op.u[2 * c], op.u[2 * c + 1]);
+            put_c(r.u, e, g);
+        }
+        // thread-bit controls: lane and wave tables of their phase products
+        std::vector<cd> lane(64, cd(1.0)), wave(8, cd(1.0));
+        for (int c = 0; c < m; ++c) {
+            if (!((ctl >> c) & 1) || L.slot_of[c] < rb) continue;
+            const int tbit = L.slot_of[c] - rb;
+            const cd p(op.u[2 * c], op.u[2 * c + 1]);
+            if (tbit < 6) {
+                for (int l = 0; l < 64; ++l)
+                    if ((l >> tbit) & 1) lane[l] *= p;
+            } else {
+                for (int w8 = 0; w8 < 8; ++w8)
+                    if ((w8 >> (tbit - 6)) & 1) wave[w8] *= p;
+            }
+        }
+        // out-of-tile controls: window tables
+        uint64_t hi_all = 0;
+        for (int h = 0; h < op.pad; ++h) hi_all |= op.fan_mask[h];
+        const std::vector<int> win = windows_of(hi_all);
+        r.w[0] = add_ctab(lblob, lane);
+        r.w[1] = add_ctab(gblob, wave);
+        r.b = int(win.size());
+        for (size_t j = 0; j < win.size(); ++j) {
+            std::vector<cd> t(64, cd(1.0));
+            for (int h = 0; h < op.pad; ++h) {
+                const uint64_t mk = op.fan_mask[h];
+                const int p = __builtin_ctzll(mk);
+                if (p < win[j] || p >= win[j] + 6) continue;
+                for (int x = 0; x < 64; ++x)
+                    if ((x >> (p - win[j])) & 1) t[x] *= cd(op.fan_ph[2 * h], op.fan_ph[2 * h + 1]);
+            }
+            r.w[2 + j] = add_ctab(gblob, t);
+            r.hw[j] = uint64_t(win[j]);
+        }
+        gpatch.push_back(out.size());
+        out.push_back(r);
+    }
+
+    void phases_of(const qcx::TileOp &op, int nt) {
+        diag_terms(nt, op.pm_lo, op.pv_lo, op.pm_hi, op.pv_hi, op.u);
+    }
+
+    void lower(int i) {
+        const qcx::TileOp &op = ops[i];
+        ensure(need[i], i);
+        switch (op.kind) {
+        case qcx::TILE_DENSE1: u1(op.b0, op.u, op.cmask_lo, op.cval_lo, op.cmask_hi, op.cval_hi); break;
+        case qcx::TILE_DIAG1: {
+            qcx::RtOp r{};
+            r.kind = qcx::RT_DIAG1;
+            r.a = L.slot_of[op.b0];
+            r.b = (op.u[0] == 1.0 && op.u[1] == 0.0) ? 1 : 0;
+            for (int k = 0; k < 4; ++k) put(r.u, k, op.u[k]);
+            out.push_back(r);
+        } break;
+        case qcx::TILE_DENSE2: {
+            qcx::RtOp r{};
+            r.kind = qcx::RT_U2;
+            r.a = L.slot_of[op.b0];
+            r.b = L.slot_of[op.b1];
+            r.hm = op.cmask_hi;
+            r.hv = op.cval_hi;
+            split(op.cmask_lo, op.cval_lo, r.tm, r.tv, r.rm, r.rv);
+            for (int k = 0; k < 32; ++k) put(r.u, k, op.u[k]);
+            out.push_back(r);
+        } break;
+        case qcx::TILE_PHASE: {
+            const uint32_t pm = op.cmask_lo, pv = op.cval_lo;
+            const uint64_t hm = op.cmask_hi, hv = op.cval_hi;
+            diag_terms(1, &pm, &pv, &hm, &hv, op.u);
+        } break;
+        case qcx::TILE_PHASES: phases_of(op, op.b0); break;
+        case qcx::TILE_FAN: fan(op); break;
+        case qcx::TILE_XPERM:
+            for (int k = 0; k < op.b0; ++k) {
+                qcx::RtOp r{};
+                r.kind = qcx::RT_CX;
+                r.a = L.slot_of[op.x_t[k]];
+                r.hm = op.x_hm[k];
+                r.hv = op.x_hv[k];
+                split(op.x_cm[k], op.x_cv[k], r.tm, r.tv, r.rm, r.rv);
+                out.push_back(r);
+            }
+            break;
+        default: break;
+        }
+    }
+
+    // global positions of the register and thread bits of layout l
+    void positions(const RtLayout &l, uint32_t *thr, uint32_t *reg) const {
+        uint32_t pos[32];
+        for (int p = 0, j = 0; p < n; ++p)
+            if ((P >> p) & 1) pos[j++] = uint32_t(p);
+        for (int i = 0; i < rb; ++i) reg[i] = pos[l.bit_of[i]];
+        for (int k = 0; k < m - rb; ++k) thr[k] = pos[l.bit_of[rb + k]];
+    }
+
+    void run(qcx::RtArgs &a) {
+        need.resize(n_ops);
+        for (int i = 0; i < n_ops; ++i) need[i] = need_of(ops[i]);
+        initial_layout();
+        const RtLayout first = L;
+        for (int i = 0; i < n_ops; ++i) lower(i);
+        if (scale != 1.0) {
+            qcx::RtOp r{};
+            r.kind = qcx::RT_SCALE;
+            put(r.u, 0, scale);
+            out.push_back(r);
+        }
+        // the store wants the lanes back on the lowest bits (coalesced stores)
+        bool lanes_ok = true;
+        for (int k = 0; k < std::min(m - rb, 6); ++k)
+            if (L.bit_of[rb + k] != first.bit_of[rb + k]) lanes_ok = false;
+        if (!lanes_ok) {
+            RtLayout back = L;
+            // lanes as at the load; the register bits stay where they are if
+            // they are not lane bits there
+            std::vector<int> lane_bits;
+            for (int k = 0; k < std::min(m - rb, 6); ++k) lane_bits.push_back(first.bit_of[rb + k]);
+            std::vector<bool> taken(m, false);
+            for (int k = 0; k < (int)lane_bits.size(); ++k) {
+                back.bit_of[rb + k] = lane_bits[k];
+                taken[lane_bits[k]] = true;
+            }
+            int sl = 0;
+            for (int i = 0; i < rb; ++i) {
+                const int b = L.bit_of[i];
+                if (!taken[b]) {
+                    back.bit_of[sl++] = b;
+                    taken[b] = true;
+                }
+            }
+            for (int b = 0; b < m && sl < rb; ++b)
+                if (!taken[b]) {
+                    back.bit_of[sl++] = b;
+                    taken[b] = true;
+                }
+            sl = rb + (int)lane_bits.size();
+            for (int b = 0; b < m; ++b)
+                if (!taken[b]) back.bit_of[sl++] = b;
+            for (int s2 = 0; s2 < m; ++s2) back.slot_of[back.bit_of[s2]] = s2;
+            emit_remap(back);
+        }
+        // the window and wave tables follow the lane tables in the blob
+        while (lblob.size() % 16) lblob.push_back(0);
+        for (size_t i : gpatch) {
+            out[i].w[1] += uint32_t(lblob.size());
+            for (int j = 0; j < out[i].b; ++j) out[i].w[2 + j] += uint32_t(lblob.size());
+        }
+        a = qcx::RtArgs{};
+        a.lds_tab_bytes = uint32_t(lblob.size());
+        a.m = m;
+        a.tb = m - rb;
+        a.n_tiles = uint64_t(1) << (n - m);
+        a.n_ops = int(out.size());
+        for (int p = 0, j = 0; p < n; ++p)
+            if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
+        positions(first, a.ld_thr, a.ld_reg);
+        positions(L, a.st_thr, a.st_reg);
+    }
+};
+
+// Split the composite tile ops into ops that each need at most two register
+// slots: a TILE_XPERM into one op per controlled-X gate (they commute), a
+// TILE_KRON into one TILE_DENSE1 per bit, and the dense-then-diagonal pairs
+// into their two halves.
+void rt_expand(const std::vector<qcx::TileOp> &in, std::vector<qcx::TileOp> &out) {
+    out.clear();
+    for (const qcx::TileOp &op : in) {
+        switch (op.kind) {
+        case qcx::TILE_XPERM:
+            for (int k = 0; k < op.b0; ++k) {
+                qcx::TileOp x{};
+                x.kind = qcx::TILE_XPERM;
+                x.b0 = 1;
+                x.x_cm[0] = op.x_cm[k];
+                x.x_cv[0] = op.x_cv[k];
+                x.x_t[0] = op.x_t[k];
+                x.x_hm[0] = op.x_hm[k];
+                x.x_hv[0] = op.x_hv[k];
+                out.push_back(x);
+            }
+            break;
+        case qcx::TILE_KRON:
+            for (int j = 0; j < op.b0; ++j) {
+                qcx::TileOp d{};
+                d.kind = qcx::TILE_DENSE1;
+                d.b0 = (op.b1 >> (5 * j)) & 31;
+                for (int i = 0; i < 8; ++i) d.u[i] = op.u[8 * j + i];
+                out.push_back(d);
+            }
+            break;
+        case qcx::TILE_DENSE1_PHASES:
+        case qcx::TILE_DENSE1_FAN: {
+            qcx::TileOp d{};
+            d.kind = qcx::TILE_DENSE1;
+            d.b0 = op.b0;
+            for (int i = 0; i < 8; ++i) d.u[i] = op.u1[i];
+            out.push_back(d);
+            qcx::TileOp p = op;
+            if (op.kind == qcx::TILE_DENSE1_PHASES) {
+                p.kind = qcx::TILE_PHASES;
+                p.b0 = op.pad;
+            } else {
+                p.kind = qcx::TILE_FAN;
+            }
+            out.push_back(p);
+        } break;
+        default: out.push_back(op);
+        }
+    }
+}
+
+// RT program of one tile run (m tile bits P, TileOp list ops), as one
+// host buffer: the RtOps, then the table blob (lane tables first)
+void rt_program(int n, int m, int dtype, uint64_t P, const std::vector<qcx::TileOp> &ops,
+                qcx::RtArgs &a, std::vector<unsigned char> &buf, size_t &tab_off) {
+    std::vector<qcx::TileOp> flat;
+    rt_expand(ops, flat);
+    RtLowering lw{n, m, qcx::rt_reg_bits(dtype), dtype, P, flat.data(), int(flat.size())};
+    lw.run(a);
+    const size_t ob = lw.out.size() * sizeof(qcx::RtOp);
+    tab_off = ob;
+    buf.resize(ob + lw.lblob.size() + lw.gblob.size());
+    std::memcpy(buf.data(), lw.out.data(), ob);
+    if (!lw.lblob.empty()) std::memcpy(buf.data() + ob, lw.lblob.data(), lw.lblob.size());
+    if (!lw.gblob.empty())
+        std::memcpy(buf.data() + ob + lw.lblob.size(), lw.gblob.data(), lw.gblob.size());
+}
+
 int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st,
                   void *stream) {
     DevCtx *c;
@@ -1367,6 +1894,7 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
     std::vector<TileRun> runs;
     form_runs(n, m, ng, gs, nullptr, runs);
     std::vector<qcx::TileOp> ops;
+    std::vector<unsigned char> rbuf;
     for (const TileRun &r : runs) {
         if (r.P == 0) {
             if ((rc = apply_gate_unfused(s, gs[r.gates[0]], st, stream))) return rc;
@@ -1374,11 +1902,21 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         }
         ops.clear();
         tile_ops_for(n, gs, r.gates, r.P, ops);
-        const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
         void *dev = nullptr;
-        if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
-        hipError_t e = qcx::launch_tile_run(s.amp, s.dtype, n, a,
-                                            static_cast<const qcx::TileOp *>(dev), hs);
+        hipError_t e;
+        qcx::RtArgs ra{};
+        size_t tab_off = 0;
+        const bool rt = g_knob_tile_engine.load() == 1 && m >= qcx::rt_reg_bits(s.dtype);
+        if (rt) rt_program(n, m, s.dtype, r.P, ops, ra, rbuf, tab_off);
+        if (rt && ra.lds_tab_bytes <= kRtLdsTabMax) {
+            if ((rc = stage(c, rbuf.data(), rbuf.size(), hs, &dev))) return rc;
+            e = qcx::launch_rt_run(s.amp, s.dtype, ra, static_cast<const qcx::RtOp *>(dev),
+                                   static_cast<const unsigned char *>(dev) + tab_off, hs);
+        } else {   // LDS-resident tiles (also for programs whose lane tables exceed the LDS budget)
+            const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
+            if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
+            e = qcx::launch_tile_run(s.amp, s.dtype, n, a, static_cast<const qcx::TileOp *>(dev), hs);
+        }
         if (e != hipSuccess) return hip_fail(e, "tile_run");
         st.launches += 1;
         st.sweeps += 1;

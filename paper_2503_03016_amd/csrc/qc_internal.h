@@ -174,6 +174,110 @@ struct TileArgs {
     uint32_t pos[kTileMaxBits];  // ascending global bit positions of the tile bits
 };
 
+// ---- register-resident tile programs ----------------------------------------
+//
+// A tile of 2^m amplitudes is held in the registers of 2^(m - RB) threads,
+// 2^RB amplitudes ("elements") per thread.  A layout assigns every
+// compressed tile bit to a slot: slots 0..RB-1 are the bits of the element
+// index e, slot RB + k is bit k of the thread index (bits 0..5: lane,
+// above: wavefront).  Element e of thread t holds tile element
+// j = dep_reg(e) | dep_thr(t).  Gates whose targets sit in register slots
+// need no communication at all; diagonal gates need none wherever their
+// bits sit; an RT_REMAP op moves bits between register and thread slots
+// through LDS (one write and one read per element).  The host schedules the
+// remaps (qc_api.cpp) so that every non-diagonal target is a register slot
+// when its gate runs.
+//
+// Conditions of an op: on out-of-tile bits (hm/hv, uniform per tile), on
+// thread-index bits (tm/tv, per thread) and on element-index bits (rm/rv,
+// uniform per element e).
+constexpr int kRtMaxRB = 4;                  // at most 16 elements per thread
+constexpr int kRtMaxE = 1 << kRtMaxRB;
+constexpr int kRtMaxTB = 9;                  // at most 512 threads per tile
+constexpr int kRtTerms = 16;                 // terms of an RT_SIGN / RT_TERMS op
+constexpr int kRtFanHi = 24;                 // out-of-tile controls of an RT_FAN op
+enum RtKind {
+    RT_U1 = 0,      // u[0..7] (2x2) on register slot a; conditions
+    RT_U1R = 1,     // real 2x2 (imaginary parts 0) on register slot a; conditions
+    RT_H = 2,       // (x0 + x1, x0 - x1) on register slot a (the 1/sqrt2 is deferred to RT_SCALE)
+    RT_DIAG1 = 3,   // diag(u[0..1], u[2..3]) on slot a (register or thread); b = 1: u[0..1] == 1
+    RT_U2 = 4,      // u[0..31] (4x4) on register slots a (msb of the local index) and b; conditions
+    RT_SIGN = 5,    // -1 where an odd number of the nt terms hold
+    RT_TERMS = 6,   // x phase k (u[2k], u[2k+1]) where term k holds, k < nt
+    RT_FAN = 7,     // controlled-phase fan on the target slot a (see RtOp)
+    RT_CX = 8,      // X on register slot a (swap of the pair); conditions
+    RT_REMAP = 9,   // new layout through LDS
+    RT_SCALE = 10,  // x u[0] (real) everywhere
+};
+// Lookup tables.  A program comes with a table blob: its first
+// RtArgs::lds_tab_bytes bytes are copied to LDS once per workgroup (tables
+// indexed by the lane number), the rest is read from memory with uniform
+// addresses (tables indexed by the wavefront number or by a window of the
+// tile's out-of-tile index bits).  Offsets are bytes from the start of the
+// blob; a window table j is indexed by (tile_base >> hw[j]) & 63.
+// RT_SIGN / RT_TERMS: the set L of terms whose thread and tile conditions
+// hold is L_lane[lane] & L_wave[wave] & (AND over the b windows of
+// L_win_j[...]), uint32 bit masks: lane table at w[0], wave table at w[1],
+// window tables at w[2 + j].  Term k then applies to element e when bit k
+// of w[32 + e] is set (its condition on the element index).
+// RT_FAN (a = target slot; for a register target the factors apply to the
+// elements with the target bit set, for a thread target to every element
+// of the threads with it set): element e is multiplied by u[2e] + i u[2e+1]
+// (the target-only phase and the register-slot controls) and by the
+// product F_lane[lane] F_wave[wave] prod_j F_win_j[...] of the phases of
+// the controls on thread bits and out-of-tile bits (complex tables in the
+// state's precision at the same offsets as above).
+// RT_REMAP: the thread part of an element's LDS slot is swz(sum of bit k of
+// t << w[32 + k]) before, swz(sum of bit k of t << w[48 + k]) after; the
+// element part is w[16 + e] before and w[e] after (both swizzled tile
+// indices); see rt_swizzle.
+// Matrix entries and phases are stored in the precision of the state
+// (float for complex64 programs, double for complex128): u and ph are
+// read through rt_u / rt_ph.
+struct RtOp {
+    int32_t kind, a, b, nt;
+    uint32_t tm, tv, rm, rv;
+    uint64_t hm, hv;
+    double u[32];
+    uint32_t w[64];
+    uint64_t hw[2 * kRtFanHi];
+    double ph[32 + 2 * kRtFanHi];
+};
+// entry i of the op's u (or ph) array in precision R: float programs pack
+// their values into the first half of the double array's bytes
+template <typename R>
+__host__ __device__ inline R *rt_vals(double *a) { return reinterpret_cast<R *>(a); }
+template <typename R>
+__host__ __device__ inline const R *rt_vals(const double *a) {
+    return reinterpret_cast<const R *>(a);
+}
+static_assert(sizeof(RtOp) % 16 == 0, "ops are read as 16-byte words");
+
+// LDS slot of tile element j for an exchange: XOR of the bank bits with a
+// fold of the higher bits (a bijection of [0, 2^m), linear over GF(2), so
+// swz(a | b) = swz(a) ^ swz(b) for disjoint a, b).  EB = log2 of the
+// elements in one 128-byte row of LDS banks.
+template <int EB>
+__host__ __device__ inline uint32_t rt_swizzle(uint32_t j) {
+    constexpr uint32_t M = (1u << EB) - 1;
+    return j ^ (((j >> EB) ^ (j >> (2 * EB)) ^ (j >> (3 * EB))) & M);
+}
+
+struct RtArgs {
+    uint64_t n_tiles;
+    int m;                       // tile bits
+    int tb;                      // thread bits (m - RB)
+    int n_ops;
+    int pad;
+    uint32_t pos[kTileMaxBits];  // ascending global positions of the tile bits
+    uint32_t ld_thr[kRtMaxTB];   // global position of thread bit k when loading
+    uint32_t st_thr[kRtMaxTB];   // ... and when storing
+    uint32_t ld_reg[kRtMaxRB];   // global position of element bit i when loading
+    uint32_t st_reg[kRtMaxRB];   // ... and when storing
+    uint32_t lds_tab_bytes;      // leading bytes of the table blob that go to LDS
+};
+constexpr int kRtWindows = 8;    // out-of-tile windows of a table-driven op
+
 // One Pauli term of a tile pass of the expectation: X bits xc and Z bits zc
 // inside the tile (compressed positions), Z bits z_hi outside it (global
 // positions), ph = number of Y factors mod 4, xtop = top bit of xc.
@@ -261,6 +365,10 @@ hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_
 
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s);
+// register bits of the register-resident tile kernel for an element type
+constexpr int rt_reg_bits(int dtype) { return dtype == 1 ? 4 : 3; }
+hipError_t launch_rt_run(void *amp, int dtype, const RtArgs &a, const RtOp *ops_dev,
+                         const unsigned char *tabs_dev, hipStream_t s);
 // new[sigma(i)] = old[i], sigma moving bit position p to sigma[p] (a
 // permutation of 0..n-1, host array); *sweeps receives 0, 1 or 2
 hipError_t launch_permute_bits(void *amp, int dtype, int n, const uint32_t *sigma, int *sweeps,

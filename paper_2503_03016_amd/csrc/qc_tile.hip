@@ -9,6 +9,7 @@
 // coalesced loads, applies the gates one after the other (one barrier per
 // gate, see qc_tile_ops.h), and writes the tile back: a run of G gates costs
 // one HBM read and one HBM write of the state instead of G of each.
+#include "qc_rt_ops.h"
 #include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
@@ -40,7 +41,78 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
     }
 }
 
+// Register-resident tile run: each thread loads its 2^RB elements of the
+// tile straight into registers (its offsets under the load layout), the op
+// program runs on the registers (LDS only for RT_REMAP), and the elements
+// are stored under the final layout.
+template <typename R, int RB>
+__global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
+                                                      const RtOp *__restrict__ ops,
+                                                      const unsigned char *__restrict__ tabs) {
+    constexpr int E = 1 << RB;
+    extern __shared__ unsigned char smem[];
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    const uint32_t tid = threadIdx.x;
+    const bool act = tid < (1u << a.tb);
+    // the lane tables go to LDS behind the exchange area, once
+    unsigned char *ltab = smem + (size_t(1) << a.m) * sizeof(cx<R>);
+    for (uint32_t i = tid; i < a.lds_tab_bytes / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(ltab)[i] = reinterpret_cast<const uint4 *>(tabs)[i];
+    __syncthreads();
+    const rt::Tabs tb{ltab, tabs, tid & 63u,
+                      uint32_t(__builtin_amdgcn_readfirstlane(int(tid >> 6)))};
+    uint64_t thr_ld = 0, thr_st = 0;
+    for (int k = 0; k < a.tb; ++k) {
+        const uint64_t bit = (tid >> k) & 1u;
+        thr_ld |= bit << a.ld_thr[k];
+        thr_st |= bit << a.st_thr[k];
+    }
+    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const uint64_t base = insert_zeros(t, a.pos, a.m);
+        cx<R> v[E];
+        if (act) {
+            const cx<R> *src = amp + base + thr_ld;
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = src[rt::reg_offset<RB>(e, a.ld_reg)];
+        }
+        rt::run_ops<R, RB>(v, lds, base, tid, act, ops, a.n_ops, tb);
+        if (act) {
+            cx<R> *dst = amp + base + thr_st;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dst[rt::reg_offset<RB>(e, a.st_reg)] = v[e];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_rt_run(void *amp, int dtype, const RtArgs &a, const RtOp *ops_dev,
+                         const unsigned char *tabs_dev, hipStream_t s) {
+    const int rb = rt_reg_bits(dtype);
+    if (a.m < rb || a.m > rb + kRtMaxTB || a.tb != a.m - rb || a.m > kTileMaxBits)
+        return hipErrorInvalidValue;
+    const size_t elem = dtype == QC_C64 ? 8 : 16;
+    if ((size_t(1) << a.m) * elem > 65536 || a.lds_tab_bytes % 16 || a.lds_tab_bytes > 16384)
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t(1) << a.m) * elem + a.lds_tab_bytes;
+    uint64_t grid = a.n_tiles;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t cap = uint64_t(cus) * uint64_t(knob(QC_KNOB_TILE_WG_PER_CU));
+    if (grid > cap) grid = cap;
+    const unsigned threads = 1u << (a.tb < 6 ? 6 : a.tb);
+    const int tok = timer_begin(dtype == QC_C64 ? "rt_run_c64" : "rt_run_c128", s);
+    if (dtype == QC_C64)
+        hipLaunchKernelGGL((k_rt_run<float, 4>), dim3(unsigned(grid)), dim3(threads), lds, s,
+                           static_cast<cx<float> *>(amp), a, ops_dev, tabs_dev);
+    else
+        hipLaunchKernelGGL((k_rt_run<double, 3>), dim3(unsigned(grid)), dim3(threads), lds, s,
+                           static_cast<cx<double> *>(amp), a, ops_dev, tabs_dev);
+    timer_end(tok, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s) {
