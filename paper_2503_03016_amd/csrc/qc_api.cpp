@@ -1500,7 +1500,7 @@ struct RtLowering {
 
     void emit_remap(const RtLayout &nl) {
         qcx::RtOp r{};
-        r.kind = qcx::RT_REMAP;
+        r.kind = qcx::rt_code(qcx::RT_REMAP, 0);
         for (int e = 0; e < E(); ++e) {
             r.w[e] = swz(dep_reg(nl, e));
             r.w[16 + e] = swz(dep_reg(L, e));
@@ -1584,13 +1584,15 @@ struct RtLowering {
         split(cm, cv, r.tm, r.tv, r.rm, r.rv);
         const bool uncond = cm == 0 && hm == 0;
         if (uncond && is_hadamard(u)) {
-            r.kind = qcx::RT_H;
+            r.kind = qcx::rt_code(qcx::RT_H, r.a);
             scale *= 0.70710678118654752440;
             out.push_back(r);
             return;
         }
         const bool real = u[1] == 0 && u[3] == 0 && u[5] == 0 && u[7] == 0;
-        r.kind = real ? qcx::RT_U1R : qcx::RT_U1;
+        const bool cond = (r.tm | r.rm) != 0 || r.hm != 0;
+        r.kind = qcx::rt_code(real ? (cond ? qcx::RT_U1RC : qcx::RT_U1R) : (cond ? qcx::RT_U1C : qcx::RT_U1),
+                              r.a);
         for (int i = 0; i < 8; ++i) put(r.u, i, u[i]);
         out.push_back(r);
     }
@@ -1604,7 +1606,7 @@ struct RtLowering {
         for (int k = 0; k < nt; ++k)
             if (!(ph[2 * k] == -1.0 && ph[2 * k + 1] == 0.0)) all_neg = false;
         qcx::RtOp r{};
-        r.kind = all_neg ? qcx::RT_SIGN : qcx::RT_TERMS;
+        r.kind = qcx::rt_code(all_neg ? qcx::RT_SIGN : qcx::RT_TERMS, 0);
         r.nt = nt;
         uint32_t lane[64], wave[8];
         for (auto &x : lane) x = 0;
@@ -1644,8 +1646,13 @@ struct RtLowering {
         const int t = op.b0;
         const uint32_t ctl = uint32_t(op.b1);
         qcx::RtOp r{};
-        r.kind = qcx::RT_FAN;
         r.a = L.slot_of[t];
+        if (r.a < rb) {
+            r.kind = qcx::rt_code(qcx::RT_FAN, r.a);
+        } else {
+            r.kind = qcx::rt_code(qcx::RT_FAN, qcx::kRtThreadSlot);
+            r.a -= rb;   // the target's thread bit
+        }
         const cd tphase(op.u[2 * t], op.u[2 * t + 1]);
         for (int e = 0; e < E(); ++e) {
             cd g = tphase;
@@ -1702,20 +1709,25 @@ struct RtLowering {
         case qcx::TILE_DENSE1: u1(op.b0, op.u, op.cmask_lo, op.cval_lo, op.cmask_hi, op.cval_hi); break;
         case qcx::TILE_DIAG1: {
             qcx::RtOp r{};
-            r.kind = qcx::RT_DIAG1;
             r.a = L.slot_of[op.b0];
+            if (r.a < rb) {
+                r.kind = qcx::rt_code(qcx::RT_DIAG1, r.a);
+            } else {
+                r.kind = qcx::rt_code(qcx::RT_DIAG1, qcx::kRtThreadSlot);
+                r.a -= rb;
+            }
             r.b = (op.u[0] == 1.0 && op.u[1] == 0.0) ? 1 : 0;
             for (int k = 0; k < 4; ++k) put(r.u, k, op.u[k]);
             out.push_back(r);
         } break;
         case qcx::TILE_DENSE2: {
             qcx::RtOp r{};
-            r.kind = qcx::RT_U2;
             r.a = L.slot_of[op.b0];
             r.b = L.slot_of[op.b1];
             r.hm = op.cmask_hi;
             r.hv = op.cval_hi;
             split(op.cmask_lo, op.cval_lo, r.tm, r.tv, r.rm, r.rv);
+            r.kind = qcx::rt_code(qcx::RT_U2, (r.tm | r.rm) != 0 || r.hm != 0 ? 1 : 0);
             for (int k = 0; k < 32; ++k) put(r.u, k, op.u[k]);
             out.push_back(r);
         } break;
@@ -1729,8 +1741,8 @@ struct RtLowering {
         case qcx::TILE_XPERM:
             for (int k = 0; k < op.b0; ++k) {
                 qcx::RtOp r{};
-                r.kind = qcx::RT_CX;
                 r.a = L.slot_of[op.x_t[k]];
+                r.kind = qcx::rt_code(qcx::RT_CX, r.a);
                 r.hm = op.x_hm[k];
                 r.hv = op.x_hv[k];
                 split(op.x_cm[k], op.x_cv[k], r.tm, r.tv, r.rm, r.rv);
@@ -1758,7 +1770,7 @@ struct RtLowering {
         for (int i = 0; i < n_ops; ++i) lower(i);
         if (scale != 1.0) {
             qcx::RtOp r{};
-            r.kind = qcx::RT_SCALE;
+            r.kind = qcx::rt_code(qcx::RT_SCALE, 0);
             put(r.u, 0, scale);
             out.push_back(r);
         }

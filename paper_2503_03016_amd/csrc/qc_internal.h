@@ -196,19 +196,26 @@ constexpr int kRtMaxE = 1 << kRtMaxRB;
 constexpr int kRtMaxTB = 9;                  // at most 512 threads per tile
 constexpr int kRtTerms = 16;                 // terms of an RT_SIGN / RT_TERMS op
 constexpr int kRtFanHi = 24;                 // out-of-tile controls of an RT_FAN op
+// An op's code is rt_code(kind, sub): sub is the register slot for the
+// kinds that act on one (kRtThreadSlot: a thread slot, whose thread bit is
+// a), 1 for a conditioned RT_U2, else 0.
 enum RtKind {
-    RT_U1 = 0,      // u[0..7] (2x2) on register slot a; conditions
-    RT_U1R = 1,     // real 2x2 (imaginary parts 0) on register slot a; conditions
-    RT_H = 2,       // (x0 + x1, x0 - x1) on register slot a (the 1/sqrt2 is deferred to RT_SCALE)
-    RT_DIAG1 = 3,   // diag(u[0..1], u[2..3]) on slot a (register or thread); b = 1: u[0..1] == 1
-    RT_U2 = 4,      // u[0..31] (4x4) on register slots a (msb of the local index) and b; conditions
-    RT_SIGN = 5,    // -1 where an odd number of the nt terms hold
-    RT_TERMS = 6,   // x phase k (u[2k], u[2k+1]) where term k holds, k < nt
-    RT_FAN = 7,     // controlled-phase fan on the target slot a (see RtOp)
-    RT_CX = 8,      // X on register slot a (swap of the pair); conditions
-    RT_REMAP = 9,   // new layout through LDS
-    RT_SCALE = 10,  // x u[0] (real) everywhere
+    RT_U1 = 0,      // u[0..7] (2x2) on register slot sub
+    RT_U1C = 1,     // the same where the conditions hold
+    RT_U1R = 2,     // real 2x2 (imaginary parts 0) on register slot sub
+    RT_U1RC = 3,    // the same where the conditions hold
+    RT_H = 4,       // (x0 + x1, x0 - x1) on register slot sub (the 1/sqrt2 is deferred to RT_SCALE)
+    RT_DIAG1 = 5,   // diag(u[0..1], u[2..3]) on slot sub; b = 1: u[0..1] == 1
+    RT_U2 = 6,      // u[0..31] (4x4) on register slots a (msb of the local index) and b
+    RT_SIGN = 7,    // -1 where an odd number of the nt terms hold
+    RT_TERMS = 8,   // x phase k (u[2k], u[2k+1]) where term k holds, k < nt
+    RT_FAN = 9,     // controlled-phase fan on the target slot sub (see below)
+    RT_CX = 10,     // X on register slot sub (swap of the pair) where the conditions hold
+    RT_REMAP = 11,  // new layout through LDS
+    RT_SCALE = 12,  // x u[0] (real) everywhere
 };
+constexpr int kRtThreadSlot = 7;
+__host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
 // Lookup tables.  A program comes with a table blob: its first
 // RtArgs::lds_tab_bytes bytes are copied to LDS once per workgroup (tables
 // indexed by the lane number), the rest is read from memory with uniform

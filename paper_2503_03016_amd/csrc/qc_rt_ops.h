@@ -57,7 +57,8 @@ __device__ __forceinline__ void u1_slot(cx<R> *v, const RtOp &op, bool tc) {
     for (int e0 = 0; e0 < E; ++e0) {
         if (e0 & (1 << S)) continue;
         const int e1 = e0 | (1 << S);
-        if (COND && (uint32_t(e0) & rm) != rv) continue;   // uniform
+        // element and thread conditions as one select (no branch per pair)
+        const bool c = tc && (uint32_t(e0) & rm) == rv;
         const cx<R> a = v[e0], b = v[e1];
         cx<R> x, y;
         if (REAL) {
@@ -68,21 +69,11 @@ __device__ __forceinline__ void u1_slot(cx<R> *v, const RtOp &op, bool tc) {
             x = cfma(u1, b, cfma(u0, a, z));
             y = cfma(u3, b, cfma(u2, a, z));
         }
-        v[e0] = COND ? csel(tc, x, a) : x;
-        v[e1] = COND ? csel(tc, y, b) : y;
+        v[e0] = COND ? csel(c, x, a) : x;
+        v[e1] = COND ? csel(c, y, b) : y;
     }
 }
 
-template <typename R, int RB, bool REAL, bool COND>
-__device__ __forceinline__ void u1(cx<R> *v, const RtOp &op, bool tc) {
-    switch (op.a) {   // uniform
-    case 0: u1_slot<R, RB, 0, REAL, COND>(v, op, tc); break;
-    case 1: if constexpr (RB > 1) u1_slot<R, RB, 1, REAL, COND>(v, op, tc); break;
-    case 2: if constexpr (RB > 2) u1_slot<R, RB, 2, REAL, COND>(v, op, tc); break;
-    case 3: if constexpr (RB > 3) u1_slot<R, RB, 3, REAL, COND>(v, op, tc); break;
-    default: break;
-    }
-}
 
 template <typename R, int RB, int S>
 __device__ __forceinline__ void h_slot(cx<R> *v) {
@@ -97,16 +88,6 @@ __device__ __forceinline__ void h_slot(cx<R> *v) {
     }
 }
 
-template <typename R, int RB>
-__device__ __forceinline__ void hgate(cx<R> *v, int slot) {
-    switch (slot) {
-    case 0: h_slot<R, RB, 0>(v); break;
-    case 1: if constexpr (RB > 1) h_slot<R, RB, 1>(v); break;
-    case 2: if constexpr (RB > 2) h_slot<R, RB, 2>(v); break;
-    case 3: if constexpr (RB > 3) h_slot<R, RB, 3>(v); break;
-    default: break;
-    }
-}
 
 // 4x4 on register slots A (most significant bit of the local index) and B
 template <typename R, int RB, int A, int B, bool COND>
@@ -116,7 +97,7 @@ __device__ __forceinline__ void u2_slots(cx<R> *v, const RtOp &op, bool tc) {
 #pragma unroll
     for (int e0 = 0; e0 < E; ++e0) {
         if (e0 & ((1 << A) | (1 << B))) continue;
-        if (COND && (uint32_t(e0) & rm) != rv) continue;
+        const bool c = tc && (uint32_t(e0) & rm) == rv;
         const int idx[4] = {e0, e0 | (1 << B), e0 | (1 << A), e0 | (1 << A) | (1 << B)};
         cx<R> x[4], y[4];
 #pragma unroll
@@ -129,7 +110,7 @@ __device__ __forceinline__ void u2_slots(cx<R> *v, const RtOp &op, bool tc) {
             y[r] = acc;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[idx[r]] = COND ? csel(tc, y[r], x[r]) : y[r];
+        for (int r = 0; r < 4; ++r) v[idx[r]] = COND ? csel(c, y[r], x[r]) : y[r];
     }
 }
 
@@ -155,28 +136,25 @@ __device__ __forceinline__ void u2(cx<R> *v, const RtOp &op, bool tc) {
     }
 }
 
-// diag(d0, d1) on slot a: a register slot picks per element (uniform), a
-// thread slot per thread
-template <typename R, int RB>
-__device__ __forceinline__ void diag1(cx<R> *v, const RtOp &op, uint32_t tid) {
+// diag(d0, d1) on register slot S: the element's bit picks the factor
+template <typename R, int RB, int S>
+__device__ __forceinline__ void diag1_slot(cx<R> *v, cx<R> d0, cx<R> d1, bool skip0) {
     constexpr int E = 1 << RB;
-    const cx<R> d0 = ldu<R>(op.u, 0), d1 = ldu<R>(op.u, 1);
-    const int a = op.a;
-    const bool skip0 = op.b != 0;   // d0 == 1
-    if (a < RB) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool hi = (e >> a) & 1;   // uniform
-            if (!hi && skip0) continue;
-            v[e] = cmul(hi ? d1 : d0, v[e]);
-        }
-    } else {
-        const bool hi = (tid >> (a - RB)) & 1u;
-        const cx<R> d = csel(hi, d1, d0);
-        if (skip0 && !hi) return;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cmul(d, v[e]);
+    for (int e = 0; e < E; ++e) {
+        if ((e >> S) & 1) v[e] = cmul(d1, v[e]);
+        else if (!skip0) v[e] = cmul(d0, v[e]);   // uniform
     }
+}
+
+// diag(d0, d1) on the thread slot a: the thread's bit picks the factor
+template <typename R, int RB>
+__device__ __forceinline__ void diag1_thread(cx<R> *v, const RtOp &op, uint32_t tid) {
+    constexpr int E = 1 << RB;
+    const bool hi = (tid >> op.a) & 1u;
+    const cx<R> d = csel(hi, ldu<R>(op.u, 1), ldu<R>(op.u, 0));
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cmul(d, v[e]);
 }
 
 // Per-op lookup tables: lane tables in LDS (ltab), wave and window tables
@@ -192,8 +170,10 @@ __device__ __forceinline__ uint32_t terms_live(const RtOp &op, const Tabs &tb, u
     uint32_t L = reinterpret_cast<const uint32_t *>(tb.ltab + op.w[0])[tb.lane];
     L &= reinterpret_cast<const uint32_t *>(tb.gtab + op.w[1])[tb.wave];
     const int nw = op.b;
-    for (int j = 0; j < nw; ++j)
-        L &= reinterpret_cast<const uint32_t *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63];
+#pragma unroll
+    for (int j = 0; j < kRtWindows; ++j)
+        if (j < nw)   // uniform
+            L &= reinterpret_cast<const uint32_t *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63];
     return L;
 }
 
@@ -218,11 +198,8 @@ __device__ __forceinline__ void sign(cx<R> *v, const RtOp &op, const Tabs &tb, u
     constexpr int E = 1 << RB;
     const uint32_t L = terms_live(op, tb, base);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t re = op.w[32 + e];
-        if (!re) continue;   // uniform
-        v[e] = negate_if(v[e], uint32_t(__builtin_popcount(L & re)) & 1u);
-    }
+    for (int e = 0; e < E; ++e)
+        v[e] = negate_if(v[e], uint32_t(__builtin_popcount(L & op.w[32 + e])) & 1u);
 }
 
 template <typename R, int RB>
@@ -230,37 +207,43 @@ __device__ __forceinline__ void terms(cx<R> *v, const RtOp &op, const Tabs &tb, 
     constexpr int E = 1 << RB;
     const uint32_t L = terms_live(op, tb, base);
     const int nt = op.nt;
+    for (int k = 0; k < nt; ++k) {
+        const cx<R> p = ldu<R>(op.u, k);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t re = op.w[32 + e];
-        for (int k = 0; k < nt; ++k) {
-            if (!((re >> k) & 1u)) continue;   // uniform
-            const cx<R> p = ldu<R>(op.u, k);
-            v[e] = csel((L >> k) & 1u, cmul(p, v[e]), v[e]);
-        }
+        for (int e = 0; e < E; ++e)
+            v[e] = csel((L & op.w[32 + e]) >> k & 1u, cmul(p, v[e]), v[e]);
     }
 }
 
-template <typename R, int RB>
-__device__ __forceinline__ void fan(cx<R> *v, const RtOp &op, const Tabs &tb, uint64_t base) {
-    constexpr int E = 1 << RB;
-    // the factor of the out-of-tile controls (uniform), then the thread part
+// the thread's phase factor of a fan: its wave entry, the windows of the
+// tile's out-of-tile bits (uniform) and its lane entry
+template <typename R>
+__device__ __forceinline__ cx<R> fan_factor(const RtOp &op, const Tabs &tb, uint64_t base) {
     cx<R> k = reinterpret_cast<const cx<R> *>(tb.gtab + op.w[1])[tb.wave];
     const int nw = op.b;
-    for (int j = 0; j < nw; ++j)
-        k = cmul(k, reinterpret_cast<const cx<R> *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63]);
-    const cx<R> f = cmul(k, reinterpret_cast<const cx<R> *>(tb.ltab + op.w[0])[tb.lane]);
-    const int a = op.a;
-    if (a < RB) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if (!((e >> a) & 1)) continue;   // uniform
-            v[e] = cmul(cmul(f, ldu<R>(op.u, e)), v[e]);
-        }
-    } else {
-        // a thread target: the threads with it set (the tables hold 1 for
-        // the others would cost a multiply per element; skip them instead)
-        if (!((tb.lane | (tb.wave << 6)) >> (a - RB) & 1u)) return;
+    for (int j = 0; j < kRtWindows; ++j)
+        if (j < nw)   // uniform
+            k = cmul(k, reinterpret_cast<const cx<R> *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63]);
+    return cmul(k, reinterpret_cast<const cx<R> *>(tb.ltab + op.w[0])[tb.lane]);
+}
+
+// the elements with register bit S set take f times their element factor
+template <typename R, int RB, int S>
+__device__ __forceinline__ void fan_slot(cx<R> *v, const RtOp &op, cx<R> f) {
+    constexpr int E = 1 << RB;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if ((e >> S) & 1) v[e] = cmul(cmul(f, ldu<R>(op.u, e)), v[e]);
+}
+
+// a fan whose target is thread bit a: every element of the threads that
+// have it set
+template <typename R, int RB>
+__device__ __forceinline__ void fan_thread(cx<R> *v, const RtOp &op, const Tabs &tb, uint64_t base) {
+    constexpr int E = 1 << RB;
+    const cx<R> f = fan_factor<R>(op, tb, base);
+    if (((tb.lane | (tb.wave << 6)) >> op.a) & 1u) {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = cmul(cmul(f, ldu<R>(op.u, e)), v[e]);
     }
@@ -280,20 +263,6 @@ __device__ __forceinline__ void xgate_slot(cx<R> *v, uint32_t rm, uint32_t rv, b
     }
 }
 
-// controlled X on register slot a: swap the pairs whose element condition
-// (rm/rv) and thread condition (tm/tv) hold
-template <typename R, int RB>
-__device__ __forceinline__ void cx_gate(cx<R> *v, const RtOp &op, uint32_t tid) {
-    const uint32_t rm = op.rm, rv = op.rv;
-    const bool tc = (tid & op.tm) == op.tv;
-    switch (op.a) {
-    case 0: xgate_slot<R, RB, 0>(v, rm, rv, tc); break;
-    case 1: if constexpr (RB > 1) xgate_slot<R, RB, 1>(v, rm, rv, tc); break;
-    case 2: if constexpr (RB > 2) xgate_slot<R, RB, 2>(v, rm, rv, tc); break;
-    case 3: if constexpr (RB > 3) xgate_slot<R, RB, 3>(v, rm, rv, tc); break;
-    default: break;
-    }
-}
 
 // Exchange through LDS: every thread writes its elements at their slots
 // under the old layout, then reads the elements of the new layout.  The
@@ -324,49 +293,53 @@ __device__ __forceinline__ void remap(cx<R> *v, cx<R> *lds, const RtOp &op, uint
     }
 }
 
-// Run ops[0 .. n_ops) on the tile at `base` held in v.
+// Run ops[0 .. n_ops) on the tile at `base` held in v.  The op code is
+// kind * 8 + register slot (rt_code), so one flat switch picks the code
+// for the op and its slot: one merge of the element registers per op
+// (nested switches made the compiler copy all of them at every level).
+#define QC_RT_SLOT_CASES(KIND, STMT)                                    \
+    case rt_code(KIND, 0): { constexpr int S = 0; STMT; } break;        \
+    case rt_code(KIND, 1): if constexpr (RB > 1) { constexpr int S = 1; STMT; } break; \
+    case rt_code(KIND, 2): if constexpr (RB > 2) { constexpr int S = 2; STMT; } break; \
+    case rt_code(KIND, 3): if constexpr (RB > 3) { constexpr int S = 3; STMT; } break;
+
 template <typename R, int RB>
 __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uint32_t tid, bool act,
                                const RtOp *__restrict__ ops, int n_ops, const Tabs &tb) {
     constexpr int E = 1 << RB;
     for (int o = 0; o < n_ops; ++o) {
         const RtOp &op = ops[o];
-        const int kind = op.kind;
-        if ((base & op.hm) != op.hv) continue;   // uniform per tile
-        switch (kind) {
-        case RT_U1:
-        case RT_U1R: {
-            const bool cond = (op.tm | op.rm) != 0;
-            const bool tc = (tid & op.tm) == op.tv;
-            if (kind == RT_U1R) {
-                if (cond) u1<R, RB, true, true>(v, op, tc);
-                else u1<R, RB, true, false>(v, op, tc);
-            } else {
-                if (cond) u1<R, RB, false, true>(v, op, tc);
-                else u1<R, RB, false, false>(v, op, tc);
-            }
-        } break;
-        case RT_H: hgate<R, RB>(v, op.a); break;
-        case RT_DIAG1: diag1<R, RB>(v, op, tid); break;
-        case RT_U2: {
-            const bool tc = (tid & op.tm) == op.tv;
-            if ((op.tm | op.rm) != 0) u2<R, RB, true>(v, op, tc);
-            else u2<R, RB, false>(v, op, tc);
-        } break;
-        case RT_SIGN: sign<R, RB>(v, op, tb, base); break;
-        case RT_TERMS: terms<R, RB>(v, op, tb, base); break;
-        case RT_FAN: fan<R, RB>(v, op, tb, base); break;
-        case RT_CX: cx_gate<R, RB>(v, op, tid); break;
-        case RT_REMAP: remap<R, RB>(v, lds, op, tid, act); break;
-        case RT_SCALE: {
-            const R s = rt_vals<R>(op.u)[0];
+        const int code = op.kind;
+        // thread condition and the tile's out-of-tile condition, folded into
+        // the selects of the conditioned kinds (no branch around the op, so
+        // every path through the loop body changes the registers in place)
+        const bool tc = (tid & op.tm) == op.tv && (base & op.hm) == op.hv;
+        switch (code) {
+            QC_RT_SLOT_CASES(RT_U1, (u1_slot<R, RB, S, false, false>(v, op, tc)))
+            QC_RT_SLOT_CASES(RT_U1C, (u1_slot<R, RB, S, false, true>(v, op, tc)))
+            QC_RT_SLOT_CASES(RT_U1R, (u1_slot<R, RB, S, true, false>(v, op, tc)))
+            QC_RT_SLOT_CASES(RT_U1RC, (u1_slot<R, RB, S, true, true>(v, op, tc)))
+            QC_RT_SLOT_CASES(RT_H, (h_slot<R, RB, S>(v)))
+            QC_RT_SLOT_CASES(RT_DIAG1, (diag1_slot<R, RB, S>(v, ldu<R>(op.u, 0), ldu<R>(op.u, 1), op.b != 0)))
+            QC_RT_SLOT_CASES(RT_FAN, (fan_slot<R, RB, S>(v, op, fan_factor<R>(op, tb, base))))
+            QC_RT_SLOT_CASES(RT_CX, (xgate_slot<R, RB, S>(v, op.rm, op.rv, tc)))
+        case rt_code(RT_DIAG1, kRtThreadSlot): diag1_thread<R, RB>(v, op, tid); break;
+        case rt_code(RT_FAN, kRtThreadSlot): fan_thread<R, RB>(v, op, tb, base); break;
+        case rt_code(RT_U2, 0): u2<R, RB, false>(v, op, tc); break;
+        case rt_code(RT_U2, 1): u2<R, RB, true>(v, op, tc); break;
+        case rt_code(RT_SIGN, 0): sign<R, RB>(v, op, tb, base); break;
+        case rt_code(RT_TERMS, 0): terms<R, RB>(v, op, tb, base); break;
+        case rt_code(RT_REMAP, 0): remap<R, RB>(v, lds, op, tid, act); break;
+        case rt_code(RT_SCALE, 0): {
+            const R sc = rt_vals<R>(op.u)[0];
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cx<R>{v[e].re * s, v[e].im * s};
+            for (int e = 0; e < E; ++e) v[e] = cx<R>{v[e].re * sc, v[e].im * sc};
         } break;
-        default: break;
+        default: __builtin_unreachable();   // the host emits only the codes above
         }
     }
 }
+#undef QC_RT_SLOT_CASES
 
 }  // namespace rt
 }  // namespace qcx
