@@ -1373,6 +1373,7 @@ qcx::TileArgs tile_args(int n, int m, uint64_t P, int n_ops) {
 // next use comes soonest (farthest next use leaves first), so one exchange
 // serves as many later ops as possible.
 constexpr uint32_t kRtLdsTabMax = 16384;   // LDS bytes for the lane tables of one program
+constexpr int kRtMinTileBits = 8;           // register tiles need >= 2^8 tiles in the register
 struct RtLayout {
     int m = 0, rb = 0;
     int bit_of[32];    // slot -> compressed tile bit
@@ -1390,7 +1391,7 @@ struct RtLowering {
     double scale = 1.0;           // deferred factor of the unscaled Hadamards
     // table blob: lane tables (copied to LDS) and wave / window tables
     std::vector<unsigned char> lblob, gblob;
-    std::vector<size_t> gpatch;   // (op index) whose w[1], w[2..] are gblob offsets
+    bool too_wide = false;        // an op needs more out-of-tile windows than kRtWindows
 
     static uint32_t add_tab(std::vector<unsigned char> &b, const void *p, size_t bytes) {
         while (b.size() % 16) b.push_back(0);
@@ -1416,13 +1417,13 @@ struct RtLowering {
         }
         return add_tab(b, d.data(), d.size() * sizeof(double));
     }
-    // windows of 6 consecutive global positions covering the bits of `hi`
+    // windows of 3 consecutive global positions covering the bits of `hi`
     static std::vector<int> windows_of(uint64_t hi) {
         std::vector<int> lo;
         for (int p = 0; p < 64; ++p)
             if ((hi >> p) & 1) {
                 lo.push_back(p);
-                p += 5;
+                p += 2;
             }
         return lo;
     }
@@ -1614,7 +1615,8 @@ struct RtLowering {
         uint64_t hi_all = 0;
         for (int k = 0; k < nt; ++k) hi_all |= hm[k];
         const std::vector<int> win = windows_of(hi_all);
-        std::vector<std::vector<uint32_t>> wt(win.size(), std::vector<uint32_t>(64, 0));
+        if (win.size() > size_t(qcx::kRtWindows)) too_wide = true;
+        std::vector<std::vector<uint32_t>> wt(win.size(), std::vector<uint32_t>(8, 0));
         for (int k = 0; k < nt; ++k) {
             uint32_t tm, tv, rm, rv;
             split(pm[k], pv[k], tm, tv, rm, rv);
@@ -1623,8 +1625,8 @@ struct RtLowering {
             for (uint32_t w8 = 0; w8 < 8; ++w8)
                 if ((w8 & (tm >> 6)) == (tv >> 6)) wave[w8] |= 1u << k;
             for (size_t j = 0; j < win.size(); ++j) {
-                const uint64_t wm = uint64_t(63) << win[j];
-                for (uint64_t x = 0; x < 64; ++x)
+                const uint64_t wm = uint64_t(7) << win[j];
+                for (uint64_t x = 0; x < 8; ++x)
                     if (((x << win[j]) & hm[k] & wm) == (hv[k] & wm)) wt[j][x] |= 1u << k;
             }
             for (int e = 0; e < E(); ++e)
@@ -1632,13 +1634,11 @@ struct RtLowering {
             if (!all_neg) put_c(r.u, k, cd(ph[2 * k], ph[2 * k + 1]));
         }
         r.w[0] = add_tab(lblob, lane, sizeof(lane));
-        r.w[1] = add_tab(gblob, wave, sizeof(wave));
-        r.b = int(win.size());
-        for (size_t j = 0; j < win.size(); ++j) {
-            r.w[2 + j] = add_tab(gblob, wt[j].data(), 64 * sizeof(uint32_t));
-            r.hw[j] = uint64_t(win[j]);
-        }
-        gpatch.push_back(out.size());
+        for (int w8 = 0; w8 < 8; ++w8) r.w[8 + w8] = wave[w8];
+        r.b = int(std::min(win.size(), size_t(qcx::kRtWindows)));
+        for (int j = 0; j < qcx::kRtWindows; ++j)   // unused windows: all terms pass
+            for (int x = 0; x < 8; ++x) r.wt[8 * j + x] = j < r.b ? wt[j][x] : ~0u;
+        for (int j = 0; j < r.b; ++j) r.hw[j] = uint64_t(win[j]);
         out.push_back(r);
     }
 
@@ -1675,26 +1675,28 @@ struct RtLowering {
                     if ((w8 >> (tbit - 6)) & 1) wave[w8] *= p;
             }
         }
-        // out-of-tile controls: window tables
+        // out-of-tile controls: window tables in the op
         uint64_t hi_all = 0;
         for (int h = 0; h < op.pad; ++h) hi_all |= op.fan_mask[h];
         const std::vector<int> win = windows_of(hi_all);
+        if (win.size() > size_t(qcx::kRtWindows)) too_wide = true;
         r.w[0] = add_ctab(lblob, lane);
-        r.w[1] = add_ctab(gblob, wave);
-        r.b = int(win.size());
-        for (size_t j = 0; j < win.size(); ++j) {
-            std::vector<cd> t(64, cd(1.0));
-            for (int h = 0; h < op.pad; ++h) {
-                const uint64_t mk = op.fan_mask[h];
-                const int p = __builtin_ctzll(mk);
-                if (p < win[j] || p >= win[j] + 6) continue;
-                for (int x = 0; x < 64; ++x)
-                    if ((x >> (p - win[j])) & 1) t[x] *= cd(op.fan_ph[2 * h], op.fan_ph[2 * h + 1]);
+        for (int w8 = 0; w8 < 8; ++w8) put_c(r.ph, w8, wave[w8]);
+        r.b = int(std::min(win.size(), size_t(qcx::kRtWindows)));
+        for (int j = r.b; j < qcx::kRtWindows; ++j)   // unused windows: factor 1
+            for (int x = 0; x < 8; ++x) put_c(r.ph, 8 + 8 * j + x, cd(1.0));
+        for (int j = 0; j < r.b; ++j) {
+            for (int x = 0; x < 8; ++x) {
+                cd t(1.0);
+                for (int h = 0; h < op.pad; ++h) {
+                    const int p = __builtin_ctzll(op.fan_mask[h]);
+                    if (p >= win[j] && p < win[j] + 3 && ((x >> (p - win[j])) & 1))
+                        t *= cd(op.fan_ph[2 * h], op.fan_ph[2 * h + 1]);
+                }
+                put_c(r.ph, 8 + 8 * j + x, t);
             }
-            r.w[2 + j] = add_ctab(gblob, t);
             r.hw[j] = uint64_t(win[j]);
         }
-        gpatch.push_back(out.size());
         out.push_back(r);
     }
 
@@ -1774,10 +1776,13 @@ struct RtLowering {
             put(r.u, 0, scale);
             out.push_back(r);
         }
-        // the store wants the lanes back on the lowest bits (coalesced stores)
-        bool lanes_ok = true;
+        // the store wants most lanes on the lowest bits (runs of >= 16
+        // contiguous amplitudes per wavefront store); otherwise one more
+        // exchange puts the load's lanes back
+        int low_lanes = 0;
         for (int k = 0; k < std::min(m - rb, 6); ++k)
-            if (L.bit_of[rb + k] != first.bit_of[rb + k]) lanes_ok = false;
+            if (L.bit_of[rb + k] < 5) ++low_lanes;
+        const bool lanes_ok = low_lanes >= std::min({m - rb, 6, 4});
         if (!lanes_ok) {
             RtLayout back = L;
             // lanes as at the load; the register bits stay where they are if
@@ -1808,12 +1813,7 @@ struct RtLowering {
             for (int s2 = 0; s2 < m; ++s2) back.slot_of[back.bit_of[s2]] = s2;
             emit_remap(back);
         }
-        // the window and wave tables follow the lane tables in the blob
         while (lblob.size() % 16) lblob.push_back(0);
-        for (size_t i : gpatch) {
-            out[i].w[1] += uint32_t(lblob.size());
-            for (int j = 0; j < out[i].b; ++j) out[i].w[2 + j] += uint32_t(lblob.size());
-        }
         a = qcx::RtArgs{};
         a.lds_tab_bytes = uint32_t(lblob.size());
         a.m = m;
@@ -1886,6 +1886,7 @@ void rt_program(int n, int m, int dtype, uint64_t P, const std::vector<qcx::Tile
     rt_expand(ops, flat);
     RtLowering lw{n, m, qcx::rt_reg_bits(dtype), dtype, P, flat.data(), int(flat.size())};
     lw.run(a);
+    if (lw.too_wide) a.lds_tab_bytes = ~0u;   // not expressible: the caller takes the LDS engine
     const size_t ob = lw.out.size() * sizeof(qcx::RtOp);
     tab_off = ob;
     buf.resize(ob + lw.lblob.size() + lw.gblob.size());
@@ -1918,7 +1919,11 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         hipError_t e;
         qcx::RtArgs ra{};
         size_t tab_off = 0;
-        const bool rt = g_knob_tile_engine.load() == 1 && m >= qcx::rt_reg_bits(s.dtype);
+        // register tiles pay off when there are tiles enough for every CU;
+        // a few tiles (small registers) are latency-bound per op, where the
+        // LDS-resident engine's cheaper ops win
+        const bool rt = g_knob_tile_engine.load() == 1 && m >= qcx::rt_reg_bits(s.dtype) &&
+                        n - m >= kRtMinTileBits;
         if (rt) rt_program(n, m, s.dtype, r.P, ops, ra, rbuf, tab_off);
         if (rt && ra.lds_tab_bytes <= kRtLdsTabMax) {
             if ((rc = stage(c, rbuf.data(), rbuf.size(), hs, &dev))) return rc;

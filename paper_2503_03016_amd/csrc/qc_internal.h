@@ -196,6 +196,7 @@ constexpr int kRtMaxE = 1 << kRtMaxRB;
 constexpr int kRtMaxTB = 9;                  // at most 512 threads per tile
 constexpr int kRtTerms = 16;                 // terms of an RT_SIGN / RT_TERMS op
 constexpr int kRtFanHi = 24;                 // out-of-tile controls of an RT_FAN op
+constexpr int kRtWindows = 8;                // 3-bit out-of-tile windows of an op's tables
 // An op's code is rt_code(kind, sub): sub is the register slot for the
 // kinds that act on one (kRtThreadSlot: a thread slot, whose thread bit is
 // a), 1 for a conditioned RT_U2, else 0.
@@ -216,24 +217,24 @@ enum RtKind {
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
-// Lookup tables.  A program comes with a table blob: its first
-// RtArgs::lds_tab_bytes bytes are copied to LDS once per workgroup (tables
-// indexed by the lane number), the rest is read from memory with uniform
-// addresses (tables indexed by the wavefront number or by a window of the
-// tile's out-of-tile index bits).  Offsets are bytes from the start of the
-// blob; a window table j is indexed by (tile_base >> hw[j]) & 63.
+// Lookup tables.  Tables indexed by the lane number sit in the program's
+// table blob, which is copied to LDS once per workgroup (byte offset w[0]);
+// tables indexed by the wavefront number (8 entries) or by a window of 3
+// out-of-tile index bits (8 entries, window j at bit hw[j] of the tile
+// base, b windows) are stored in the op itself and read with uniform loads.
 // RT_SIGN / RT_TERMS: the set L of terms whose thread and tile conditions
-// hold is L_lane[lane] & L_wave[wave] & (AND over the b windows of
-// L_win_j[...]), uint32 bit masks: lane table at w[0], wave table at w[1],
-// window tables at w[2 + j].  Term k then applies to element e when bit k
-// of w[32 + e] is set (its condition on the element index).
-// RT_FAN (a = target slot; for a register target the factors apply to the
-// elements with the target bit set, for a thread target to every element
-// of the threads with it set): element e is multiplied by u[2e] + i u[2e+1]
-// (the target-only phase and the register-slot controls) and by the
-// product F_lane[lane] F_wave[wave] prod_j F_win_j[...] of the phases of
-// the controls on thread bits and out-of-tile bits (complex tables in the
-// state's precision at the same offsets as above).
+// hold is L_lane[lane] & w[8 + wave] & (AND over the windows of
+// wt[8j + window value]) (uint32 bit masks); term k then applies to
+// element e when bit k of w[32 + e] is set (its condition on the element
+// index).
+// RT_FAN (sub = target slot; for a register target the factors apply to
+// the elements with the target bit set, for a thread target to every
+// element of the threads with it set): element e is multiplied by
+// u[2e] + i u[2e+1] (the target-only phase and the register-slot controls)
+// and by the product of the phases of the controls on thread bits and
+// out-of-tile bits: F_lane[lane] (complex lane table), ph entry wave
+// (complex index) and ph entry 8 + 8j + window value for every window j
+// (values in the state's precision).
 // RT_REMAP: the thread part of an element's LDS slot is swz(sum of bit k of
 // t << w[32 + k]) before, swz(sum of bit k of t << w[48 + k]) after; the
 // element part is w[16 + e] before and w[e] after (both swizzled tile
@@ -248,7 +249,8 @@ struct RtOp {
     double u[32];
     uint32_t w[64];
     uint64_t hw[2 * kRtFanHi];
-    double ph[32 + 2 * kRtFanHi];
+    double ph[2 * (8 + 8 * kRtWindows)];   // RT_FAN: wave table, then the window tables
+    uint32_t wt[8 * kRtWindows];            // RT_SIGN / RT_TERMS window tables
 };
 // entry i of the op's u (or ph) array in precision R: float programs pack
 // their values into the first half of the double array's bytes
@@ -283,7 +285,6 @@ struct RtArgs {
     uint32_t st_reg[kRtMaxRB];   // ... and when storing
     uint32_t lds_tab_bytes;      // leading bytes of the table blob that go to LDS
 };
-constexpr int kRtWindows = 8;    // out-of-tile windows of a table-driven op
 
 // One Pauli term of a tile pass of the expectation: X bits xc and Z bits zc
 // inside the tile (compressed positions), Z bits z_hi outside it (global

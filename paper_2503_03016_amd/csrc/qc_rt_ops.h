@@ -167,13 +167,12 @@ struct Tabs {
 
 // bit set L of the terms whose thread and tile conditions hold
 __device__ __forceinline__ uint32_t terms_live(const RtOp &op, const Tabs &tb, uint64_t base) {
-    uint32_t L = reinterpret_cast<const uint32_t *>(tb.ltab + op.w[0])[tb.lane];
-    L &= reinterpret_cast<const uint32_t *>(tb.gtab + op.w[1])[tb.wave];
+    uint32_t L = reinterpret_cast<const uint32_t *>(tb.ltab + op.w[0])[tb.lane] & op.w[8 + tb.wave];
     const int nw = op.b;
 #pragma unroll
     for (int j = 0; j < kRtWindows; ++j)
         if (j < nw)   // uniform
-            L &= reinterpret_cast<const uint32_t *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63];
+            L &= op.wt[8 * j + ((base >> op.hw[j]) & 7)];
     return L;
 }
 
@@ -219,12 +218,12 @@ __device__ __forceinline__ void terms(cx<R> *v, const RtOp &op, const Tabs &tb, 
 // tile's out-of-tile bits (uniform) and its lane entry
 template <typename R>
 __device__ __forceinline__ cx<R> fan_factor(const RtOp &op, const Tabs &tb, uint64_t base) {
-    cx<R> k = reinterpret_cast<const cx<R> *>(tb.gtab + op.w[1])[tb.wave];
+    cx<R> k = ldu<R>(op.ph, int(tb.wave));
     const int nw = op.b;
 #pragma unroll
     for (int j = 0; j < kRtWindows; ++j)
         if (j < nw)   // uniform
-            k = cmul(k, reinterpret_cast<const cx<R> *>(tb.gtab + op.w[2 + j])[(base >> op.hw[j]) & 63]);
+            k = cmul(k, ldu<R>(op.ph, 8 + 8 * j + int((base >> op.hw[j]) & 7)));
     return cmul(k, reinterpret_cast<const cx<R> *>(tb.ltab + op.w[0])[tb.lane]);
 }
 

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
 // tile straight into registers (its offsets under the load layout), the op
 // program runs on the registers (LDS only for RT_REMAP), and the elements
 // are stored under the final layout.
-template <typename R, int RB>
+template <typename R, int RB, bool PF>
 __global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
                                                       const RtOp *__restrict__ ops,
@@ -68,10 +68,29 @@ void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
         thr_ld |= bit << a.ld_thr[k];
         thr_st |= bit << a.st_thr[k];
     }
-    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    // PF: the next tile's loads are issued before the current tile's ops run
+    // (a second register set; the ops issue no vector memory instructions,
+    // so nothing waits for those loads before the next tile starts)
+    cx<R> nx[E];
+    uint64_t t = blockIdx.x;
+    if (PF && act && t < a.n_tiles) {
+        const cx<R> *src = amp + insert_zeros(t, a.pos, a.m) + thr_ld;
+#pragma unroll
+        for (int e = 0; e < E; ++e) nx[e] = src[rt::reg_offset<RB>(e, a.ld_reg)];
+    }
+    for (; t < a.n_tiles; t += gridDim.x) {
         const uint64_t base = insert_zeros(t, a.pos, a.m);
         cx<R> v[E];
-        if (act) {
+        if (PF) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = nx[e];
+            const uint64_t t2 = t + gridDim.x;
+            if (act && t2 < a.n_tiles) {
+                const cx<R> *src = amp + insert_zeros(t2, a.pos, a.m) + thr_ld;
+#pragma unroll
+                for (int e = 0; e < E; ++e) nx[e] = src[rt::reg_offset<RB>(e, a.ld_reg)];
+            }
+        } else if (act) {
             const cx<R> *src = amp + base + thr_ld;
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = src[rt::reg_offset<RB>(e, a.ld_reg)];
@@ -105,10 +124,10 @@ hipError_t launch_rt_run(void *amp, int dtype, const RtArgs &a, const RtOp *ops_
     const unsigned threads = 1u << (a.tb < 6 ? 6 : a.tb);
     const int tok = timer_begin(dtype == QC_C64 ? "rt_run_c64" : "rt_run_c128", s);
     if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_rt_run<float, 4>), dim3(unsigned(grid)), dim3(threads), lds, s,
+        hipLaunchKernelGGL((k_rt_run<float, 4, true>), dim3(unsigned(grid)), dim3(threads), lds, s,
                            static_cast<cx<float> *>(amp), a, ops_dev, tabs_dev);
     else
-        hipLaunchKernelGGL((k_rt_run<double, 3>), dim3(unsigned(grid)), dim3(threads), lds, s,
+        hipLaunchKernelGGL((k_rt_run<double, 3, false>), dim3(unsigned(grid)), dim3(threads), lds, s,
                            static_cast<cx<double> *>(amp), a, ops_dev, tabs_dev);
     timer_end(tok, s);
     return hipGetLastError();
