@@ -250,6 +250,20 @@ int qc_apply_circuit(qc_state_t s, int n_gates, const qc_gate_t *gates, int mode
 int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k,
                  int *block_of, int *n_blocks);
 
+/* The FP64 matrices the fuser builds for one multiplexed block (host only:
+ * no device work).  A run of gates on k qubits is one 2^k x 2^k unitary,
+ * the product of the gates' register operators in circuit order (section
+ * 3.2, the Kronecker extension P_c (x) U + (I - P_c) (x) I of each gate);
+ * with n_sel selector qubits the product splits into one such matrix per
+ * selector value v (sel_qubits[0] = most significant bit of v).  Every gate
+ * target must be one of `qubits`, or a selector qubit if the gate's matrix
+ * is diagonal; every control one of the k + n_sel labels (QC_ERR_QUBIT
+ * otherwise).  out receives 2^n_sel matrices of 2^k x 2^k, row-major,
+ * interleaved FP64 (matrix v at out + v * 2 * 4^k), in the layout
+ * qc_apply_multiplexed takes.  Limits as for qc_apply_multiplexed. */
+int qc_block_matrices(int n_gates, const qc_gate_t *gates, int k, const int *qubits, int n_sel,
+                      const int *sel_qubits, double *out);
+
 /* ---- measurement and reductions (section 3.3 "Measurement") --------- */
 
 /* Marginal outcome distribution over the m listed qubits:

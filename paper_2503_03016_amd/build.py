@@ -28,7 +28,8 @@ FLAGS = [
 # run-time value and move it to scratch memory, so common-code sinking is off.
 EXTRA_FLAGS = {"qc_fused_mfma.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
                "qc_fused_mfma_c128.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
-               "qc_tile.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
+               "qc_tile.hip": ["-mllvm", "-simplifycfg-sink-common=false"],
+               "qc_adjoint.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
 
 
 def build(verbose: bool = False) -> str:

@@ -13,6 +13,7 @@
 // to both tiles.  A run of G gates costs 4 state-sizes of HBM traffic in
 // total instead of 4 per gate.  Partials are kept per (rotation,
 // workgroup) and summed in a fixed order afterwards.
+#include "qc_rt_ops.h"
 #include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
@@ -294,6 +295,68 @@ void k_adjoint_tiles(cx<R> *phi, cx<R> *lam, const TileArgs a,
         partial[size_t(slot_row[s]) * cols + blockIdx.x] = acc[s];
 }
 
+// Backward pass on register tiles: a tile of phi and the matching tile of
+// lam live in registers under one layout; gradient ops take their partial
+// before applying the inverse rotation to both, every other op is applied
+// to each vector in turn (exchanges through LDS one vector at a time).
+// Partials: one column per wavefront in LDS, folded in wavefront order at
+// the end, one value per (gradient slot, workgroup).
+template <typename R, int RB>
+__global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_rt_adjoint(cx<R> *__restrict__ phi, cx<R> *__restrict__ lam, const RtArgs a,
+                  const RtOp *__restrict__ ops, const unsigned char *__restrict__ tabs,
+                  const int32_t *slot_row, int n_slots, double *partial, int cols) {
+    constexpr int E = 1 << RB;
+    extern __shared__ unsigned char smem[];
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    const size_t xbytes = (size_t(1) << a.m) * sizeof(cx<R>);
+    double *gacc = reinterpret_cast<double *>(smem + xbytes);              // [slot][wave]
+    unsigned char *ltab = smem + xbytes + size_t(kRtAdjSlots) * 8 * sizeof(double);
+    const uint32_t tid = threadIdx.x;
+    const bool act = tid < (1u << a.tb);
+    for (uint32_t i = tid; i < uint32_t(n_slots) * 8; i += blockDim.x) gacc[i] = 0.0;
+    for (uint32_t i = tid; i < a.lds_tab_bytes / 16; i += blockDim.x)
+        reinterpret_cast<uint4 *>(ltab)[i] = reinterpret_cast<const uint4 *>(tabs)[i];
+    __syncthreads();
+    const rt::Tabs tb{ltab, tabs, tid & 63u,
+                      uint32_t(__builtin_amdgcn_readfirstlane(int(tid >> 6)))};
+    uint64_t thr_ld = 0, thr_st = 0;
+    for (int k = 0; k < a.tb; ++k) {
+        const uint64_t bit = (tid >> k) & 1u;
+        thr_ld |= bit << a.ld_thr[k];
+        thr_st |= bit << a.st_thr[k];
+    }
+    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const uint64_t base = insert_zeros(t, a.pos, a.m);
+        cx<R> vp[E], vl[E];
+        if (act) {
+            const cx<R> *sp = phi + base + thr_ld, *sl = lam + base + thr_ld;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint64_t off = rt::reg_offset<RB>(e, a.ld_reg);
+                vp[e] = sp[off];
+                vl[e] = sl[off];
+            }
+        }
+        rt::run_ops2<R, RB>(vp, vl, lds, gacc, base, tid, act, ops, a.n_ops, tb);
+        if (act) {
+            cx<R> *dp = phi + base + thr_st, *dl = lam + base + thr_st;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint64_t off = rt::reg_offset<RB>(e, a.st_reg);
+                dp[off] = vp[e];
+                dl[off] = vl[e];
+            }
+        }
+    }
+    __syncthreads();
+    for (int sl = int(tid); sl < n_slots; sl += int(blockDim.x)) {
+        double v = 0.0;
+        for (int w = 0; w < 8; ++w) v += gacc[sl * 8 + w];
+        partial[size_t(slot_row[sl]) * cols + blockIdx.x] = v;
+    }
+}
+
 // g_op[i] = sum of row i of the partials (fixed order), then
 // grad[p] = sum over the rotations of parameter p (CSR, op order).
 __global__ __launch_bounds__(kBlock) void k_grad_rows(const double *partial, int cols,
@@ -366,6 +429,31 @@ hipError_t launch_adjoint_tiles(void *phi, void *lam, int dtype, const TileArgs 
         hipLaunchKernelGGL((k_adjoint_tiles<double>), dim3(cols), dim3(kBlock), lds, s,
                            static_cast<cx<double> *>(phi), static_cast<cx<double> *>(lam), a,
                            ops_dev, slot_row_dev, n_slots, partial, int(cols));
+    timer_end(tok, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_rt_adjoint(void *phi, void *lam, int dtype, const RtArgs &a, const RtOp *ops_dev,
+                             const unsigned char *tabs_dev, const int32_t *slot_row_dev,
+                             int n_slots, double *partial, unsigned cols, hipStream_t s) {
+    const int rb = rt_adj_reg_bits(dtype);
+    if (n_slots < 0 || n_slots > kRtAdjSlots || a.m < rb || a.m > rb + kRtMaxTB ||
+        a.tb != a.m - rb || a.lds_tab_bytes % 16)
+        return hipErrorInvalidValue;
+    const size_t elem = dtype == QC_C64 ? 8 : 16;
+    const size_t lds = (size_t(1) << a.m) * elem + size_t(kRtAdjSlots) * 8 * sizeof(double) +
+                       a.lds_tab_bytes;
+    if (lds > 80 * 1024) return hipErrorInvalidValue;
+    const unsigned threads = 1u << (a.tb < 6 ? 6 : a.tb);
+    const int tok = timer_begin(dtype == QC_C64 ? "rt_adjoint_c64" : "rt_adjoint_c128", s);
+    if (dtype == QC_C64)
+        hipLaunchKernelGGL((k_rt_adjoint<float, 3>), dim3(cols), dim3(threads), lds, s,
+                           static_cast<cx<float> *>(phi), static_cast<cx<float> *>(lam), a, ops_dev,
+                           tabs_dev, slot_row_dev, n_slots, partial, int(cols));
+    else
+        hipLaunchKernelGGL((k_rt_adjoint<double, 2>), dim3(cols), dim3(threads), lds, s,
+                           static_cast<cx<double> *>(phi), static_cast<cx<double> *>(lam), a,
+                           ops_dev, tabs_dev, slot_row_dev, n_slots, partial, int(cols));
     timer_end(tok, s);
     return hipGetLastError();
 }

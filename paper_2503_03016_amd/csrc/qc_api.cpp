@@ -1392,6 +1392,7 @@ struct RtLowering {
     // table blob: lane tables (copied to LDS) and wave / window tables
     std::vector<unsigned char> lblob, gblob;
     bool too_wide = false;        // an op needs more out-of-tile windows than kRtWindows
+    bool adjoint = false;         // backward program: gradient ops, no deferred scale
 
     static uint32_t add_tab(std::vector<unsigned char> &b, const void *p, size_t bytes) {
         while (b.size() % 16) b.push_back(0);
@@ -1459,6 +1460,11 @@ struct RtLowering {
             for (int k = 0; k < op.b0; ++k) b |= 1u << op.x_t[k];
             return b;
         }
+        case qcx::TILE_GRAD:
+        case qcx::TILE_GRAD_APPLY:
+        case qcx::TILE_GRAD_APPLY_REAL:
+        case qcx::TILE_GRAD_APPLY_DIAG:
+        case qcx::TILE_GRAD_APPLY2_DIAG_REAL: return 1u << op.b0;
         default: return 0;   // diagonal ops: any slot
         }
     }
@@ -1584,7 +1590,7 @@ struct RtLowering {
         r.hv = hv;
         split(cm, cv, r.tm, r.tv, r.rm, r.rv);
         const bool uncond = cm == 0 && hm == 0;
-        if (uncond && is_hadamard(u)) {
+        if (uncond && !adjoint && is_hadamard(u)) {   // gradients need the true scale
             r.kind = qcx::rt_code(qcx::RT_H, r.a);
             scale *= 0.70710678118654752440;
             out.push_back(r);
@@ -1740,6 +1746,33 @@ struct RtLowering {
         } break;
         case qcx::TILE_PHASES: phases_of(op, op.b0); break;
         case qcx::TILE_FAN: fan(op); break;
+        case qcx::TILE_GRAD:
+        case qcx::TILE_GRAD_APPLY:
+        case qcx::TILE_GRAD_APPLY_REAL:
+        case qcx::TILE_GRAD_APPLY_DIAG: {
+            qcx::RtOp r{};
+            const int sl = L.slot_of[op.b0];
+            const int kind = op.kind == qcx::TILE_GRAD ? qcx::RT_GRAD0
+                             : op.kind == qcx::TILE_GRAD_APPLY ? qcx::RT_GRAD
+                             : op.kind == qcx::TILE_GRAD_APPLY_REAL ? qcx::RT_GRADR : qcx::RT_GRADD;
+            r.kind = qcx::rt_code(kind, sl);
+            r.b = op.b1;
+            r.w[0] = uint32_t(op.pad);
+            for (int k = 0; k < 8; ++k) put(r.u, k, op.u[k]);
+            out.push_back(r);
+        } break;
+        case qcx::TILE_GRAD_APPLY2_DIAG_REAL: {
+            qcx::RtOp r{};
+            r.kind = qcx::rt_code(qcx::RT_GRAD2, L.slot_of[op.b0]);
+            r.b = op.b1;
+            r.w[0] = uint32_t(op.pad) & 0xffffu;
+            r.w[1] = uint32_t(op.pad) >> 16;
+            for (int k = 0; k < 8; ++k) {
+                put(r.u, k, op.u[k]);
+                put(r.ph, k, op.u1[k]);
+            }
+            out.push_back(r);
+        } break;
         case qcx::TILE_XPERM:
             for (int k = 0; k < op.b0; ++k) {
                 qcx::RtOp r{};
@@ -1879,12 +1912,16 @@ void rt_expand(const std::vector<qcx::TileOp> &in, std::vector<qcx::TileOp> &out
 }
 
 // RT program of one tile run (m tile bits P, TileOp list ops), as one
-// host buffer: the RtOps, then the table blob (lane tables first)
+// host buffer: the RtOps, then the table blob (lane tables first).
+// adjoint: a backward program for the two-vector kernel.
 void rt_program(int n, int m, int dtype, uint64_t P, const std::vector<qcx::TileOp> &ops,
-                qcx::RtArgs &a, std::vector<unsigned char> &buf, size_t &tab_off) {
+                qcx::RtArgs &a, std::vector<unsigned char> &buf, size_t &tab_off,
+                bool adjoint = false) {
     std::vector<qcx::TileOp> flat;
     rt_expand(ops, flat);
-    RtLowering lw{n, m, qcx::rt_reg_bits(dtype), dtype, P, flat.data(), int(flat.size())};
+    const int rb = adjoint ? qcx::rt_adj_reg_bits(dtype) : qcx::rt_reg_bits(dtype);
+    RtLowering lw{n, m, rb, dtype, P, flat.data(), int(flat.size())};
+    lw.adjoint = adjoint;
     lw.run(a);
     if (lw.too_wide) a.lds_tab_bytes = ~0u;   // not expressible: the caller takes the LDS engine
     const size_t ob = lw.out.size() * sizeof(qcx::RtOp);
@@ -2062,6 +2099,42 @@ int qc_fuse_plan(int n, int n_gates, const qc_gate_t *gates, int fuse_k, int *bl
     fuse_plan(n, n_gates, gates, fuse_k, qcx::kMaxSel, g_knob_look.load(), bo, nb);
     std::copy(bo.begin(), bo.end(), block_of);
     *n_blocks = nb;
+    return QC_OK;
+}
+
+int qc_block_matrices(int n_gates, const qc_gate_t *gates, int k, const int *qubits, int n_sel,
+                      const int *sel_qubits, double *out) {
+    if (k < 1 || k > QC_MAX_FUSED) return fail(QC_ERR_ARG, "k out of range");
+    if (n_sel < 0 || n_sel > QC_MAX_SEL) return fail(QC_ERR_ARG, "selector count out of range");
+    if (!qubits || (n_sel > 0 && !sel_qubits) || !out || (n_gates > 0 && !gates) || n_gates < 0)
+        return fail(QC_ERR_ARG, "NULL argument");
+    int all[QC_MAX_FUSED + QC_MAX_SEL];
+    for (int j = 0; j < k; ++j) all[j] = qubits[j];
+    for (int j = 0; j < n_sel; ++j) all[k + j] = sel_qubits[j];
+    int rc = check_qubits(QC_MAX_QUBITS, all, k + n_sel, "block qubit");
+    if (rc) return rc;
+    std::vector<const qc_gate_t *> gs(static_cast<size_t>(n_gates));
+    for (int i = 0; i < n_gates; ++i) {
+        const qc_gate_t &g = gates[i];
+        if ((rc = check_gate(QC_MAX_QUBITS, g))) return rc;
+        auto in = [&](int q, int lo, int hi) {
+            for (int j = lo; j < hi; ++j)
+                if (all[j] == q) return true;
+            return false;
+        };
+        const bool diag = matrix_is_diagonal(g.matrix, g.n_targets);
+        for (int j = 0; j < g.n_targets; ++j)
+            if (!in(g.targets[j], 0, k) && !(diag && in(g.targets[j], k, k + n_sel)))
+                return fail(QC_ERR_QUBIT, "gate target outside the block (or non-diagonal on a selector)");
+        for (int j = 0; j < g.n_ctrls; ++j)
+            if (!in(g.ctrls[j], 0, k + n_sel)) return fail(QC_ERR_QUBIT, "gate control outside the block");
+        gs[size_t(i)] = &g;
+    }
+    const std::vector<cd> m = block_matrices(k, qubits, n_sel, sel_qubits, gs);
+    for (size_t i = 0; i < m.size(); ++i) {
+        out[2 * i] = m[i].real();
+        out[2 * i + 1] = m[i].imag();
+    }
     return QC_OK;
 }
 
@@ -2704,9 +2777,32 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
     form_runs(n, mb, n_ops, bwd.data(), extra.data(), runs);
     std::vector<qcx::TileOp> tops;
     std::vector<int32_t> slot_row;
+    const bool rt = g_knob_tile_engine.load() == 1 && mb == qcx::rt_adj_reg_bits(psi.dtype) + 9 &&
+                    n - mb >= kRtMinTileBits;
+    const int max_slots = rt ? qcx::kRtAdjSlots : qcx::kAdjointMaxSlots;
+    std::vector<unsigned char> rbuf;
     auto flush = [&](uint64_t P) -> int {
         if (tops.empty()) return QC_OK;
         merge_grad_pairs(tops);
+        if (rt) {   // register tiles: both vectors in registers
+            qcx::RtArgs ra{};
+            size_t tab_off = 0;
+            rt_program(n, mb, psi.dtype, P, tops, ra, rbuf, tab_off, true);
+            if (ra.lds_tab_bytes <= kRtLdsTabMax) {
+                void *pdev = nullptr, *sdev = nullptr;
+                int r2 = stage(c, rbuf.data(), rbuf.size(), hs, &pdev);
+                if (!r2 && !slot_row.empty())
+                    r2 = stage(c, slot_row.data(), slot_row.size() * sizeof(int32_t), hs, &sdev);
+                if (r2) return r2;
+                hipError_t e2 = qcx::launch_rt_adjoint(
+                    psi.amp, lam.amp, psi.dtype, ra, static_cast<const qcx::RtOp *>(pdev),
+                    static_cast<const unsigned char *>(pdev) + tab_off,
+                    static_cast<const int32_t *>(sdev), int(slot_row.size()), partial, cols, hs);
+                tops.clear();
+                slot_row.clear();
+                return e2 == hipSuccess ? QC_OK : hip_fail(e2, "rt_adjoint");
+            }
+        }
         const qcx::TileArgs a = tile_args(n, mb, P, int(tops.size()));
         void *odev = nullptr, *sdev = nullptr;
         int r2 = stage(c, tops.data(), tops.size() * sizeof(qcx::TileOp), hs, &odev);
@@ -2729,7 +2825,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         B.xperms = false;   // nor with the X permutations
         for (int j : r.gates) {
             if (rot_row[j] >= 0) {
-                if (int(slot_row.size()) == qcx::kAdjointMaxSlots) {
+                if (int(slot_row.size()) == max_slots) {
                     B.finish();
                     if ((rc = flush(r.P))) return rc;
                 }

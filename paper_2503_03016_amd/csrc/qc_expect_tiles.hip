@@ -51,6 +51,44 @@ __host__ __device__ inline size_t diag_region(int T, size_t elem) {
 }
 static_assert(kWaves == 8, "frequency bits 6..8 are the wavefront index");
 
+constexpr int kXReg = 12;   // terms per launch whose partial sums stay in registers
+
+// This thread's share of <psi|P|psi> over the tile in LDS for term tm
+// (without the sign of its Z bits outside the tile).  Diagonal terms take
+// the per-thread Walsh sums W (see below) instead.
+template <typename R>
+__device__ inline double term_pairs(const cx<R> *lds, const ExpectTerm &tm, int half) {
+    double acc = 0.0;
+    const uint32_t hb = tm.xtop;
+    if (tm.zc == 0 && tm.ph == 0) {   // uniform: X factors only, both signs +1
+        for (int g = threadIdx.x; g < half; g += kBlock) {
+            const uint32_t i = ((uint32_t(g) >> hb) << (hb + 1)) | (uint32_t(g) & ((1u << hb) - 1));
+            const uint32_t ix = i ^ tm.xc;
+            const double ar = double(lds[i].re), ai = double(lds[i].im);
+            const double br = double(lds[ix].re), bi = double(lds[ix].im);
+            acc += br * ar + bi * ai;
+        }
+        return 2.0 * acc;
+    }
+    for (int g = threadIdx.x; g < half; g += kBlock) {
+        const uint32_t i = ((uint32_t(g) >> hb) << (hb + 1)) | (uint32_t(g) & ((1u << hb) - 1));
+        const uint32_t ix = i ^ tm.xc;
+        const double ar = double(lds[i].re), ai = double(lds[i].im);
+        const double br = double(lds[ix].re), bi = double(lds[ix].im);
+        const double c1 = br * ar + bi * ai;
+        const double c2 = br * ai - bi * ar;
+        const double si = (__popc(i & tm.zc) & 1) ? -1.0 : 1.0;
+        const double sx = (__popc(ix & tm.zc) & 1) ? -1.0 : 1.0;
+        switch (tm.ph) {
+        case 0: acc += (si + sx) * c1; break;
+        case 1: acc -= (si - sx) * c2; break;
+        case 2: acc -= (si + sx) * c1; break;
+        default: acc += (si - sx) * c2; break;
+        }
+    }
+    return acc;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const TileArgs a,
                                                          const ExpectTerm *terms, int nt,
@@ -67,6 +105,9 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
     int nd = 0;
     while (nd < nt && nd < kBlock && terms[nd].xc == 0) ++nd;
     double dacc = 0.0;
+    double xacc[kXReg];
+#pragma unroll
+    for (int j = 0; j < kXReg; ++j) xacc[j] = 0.0;
     const uint64_t off_lo =
         tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
     const uint64_t mask = tile::hi_mask(a.pos, a.m);
@@ -94,7 +135,29 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
                     W[k] = u + v;
                     W[k | h] = u - v;
                 }
-        for (int k = nd; k < nt; ++k) {
+        // the first kXReg terms after the leading diagonal ones keep their
+        // per-thread sums in registers across tiles (one reduction per
+        // launch); further terms are reduced per tile
+#pragma unroll
+        for (int j = 0; j < kXReg; ++j) {
+            const int k = nd + j;
+            if (k >= nt) break;   // uniform
+            const ExpectTerm tm = terms[k];
+            double v;
+            if (tm.xc == 0) {   // a diagonal term after an X term: its Walsh sum
+                const uint32_t zk = tm.zc >> tile::kLoBits;   // uniform, < K
+                double w = W[0];
+#pragma unroll
+                for (int h = 1; h < kMaxK; ++h)
+                    if (zk == uint32_t(h)) w = W[h];
+                v = (__popc(threadIdx.x & tm.zc) & 1) ? -w : w;
+            } else {
+                v = term_pairs<R>(lds, tm, half);
+            }
+            // the Z bits outside the tile give every amplitude of it one sign
+            xacc[j] += (__popcll(base & terms[k].z_hi) & 1) ? -v : v;
+        }
+        for (int k = nd + kXReg; k < nt; ++k) {
             const ExpectTerm tm = terms[k];
             double acc = 0.0;
             if (tm.xc == 0) {
@@ -172,6 +235,13 @@ __global__ __launch_bounds__(kBlock) void k_expect_tiles(const cx<R> *amp, const
             }
         }
         __syncthreads();
+    }
+    // the register-held sums: one wavefront reduction per term per launch
+#pragma unroll
+    for (int j = 0; j < kXReg; ++j) {
+        if (nd + j >= nt) break;   // uniform
+        const double v = wave_sum(xacc[j]);
+        if (lane == 0) wacc[(nd + j) * kWaves + wave] += v;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nt; k += kBlock) {

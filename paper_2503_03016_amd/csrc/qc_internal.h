@@ -214,6 +214,18 @@ enum RtKind {
     RT_CX = 10,     // X on register slot sub (swap of the pair) where the conditions hold
     RT_REMAP = 11,  // new layout through LDS
     RT_SCALE = 12,  // x u[0] (real) everywhere
+    // adjoint backward only (two vectors phi, lam in registers): the
+    // partial Im <lam|G|phi> of generator G (b: 1 = X, 2 = Y, 3 = Z) on
+    // register slot sub, added to gradient slot w[0], taken before the
+    // one-qubit matrix u is applied to both vectors: RT_GRAD0 applies none,
+    // RT_GRAD a general one, RT_GRADR a real one, RT_GRADD a diagonal one
+    RT_GRAD0 = 13,
+    RT_GRAD = 14,
+    RT_GRADR = 15,
+    RT_GRADD = 16,
+    // an RT_GRADD step and an RT_GRADR step on the same slot: generator
+    // b & 15, slot w[0], matrix u; then generator b >> 4, slot w[1], matrix ph
+    RT_GRAD2 = 17,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
@@ -408,6 +420,14 @@ static_assert(kAdjointMaxSlots <= 65536, "TILE_GRAD_APPLY2 packs two slots in 16
 unsigned adjoint_tile_grid(uint64_t n_tiles);
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
                               const PauliTermDev *terms, int nt, hipStream_t s);
+// backward pass on register tiles: both vectors; partial[row][col] as for
+// launch_adjoint_tiles (slot_row maps the program's gradient slots to rows)
+hipError_t launch_rt_adjoint(void *phi, void *lam, int dtype, const RtArgs &a, const RtOp *ops_dev,
+                             const unsigned char *tabs_dev, const int32_t *slot_row_dev,
+                             int n_slots, double *partial, unsigned cols, hipStream_t s);
+constexpr int kRtAdjSlots = 256;   // gradient slots of one register-tile backward launch
+// register bits of the backward kernel (two vectors share the registers)
+constexpr int rt_adj_reg_bits(int dtype) { return dtype == 1 ? 3 : 2; }
 hipError_t launch_adjoint_tiles(void *phi, void *lam, int dtype, const TileArgs &a,
                                 const TileOp *ops_dev, const int32_t *slot_row_dev, int n_slots,
                                 double *partial, unsigned cols, hipStream_t s);

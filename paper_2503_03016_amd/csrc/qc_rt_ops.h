@@ -338,6 +338,145 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
         }
     }
 }
+
+// ---- adjoint backward: the same ops on two vectors, plus gradient steps
+
+#define QC_RT_SLOT_CASES2(KIND, STMT)                                   \
+    case rt_code(KIND, 0): { constexpr int S = 0; { cx<R> *V = vp; STMT; } { cx<R> *V = vl; STMT; } } break; \
+    case rt_code(KIND, 1): if constexpr (RB > 1) { constexpr int S = 1; { cx<R> *V = vp; STMT; } { cx<R> *V = vl; STMT; } } break; \
+    case rt_code(KIND, 2): if constexpr (RB > 2) { constexpr int S = 2; { cx<R> *V = vp; STMT; } { cx<R> *V = vl; STMT; } } break; \
+    case rt_code(KIND, 3): if constexpr (RB > 3) { constexpr int S = 3; { cx<R> *V = vp; STMT; } { cx<R> *V = vl; STMT; } } break;
+
+// Im <lam|G|phi> over the pair (phi0, phi1), (lam0, lam1) of one register
+// bit for generator G (1 = X, 2 = Y, 3 = Z), in the state's precision
+template <typename R>
+__device__ __forceinline__ R grad_pair_rt(cx<R> f0, cx<R> f1, cx<R> l0, cx<R> l1, int gen) {
+    if (gen == 3) return (l0.re * f0.im - l0.im * f0.re) - (l1.re * f1.im - l1.im * f1.re);
+    if (gen == 1) return (l0.re * f1.im - l0.im * f1.re) + (l1.re * f0.im - l1.im * f0.re);
+    return -(l0.re * f1.re + l0.im * f1.im) + (l1.re * f0.re + l1.im * f0.im);
+}
+
+// the one-qubit matrix (MODE 0 none, 1 general, 2 real, 3 diagonal) on a pair
+template <typename R, int MODE>
+__device__ __forceinline__ void apply_mode(cx<R> &a0, cx<R> &a1, const cx<R> *u) {
+    constexpr int mode = MODE;
+    if (mode == 1) {
+        const cx<R> z{R(0), R(0)};
+        const cx<R> b0 = cfma(u[1], a1, cfma(u[0], a0, z));
+        a1 = cfma(u[3], a1, cfma(u[2], a0, z));
+        a0 = b0;
+    } else if (mode == 2) {
+        const cx<R> b0{u[0].re * a0.re + u[1].re * a1.re, u[0].re * a0.im + u[1].re * a1.im};
+        a1 = cx<R>{u[2].re * a0.re + u[3].re * a1.re, u[2].re * a0.im + u[3].re * a1.im};
+        a0 = b0;
+    } else if (mode == 3) {
+        a0 = cmul(u[0], a0);
+        a1 = cmul(u[3], a1);
+    }
+}
+
+__device__ __forceinline__ double wave_sum_rt(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// add this wavefront's sum of v into its column of gradient slot `slot`
+// (each wavefront owns one column: the additions keep a fixed order)
+__device__ __forceinline__ void grad_add(double *acc, int slot, uint32_t wave, double v) {
+    v = wave_sum_rt(v);
+    if ((threadIdx.x & 63u) == 0) acc[slot * 8 + int(wave)] += v;
+}
+
+// partial of generator gen on slot S, then the matrix on both vectors;
+// FP64 accumulation of the pair terms
+template <typename R, int RB, int S, int MODE>
+__device__ __forceinline__ double grad_slot(cx<R> *vp, cx<R> *vl, int gen, const cx<R> *u) {
+    constexpr int E = 1 << RB;
+    double acc = 0.0;
+#pragma unroll
+    for (int e0 = 0; e0 < E; ++e0) {
+        if (e0 & (1 << S)) continue;
+        const int e1 = e0 | (1 << S);
+        acc += double(grad_pair_rt<R>(vp[e0], vp[e1], vl[e0], vl[e1], gen));
+        apply_mode<R, MODE>(vp[e0], vp[e1], u);
+        apply_mode<R, MODE>(vl[e0], vl[e1], u);
+    }
+    return acc;
+}
+
+// a gradient step of MODE on slot S (two for RT_GRAD2)
+template <typename R, int RB, int S, int MODE>
+__device__ __forceinline__ void grad_op(cx<R> *vp, cx<R> *vl, double *gacc, const RtOp &op, uint32_t wave) {
+    cx<R> u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = ldu<R>(op.u, i);
+    if (MODE == 4) {   // RT_GRAD2: diagonal step, then real step
+        grad_add(gacc, int(op.w[0]), wave, grad_slot<R, RB, S, 3>(vp, vl, op.b & 15, u));
+        cx<R> w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = ldu<R>(op.ph, i);
+        grad_add(gacc, int(op.w[1]), wave, grad_slot<R, RB, S, 2>(vp, vl, op.b >> 4, w));
+    } else {
+        grad_add(gacc, int(op.w[0]), wave, grad_slot<R, RB, S, MODE>(vp, vl, op.b, u));
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, double *gacc, uint64_t base,
+                                uint32_t tid, bool act, const RtOp *__restrict__ ops, int n_ops,
+                                const Tabs &tb) {
+    for (int o = 0; o < n_ops; ++o) {
+        const RtOp &op = ops[o];
+        const int code = op.kind;
+        const bool tc = (tid & op.tm) == op.tv && (base & op.hm) == op.hv;
+        switch (code) {
+            QC_RT_SLOT_CASES(RT_GRAD0, (grad_op<R, RB, S, 0>(vp, vl, gacc, op, tb.wave)))
+            QC_RT_SLOT_CASES(RT_GRAD, (grad_op<R, RB, S, 1>(vp, vl, gacc, op, tb.wave)))
+            QC_RT_SLOT_CASES(RT_GRADR, (grad_op<R, RB, S, 2>(vp, vl, gacc, op, tb.wave)))
+            QC_RT_SLOT_CASES(RT_GRADD, (grad_op<R, RB, S, 3>(vp, vl, gacc, op, tb.wave)))
+            QC_RT_SLOT_CASES(RT_GRAD2, (grad_op<R, RB, S, 4>(vp, vl, gacc, op, tb.wave)))
+            QC_RT_SLOT_CASES2(RT_U1, (u1_slot<R, RB, S, false, false>(V, op, tc)))
+            QC_RT_SLOT_CASES2(RT_U1C, (u1_slot<R, RB, S, false, true>(V, op, tc)))
+            QC_RT_SLOT_CASES2(RT_U1R, (u1_slot<R, RB, S, true, false>(V, op, tc)))
+            QC_RT_SLOT_CASES2(RT_U1RC, (u1_slot<R, RB, S, true, true>(V, op, tc)))
+            QC_RT_SLOT_CASES2(RT_DIAG1, (diag1_slot<R, RB, S>(V, ldu<R>(op.u, 0), ldu<R>(op.u, 1), op.b != 0)))
+            QC_RT_SLOT_CASES2(RT_CX, (xgate_slot<R, RB, S>(V, op.rm, op.rv, tc)))
+        case rt_code(RT_DIAG1, kRtThreadSlot):
+            diag1_thread<R, RB>(vp, op, tid);
+            diag1_thread<R, RB>(vl, op, tid);
+            break;
+        case rt_code(RT_U2, 0):
+            u2<R, RB, false>(vp, op, tc);
+            u2<R, RB, false>(vl, op, tc);
+            break;
+        case rt_code(RT_U2, 1):
+            u2<R, RB, true>(vp, op, tc);
+            u2<R, RB, true>(vl, op, tc);
+            break;
+        case rt_code(RT_SIGN, 0): {
+            const uint32_t L = terms_live(op, tb, base);
+#pragma unroll
+            for (int e = 0; e < (1 << RB); ++e) {
+                const uint32_t odd = uint32_t(__builtin_popcount(L & op.w[32 + e])) & 1u;
+                vp[e] = negate_if(vp[e], odd);
+                vl[e] = negate_if(vl[e], odd);
+            }
+        } break;
+        case rt_code(RT_TERMS, 0):
+            terms<R, RB>(vp, op, tb, base);
+            terms<R, RB>(vl, op, tb, base);
+            break;
+        case rt_code(RT_REMAP, 0):
+            remap<R, RB>(vp, lds, op, tid, act);
+            remap<R, RB>(vl, lds, op, tid, act);
+            break;
+        default: __builtin_unreachable();   // the backward programs hold no other codes
+        }
+    }
+}
+
+#undef QC_RT_SLOT_CASES2
 #undef QC_RT_SLOT_CASES
 
 }  // namespace rt

@@ -28,7 +28,7 @@ EXPORTS = [
     "qc_status_string", "qc_last_error", "qc_version", "qc_state_init", "qc_state_copy",
     "qc_state_diff", "qc_apply_1q", "qc_apply_2q", "qc_apply_controlled", "qc_apply_fused_k",
     "qc_apply_multiplexed", "qc_permute_qubits",
-    "qc_apply_circuit", "qc_fuse_plan", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
+    "qc_apply_circuit", "qc_fuse_plan", "qc_block_matrices", "qc_probs", "qc_expect_pauli", "qc_adjoint_grad",
     "qc_timing_enable", "qc_timing_query", "qc_batch_create", "qc_batch_info", "qc_run_batch",
     "qc_batch_state", "qc_batch_status", "qc_batch_destroy", "qc_collapse", "qc_reduced_state",
     "qc_sample", "qc_set_knob", "qc_get_knob", "qc_autotune", "qc_reset", "qc_counts",
@@ -110,6 +110,7 @@ def _load():
         "qc_permute_qubits": ([S, ip, vp], i),
         "qc_apply_circuit": ([S, i, ctypes.POINTER(QcGate), i, i, ctypes.POINTER(QcStats), vp], i),
         "qc_fuse_plan": ([i, i, ctypes.POINTER(QcGate), i, ip, ip], i),
+        "qc_block_matrices": ([i, ctypes.POINTER(QcGate), i, ip, i, ip, dp], i),
         "qc_probs": ([S, i, ip, vp, vp], i),
         "qc_expect_pauli": ([S, i, ctypes.c_char_p, dp, i, vp, vp], i),
         "qc_adjoint_grad": ([S, S, ctypes.POINTER(QcOp), i, dp, i, i, ctypes.c_char_p, dp, vp,
@@ -306,6 +307,20 @@ def fuse_plan(n: int, gates: GateList, fuse_k: int = 5) -> Tuple[List[int], int]
     _check(lib.qc_fuse_plan(int(n), gates.count, gates.arr, int(fuse_k), block_of,
                             ctypes.byref(nb)), "qc_fuse_plan")
     return list(block_of[:gates.count]), nb.value
+
+
+def block_matrices(gates: GateList, qubits: Sequence[int], sel: Sequence[int] = ()
+                   ) -> np.ndarray:
+    """qc_block_matrices: the fuser's FP64 block matrices of `gates` on the
+    block `qubits` (qubits[0] = MSB) for every value of the selector qubits
+    `sel`; shape (2^len(sel), 2^k, 2^k), complex128.  Host only."""
+    k, ns = len(qubits), len(sel)
+    out = np.zeros(2 * (4 ** k << ns), dtype=np.float64)
+    _check(lib.qc_block_matrices(gates.count, gates.arr, k, _ints(qubits), ns,
+                                 _ints(sel) if ns else None,
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "qc_block_matrices")
+    return out.view(np.complex128).reshape(1 << ns, 1 << k, 1 << k)
 
 
 def probs(psi: torch.Tensor, qubits: Optional[Sequence[int]] = None) -> torch.Tensor:
@@ -546,6 +561,7 @@ qc_apply_multiplexed = apply_multiplexed
 qc_permute_qubits = permute_qubits
 qc_apply_circuit = apply_circuit
 qc_fuse_plan = fuse_plan
+qc_block_matrices = block_matrices
 qc_probs = probs
 qc_expect_pauli = expect_pauli
 qc_adjoint_grad = adjoint_grad

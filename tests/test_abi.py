@@ -321,3 +321,69 @@ def test_gate_list_marshalling_round_trip(qc):
         qc.GateList([((0,), (), (), np.eye(4))])     # 4x4 matrix on one target
     empty = qc.GateList([])
     assert empty.count == 0
+
+
+def _random_block_gates(rng, blk, sel, count):
+    """Gates on the block labels `blk` with controls anywhere in blk + sel
+    and diagonal gates allowed on the selector labels."""
+    from tests.dense_ref import random_unitary
+    every = list(blk) + list(sel)
+    out = []
+    for _ in range(count):
+        kind = rng.integers(4)
+        if kind == 0:   # diagonal gate over block and selector labels
+            nt = int(rng.integers(1, min(3, len(every)) + 1))
+            t = [int(x) for x in rng.choice(every, nt, replace=False)]
+            u = np.diag(np.exp(1j * rng.uniform(-np.pi, np.pi, 1 << nt)))
+        else:
+            nt = int(rng.integers(1, min(3, len(blk)) + 1))
+            t = [int(x) for x in rng.choice(blk, nt, replace=False)]
+            u = random_unitary(1 << nt, rng)
+        rest = [q for q in every if q not in t]
+        nc = int(rng.integers(0, min(2, len(rest)) + 1))
+        c = [int(x) for x in rng.choice(rest, nc, replace=False)] if nc else []
+        cv = [int(x) for x in rng.integers(0, 2, nc)]
+        out.append((t, c, cv, u))
+    return out
+
+
+@pytest.mark.parametrize("k,ns,seed", [(1, 0, 1), (2, 1, 2), (3, 2, 3), (4, 1, 4), (5, 0, 5),
+                                       (5, 2, 6)])
+def test_block_matrices_vs_dense_kronecker(qc, k, ns, seed):
+    """The fuser's FP64 block products (section 3.2: a gate run on k qubits
+    is the product of the gates' Kronecker-extended register operators)
+    against brute-force dense operators: the register is the selector
+    labels (most significant) then the block labels; its operator is block
+    diagonal over the selector value, and block v is the fuser's matrix v."""
+    from tests.dense_ref import dense_gate
+    rng = np.random.default_rng(seed)
+    labels = [int(x) for x in rng.permutation(9)[:k + ns]]
+    blk, sel = labels[:k], labels[k:]
+    gates = _random_block_gates(rng, blk, sel, 12)
+    got = qc.block_matrices(qc.GateList(gates), blk, sel)
+    order = sel + blk   # local qubit 0 = most significant
+    nl = k + ns
+    full = np.eye(1 << nl, dtype=np.complex128)
+    for t, c, cv, u in gates:
+        full = dense_gate(nl, [order.index(q) for q in t], u,
+                          [order.index(q) for q in c], cv) @ full
+    d = 1 << k
+    for v in range(1 << ns):
+        for w in range(1 << ns):
+            blkvw = full[v * d:(v + 1) * d, w * d:(w + 1) * d]
+            if v == w:
+                assert np.max(np.abs(got[v] - blkvw)) <= 1e-14, (v, np.max(np.abs(got[v] - blkvw)))
+            else:
+                assert np.max(np.abs(blkvw)) == 0.0
+
+
+def test_block_matrices_rejects_gates_outside_the_block(qc):
+    from tests.dense_ref import random_unitary
+    rng = np.random.default_rng(0)
+    u = random_unitary(2, rng)
+    with pytest.raises(RuntimeError):   # non-diagonal on a selector label
+        qc.block_matrices(qc.GateList([([3], [], [], u)]), [0, 1], [3])
+    with pytest.raises(RuntimeError):   # control outside every label
+        qc.block_matrices(qc.GateList([([0], [5], [1], u)]), [0, 1], [3])
+    with pytest.raises(RuntimeError):   # repeated label
+        qc.block_matrices(qc.GateList([([0], [], [], u)]), [0, 1], [1])
