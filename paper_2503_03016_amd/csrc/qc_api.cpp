@@ -2336,114 +2336,21 @@ int qc_probs_noalloc(qc_state_t s, int m, const int *qubits, double *out_dev, vo
     return e == hipSuccess ? QC_OK : hip_fail(e, "probs_noalloc");
 }
 
-int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
-                    int per_term, double *out_dev, void *stream) {
-    int rc = check_state(s);
-    if (rc) return rc;
-    if (n_terms < 1 || n_terms > 65536) return fail(QC_ERR_ARG, "term count out of range");
-    if (!paulis || !coeff || !out_dev) return fail(QC_ERR_ARG, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// The terms no tile pass took (X bits spread wider than a tile) with the
+// pair kernel, grouped by x mask; then out[0] = sum_t c_t v_t and
+// out[1 + t] = v_t in the caller's order (where[t] = slot of term t).
+int expect_finish(qc_state_t s, int n_terms, const std::vector<uint64_t> &xm,
+                  const std::vector<uint64_t> &zm, const std::vector<int> &ph, const double *coeff,
+                  int per_term, double *out_dev, DevCtx *c, hipStream_t hs, std::vector<int> &where,
+                  int slot, std::vector<int> &order) {
     const int n = s.n;
-    std::vector<uint64_t> xm(n_terms), zm(n_terms);
-    std::vector<int> ph(n_terms);
-    for (int t = 0; t < n_terms; ++t) {
-        uint64_t x = 0, z = 0;
-        int ny = 0;
-        for (int q = 0; q < n; ++q) {
-            const char ch = paulis[size_t(t) * n + q];
-            const uint64_t b = uint64_t(1) << bitpos(n, q);
-            switch (ch) {
-            case 'I': break;
-            case 'X': x |= b; break;
-            case 'Y': x |= b; z |= b; ++ny; break;
-            case 'Z': z |= b; break;
-            default: return fail(QC_ERR_ARG, "Pauli character not in {I,X,Y,Z}");
-            }
-        }
-        xm[t] = x;
-        zm[t] = z;
-        ph[t] = ny & 3;
-    }
-    DevCtx *c;
-    if ((rc = get_ctx(&c))) return rc;
-    const hipStream_t hs = (hipStream_t)stream;
-    double *vals = c->work;                         // n_terms values
-    double *part = c->work + ((n_terms + 255) & ~255);  // per-block partials
-    // Tile passes: the tile is the kExpectLowBits lowest bits plus up to
-    // m - kExpectLowBits more; a term whose X bits all lie in a pass's tile
-    // bits is evaluated in that pass (the pair j, j ^ x is in one tile), and
-    // every diagonal term rides in the first pass.  Terms that fit no tile
-    // (more X bits above the low ones than a tile has room for) are
-    // evaluated one X mask at a time with the pair kernel.
-    const int m = std::min(n, s.dtype == QC_C64 ? 12 : 11);
-    const int L = std::min(qcx::kExpectLowBits, m);
-    const uint64_t low = (uint64_t(1) << L) - 1;
-    std::vector<int> rest, diag, order;
-    for (int t = 0; t < n_terms; ++t) {
-        if (xm[t] == 0) diag.push_back(t);
-        else if (__builtin_popcountll(xm[t] & ~low) <= m - L) rest.push_back(t);
-        else order.push_back(t);   // pair kernel
-    }
-    struct ExpPass {
-        uint64_t P;
-        std::vector<int> terms;
-    };
-    std::vector<ExpPass> passes;
-    while (!rest.empty()) {
-        uint64_t S = 0;
-        for (int t : rest) {
-            const uint64_t hb = xm[t] & ~low;
-            if (__builtin_popcountll(S | hb) <= m - L) S |= hb;
-        }
-        for (int p = L; __builtin_popcountll(S) < m - L && p < n; ++p) S |= uint64_t(1) << p;
-        ExpPass ps{low | S, {}};
-        std::vector<int> left;
-        for (int t : rest) ((xm[t] & ~ps.P) == 0 ? ps.terms : left).push_back(t);
-        passes.push_back(std::move(ps));
-        rest.swap(left);
-    }
-    if (!diag.empty()) {
-        if (passes.empty()) {
-            uint64_t P = 0;
-            for (int p = 0; p < m; ++p) P |= uint64_t(1) << p;
-            passes.push_back({P, {}});
-        }
-        passes[0].terms.insert(passes[0].terms.begin(), diag.begin(), diag.end());
-    }
-    // term values: tile-pass terms first (pass order), then the pair
-    // kernel's terms grouped by x mask; combine permutes them back
-    std::vector<int> where(n_terms);
-    int slot = 0;
-    for (const ExpPass &ps : passes) {
-        for (size_t k0 = 0; k0 < ps.terms.size(); k0 += qcx::kExpectTileMaxTerms) {
-            const size_t k1 = std::min(ps.terms.size(), k0 + qcx::kExpectTileMaxTerms);
-            std::vector<qcx::ExpectTerm> et(k1 - k0);
-            for (size_t k = k0; k < k1; ++k) {
-                const int t = ps.terms[k];
-                uint32_t xc = 0, zc = 0;
-                for (int p = 0, j = 0; p < n; ++p) {
-                    if (!((ps.P >> p) & 1)) continue;
-                    if ((xm[t] >> p) & 1) xc |= 1u << j;
-                    if ((zm[t] >> p) & 1) zc |= 1u << j;
-                    ++j;
-                }
-                qcx::ExpectTerm &e = et[k - k0];
-                e.z_hi = zm[t] & ~ps.P;
-                e.xc = xc;
-                e.zc = zc;
-                e.ph = ph[t];
-                e.xtop = xc ? 31 - __builtin_clz(xc) : -1;
-                where[t] = slot + int(k - k0);
-            }
-            void *tdev = nullptr;
-            if ((rc = stage(c, et.data(), et.size() * sizeof(qcx::ExpectTerm), hs, &tdev))) return rc;
-            const qcx::TileArgs a = tile_args(n, m, ps.P, 0);
-            hipError_t e = qcx::launch_expect_tiles(s.amp, s.dtype, a,
-                                                    static_cast<const qcx::ExpectTerm *>(tdev),
-                                                    int(k1 - k0), vals + slot, part, hs);
-            if (e != hipSuccess) return hip_fail(e, "expect_tiles");
-            slot += int(k1 - k0);
-        }
-    }
+    int rc;
+    double *vals = c->work;
+    double *part = c->work + ((n_terms + 255) & ~255);
     // pair kernel: group the remaining terms by x mask, preserving first-seen order
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xm[a] < xm[b]; });
     for (size_t i = 0; i < order.size(); ++i) where[order[i]] = slot + int(i);
@@ -2482,6 +2389,286 @@ int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double 
     return QC_OK;
 }
 
+
+
+// Register-tile passes (k_expect_reg): a wavefront tile is 6 lane bits and
+// kExpRegB element bits.  The first pass has the six lowest bits on the
+// lanes (512 contiguous bytes or more per load); later passes keep only the
+// bits of one 128-byte run on the lanes (4 for complex64, 3 for
+// complex128) and put new bits on the other lanes and the elements, so a
+// later pass covers up to 6 - LL + kExpRegB new bits.  A term is evaluated
+// in the first pass whose tile holds its X bits all on the lanes or on one
+// element bit; every diagonal term rides in the first pass.  Terms that
+// fit no pass are appended to `left` (the LDS tile passes take them).
+int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t> &xm,
+                           const std::vector<uint64_t> &zm, const std::vector<int> &ph, DevCtx *c,
+                           hipStream_t hs, double *vals, double *part, std::vector<int> &where,
+                           int &slot, std::vector<int> &left) {
+    constexpr int RB = qcx::kExpRegB;
+    const int n = s.n;
+    const int LL = s.dtype == QC_C64 ? 4 : 3;
+    const uint64_t low6 = 63, lowL = (uint64_t(1) << LL) - 1;
+    const int capL = 6 - LL + RB;
+    std::vector<int> diag, rest;
+    for (int t = 0; t < n_terms; ++t) {
+        if (xm[t] == 0) diag.push_back(t);
+        else if (__builtin_popcountll(xm[t] & ~low6) <= RB ||
+                 __builtin_popcountll(xm[t] & ~lowL) <= capL)
+            rest.push_back(t);
+        else
+            left.push_back(t);
+    }
+    // choose the new bits of a pass: the high X bits of the remaining terms
+    // in order while they fit, then the bits most used by the rest, then the
+    // lowest free ones
+    auto choose = [&](uint64_t fixed, int cap) {
+        uint64_t S = 0;
+        for (int t : rest) {
+            const uint64_t hb = xm[t] & ~fixed;
+            if (__builtin_popcountll(S | hb) <= cap) S |= hb;
+        }
+        std::vector<int> cnt(n, 0);
+        for (int t : rest)
+            for (int p = 0; p < n; ++p)
+                if (((xm[t] & ~fixed) >> p) & 1) ++cnt[p];
+        while (__builtin_popcountll(S) < cap) {
+            int best = -1;
+            for (int p = 0; p < n; ++p)
+                if (!((S | fixed) >> p & 1) && (best < 0 || cnt[p] > cnt[best])) best = p;
+            if (best < 0) break;
+            S |= uint64_t(1) << best;
+        }
+        return S;
+    };
+    bool first = true;
+    while (first || !rest.empty()) {
+        qcx::ExpRegArgs a{};
+        uint64_t P;
+        if (first) {
+            const uint64_t S = choose(low6, RB);
+            for (int k = 0; k < 6; ++k) a.lpos[k] = uint32_t(k);
+            for (int i = 0, p = 0; p < n; ++p)
+                if ((S >> p) & 1) a.rpos[i++] = uint32_t(p);
+            P = low6 | S;
+        } else {
+            const uint64_t S = choose(lowL, capL);
+            int k = 0, i = 0;
+            for (; k < LL; ++k) a.lpos[k] = uint32_t(k);
+            for (int p = 0; p < n; ++p) {
+                if (!((S >> p) & 1)) continue;
+                if (k < 6) a.lpos[k++] = uint32_t(p);   // the lowest new bits go to the lanes
+                else a.rpos[i++] = uint32_t(p);
+            }
+            P = lowL | S;
+        }
+        // slot masks of a global bit mask
+        auto on_lanes = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (int k = 0; k < 6; ++k)
+                if ((m >> a.lpos[k]) & 1) r |= 1u << k;
+            return r;
+        };
+        auto on_elems = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (int i = 0; i < RB; ++i)
+                if ((m >> a.rpos[i]) & 1) r |= 1u << i;
+            return r;
+        };
+        // a term whose X bits are all on the lanes, or one element bit
+        std::vector<int> xs, stay;
+        for (int t : rest) {
+            const bool fits = (xm[t] & ~P) == 0 &&
+                              (on_elems(xm[t]) == 0 ||
+                               (on_lanes(xm[t]) == 0 && __builtin_popcount(on_elems(xm[t])) == 1));
+            (fits ? xs : stay).push_back(t);
+        }
+        rest.swap(stay);
+        const std::vector<int> ds = first ? diag : std::vector<int>();
+        const bool was_first = first;
+        first = false;
+        if (xs.empty() && ds.empty()) {
+            if (was_first) continue;
+            break;   // no progress: the LDS tile passes take the rest
+        }
+        for (int j = 0, p = 0; p < n; ++p)
+            if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
+        a.n_tiles = uint64_t(1) << (n - 6 - RB);
+        auto term = [&](int t) {
+            qcx::ExpRegTerm e{};
+            e.z_hi = zm[t] & ~P;
+            e.xl = on_lanes(xm[t]);
+            e.xr = on_elems(xm[t]);
+            e.zl = on_lanes(zm[t]);
+            const uint32_t zr = on_elems(zm[t]);
+            for (int el = 0; el < (1 << RB); ++el)
+                if (__builtin_popcount(uint32_t(el) & zr) & 1) e.zsign |= 1u << el;
+            e.ph = ph[t];
+            e.hk = -1;
+            return e;
+        };
+        size_t xi = 0, di = 0;
+        while (xi < xs.size() || di < ds.size()) {
+            const size_t x1 = std::min(xs.size(), xi + qcx::kExpRegMaxX);
+            const size_t d1 = std::min(ds.size(), di + qcx::kExpRegMaxD);
+            std::vector<qcx::ExpRegTerm> et;
+            for (size_t k = xi; k < x1; ++k) {
+                et.push_back(term(xs[k]));
+                where[xs[k]] = slot + int(k - xi);
+            }
+            a.n_x = int(x1 - xi);
+            a.n_h = 0;
+            for (size_t k = di; k < d1; ++k) {
+                qcx::ExpRegTerm e = term(ds[k]);
+                const uint32_t zr = on_elems(zm[ds[k]]);
+                int h = 0;
+                while (h < a.n_h && a.hval[h] != zr) ++h;
+                if (h == a.n_h) a.hval[a.n_h++] = zr;
+                e.hk = h;
+                et.push_back(e);
+                where[ds[k]] = slot + a.n_x + int(k - di);
+            }
+            a.n_d = int(d1 - di);
+            void *tdev = nullptr;
+            int rc = stage(c, et.data(), et.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
+            if (rc) return rc;
+            hipError_t e = qcx::launch_expect_reg(s.amp, s.dtype, a,
+                                                  static_cast<const qcx::ExpRegTerm *>(tdev),
+                                                  vals + slot, part, hs);
+            if (e != hipSuccess) return hip_fail(e, "expect_reg");
+            slot += a.n_x + a.n_d;
+            xi = x1;
+            di = d1;
+        }
+    }
+    left.insert(left.end(), rest.begin(), rest.end());
+    return QC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+int qc_expect_pauli(qc_state_t s, int n_terms, const char *paulis, const double *coeff,
+                    int per_term, double *out_dev, void *stream) {
+    int rc = check_state(s);
+    if (rc) return rc;
+    if (n_terms < 1 || n_terms > 65536) return fail(QC_ERR_ARG, "term count out of range");
+    if (!paulis || !coeff || !out_dev) return fail(QC_ERR_ARG, "NULL argument");
+    const int n = s.n;
+    std::vector<uint64_t> xm(n_terms), zm(n_terms);
+    std::vector<int> ph(n_terms);
+    for (int t = 0; t < n_terms; ++t) {
+        uint64_t x = 0, z = 0;
+        int ny = 0;
+        for (int q = 0; q < n; ++q) {
+            const char ch = paulis[size_t(t) * n + q];
+            const uint64_t b = uint64_t(1) << bitpos(n, q);
+            switch (ch) {
+            case 'I': break;
+            case 'X': x |= b; break;
+            case 'Y': x |= b; z |= b; ++ny; break;
+            case 'Z': z |= b; break;
+            default: return fail(QC_ERR_ARG, "Pauli character not in {I,X,Y,Z}");
+            }
+        }
+        xm[t] = x;
+        zm[t] = z;
+        ph[t] = ny & 3;
+    }
+    DevCtx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    const hipStream_t hs = (hipStream_t)stream;
+    double *vals = c->work;                         // n_terms values
+    double *part = c->work + ((n_terms + 255) & ~255);  // per-block partials
+    std::vector<int> where(n_terms);
+    int slot = 0;
+    std::vector<int> order;   // terms left to the pair kernel
+    // registers tiles first (every diagonal term and every term whose X
+    // bits fit one of their passes); the LDS tile passes take the rest
+    std::vector<int> left;
+    if (n >= 6 + qcx::kExpRegB + 2) {
+        if ((rc = expect_register_passes(s, n_terms, xm, zm, ph, c, hs, vals, part, where, slot,
+                                         left)))
+            return rc;
+    } else {
+        for (int t = 0; t < n_terms; ++t) left.push_back(t);
+    }
+    // Tile passes: the tile is the kExpectLowBits lowest bits plus up to
+    // m - kExpectLowBits more; a term whose X bits all lie in a pass's tile
+    // bits is evaluated in that pass (the pair j, j ^ x is in one tile), and
+    // every diagonal term rides in the first pass.  Terms that fit no tile
+    // (more X bits above the low ones than a tile has room for) are
+    // evaluated one X mask at a time with the pair kernel.
+    const int m = std::min(n, s.dtype == QC_C64 ? 12 : 11);
+    const int L = std::min(qcx::kExpectLowBits, m);
+    const uint64_t low = (uint64_t(1) << L) - 1;
+    std::vector<int> rest, diag;
+    for (int t : left) {
+        if (xm[t] == 0) diag.push_back(t);
+        else if (__builtin_popcountll(xm[t] & ~low) <= m - L) rest.push_back(t);
+        else order.push_back(t);   // pair kernel
+    }
+    struct ExpPass {
+        uint64_t P;
+        std::vector<int> terms;
+    };
+    std::vector<ExpPass> passes;
+    while (!rest.empty()) {
+        uint64_t S = 0;
+        for (int t : rest) {
+            const uint64_t hb = xm[t] & ~low;
+            if (__builtin_popcountll(S | hb) <= m - L) S |= hb;
+        }
+        for (int p = L; __builtin_popcountll(S) < m - L && p < n; ++p) S |= uint64_t(1) << p;
+        ExpPass ps{low | S, {}};
+        std::vector<int> left;
+        for (int t : rest) ((xm[t] & ~ps.P) == 0 ? ps.terms : left).push_back(t);
+        passes.push_back(std::move(ps));
+        rest.swap(left);
+    }
+    if (!diag.empty()) {
+        if (passes.empty()) {
+            uint64_t P = 0;
+            for (int p = 0; p < m; ++p) P |= uint64_t(1) << p;
+            passes.push_back({P, {}});
+        }
+        passes[0].terms.insert(passes[0].terms.begin(), diag.begin(), diag.end());
+    }
+    // term values: tile-pass terms first (pass order), then the pair
+    // kernel's terms grouped by x mask; combine permutes them back
+    for (const ExpPass &ps : passes) {
+        for (size_t k0 = 0; k0 < ps.terms.size(); k0 += qcx::kExpectTileMaxTerms) {
+            const size_t k1 = std::min(ps.terms.size(), k0 + qcx::kExpectTileMaxTerms);
+            std::vector<qcx::ExpectTerm> et(k1 - k0);
+            for (size_t k = k0; k < k1; ++k) {
+                const int t = ps.terms[k];
+                uint32_t xc = 0, zc = 0;
+                for (int p = 0, j = 0; p < n; ++p) {
+                    if (!((ps.P >> p) & 1)) continue;
+                    if ((xm[t] >> p) & 1) xc |= 1u << j;
+                    if ((zm[t] >> p) & 1) zc |= 1u << j;
+                    ++j;
+                }
+                qcx::ExpectTerm &e = et[k - k0];
+                e.z_hi = zm[t] & ~ps.P;
+                e.xc = xc;
+                e.zc = zc;
+                e.ph = ph[t];
+                e.xtop = xc ? 31 - __builtin_clz(xc) : -1;
+                where[t] = slot + int(k - k0);
+            }
+            void *tdev = nullptr;
+            if ((rc = stage(c, et.data(), et.size() * sizeof(qcx::ExpectTerm), hs, &tdev))) return rc;
+            const qcx::TileArgs a = tile_args(n, m, ps.P, 0);
+            hipError_t e = qcx::launch_expect_tiles(s.amp, s.dtype, a,
+                                                    static_cast<const qcx::ExpectTerm *>(tdev),
+                                                    int(k1 - k0), vals + slot, part, hs);
+            if (e != hipSuccess) return hip_fail(e, "expect_tiles");
+            slot += int(k1 - k0);
+        }
+    }
+    return expect_finish(s, n_terms, xm, zm, ph, coeff, per_term, out_dev, c, hs, where, slot,
+                         order);
+}
 int qc_collapse(qc_state_t s, int q, int outcome, double *prob_dev, void *stream) {
     int rc = check_state(s);
     if (rc) return rc;

@@ -268,7 +268,305 @@ __global__ __launch_bounds__(kBlock) void k_expect_rows(const double *part, int 
     }
 }
 
+// ---- register tiles: one wavefront per tile, no LDS staging -----------------
+//
+// Lane l holds the 16 amplitudes e of its tile in registers, in the state's
+// precision; every product is formed in FP64.  For a term whose X bits lie
+// in the tile, the partner of element (l, e) is element (l ^ xl, e ^ xr).
+// The kernel takes the terms whose X bits are on the lanes only (the
+// partner comes from lane l ^ xl by a shuffle) or on one element bit (a
+// register of the lane itself, compile-time index per bit); each lane sums
+// over its elements
+//   Re[i^ph (-1)^popc(j & z) conj(psi_{j ^ x}) psi_j],
+// so the two members of a pair across lanes are counted on their own sides,
+// and a pair inside one lane is taken once and doubled.  The sign of the Z
+// bits outside the tile and on the lane bits is applied per tile and lane.
+//
+// Diagonal terms: |psi|^2 of the 16 elements, its Walsh transform over the
+// element bits, the entry of the term's element mask zr continued by a
+// Walsh transform over the lane bits (butterflies between lanes): lane f
+// then holds sum_j (-1)^popc(j & z) |psi_j|^2 for lane mask f, and lane d,
+// which owns diagonal term d, fetches the entry of its lane mask zl.  One
+// transform over the lanes serves every term with the same zr.
+//
+// The next tile's loads are issued before the current tile is evaluated.
+// Tiles are dealt to wavefronts round-robin for a fixed grid, and every
+// sum runs in a fixed order: the result is deterministic.
+constexpr int kRegE = 1 << kExpRegB;
+constexpr int kRegBlock = 256;
+constexpr int kRegWaves = kRegBlock / 64;
+static_assert(kRegE == 16, "the element switches below cover 16 elements");
+
+// streaming load of one amplitude (read once: non-temporal)
+template <typename R>
+__device__ __forceinline__ cx<R> load_stream(const cx<R> *p) {
+    typedef R r2 __attribute__((ext_vector_type(2)));
+    const r2 v = __builtin_nontemporal_load(reinterpret_cast<const r2 *>(p));
+    return cx<R>{v.x, v.y};
+}
+
+// Re[conj(b) a] (ODD false) or Im[conj(b) a] (ODD true) in FP64
+template <typename R, bool ODD>
+__device__ __forceinline__ double pair_prod(cx<R> a, cx<R> b) {
+    const double ar = double(a.re), ai = double(a.im), br = double(b.re), bi = double(b.im);
+    return ODD ? fma(br, ai, -bi * ar) : fma(br, ar, bi * ai);
+}
+
+// -1.0 when bit e of the uniform mask is set, else +1.0 (a scalar value)
+__device__ __forceinline__ double elem_sign(uint32_t zsign, int e) {
+    return ((zsign >> e) & 1u) ? -1.0 : 1.0;
+}
+
+// Sum over the lane's elements of a term whose X bits are the element mask
+// XR != 0 (no lane bits): the member with the lowest bit of XR clear.
+template <typename R, int XR, bool ODD>
+__device__ __forceinline__ double elem_pairs(const cx<R> *v, uint32_t zsign) {
+    constexpr int lowb = XR & -XR;
+    double acc = 0.0;
+    if (!ODD && zsign == 0) {   // uniform: no element signs
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            if (e & lowb) continue;
+            const cx<R> a = v[e], b = v[e ^ XR];
+            acc = fma(double(b.re), double(a.re), acc);
+            acc = fma(double(b.im), double(a.im), acc);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            if (e & lowb) continue;
+            acc = fma(elem_sign(zsign, e), pair_prod<R, ODD>(v[e], v[e ^ XR]), acc);
+        }
+    }
+    return 2.0 * acc;
+}
+
+// an element mask of one bit (the host gives the element slots no other)
+template <typename R, bool ODD>
+__device__ __forceinline__ double elem_term(const cx<R> *v, uint32_t xr, uint32_t zsign) {
+    switch (xr) {
+    case 1: return elem_pairs<R, 1, ODD>(v, zsign);
+    case 2: return elem_pairs<R, 2, ODD>(v, zsign);
+    case 4: return elem_pairs<R, 4, ODD>(v, zsign);
+    case 8: return elem_pairs<R, 8, ODD>(v, zsign);
+    default: return 0.0;
+    }
+}
+
+// amplitude of lane (lane ^ m) (m uniform)
+__device__ __forceinline__ cx<float> shfl_amp(cx<float> x, uint32_t m) {
+    return cx<float>{__shfl_xor(x.re, int(m), 64), __shfl_xor(x.im, int(m), 64)};
+}
+__device__ __forceinline__ cx<double> shfl_amp(cx<double> x, uint32_t m) {
+    return cx<double>{__shfl_xor(x.re, int(m), 64), __shfl_xor(x.im, int(m), 64)};
+}
+
+// Sum over the lane's elements of a term whose X bits are the lane mask xl
+template <typename R, bool ODD>
+__device__ __forceinline__ double lane_term(const cx<R> *v, uint32_t xl, uint32_t zsign) {
+    double acc = 0.0;
+    if (!ODD && zsign == 0) {   // uniform: no element signs
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const cx<R> a = v[e], b = shfl_amp(v[e], xl);
+            acc = fma(double(b.re), double(a.re), acc);
+            acc = fma(double(b.im), double(a.im), acc);
+            if (e % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound the shuffles in flight
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            acc = fma(elem_sign(zsign, e), pair_prod<R, ODD>(v[e], shfl_amp(v[e], xl)), acc);
+            if (e % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound the shuffles in flight
+        }
+    }
+    return acc;
+}
+
+// entry h (uniform) of the element Walsh transform W
+__device__ __forceinline__ double walsh_entry(const double *W, uint32_t h) {
+    switch (h) {
+#define QC_W_CASE(V) case V: return W[V];
+        QC_W_CASE(0) QC_W_CASE(1) QC_W_CASE(2) QC_W_CASE(3)
+        QC_W_CASE(4) QC_W_CASE(5) QC_W_CASE(6) QC_W_CASE(7)
+        QC_W_CASE(8) QC_W_CASE(9) QC_W_CASE(10) QC_W_CASE(11)
+        QC_W_CASE(12) QC_W_CASE(13) QC_W_CASE(14) QC_W_CASE(15)
+#undef QC_W_CASE
+    default: return 0.0;
+    }
+}
+
+template <typename R, bool DIAG>
+__global__ __launch_bounds__(kRegBlock) void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
+                                                          const ExpRegTerm *__restrict__ terms,
+                                                          double *__restrict__ part) {
+    __shared__ double red[kRegWaves][kExpRegMaxX + kExpRegMaxD];
+    __shared__ double acc_lds[kRegWaves][kExpRegMaxX][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+    const uint64_t nw = uint64_t(gridDim.x) * kRegWaves;
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if ((lane >> k) & 1u) lane_off |= uint64_t(1) << a.lpos[k];
+    uint64_t reg_off[kRegE];
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int i = 0; i < kExpRegB; ++i)
+            if ((e >> i) & 1) o |= uint64_t(1) << a.rpos[i];
+        reg_off[e] = o;
+    }
+    const int nx = a.n_x;
+    // per-lane sums of the X terms across tiles, in LDS (one slot per lane)
+    double *xacc = &acc_lds[wave][0][lane];
+    for (int k = 0; k < nx; ++k) xacc[64 * k] = 0.0;
+    // this lane's diagonal term (lanes past the last one take none)
+    ExpRegTerm dt{0, 0, 0, 0, 0, 0, -1};
+    if (DIAG && int(lane) < a.n_d) dt = terms[nx + int(lane)];
+    double dacc = 0.0;
+    double lsign[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) lsign[b] = ((lane >> b) & 1u) ? -1.0 : 1.0;
+
+    cx<R> nxt[kRegE];
+    uint64_t t = uint64_t(blockIdx.x) * kRegWaves + wave;
+    uint64_t nbase = 0;
+    if (t < a.n_tiles) {
+        nbase = insert_zeros(t, a.pos, 6 + kExpRegB);
+        const cx<R> *src = amp + nbase + lane_off;
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) nxt[e] = load_stream<R>(src + reg_off[e]);
+    }
+    for (; t < a.n_tiles; t += nw) {
+        const uint64_t base = nbase;
+        cx<R> v[kRegE];
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) v[e] = nxt[e];
+        const uint64_t t2 = t + nw;
+        if (t2 < a.n_tiles) {
+            nbase = insert_zeros(t2, a.pos, 6 + kExpRegB);
+            const cx<R> *src = amp + nbase + lane_off;
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) nxt[e] = load_stream<R>(src + reg_off[e]);
+        }
+        // the tile in FP64, converted once
+        cx<double> w[kRegE];
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) w[e] = cx<double>{double(v[e].re), double(v[e].im)};
+        for (int k = 0; k < nx; ++k) {   // uniform
+            const ExpRegTerm tm = terms[k];
+            const bool odd_ph = tm.ph & 1;
+            // an empty asm that claims to change w: the pair products of
+            // every element mask would otherwise be hoisted out of the term
+            // loop (64 FP64 values held across it, spilled registers)
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) asm volatile("" : "+v"(w[e].re), "+v"(w[e].im));
+            double s;
+            if (tm.xr == 0)
+                s = odd_ph ? lane_term<double, true>(w, tm.xl, tm.zsign) : lane_term<double, false>(w, tm.xl, tm.zsign);
+            else
+                s = odd_ph ? elem_term<double, true>(w, tm.xr, tm.zsign) : elem_term<double, false>(w, tm.xr, tm.zsign);
+            // Re[i^ph c]: ph 0 -> Re c, 1 -> -Im c, 2 -> -Re c, 3 -> Im c; then
+            // the signs of the Z bits on the lane and outside the tile
+            const uint32_t neg = uint32_t((tm.ph == 1 || tm.ph == 2) + __popc(lane & tm.zl) +
+                                          __popcll(base & tm.z_hi)) & 1u;
+            xacc[64 * k] += neg ? -s : s;
+        }
+        if (DIAG) {
+            double W[kRegE];
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) W[e] = fma(w[e].re, w[e].re, w[e].im * w[e].im);
+#pragma unroll
+            for (int h = 1; h < kRegE; h <<= 1)
+#pragma unroll
+                for (int e = 0; e < kRegE; ++e)
+                    if (!(e & h)) {
+                        const double u = W[e], w = W[e | h];
+                        W[e] = u + w;
+                        W[e | h] = u - w;
+                    }
+            // four element masks at a time: their lane transforms are
+            // independent, so their shuffles overlap
+            double mine = 0.0;
+            for (int k0 = 0; k0 < a.n_h; k0 += 4) {   // uniform
+                double S[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) S[j] = k0 + j < a.n_h ? walsh_entry(W, a.hval[k0 + j]) : 0.0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b)   // bit b set: partner - own, else own + partner
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) S[j] = fma(lsign[b], S[j], __shfl_xor(S[j], 1 << b, 64));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double g = __shfl(S[j], int(dt.zl), 64);
+                    mine = dt.hk == k0 + j ? g : mine;
+                }
+            }
+            dacc += (__popcll(base & dt.z_hi) & 1) ? -mine : mine;
+        }
+    }
+    // per-wavefront sums, then the block's partial per term in wavefront order
+    for (int k = 0; k < nx; ++k) {   // uniform
+        double s = xacc[64 * k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) red[wave][k] = s;
+    }
+    if (DIAG && int(lane) < a.n_d) red[wave][kExpRegMaxX + lane] = dacc;
+    __syncthreads();
+    const int nt = nx + (DIAG ? a.n_d : 0);
+    for (int k = threadIdx.x; k < nt; k += kRegBlock) {
+        const int col = k < nx ? k : kExpRegMaxX + (k - nx);
+        double s = 0.0;
+#pragma unroll
+        for (int wv = 0; wv < kRegWaves; ++wv) s += red[wv][col];
+        part[size_t(k) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
 }  // namespace
+
+unsigned expect_reg_grid(uint64_t n_tiles) {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    uint64_t g = uint64_t(cus) * 2;
+    const uint64_t need = (n_tiles + kRegWaves - 1) / kRegWaves;
+    if (g > need) g = need;
+    return unsigned(g < 1 ? 1 : g);
+}
+
+hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
+                             const ExpRegTerm *terms_dev, double *vals, double *part,
+                             hipStream_t s) {
+    const int nt = a.n_x + a.n_d;
+    if (a.n_x < 0 || a.n_x > kExpRegMaxX || a.n_d < 0 || a.n_d > kExpRegMaxD || nt < 1 ||
+        a.n_h < 0 || a.n_h > kExpRegMaxH || (a.n_d > 0 && a.n_h < 1) || a.n_tiles < 1)
+        return hipErrorInvalidValue;
+    const unsigned grid = expect_reg_grid(a.n_tiles);
+    const bool diag = a.n_d > 0;
+    const int tok = timer_begin("expect_reg", s);
+    if (dtype == QC_C64) {
+        if (diag)
+            hipLaunchKernelGGL((k_expect_reg<float, true>), dim3(grid), dim3(kRegBlock), 0, s,
+                               static_cast<const cx<float> *>(amp), a, terms_dev, part);
+        else
+            hipLaunchKernelGGL((k_expect_reg<float, false>), dim3(grid), dim3(kRegBlock), 0, s,
+                               static_cast<const cx<float> *>(amp), a, terms_dev, part);
+    } else {
+        if (diag)
+            hipLaunchKernelGGL((k_expect_reg<double, true>), dim3(grid), dim3(kRegBlock), 0, s,
+                               static_cast<const cx<double> *>(amp), a, terms_dev, part);
+        else
+            hipLaunchKernelGGL((k_expect_reg<double, false>), dim3(grid), dim3(kRegBlock), 0, s,
+                               static_cast<const cx<double> *>(amp), a, terms_dev, part);
+    }
+    hipLaunchKernelGGL(k_expect_rows, dim3(unsigned(nt)), dim3(kBlock), 0, s, part, int(grid), vals);
+    timer_end(tok, s);
+    return hipGetLastError();
+}
 
 unsigned expect_tiles_grid(uint64_t n_tiles) {
     int dev = 0, cus = 256;

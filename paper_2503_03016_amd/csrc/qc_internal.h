@@ -309,6 +309,32 @@ struct ExpectTerm {
 constexpr int kExpectTileMaxTerms = 512;   // terms per tile-pass launch
 constexpr int kExpectLowBits = 6;          // lowest bits, always tile bits (runs of 64)
 
+// Register-tile expectation passes (qc_expect_tiles.hip): a wavefront owns
+// a tile of 2^(6 + kExpRegB) amplitudes, lane k of the index on global bit
+// lpos[k], element bit i on rpos[i]; lane l holds elements e = 0..15 at
+// base | dep(l, lpos) | dep(e, rpos).  A term P = i^ph X^x Z^z with x inside
+// the tile is split over the slots: x = (xl on lanes, xr on elements), the
+// Z bits on lanes zl, on elements zr (zsign: bit e set when e & zr has odd
+// parity), outside the tile z_hi.  Diagonal terms (x = 0) name the index
+// hk of their zr in the launch's list of distinct element masks hval.
+struct ExpRegTerm {
+    uint64_t z_hi;
+    uint32_t xl, xr, zl, zsign;
+    int32_t ph, hk;
+};
+constexpr int kExpRegB = 4;            // element bits per lane (16 amplitudes)
+constexpr int kExpRegMaxX = 16;        // X terms per launch (register accumulators)
+constexpr int kExpRegMaxD = 64;        // diagonal terms per launch (one per lane)
+constexpr int kExpRegMaxH = 1 << kExpRegB;
+struct ExpRegArgs {
+    uint64_t n_tiles;                  // wavefront tiles, 2^(n - 6 - kExpRegB)
+    uint32_t pos[6 + kExpRegB];        // ascending global positions of the tile bits
+    uint32_t lpos[6];
+    uint32_t rpos[kExpRegB];
+    uint32_t hval[kExpRegMaxH];
+    int32_t n_x, n_d, n_h;             // X terms (first in the term array), diagonal terms, masks
+};
+
 // ---- batched persistent launch: device program ---------------------------
 enum BatchFlags { BATCH_INIT = 1, BATCH_STORE = 2 };
 struct BatchPhase {
@@ -398,6 +424,12 @@ hipError_t launch_permute_bits(void *amp, int dtype, int n, const uint32_t *sigm
 hipError_t launch_expect_tiles(const void *amp, int dtype, const TileArgs &a,
                                const ExpectTerm *terms_dev, int nt, double *vals, double *part,
                                hipStream_t s);
+// vals[k] = <psi|P_k|psi> for the n_x + n_d terms of one register-tile
+// launch (X terms first); part holds (n_x + n_d) x grid partials
+hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
+                             const ExpRegTerm *terms_dev, double *vals, double *part,
+                             hipStream_t s);
+unsigned expect_reg_grid(uint64_t n_tiles);
 
 hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const double *prob,
                            double *prob_out, hipStream_t s);
