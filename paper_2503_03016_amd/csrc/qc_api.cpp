@@ -1706,6 +1706,25 @@ struct RtLowering {
         out.push_back(r);
     }
 
+    // a Hadamard followed by the fan on the same register slot: one op
+    void fuse_h_fan() {
+        std::vector<qcx::RtOp> f;
+        f.reserve(out.size());
+        for (size_t i = 0; i < out.size(); ++i) {
+            const int k = out[i].kind;
+            if (!adjoint && i + 1 < out.size() && k / 8 == qcx::RT_H &&
+                out[i + 1].kind == qcx::rt_code(qcx::RT_FAN, k % 8)) {
+                qcx::RtOp r = out[i + 1];
+                r.kind = qcx::rt_code(qcx::RT_HFAN, k % 8);
+                f.push_back(r);
+                ++i;
+            } else {
+                f.push_back(out[i]);
+            }
+        }
+        out.swap(f);
+    }
+
     void phases_of(const qcx::TileOp &op, int nt) {
         diag_terms(nt, op.pm_lo, op.pv_lo, op.pm_hi, op.pv_hi, op.u);
     }
@@ -1803,6 +1822,7 @@ struct RtLowering {
         initial_layout();
         const RtLayout first = L;
         for (int i = 0; i < n_ops; ++i) lower(i);
+        fuse_h_fan();
         if (scale != 1.0) {
             qcx::RtOp r{};
             r.kind = qcx::rt_code(qcx::RT_SCALE, 0);

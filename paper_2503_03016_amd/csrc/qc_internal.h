@@ -226,6 +226,9 @@ enum RtKind {
     // an RT_GRADD step and an RT_GRADR step on the same slot: generator
     // b & 15, slot w[0], matrix u; then generator b >> 4, slot w[1], matrix ph
     RT_GRAD2 = 17,
+    // forward only: RT_H on register slot sub, then the RT_FAN of that
+    // target slot (one op, one pass over the registers)
+    RT_HFAN = 18,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

@@ -321,6 +321,7 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             QC_RT_SLOT_CASES(RT_H, (h_slot<R, RB, S>(v)))
             QC_RT_SLOT_CASES(RT_DIAG1, (diag1_slot<R, RB, S>(v, ldu<R>(op.u, 0), ldu<R>(op.u, 1), op.b != 0)))
             QC_RT_SLOT_CASES(RT_FAN, (fan_slot<R, RB, S>(v, op, fan_factor<R>(op, tb, base))))
+            QC_RT_SLOT_CASES(RT_HFAN, (h_slot<R, RB, S>(v), fan_slot<R, RB, S>(v, op, fan_factor<R>(op, tb, base))))
             QC_RT_SLOT_CASES(RT_CX, (xgate_slot<R, RB, S>(v, op.rm, op.rv, tc)))
         case rt_code(RT_DIAG1, kRtThreadSlot): diag1_thread<R, RB>(v, op, tid); break;
         case rt_code(RT_FAN, kRtThreadSlot): fan_thread<R, RB>(v, op, tb, base); break;
