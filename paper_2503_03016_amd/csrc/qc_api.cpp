@@ -1706,7 +1706,10 @@ struct RtLowering {
         out.push_back(r);
     }
 
-    // a Hadamard followed by the fan on the same register slot: one op
+    // a Hadamard followed by the fan on the same register slot: one op; two
+    // such ops in a row on different slots: one RT_HFAN2 op and the second
+    // one's data (the interpreter copies every element register once per
+    // op, so fewer ops means fewer copies)
     void fuse_h_fan() {
         std::vector<qcx::RtOp> f;
         f.reserve(out.size());
@@ -1722,7 +1725,20 @@ struct RtLowering {
                 f.push_back(out[i]);
             }
         }
-        out.swap(f);
+        out.clear();
+        for (size_t i = 0; i < f.size(); ++i) {
+            const int k = f[i].kind;
+            if (i + 1 < f.size() && k / 8 == qcx::RT_HFAN && f[i + 1].kind / 8 == qcx::RT_HFAN &&
+                f[i + 1].kind % 8 != k % 8 && k % 8 < rb && f[i + 1].kind % 8 < rb) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_hfan2_code(k % 8, f[i + 1].kind % 8);
+                out.push_back(r);
+                out.push_back(f[i + 1]);   // data of the second step
+                ++i;
+            } else {
+                out.push_back(f[i]);
+            }
+        }
     }
 
     void phases_of(const qcx::TileOp &op, int nt) {

@@ -229,9 +229,14 @@ enum RtKind {
     // forward only: RT_H on register slot sub, then the RT_FAN of that
     // target slot (one op, one pass over the registers)
     RT_HFAN = 18,
+    // forward only: two RT_HFAN steps on register slots a != b, the first
+    // with this op's fan data, the second with the next op's (a data-only
+    // op the interpreter skips); code rt_hfan2_code(a, b), kinds 19 and 20
+    RT_HFAN2 = 19,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
+__host__ __device__ constexpr int rt_hfan2_code(int a, int b) { return RT_HFAN2 * 8 + a * 4 + b; }
 // Lookup tables.  Tables indexed by the lane number sit in the program's
 // table blob, which is copied to LDS once per workgroup (byte offset w[0]);
 // tables indexed by the wavefront number (8 entries) or by a window of 3

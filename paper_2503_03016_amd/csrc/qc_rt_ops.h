@@ -302,6 +302,20 @@ __device__ __forceinline__ void remap(cx<R> *v, cx<R> *lds, const RtOp &op, uint
     case rt_code(KIND, 2): if constexpr (RB > 2) { constexpr int S = 2; STMT; } break; \
     case rt_code(KIND, 3): if constexpr (RB > 3) { constexpr int S = 3; STMT; } break;
 
+// two Hadamard + fan steps (RT_HFAN2): slot A with op's fan, slot B with the
+// next op's
+#define QC_RT_HFAN2_CASE(A, B)                                                      \
+    case rt_hfan2_code(A, B):                                                       \
+        if constexpr (A < RB && B < RB && A != B) {                                 \
+            h_slot<R, RB, A>(v);                                                    \
+            fan_slot<R, RB, A>(v, op, fan_factor<R>(op, tb, base));                 \
+            const RtOp &op2 = ops[o + 1];                                           \
+            h_slot<R, RB, B>(v);                                                    \
+            fan_slot<R, RB, B>(v, op2, fan_factor<R>(op2, tb, base));               \
+        }                                                                           \
+        ++o;                                                                        \
+        break;
+
 template <typename R, int RB>
 __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uint32_t tid, bool act,
                                const RtOp *__restrict__ ops, int n_ops, const Tabs &tb) {
@@ -322,6 +336,10 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             QC_RT_SLOT_CASES(RT_DIAG1, (diag1_slot<R, RB, S>(v, ldu<R>(op.u, 0), ldu<R>(op.u, 1), op.b != 0)))
             QC_RT_SLOT_CASES(RT_FAN, (fan_slot<R, RB, S>(v, op, fan_factor<R>(op, tb, base))))
             QC_RT_SLOT_CASES(RT_HFAN, (h_slot<R, RB, S>(v), fan_slot<R, RB, S>(v, op, fan_factor<R>(op, tb, base))))
+            QC_RT_HFAN2_CASE(0, 1) QC_RT_HFAN2_CASE(0, 2) QC_RT_HFAN2_CASE(0, 3)
+            QC_RT_HFAN2_CASE(1, 0) QC_RT_HFAN2_CASE(1, 2) QC_RT_HFAN2_CASE(1, 3)
+            QC_RT_HFAN2_CASE(2, 0) QC_RT_HFAN2_CASE(2, 1) QC_RT_HFAN2_CASE(2, 3)
+            QC_RT_HFAN2_CASE(3, 0) QC_RT_HFAN2_CASE(3, 1) QC_RT_HFAN2_CASE(3, 2)
             QC_RT_SLOT_CASES(RT_CX, (xgate_slot<R, RB, S>(v, op.rm, op.rv, tc)))
         case rt_code(RT_DIAG1, kRtThreadSlot): diag1_thread<R, RB>(v, op, tid); break;
         case rt_code(RT_FAN, kRtThreadSlot): fan_thread<R, RB>(v, op, tb, base); break;
@@ -478,6 +496,7 @@ __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, doubl
 }
 
 #undef QC_RT_SLOT_CASES2
+#undef QC_RT_HFAN2_CASE
 #undef QC_RT_SLOT_CASES
 
 }  // namespace rt
