@@ -31,8 +31,8 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// lam = H psi = sum_t c_t i^ny (-1)^popc((j^x) & z) psi_{j^x}
-template <typename R>
+// lam = H psi = sum_t c_t i^ny (-1)^popc((j^x) & z) psi_{j^x}  (ACC: lam +=)
+template <typename R, bool ACC>
 __global__ __launch_bounds__(kBlock) void k_pauli_apply(const cx<R> *psi, cx<R> *out,
                                                         uint64_t count,
                                                         const PauliTermDev *terms, int nt) {
@@ -40,6 +40,10 @@ __global__ __launch_bounds__(kBlock) void k_pauli_apply(const cx<R> *psi, cx<R> 
     for (uint64_t j = uint64_t(blockIdx.x) * kBlock + threadIdx.x; j < count; j += stride) {
         const cx<R> pj = psi[j];
         double ar = 0.0, ai = 0.0;
+        if (ACC) {
+            ar = double(out[j].re);
+            ai = double(out[j].im);
+        }
         for (int t = 0; t < nt; ++t) {
             const PauliTermDev T = terms[t];
             const uint64_t k = j ^ T.x;
@@ -396,19 +400,20 @@ unsigned adjoint_tile_grid(uint64_t n_tiles) {
 }
 
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
-                              const PauliTermDev *terms, int nt, hipStream_t s) {
+                              const PauliTermDev *terms, int nt, bool accumulate, hipStream_t s) {
     const uint64_t count = uint64_t(1) << n;
     uint64_t g = (count + kBlock * 4 - 1) / (kBlock * 4);
     if (g > 256u * 64u) g = 256u * 64u;
     const int tok = timer_begin("pauli_apply", s);
-    if (dtype == QC_C64)
-        hipLaunchKernelGGL((k_pauli_apply<float>), dim3(unsigned(g)), dim3(kBlock), 0, s,
-                           static_cast<const cx<float> *>(psi), static_cast<cx<float> *>(out), count,
-                           terms, nt);
-    else
-        hipLaunchKernelGGL((k_pauli_apply<double>), dim3(unsigned(g)), dim3(kBlock), 0, s,
-                           static_cast<const cx<double> *>(psi), static_cast<cx<double> *>(out),
-                           count, terms, nt);
+#define QC_PA_LAUNCH(R, A)                                                                       \
+    hipLaunchKernelGGL((k_pauli_apply<R, A>), dim3(unsigned(g)), dim3(kBlock), 0, s,             \
+                       static_cast<const cx<R> *>(psi), static_cast<cx<R> *>(out), count, terms, nt)
+    if (dtype == QC_C64) {
+        if (accumulate) QC_PA_LAUNCH(float, true); else QC_PA_LAUNCH(float, false);
+    } else {
+        if (accumulate) QC_PA_LAUNCH(double, true); else QC_PA_LAUNCH(double, false);
+    }
+#undef QC_PA_LAUNCH
     timer_end(tok, s);
     return hipGetLastError();
 }

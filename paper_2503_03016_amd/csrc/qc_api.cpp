@@ -2427,22 +2427,28 @@ int expect_finish(qc_state_t s, int n_terms, const std::vector<uint64_t> &xm,
 
 
 
-// Register-tile passes (k_expect_reg): a wavefront tile is 6 lane bits and
-// kExpRegB element bits.  The first pass has the six lowest bits on the
-// lanes (512 contiguous bytes or more per load); later passes keep only the
-// bits of one 128-byte run on the lanes (4 for complex64, 3 for
-// complex128) and put new bits on the other lanes and the elements, so a
-// later pass covers up to 6 - LL + kExpRegB new bits.  A term is evaluated
-// in the first pass whose tile holds its X bits all on the lanes or on one
-// element bit; every diagonal term rides in the first pass.  Terms that
-// fit no pass are appended to `left` (the LDS tile passes take them).
-int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t> &xm,
-                           const std::vector<uint64_t> &zm, const std::vector<int> &ph, DevCtx *c,
-                           hipStream_t hs, double *vals, double *part, std::vector<int> &where,
-                           int &slot, std::vector<int> &left) {
+// Register-tile passes (k_expect_reg, k_pauli_reg): a wavefront tile is 6
+// lane bits and kExpRegB element bits.  The first pass has the six lowest
+// bits on the lanes (512 contiguous bytes or more per load); later passes
+// keep only the bits of one 128-byte run on the lanes (4 for complex64, 3
+// for complex128) and put new bits on the other lanes and the elements, so a
+// later pass covers up to 6 - LL + kExpRegB new bits.  A term is taken in
+// the first pass whose tile holds its X bits all on the lanes or on one
+// element bit; every diagonal term rides in the first pass.  Each launch
+// lists its X terms, then its diagonal terms grouped by element mask (the
+// ranges in hoff); ids gives the caller's term index of every entry.
+// Terms that fit no pass are appended to `left`.
+struct RegLaunch {
+    qcx::ExpRegArgs a;
+    std::vector<qcx::ExpRegTerm> terms;
+    std::vector<int> ids;
+};
+
+void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint64_t> &xm,
+                          const std::vector<uint64_t> &zm, const std::vector<int> &ph,
+                          std::vector<RegLaunch> &launches, std::vector<int> &left) {
     constexpr int RB = qcx::kExpRegB;
-    const int n = s.n;
-    const int LL = s.dtype == QC_C64 ? 4 : 3;
+    const int LL = dtype == QC_C64 ? 4 : 3;
     const uint64_t low6 = 63, lowL = (uint64_t(1) << LL) - 1;
     const int capL = 6 - LL + RB;
     std::vector<int> diag, rest;
@@ -2519,13 +2525,16 @@ int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t
             (fits ? xs : stay).push_back(t);
         }
         rest.swap(stay);
-        const std::vector<int> ds = first ? diag : std::vector<int>();
+        std::vector<int> ds = first ? diag : std::vector<int>();
         const bool was_first = first;
         first = false;
         if (xs.empty() && ds.empty()) {
             if (was_first) continue;
-            break;   // no progress: the LDS tile passes take the rest
+            break;   // no progress: the caller's other paths take the rest
         }
+        // diagonal terms grouped by their element mask
+        std::stable_sort(ds.begin(), ds.end(),
+                         [&](int p, int q) { return on_elems(zm[p]) < on_elems(zm[q]); });
         for (int j = 0, p = 0; p < n; ++p)
             if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
         a.n_tiles = uint64_t(1) << (n - 6 - RB);
@@ -2546,37 +2555,102 @@ int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t
         while (xi < xs.size() || di < ds.size()) {
             const size_t x1 = std::min(xs.size(), xi + qcx::kExpRegMaxX);
             const size_t d1 = std::min(ds.size(), di + qcx::kExpRegMaxD);
-            std::vector<qcx::ExpRegTerm> et;
+            RegLaunch L;
+            L.a = a;
             for (size_t k = xi; k < x1; ++k) {
-                et.push_back(term(xs[k]));
-                where[xs[k]] = slot + int(k - xi);
+                L.terms.push_back(term(xs[k]));
+                L.ids.push_back(xs[k]);
             }
-            a.n_x = int(x1 - xi);
-            a.n_h = 0;
+            L.a.n_x = int(x1 - xi);
+            L.a.n_h = 0;
             for (size_t k = di; k < d1; ++k) {
                 qcx::ExpRegTerm e = term(ds[k]);
                 const uint32_t zr = on_elems(zm[ds[k]]);
                 int h = 0;
-                while (h < a.n_h && a.hval[h] != zr) ++h;
-                if (h == a.n_h) a.hval[a.n_h++] = zr;
+                while (h < L.a.n_h && L.a.hval[h] != zr) ++h;
+                if (h == L.a.n_h) {
+                    L.a.hoff[h] = uint32_t(k - di);
+                    L.a.hval[L.a.n_h++] = zr;
+                }
                 e.hk = h;
-                et.push_back(e);
-                where[ds[k]] = slot + a.n_x + int(k - di);
+                L.terms.push_back(e);
+                L.ids.push_back(ds[k]);
             }
-            a.n_d = int(d1 - di);
-            void *tdev = nullptr;
-            int rc = stage(c, et.data(), et.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
-            if (rc) return rc;
-            hipError_t e = qcx::launch_expect_reg(s.amp, s.dtype, a,
-                                                  static_cast<const qcx::ExpRegTerm *>(tdev),
-                                                  vals + slot, part, hs);
-            if (e != hipSuccess) return hip_fail(e, "expect_reg");
-            slot += a.n_x + a.n_d;
+            L.a.n_d = int(d1 - di);
+            L.a.hoff[L.a.n_h] = uint32_t(L.a.n_d);
+            launches.push_back(std::move(L));
             xi = x1;
             di = d1;
         }
     }
     left.insert(left.end(), rest.begin(), rest.end());
+}
+
+// lam = H psi: register-tile passes (the first writes lam, the others add),
+// then the gather kernel for the terms no pass takes; the gather kernel
+// alone below 12 qubits.
+int pauli_apply(qc_state_t psi, qc_state_t lam, const std::vector<qcx::PauliTermDev> &terms,
+                DevCtx *c, hipStream_t hs) {
+    const int nt = int(terms.size());
+    std::vector<RegLaunch> launches;
+    std::vector<int> left;
+    if (psi.n >= 6 + qcx::kExpRegB + 2) {
+        std::vector<uint64_t> xm(nt), zm(nt);
+        std::vector<int> ph(nt);
+        for (int t = 0; t < nt; ++t) {
+            xm[t] = terms[t].x;
+            zm[t] = terms[t].z;
+            ph[t] = terms[t].ph;
+        }
+        plan_register_passes(psi.n, psi.dtype, nt, xm, zm, ph, launches, left);
+    } else {
+        for (int t = 0; t < nt; ++t) left.push_back(t);
+    }
+    bool written = false;
+    for (const RegLaunch &L : launches) {
+        std::vector<double> coef(L.ids.size());
+        for (size_t k = 0; k < L.ids.size(); ++k) coef[k] = terms[L.ids[k]].c;
+        void *tdev = nullptr, *cdev = nullptr;
+        int rc = stage(c, L.terms.data(), L.terms.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
+        if (!rc) rc = stage(c, coef.data(), coef.size() * sizeof(double), hs, &cdev);
+        if (rc) return rc;
+        hipError_t e = qcx::launch_pauli_reg(psi.amp, lam.amp, psi.dtype, L.a,
+                                             static_cast<const qcx::ExpRegTerm *>(tdev),
+                                             static_cast<const double *>(cdev), written, hs);
+        if (e != hipSuccess) return hip_fail(e, "pauli_reg");
+        written = true;
+    }
+    if (!left.empty()) {
+        std::vector<qcx::PauliTermDev> rest;
+        for (int t : left) rest.push_back(terms[t]);
+        void *tdev = nullptr;
+        int rc = stage(c, rest.data(), rest.size() * sizeof(qcx::PauliTermDev), hs, &tdev);
+        if (rc) return rc;
+        hipError_t e = qcx::launch_pauli_apply(psi.amp, lam.amp, psi.dtype, psi.n,
+                                               static_cast<const qcx::PauliTermDev *>(tdev),
+                                               int(rest.size()), written, hs);
+        if (e != hipSuccess) return hip_fail(e, "pauli_apply");
+    }
+    return QC_OK;
+}
+
+int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t> &xm,
+                           const std::vector<uint64_t> &zm, const std::vector<int> &ph, DevCtx *c,
+                           hipStream_t hs, double *vals, double *part, std::vector<int> &where,
+                           int &slot, std::vector<int> &left) {
+    std::vector<RegLaunch> launches;
+    plan_register_passes(s.n, s.dtype, n_terms, xm, zm, ph, launches, left);
+    for (const RegLaunch &L : launches) {
+        for (size_t k = 0; k < L.ids.size(); ++k) where[L.ids[k]] = slot + int(k);
+        void *tdev = nullptr;
+        int rc = stage(c, L.terms.data(), L.terms.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
+        if (rc) return rc;
+        hipError_t e = qcx::launch_expect_reg(s.amp, s.dtype, L.a,
+                                              static_cast<const qcx::ExpRegTerm *>(tdev),
+                                              vals + slot, part, hs);
+        if (e != hipSuccess) return hip_fail(e, "expect_reg");
+        slot += L.a.n_x + L.a.n_d;
+    }
     return QC_OK;
 }
 
@@ -2987,11 +3061,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
     if ((rc = tiled_execute(psi, n_ops, fwd.data(), st, stream))) return rc;
     // energy, then lam = H phi
     if ((rc = qc_expect_pauli(psi, n_terms, paulis, coeff, 0, energy_dev, stream))) return rc;
-    void *tdev = nullptr;
-    if ((rc = stage(c, terms.data(), terms.size() * sizeof(qcx::PauliTermDev), hs, &tdev))) return rc;
-    e = qcx::launch_pauli_apply(psi.amp, lam.amp, psi.dtype, n,
-                                static_cast<const qcx::PauliTermDev *>(tdev), n_terms, hs);
-    if (e != hipSuccess) return hip_fail(e, "pauli_apply");
+    if ((rc = pauli_apply(psi, lam, terms, c, hs))) return rc;
     // backward: tile runs over (phi, lam); each rotation's Im <lam|G|phi> is
     // taken in LDS right before its inverse is applied
     double *partial = c->work;

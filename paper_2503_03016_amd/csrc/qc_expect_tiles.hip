@@ -526,6 +526,140 @@ __global__ __launch_bounds__(kRegBlock) void k_expect_reg(const cx<R> *__restric
     }
 }
 
+// ---- lam = H psi on register tiles -------------------------------------------
+//
+// (P psi)_j = i^ph (-1)^popc((j ^ x) & z) psi_{j ^ x}: every amplitude of the
+// output takes, for each term of the pass, its partner's amplitude (from
+// another lane by a shuffle, or from a register of the lane) times
+// c i^ph and the sign of the partner's index.  Diagonal terms: per lane
+// A_h = sum of c (-1)^popc((base | lane) & z) over the terms of element mask
+// h, then element e takes sum_h A_h (-1)^popc(e & h).  Products and sums in
+// FP64, one rounding per amplitude and launch.  The first launch writes
+// lam; the later ones (ACC) add to it.
+
+// L += q * i^PH * b
+template <int PH>
+__device__ __forceinline__ void add_phase(double &lr, double &li, double q, double br, double bi) {
+    if (PH == 0) { lr = fma(q, br, lr); li = fma(q, bi, li); }
+    if (PH == 1) { lr = fma(-q, bi, lr); li = fma(q, br, li); }
+    if (PH == 2) { lr = fma(-q, br, lr); li = fma(-q, bi, li); }
+    if (PH == 3) { lr = fma(q, bi, lr); li = fma(-q, br, li); }
+}
+
+// a term whose X bits are the lane mask xl: the partner of (l, e) is (l ^ xl, e)
+template <int PH>
+__device__ __forceinline__ void pauli_lane(double *lr, double *li, const cx<double> *w, uint32_t xl,
+                                           uint32_t zsign, double p) {
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e) {
+        const double br = __shfl_xor(w[e].re, int(xl), 64), bi = __shfl_xor(w[e].im, int(xl), 64);
+        add_phase<PH>(lr[e], li[e], ((zsign >> e) & 1u) ? -p : p, br, bi);
+        if (e % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound the shuffles in flight
+    }
+}
+
+// a term whose X bit is element bit XR: the partner of (l, e) is (l, e ^ XR)
+template <int PH, int XR>
+__device__ __forceinline__ void pauli_elem(double *lr, double *li, const cx<double> *w, uint32_t zsign,
+                                           double p) {
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e)
+        add_phase<PH>(lr[e], li[e], ((zsign >> (e ^ XR)) & 1u) ? -p : p, w[e ^ XR].re, w[e ^ XR].im);
+}
+
+template <int PH>
+__device__ __forceinline__ void pauli_term(double *lr, double *li, const cx<double> *w,
+                                           const ExpRegTerm &tm, double p) {
+    switch (tm.xr) {
+    case 0: pauli_lane<PH>(lr, li, w, tm.xl, tm.zsign, p); break;
+    case 1: pauli_elem<PH, 1>(lr, li, w, tm.zsign, p); break;
+    case 2: pauli_elem<PH, 2>(lr, li, w, tm.zsign, p); break;
+    case 4: pauli_elem<PH, 4>(lr, li, w, tm.zsign, p); break;
+    case 8: pauli_elem<PH, 8>(lr, li, w, tm.zsign, p); break;
+    default: break;   // the host gives no other masks
+    }
+}
+
+template <typename R, bool DIAG, bool ACC>
+__global__ __launch_bounds__(kRegBlock) void k_pauli_reg(const cx<R> *__restrict__ psi,
+                                                         cx<R> *__restrict__ lam, const ExpRegArgs a,
+                                                         const ExpRegTerm *__restrict__ terms,
+                                                         const double *__restrict__ coef) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
+    const uint64_t nw = uint64_t(gridDim.x) * kRegWaves;
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if ((lane >> k) & 1u) lane_off |= uint64_t(1) << a.lpos[k];
+    uint64_t reg_off[kRegE];
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int i = 0; i < kExpRegB; ++i)
+            if ((e >> i) & 1) o |= uint64_t(1) << a.rpos[i];
+        reg_off[e] = o;
+    }
+    const int nx = a.n_x;
+    for (uint64_t t = uint64_t(blockIdx.x) * kRegWaves + wave; t < a.n_tiles; t += nw) {
+        const uint64_t base = insert_zeros(t, a.pos, 6 + kExpRegB);
+        const cx<R> *src = psi + base + lane_off;
+        cx<R> *dst = lam + base + lane_off;
+        cx<double> w[kRegE];
+        double lr[kRegE], li[kRegE];
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const cx<R> x = load_stream<R>(src + reg_off[e]);
+            w[e] = cx<double>{double(x.re), double(x.im)};
+            if (ACC) {
+                const cx<R> y = dst[reg_off[e]];
+                lr[e] = double(y.re);
+                li[e] = double(y.im);
+            } else {
+                lr[e] = 0.0;
+                li[e] = 0.0;
+            }
+        }
+        for (int k = 0; k < nx; ++k) {   // uniform
+            const ExpRegTerm tm = terms[k];
+            // the partner's sign outside the element bits: its lane is lane ^ xl
+            const uint32_t odd = uint32_t(__popc((lane ^ tm.xl) & tm.zl) + __popcll(base & tm.z_hi)) & 1u;
+            const double p = odd ? -coef[k] : coef[k];
+            switch (tm.ph) {
+            case 0: pauli_term<0>(lr, li, w, tm, p); break;
+            case 1: pauli_term<1>(lr, li, w, tm, p); break;
+            case 2: pauli_term<2>(lr, li, w, tm, p); break;
+            default: pauli_term<3>(lr, li, w, tm, p); break;
+            }
+        }
+        if (DIAG) {
+            double dg[kRegE];
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) dg[e] = 0.0;
+            for (int h = 0; h < a.n_h; ++h) {   // uniform
+                double A = 0.0;
+                for (uint32_t d = a.hoff[h]; d < a.hoff[h + 1]; ++d) {   // uniform
+                    const ExpRegTerm tm = terms[nx + int(d)];
+                    const uint32_t odd = uint32_t(__popc(lane & tm.zl) + __popcll(base & tm.z_hi)) & 1u;
+                    A += odd ? -coef[nx + int(d)] : coef[nx + int(d)];
+                }
+                const uint32_t hv = a.hval[h];
+#pragma unroll
+                for (int e = 0; e < kRegE; ++e)
+                    dg[e] = (__popc(uint32_t(e) & hv) & 1) ? dg[e] - A : dg[e] + A;
+            }
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) {
+                lr[e] = fma(dg[e], w[e].re, lr[e]);
+                li[e] = fma(dg[e], w[e].im, li[e]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) dst[reg_off[e]] = cx<R>{R(lr[e]), R(li[e])};
+    }
+}
+
 }  // namespace
 
 unsigned expect_reg_grid(uint64_t n_tiles) {
@@ -564,6 +698,32 @@ hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
                                static_cast<const cx<double> *>(amp), a, terms_dev, part);
     }
     hipLaunchKernelGGL(k_expect_rows, dim3(unsigned(nt)), dim3(kBlock), 0, s, part, int(grid), vals);
+    timer_end(tok, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_reg(const void *psi, void *lam, int dtype, const ExpRegArgs &a,
+                            const ExpRegTerm *terms_dev, const double *coef_dev, bool accumulate,
+                            hipStream_t s) {
+    const int nt = a.n_x + a.n_d;
+    if (a.n_x < 0 || a.n_x > kExpRegMaxX || a.n_d < 0 || a.n_d > kExpRegMaxD || nt < 1 ||
+        a.n_h < 0 || a.n_h > kExpRegMaxH || (a.n_d > 0 && a.n_h < 1) || a.n_tiles < 1)
+        return hipErrorInvalidValue;
+    const unsigned grid = expect_reg_grid(a.n_tiles);
+    const bool diag = a.n_d > 0;
+    const int tok = timer_begin("pauli_reg", s);
+#define QC_PAULI_LAUNCH(R, D, A)                                                               \
+    hipLaunchKernelGGL((k_pauli_reg<R, D, A>), dim3(grid), dim3(kRegBlock), 0, s,               \
+                       static_cast<const cx<R> *>(psi), static_cast<cx<R> *>(lam), a, terms_dev, \
+                       coef_dev)
+    if (dtype == QC_C64) {
+        if (diag) { if (accumulate) QC_PAULI_LAUNCH(float, true, true); else QC_PAULI_LAUNCH(float, true, false); }
+        else { if (accumulate) QC_PAULI_LAUNCH(float, false, true); else QC_PAULI_LAUNCH(float, false, false); }
+    } else {
+        if (diag) { if (accumulate) QC_PAULI_LAUNCH(double, true, true); else QC_PAULI_LAUNCH(double, true, false); }
+        else { if (accumulate) QC_PAULI_LAUNCH(double, false, true); else QC_PAULI_LAUNCH(double, false, false); }
+    }
+#undef QC_PAULI_LAUNCH
     timer_end(tok, s);
     return hipGetLastError();
 }

@@ -340,6 +340,7 @@ struct ExpRegArgs {
     uint32_t lpos[6];
     uint32_t rpos[kExpRegB];
     uint32_t hval[kExpRegMaxH];
+    uint32_t hoff[kExpRegMaxH + 1];    // diagonal terms of mask hval[h]: [hoff[h], hoff[h + 1])
     int32_t n_x, n_d, n_h;             // X terms (first in the term array), diagonal terms, masks
 };
 
@@ -438,6 +439,11 @@ hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
                              const ExpRegTerm *terms_dev, double *vals, double *part,
                              hipStream_t s);
 unsigned expect_reg_grid(uint64_t n_tiles);
+// lam = sum over the launch's terms of coef[k] P_k psi (the terms in the
+// k_expect_reg layout, coefficients in the same order); accumulate: lam +=
+hipError_t launch_pauli_reg(const void *psi, void *lam, int dtype, const ExpRegArgs &a,
+                            const ExpRegTerm *terms_dev, const double *coef_dev, bool accumulate,
+                            hipStream_t s);
 
 hipError_t launch_collapse(void *amp, int dtype, int n, int p, int b, const double *prob,
                            double *prob_out, hipStream_t s);
@@ -458,8 +464,9 @@ hipError_t launch_batch(const BatchArgs &a, int dtype, unsigned grid, size_t lds
 constexpr int kAdjointMaxSlots = 512;   // rotations per adjoint tile run
 static_assert(kAdjointMaxSlots <= 65536, "TILE_GRAD_APPLY2 packs two slots in 16 bits each");
 unsigned adjoint_tile_grid(uint64_t n_tiles);
+// out = H psi (accumulate: out += H psi), one gather per term and amplitude
 hipError_t launch_pauli_apply(const void *psi, void *out, int dtype, int n,
-                              const PauliTermDev *terms, int nt, hipStream_t s);
+                              const PauliTermDev *terms, int nt, bool accumulate, hipStream_t s);
 // backward pass on register tiles: both vectors; partial[row][col] as for
 // launch_adjoint_tiles (slot_row maps the program's gradient slots to rows)
 hipError_t launch_rt_adjoint(void *phi, void *lam, int dtype, const RtArgs &a, const RtOp *ops_dev,

@@ -667,6 +667,52 @@ def test_adjoint_shared_parameters_and_all_kinds(qc):
     assert abs(e.item() - oracle.energy(oracle.run(ops, psi0, theta), terms)) < 1e-12
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_general_hamiltonian_register_passes(qc, dt):
+    """lam = H phi on a 14-qubit register (register-tile passes): terms with
+    X bits on the lanes, on one element bit, on the lanes and an element at
+    once or on two element bits (the gather kernel adds those), Y phases,
+    Z signs inside and outside the tile, against the oracle's energy and
+    parameter-shift gradients."""
+    n = 14
+    ops = [W.Op("H", (q,)) for q in range(n)]
+    ops += [W.Op("RY", (q,), pidx=(q // 2) % 6) for q in range(0, n, 2)]
+    ops += [W.Op("CZ", (q, q + 1)) for q in range(n - 1)]
+    ops += [W.Op("RX", (q,), pidx=6 + q % 3) for q in range(1, n, 3)]
+    ops += [W.Op("RZ", (q,), pidx=9 + q % 2) for q in range(n)]
+
+    def one(spec):
+        s = ["I"] * n
+        for q, c in spec.items():
+            s[q] = c
+        return "".join(s)
+    terms = list(W.tfim_terms(n))
+    terms += [(one({n - 1: "X", 0: "X"}), 0.7),            # lane bit + high bit
+              (one({0: "Y", 1: "Y"}), -0.4),                # two high bits
+              (one({n - 2: "Y", n - 3: "Z", 3: "Z"}), 0.25),
+              (one({n - 1: "Y", n - 6: "X"}), 0.6),         # two lane bits, Y phase
+              (one({2: "X", 5: "Z", n - 1: "Z"}), -0.35),
+              (one({q: "Z" for q in range(0, n, 3)}), 0.15),
+              (one({4: "Y"}), 0.5)]
+    theta = np.random.default_rng(14).uniform(0, 2 * math.pi, 11)
+    psi0 = oracle.basis_state(n, 0)
+    g_ref = oracle.param_shift_grad(ops, theta, terms, psi0)
+    e_ref = oracle.energy(oracle.run(ops, psi0, theta), terms)
+    psi = qc.new_state(n, DT[dt])
+    lam = qc.new_state(n, DT[dt])
+    qc.state_init(psi, 0)
+    e, g = qc.adjoint_grad(psi, lam, ops, theta, terms)
+    e, g = e.item(), g.cpu().numpy()
+    if dt == "c128":
+        assert abs(e - e_ref) < 1e-11
+        np.testing.assert_allclose(g, g_ref, atol=1e-10)
+    else:
+        norm_h = sum(abs(c) for _, c in terms)
+        bound = 2 * norm_h * 1e-5
+        assert abs(e - e_ref) < bound
+        assert np.max(np.abs(g - g_ref)) < bound
+
+
 def test_deterministic_reductions(qc):
     n = 16
     t = dev(W.random_state(n, 3), torch.complex64)
