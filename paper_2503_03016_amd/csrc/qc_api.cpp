@@ -2444,9 +2444,15 @@ struct RegLaunch {
     std::vector<int> ids;
 };
 
+// for_expect: the launches feed k_expect_reg, whose diagonal terms with Z
+// bits outside the tile share at most kExpRegMaxC (zsign, zl) pairs per
+// launch; diagonal terms that would need more than one launch beyond those
+// the X terms of the first pass need go to `left` (one LDS tile pass takes
+// any number of them)
 void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint64_t> &xm,
                           const std::vector<uint64_t> &zm, const std::vector<int> &ph,
-                          std::vector<RegLaunch> &launches, std::vector<int> &left) {
+                          std::vector<RegLaunch> &launches, std::vector<int> &left,
+                          bool for_expect) {
     constexpr int RB = qcx::kExpRegB;
     const int LL = dtype == QC_C64 ? 4 : 3;
     const uint64_t low6 = 63, lowL = (uint64_t(1) << LL) - 1;
@@ -2538,33 +2544,96 @@ void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint6
         for (int j = 0, p = 0; p < n; ++p)
             if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
         a.n_tiles = uint64_t(1) << (n - 6 - RB);
+        // the transposed tile of the first complex64 expectation pass: lane
+        // bits on lpos[4], lpos[5], rpos[0..3], element bits on lpos[0..3]
+        const bool transpose = for_expect && was_first && dtype == QC_C64;
+        uint32_t tl_pos[6] = {a.lpos[4], a.lpos[5], a.rpos[0], a.rpos[1], a.rpos[2], a.rpos[3]};
+        auto on_tlanes = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (int k = 0; k < 6; ++k)
+                if ((m >> tl_pos[k]) & 1) r |= 1u << k;
+            return r;
+        };
+        auto on_telems = [&](uint64_t m) {
+            uint32_t r = 0;
+            for (int i = 0; i < RB; ++i)
+                if ((m >> a.lpos[i]) & 1) r |= 1u << i;
+            return r;
+        };
+        // an X term on one lane bit goes to the transposed tile: bits 0..3
+        // become element bits there, bits 4, 5 lane bits 0, 1 (DPP partners)
+        auto to_transposed = [&](int t) {
+            return transpose && on_elems(xm[t]) == 0 && __builtin_popcount(on_lanes(xm[t])) == 1;
+        };
         auto term = [&](int t) {
+            const bool tr = to_transposed(t);
             qcx::ExpRegTerm e{};
             e.z_hi = zm[t] & ~P;
-            e.xl = on_lanes(xm[t]);
-            e.xr = on_elems(xm[t]);
-            e.zl = on_lanes(zm[t]);
-            const uint32_t zr = on_elems(zm[t]);
+            e.xl = tr ? on_tlanes(xm[t]) : on_lanes(xm[t]);
+            e.xr = tr ? on_telems(xm[t]) : on_elems(xm[t]);
+            e.zl = tr ? on_tlanes(zm[t]) : on_lanes(zm[t]);
+            const uint32_t zr = tr ? on_telems(zm[t]) : on_elems(zm[t]);
             for (int el = 0; el < (1 << RB); ++el)
                 if (__builtin_popcount(uint32_t(el) & zr) & 1) e.zsign |= 1u << el;
             e.ph = ph[t];
             e.hk = -1;
+            e.ck = -1;
             return e;
         };
         size_t xi = 0, di = 0;
+        const size_t diag_launches =
+            for_expect ? std::max<size_t>(1, (xs.size() + qcx::kExpRegMaxX - 1) / qcx::kExpRegMaxX) + 1
+                       : ds.size();
+        size_t n_launch = 0;
         while (xi < xs.size() || di < ds.size()) {
+            if (di < ds.size() && n_launch == diag_launches) {
+                left.insert(left.end(), ds.begin() + long(di), ds.end());
+                di = ds.size();
+                if (xi == xs.size()) break;
+            }
+            ++n_launch;
             const size_t x1 = std::min(xs.size(), xi + qcx::kExpRegMaxX);
-            const size_t d1 = std::min(ds.size(), di + qcx::kExpRegMaxD);
             RegLaunch L;
             L.a = a;
-            for (size_t k = xi; k < x1; ++k) {
-                L.terms.push_back(term(xs[k]));
-                L.ids.push_back(xs[k]);
-            }
+            L.a.n_xb = 0;
+            for (int pass_b = 0; pass_b < 2; ++pass_b)   // untransposed terms first
+                for (size_t k = xi; k < x1; ++k) {
+                    if (to_transposed(xs[k]) != (pass_b == 1)) continue;
+                    L.terms.push_back(term(xs[k]));
+                    L.ids.push_back(xs[k]);
+                    L.a.n_xb += pass_b;
+                }
             L.a.n_x = int(x1 - xi);
             L.a.n_h = 0;
+            L.a.n_c = 0;
+            L.a.n_din = 0;
+            // diagonal terms in order while the launch has room: at most
+            // kExpRegMaxD, and at most kExpRegMaxC distinct (zsign, zl) pairs
+            // among those with Z bits outside the tile
+            size_t d1 = di;
+            for (; d1 < ds.size() && d1 - di < size_t(qcx::kExpRegMaxD); ++d1) {
+                const qcx::ExpRegTerm e = term(ds[d1]);
+                if (!for_expect || e.z_hi == 0) continue;
+                int c = 0;
+                while (c < L.a.n_c && !(L.a.csign[c] == e.zsign && L.a.clane[c] == e.zl)) ++c;
+                if (c == L.a.n_c) {
+                    if (c == qcx::kExpRegMaxC) break;
+                    L.a.csign[c] = e.zsign;
+                    L.a.clane[c] = e.zl;
+                    ++L.a.n_c;
+                }
+            }
             for (size_t k = di; k < d1; ++k) {
                 qcx::ExpRegTerm e = term(ds[k]);
+                if (!for_expect) {
+                    // k_pauli_reg takes every diagonal term per lane
+                } else if (e.z_hi == 0) {
+                    ++L.a.n_din;
+                } else {
+                    int c = 0;
+                    while (!(L.a.csign[c] == e.zsign && L.a.clane[c] == e.zl)) ++c;
+                    e.ck = c;
+                }
                 const uint32_t zr = on_elems(zm[ds[k]]);
                 int h = 0;
                 while (h < L.a.n_h && L.a.hval[h] != zr) ++h;
@@ -2602,7 +2671,7 @@ int pauli_apply(qc_state_t psi, qc_state_t lam, const std::vector<qcx::PauliTerm
             zm[t] = terms[t].z;
             ph[t] = terms[t].ph;
         }
-        plan_register_passes(psi.n, psi.dtype, nt, xm, zm, ph, launches, left);
+        plan_register_passes(psi.n, psi.dtype, nt, xm, zm, ph, launches, left, false);
     } else {
         for (int t = 0; t < nt; ++t) left.push_back(t);
     }
@@ -2639,7 +2708,7 @@ int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t
                            hipStream_t hs, double *vals, double *part, std::vector<int> &where,
                            int &slot, std::vector<int> &left) {
     std::vector<RegLaunch> launches;
-    plan_register_passes(s.n, s.dtype, n_terms, xm, zm, ph, launches, left);
+    plan_register_passes(s.n, s.dtype, n_terms, xm, zm, ph, launches, left, true);
     for (const RegLaunch &L : launches) {
         for (size_t k = 0; k < L.ids.size(); ++k) where[L.ids[k]] = slot + int(k);
         void *tdev = nullptr;

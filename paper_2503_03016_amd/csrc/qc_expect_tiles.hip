@@ -24,6 +24,7 @@
 // its coefficient from the eight wavefronts (through LDS) with their signs:
 // one thread per term, no reduction per term.  Diagonal terms after the
 // first X term take one W entry and one sign and a wavefront sum.
+#include "qc_lanes.h"
 #include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
@@ -362,6 +363,8 @@ __device__ __forceinline__ cx<double> shfl_amp(cx<double> x, uint32_t m) {
 }
 
 // Sum over the lane's elements of a term whose X bits are the lane mask xl
+// (any mask: the partner comes from an LDS permute; every lane counts its
+// own side of each pair)
 template <typename R, bool ODD>
 __device__ __forceinline__ double lane_term(const cx<R> *v, uint32_t xl, uint32_t zsign) {
     double acc = 0.0;
@@ -383,25 +386,64 @@ __device__ __forceinline__ double lane_term(const cx<R> *v, uint32_t xl, uint32_
     return acc;
 }
 
-// entry h (uniform) of the element Walsh transform W
-__device__ __forceinline__ double walsh_entry(const double *W, uint32_t h) {
-    switch (h) {
-#define QC_W_CASE(V) case V: return W[V];
-        QC_W_CASE(0) QC_W_CASE(1) QC_W_CASE(2) QC_W_CASE(3)
-        QC_W_CASE(4) QC_W_CASE(5) QC_W_CASE(6) QC_W_CASE(7)
-        QC_W_CASE(8) QC_W_CASE(9) QC_W_CASE(10) QC_W_CASE(11)
-        QC_W_CASE(12) QC_W_CASE(13) QC_W_CASE(14) QC_W_CASE(15)
-#undef QC_W_CASE
-    default: return 0.0;
+// A term whose X bits are the one lane bit B < 4: the lanes with bit B
+// clear fetch their partner's amplitudes through a DPP row shift (VALU, no
+// LDS) and count each pair twice; the lanes with bit B set count nothing.
+template <int B, bool ODD>
+__device__ __forceinline__ double lane_bit_term(const cx<double> *w, uint32_t zsign, uint32_t lane) {
+    double acc = 0.0;
+    if (!ODD && zsign == 0) {   // uniform: no element signs
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            acc = fma(lanes::up<B>(w[e].re), w[e].re, acc);
+            acc = fma(lanes::up<B>(w[e].im), w[e].im, acc);
+            if (e % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound the partners held at once
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const cx<double> b{lanes::up<B>(w[e].re), lanes::up<B>(w[e].im)};
+            acc = fma(elem_sign(zsign, e), pair_prod<double, ODD>(w[e], b), acc);
+            if (e % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound the partners held at once
+        }
+    }
+    return ((lane >> B) & 1u) ? 0.0 : 2.0 * acc;
+}
+
+// Lane bits 0..3 take their partner through DPP row shifts (VALU); bits 4
+// and 5, and masks of several bits, through LDS permutes: a permlane swap
+// needs copies of both registers and costs more VALU than the permute
+// leaves to the LDS.
+template <bool ODD>
+__device__ __forceinline__ double lane_any(const cx<double> *w, uint32_t xl, uint32_t zsign, uint32_t lane) {
+    switch (xl) {   // uniform
+    case 1: return lane_bit_term<0, ODD>(w, zsign, lane);
+    case 2: return lane_bit_term<1, ODD>(w, zsign, lane);
+    case 4: return lane_bit_term<2, ODD>(w, zsign, lane);
+    case 8: return lane_bit_term<3, ODD>(w, zsign, lane);
+    default: return lane_term<double, ODD>(w, xl, zsign);
     }
 }
 
+// Register-tile pass.  Diagonal terms, with p_e = |psi|^2 of element e:
+//  - z_hi = 0 (every Z bit in the tile): the lane adds p_e over its tiles
+//    (pacc); after the last tile, sum_e (-1)^popc(e & zr) pacc_e with the
+//    sign of the lane bits, over the wavefront;
+//  - z_hi != 0: the sign outside the tile changes from tile to tile.  For
+//    each distinct pair (zsign, zl) of the launch the wavefront forms the
+//    tile's sum sum_{l,e} (-1)^popc(l & zl) (-1)^popc(e & zr) p_{l,e} and
+//    parks it on lane k for the k-th tile of a group of 64; after 64 tiles
+//    each term takes the signs of its z_hi over the 64 tile bases at once
+//    (one lane each) and one wavefront sum.
+// X terms: one lane-local sum per tile and term, added to the lane's slot
+// in LDS with the signs outside the element bits.
 template <typename R, bool DIAG>
-__global__ __launch_bounds__(kRegBlock) void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
+__global__ __launch_bounds__(kRegBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
                                                           const ExpRegTerm *__restrict__ terms,
                                                           double *__restrict__ part) {
     __shared__ double red[kRegWaves][kExpRegMaxX + kExpRegMaxD];
-    __shared__ double acc_lds[kRegWaves][kExpRegMaxX][64];
+    extern __shared__ double dyn_lds[];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)));
     const uint64_t nw = uint64_t(gridDim.x) * kRegWaves;
@@ -418,103 +460,169 @@ __global__ __launch_bounds__(kRegBlock) void k_expect_reg(const cx<R> *__restric
             if ((e >> i) & 1) o |= uint64_t(1) << a.rpos[i];
         reg_off[e] = o;
     }
-    const int nx = a.n_x;
-    // per-lane sums of the X terms across tiles, in LDS (one slot per lane)
-    double *xacc = &acc_lds[wave][0][lane];
+    const int nx = a.n_x, nxa = a.n_x - a.n_xb;
+    double *wlds = dyn_lds + size_t(wave) * (expect_reg_wave_lds(a, sizeof(cx<R>)) / sizeof(double));
+    // per-lane sums of the X terms across tiles (one slot per lane)
+    double *xacc = wlds + lane;
     for (int k = 0; k < nx; ++k) xacc[64 * k] = 0.0;
-    // this lane's diagonal term (lanes past the last one take none)
-    ExpRegTerm dt{0, 0, 0, 0, 0, 0, -1};
-    if (DIAG && int(lane) < a.n_d) dt = terms[nx + int(lane)];
-    double dacc = 0.0;
-    double lsign[6];
-#pragma unroll
-    for (int b = 0; b < 6; ++b) lsign[b] = ((lane >> b) & 1u) ? -1.0 : 1.0;
-
-    cx<R> nxt[kRegE];
-    uint64_t t = uint64_t(blockIdx.x) * kRegWaves + wave;
-    uint64_t nbase = 0;
-    if (t < a.n_tiles) {
-        nbase = insert_zeros(t, a.pos, 6 + kExpRegB);
-        const cx<R> *src = amp + nbase + lane_off;
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e) nxt[e] = load_stream<R>(src + reg_off[e]);
+    // lane k of rc: a pair's sum over the k-th tile of the current group
+    double *rc = wlds + 64 * nx + lane;
+    // transposition buffer: amplitude i of the tile at i + pad (i / 16)
+    constexpr int pad = 16 / int(sizeof(cx<R>));
+    constexpr bool kTrans = sizeof(R) == 4;   // complex64 only (LDS budget)
+    cx<R> *tb = reinterpret_cast<cx<R> *>(wlds + 64 * (nx + a.n_c));
+    if (DIAG) {
+        for (int d = int(lane); d < a.n_d; d += 64) red[wave][kExpRegMaxX + d] = 0.0;
+        for (int c = 0; c < a.n_c; ++c) rc[64 * c] = 0.0;
     }
-    for (; t < a.n_tiles; t += nw) {
-        const uint64_t base = nbase;
-        cx<R> v[kRegE];
+    double pacc[kRegE];
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = nxt[e];
-        const uint64_t t2 = t + nw;
-        if (t2 < a.n_tiles) {
-            nbase = insert_zeros(t2, a.pos, 6 + kExpRegB);
-            const cx<R> *src = amp + nbase + lane_off;
+    for (int e = 0; e < kRegE; ++e) pacc[e] = 0.0;
+    // this tile's lane in rc, and the first tile of the group there
+    uint32_t slot = 0;
+    uint64_t t_grp = 0;
+
+    // tiles in flight per wavefront, each in its own registers (two tiles
+    // of complex64 measured no faster than one)
+    constexpr int PF = 1;
+    cx<R> buf[PF][kRegE];
+    uint64_t bbase[PF];
+    uint64_t t = uint64_t(blockIdx.x) * kRegWaves + wave;
+    auto issue = [&](cx<R> *dst, uint64_t &b, uint64_t tt) {
+        if (tt < a.n_tiles) {
+            b = insert_zeros(tt, a.pos, 6 + kExpRegB);
+            const cx<R> *src = amp + b + lane_off;
 #pragma unroll
-            for (int e = 0; e < kRegE; ++e) nxt[e] = load_stream<R>(src + reg_off[e]);
+            for (int e = 0; e < kRegE; ++e) dst[e] = load_stream<R>(src + reg_off[e]);
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < PF; ++p) issue(buf[p], bbase[p], t + uint64_t(p) * nw);
+    t_grp = t;
+    // one tile: the tile in buffer `cur`, whose registers then take the
+    // loads of the tile PF steps ahead
+    auto one_tile = [&](cx<R> *cur, uint64_t &cbase) {
+        const uint64_t base = cbase;
+        if (kTrans && a.n_xb > 0) {   // uniform: the tile into the transposition buffer
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) {
+                const uint32_t i = lane + 64u * uint32_t(e);
+                tb[i + pad * (i >> 4)] = cur[e];
+            }
         }
         // the tile in FP64, converted once
         cx<double> w[kRegE];
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) w[e] = cx<double>{double(v[e].re), double(v[e].im)};
-        for (int k = 0; k < nx; ++k) {   // uniform
-            const ExpRegTerm tm = terms[k];
-            const bool odd_ph = tm.ph & 1;
-            // an empty asm that claims to change w: the pair products of
-            // every element mask would otherwise be hoisted out of the term
-            // loop (64 FP64 values held across it, spilled registers)
-#pragma unroll
-            for (int e = 0; e < kRegE; ++e) asm volatile("" : "+v"(w[e].re), "+v"(w[e].im));
-            double s;
-            if (tm.xr == 0)
-                s = odd_ph ? lane_term<double, true>(w, tm.xl, tm.zsign) : lane_term<double, false>(w, tm.xl, tm.zsign);
-            else
-                s = odd_ph ? elem_term<double, true>(w, tm.xr, tm.zsign) : elem_term<double, false>(w, tm.xr, tm.zsign);
-            // Re[i^ph c]: ph 0 -> Re c, 1 -> -Im c, 2 -> -Re c, 3 -> Im c; then
-            // the signs of the Z bits on the lane and outside the tile
-            const uint32_t neg = uint32_t((tm.ph == 1 || tm.ph == 2) + __popc(lane & tm.zl) +
-                                          __popcll(base & tm.z_hi)) & 1u;
-            xacc[64 * k] += neg ? -s : s;
-        }
-        if (DIAG) {
-            double W[kRegE];
-#pragma unroll
-            for (int e = 0; e < kRegE; ++e) W[e] = fma(w[e].re, w[e].re, w[e].im * w[e].im);
-#pragma unroll
-            for (int h = 1; h < kRegE; h <<= 1)
-#pragma unroll
-                for (int e = 0; e < kRegE; ++e)
-                    if (!(e & h)) {
-                        const double u = W[e], w = W[e | h];
-                        W[e] = u + w;
-                        W[e | h] = u - w;
-                    }
-            // four element masks at a time: their lane transforms are
-            // independent, so their shuffles overlap
-            double mine = 0.0;
-            for (int k0 = 0; k0 < a.n_h; k0 += 4) {   // uniform
-                double S[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) S[j] = k0 + j < a.n_h ? walsh_entry(W, a.hval[k0 + j]) : 0.0;
-#pragma unroll
-                for (int b = 0; b < 6; ++b)   // bit b set: partner - own, else own + partner
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) S[j] = fma(lsign[b], S[j], __shfl_xor(S[j], 1 << b, 64));
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double g = __shfl(S[j], int(dt.zl), 64);
-                    mine = dt.hk == k0 + j ? g : mine;
-                }
+        for (int e = 0; e < kRegE; ++e) w[e] = cx<double>{double(cur[e].re), double(cur[e].im)};
+        issue(cur, cbase, t + uint64_t(PF) * nw);
+        // X terms [k0, k1) on the tile w
+        auto x_terms = [&](int k0, int k1) {
+            for (int k = k0; k < k1; ++k) {   // uniform
+                const ExpRegTerm tm = terms[k];
+                const bool odd_ph = tm.ph & 1;
+                // an empty asm that claims to change w: the pair products of
+                // every element mask would otherwise be hoisted out of the term
+                // loop (64 FP64 values held across it, spilled registers)
+    #pragma unroll
+                for (int e = 0; e < kRegE; ++e) asm volatile("" : "+v"(w[e].re), "+v"(w[e].im));
+                double s;
+                if (tm.xr == 0)
+                    s = odd_ph ? lane_any<true>(w, tm.xl, tm.zsign, lane) : lane_any<false>(w, tm.xl, tm.zsign, lane);
+                else
+                    s = odd_ph ? elem_term<double, true>(w, tm.xr, tm.zsign) : elem_term<double, false>(w, tm.xr, tm.zsign);
+                // Re[i^ph c]: ph 0 -> Re c, 1 -> -Im c, 2 -> -Re c, 3 -> Im c; then
+                // the signs of the Z bits on the lane and outside the tile
+                const uint32_t neg = uint32_t((tm.ph == 1 || tm.ph == 2) + __popc(lane & tm.zl) +
+                                              __popcll(base & tm.z_hi)) & 1u;
+                xacc[64 * k] += neg ? -s : s;
             }
-            dacc += (__popcll(base & dt.z_hi) & 1) ? -mine : mine;
+        };
+        x_terms(0, nxa);
+        if (DIAG) {
+            double p[kRegE];
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) p[e] = fma(w[e].re, w[e].re, w[e].im * w[e].im);
+            if (a.n_din > 0) {   // uniform
+#pragma unroll
+                for (int e = 0; e < kRegE; ++e) pacc[e] += p[e];
+            }
+            if (a.n_c > 0) {   // uniform
+                double q[kExpRegMaxC];
+#pragma unroll
+                for (int c = 0; c < kExpRegMaxC; ++c) {
+                    q[c] = 0.0;
+                    if (c < a.n_c) {   // uniform
+                        double s = 0.0;
+#pragma unroll
+                        for (int e = 0; e < kRegE; ++e) s = fma(elem_sign(a.csign[c], e), p[e], s);
+                        q[c] = (__popc(lane & a.clane[c]) & 1) ? -s : s;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < kExpRegMaxC; ++c)
+                    if (c < a.n_c) {   // uniform: every lane takes part in the sum
+                        const double qs = lanes::wave_sum(q[c]);
+                        if (lane == slot) rc[64 * c] = qs;
+                    }
+            }
+            ++slot;
+            if (slot == 64 || t + nw >= a.n_tiles) {   // uniform: the group's terms
+                if (a.n_c > 0) {
+                    const uint64_t bl = insert_zeros(t_grp + uint64_t(lane) * nw, a.pos, 6 + kExpRegB);
+                    for (int d = 0; d < a.n_d; ++d) {   // uniform
+                        const ExpRegTerm dt = terms[nx + d];
+                        if (dt.ck < 0) continue;
+                        double r = rc[64 * dt.ck];
+                        r = lane < slot ? ((__popcll(bl & dt.z_hi) & 1) ? -r : r) : 0.0;
+                        r = lanes::wave_sum(r);
+                        if (lane == 0) red[wave][kExpRegMaxX + d] += r;
+                    }
+                }
+                slot = 0;
+                t_grp = t + nw;
+            }
+        }
+        if (kTrans && a.n_xb > 0) {   // uniform: the transposed tile, lane l holding 16 l .. 16 l + 15
+            // LDS accesses of one wavefront are performed in order: the
+            // fences only keep the compiler from moving them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int f = 0; f < kRegE; ++f) {
+                const cx<R> x = tb[(16 + pad) * lane + uint32_t(f)];
+                w[f] = cx<double>{double(x.re), double(x.im)};
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            x_terms(nxa, nx);
+        }
+    };
+    while (t < a.n_tiles) {   // uniform
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            if (t >= a.n_tiles) break;
+            one_tile(buf[p], bbase[p]);
+            t += nw;
         }
     }
     // per-wavefront sums, then the block's partial per term in wavefront order
     for (int k = 0; k < nx; ++k) {   // uniform
-        double s = xacc[64 * k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        const double s = lanes::wave_sum(xacc[64 * k]);
         if (lane == 0) red[wave][k] = s;
     }
-    if (DIAG && int(lane) < a.n_d) red[wave][kExpRegMaxX + lane] = dacc;
+    if (DIAG && a.n_din > 0) {
+        for (int d = 0; d < a.n_d; ++d) {   // uniform
+            const ExpRegTerm dt = terms[nx + d];
+            if (dt.ck >= 0) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) s = fma(elem_sign(dt.zsign, e), pacc[e], s);
+            s = lanes::wave_sum((__popc(lane & dt.zl) & 1) ? -s : s);
+            if (lane == 0) red[wave][kExpRegMaxX + d] = s;
+        }
+    }
     __syncthreads();
     const int nt = nx + (DIAG ? a.n_d : 0);
     for (int k = threadIdx.x; k < nt; k += kRegBlock) {
@@ -677,24 +785,27 @@ hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
                              hipStream_t s) {
     const int nt = a.n_x + a.n_d;
     if (a.n_x < 0 || a.n_x > kExpRegMaxX || a.n_d < 0 || a.n_d > kExpRegMaxD || nt < 1 ||
-        a.n_h < 0 || a.n_h > kExpRegMaxH || (a.n_d > 0 && a.n_h < 1) || a.n_tiles < 1)
+        a.n_h < 0 || a.n_h > kExpRegMaxH || (a.n_d > 0 && a.n_h < 1) || a.n_tiles < 1 ||
+        a.n_c < 0 || a.n_c > kExpRegMaxC || a.n_din < 0 || a.n_din > a.n_d)
         return hipErrorInvalidValue;
+    if (a.n_xb < 0 || a.n_xb > a.n_x || (a.n_xb > 0 && dtype != QC_C64)) return hipErrorInvalidValue;
     const unsigned grid = expect_reg_grid(a.n_tiles);
     const bool diag = a.n_d > 0;
+    const size_t lds = kRegWaves * expect_reg_wave_lds(a, dtype == QC_C64 ? 8 : 16);
     const int tok = timer_begin("expect_reg", s);
     if (dtype == QC_C64) {
         if (diag)
-            hipLaunchKernelGGL((k_expect_reg<float, true>), dim3(grid), dim3(kRegBlock), 0, s,
+            hipLaunchKernelGGL((k_expect_reg<float, true>), dim3(grid), dim3(kRegBlock), lds, s,
                                static_cast<const cx<float> *>(amp), a, terms_dev, part);
         else
-            hipLaunchKernelGGL((k_expect_reg<float, false>), dim3(grid), dim3(kRegBlock), 0, s,
+            hipLaunchKernelGGL((k_expect_reg<float, false>), dim3(grid), dim3(kRegBlock), lds, s,
                                static_cast<const cx<float> *>(amp), a, terms_dev, part);
     } else {
         if (diag)
-            hipLaunchKernelGGL((k_expect_reg<double, true>), dim3(grid), dim3(kRegBlock), 0, s,
+            hipLaunchKernelGGL((k_expect_reg<double, true>), dim3(grid), dim3(kRegBlock), lds, s,
                                static_cast<const cx<double> *>(amp), a, terms_dev, part);
         else
-            hipLaunchKernelGGL((k_expect_reg<double, false>), dim3(grid), dim3(kRegBlock), 0, s,
+            hipLaunchKernelGGL((k_expect_reg<double, false>), dim3(grid), dim3(kRegBlock), lds, s,
                                static_cast<const cx<double> *>(amp), a, terms_dev, part);
     }
     hipLaunchKernelGGL(k_expect_rows, dim3(unsigned(nt)), dim3(kBlock), 0, s, part, int(grid), vals);

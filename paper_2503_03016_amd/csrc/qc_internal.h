@@ -324,16 +324,19 @@ constexpr int kExpectLowBits = 6;          // lowest bits, always tile bits (run
 // the tile is split over the slots: x = (xl on lanes, xr on elements), the
 // Z bits on lanes zl, on elements zr (zsign: bit e set when e & zr has odd
 // parity), outside the tile z_hi.  Diagonal terms (x = 0) name the index
-// hk of their zr in the launch's list of distinct element masks hval.
+// hk of their zr in the launch's list of distinct element masks hval, and
+// those with z_hi != 0 the index ck of their (zsign, zl) pair in the
+// launch's list of such pairs (ck = -1 when z_hi = 0).
 struct ExpRegTerm {
     uint64_t z_hi;
     uint32_t xl, xr, zl, zsign;
-    int32_t ph, hk;
+    int32_t ph, hk, ck;
 };
 constexpr int kExpRegB = 4;            // element bits per lane (16 amplitudes)
 constexpr int kExpRegMaxX = 16;        // X terms per launch (register accumulators)
 constexpr int kExpRegMaxD = 64;        // diagonal terms per launch (one per lane)
 constexpr int kExpRegMaxH = 1 << kExpRegB;
+constexpr int kExpRegMaxC = 8;         // (zsign, zl) pairs of diagonal terms with z_hi != 0
 struct ExpRegArgs {
     uint64_t n_tiles;                  // wavefront tiles, 2^(n - 6 - kExpRegB)
     uint32_t pos[6 + kExpRegB];        // ascending global positions of the tile bits
@@ -341,8 +344,22 @@ struct ExpRegArgs {
     uint32_t rpos[kExpRegB];
     uint32_t hval[kExpRegMaxH];
     uint32_t hoff[kExpRegMaxH + 1];    // diagonal terms of mask hval[h]: [hoff[h], hoff[h + 1])
+    uint32_t csign[kExpRegMaxC];       // pairs (zsign, zl) of the diagonal terms with z_hi != 0
+    uint32_t clane[kExpRegMaxC];
     int32_t n_x, n_d, n_h;             // X terms (first in the term array), diagonal terms, masks
+    int32_t n_c, n_din;                // pairs; diagonal terms with z_hi = 0
+    // the last n_xb X terms refer to the transposed tile: element bit i on
+    // lpos[i] (i < 4), lane bits 0, 1 on lpos[4], lpos[5], lane bits 2..5 on
+    // rpos[0..3] (complex64 only)
+    int32_t n_xb;
 };
+// LDS bytes per wavefront of a k_expect_reg launch: per-lane slots of the X
+// terms and of the (zsign, zl) pairs, then the transposition buffer (the
+// 2^10 amplitudes with 16 bytes of padding after every 16)
+__host__ __device__ inline size_t expect_reg_wave_lds(const ExpRegArgs &a, size_t amp_bytes) {
+    const size_t tb = a.n_xb > 0 ? (1024 + 64 * (16 / amp_bytes)) * amp_bytes : 0;
+    return size_t(a.n_x + a.n_c) * 64 * sizeof(double) + tb;
+}
 
 // ---- batched persistent launch: device program ---------------------------
 enum BatchFlags { BATCH_INIT = 1, BATCH_STORE = 2 };

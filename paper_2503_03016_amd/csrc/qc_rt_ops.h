@@ -12,6 +12,7 @@
 #pragma once
 
 #include "qc_internal.h"
+#include "qc_lanes.h"
 
 namespace qcx {
 namespace rt {
@@ -394,16 +395,11 @@ __device__ __forceinline__ void apply_mode(cx<R> &a0, cx<R> &a1, const cx<R> *u)
     }
 }
 
-__device__ __forceinline__ double wave_sum_rt(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // add this wavefront's sum of v into its column of gradient slot `slot`
-// (each wavefront owns one column: the additions keep a fixed order)
+// (each wavefront owns one column: the additions keep a fixed order); the
+// sum runs on DPP and permlane exchanges, no LDS round trips
 __device__ __forceinline__ void grad_add(double *acc, int slot, uint32_t wave, double v) {
-    v = wave_sum_rt(v);
+    v = lanes::wave_sum(v);
     if ((threadIdx.x & 63u) == 0) acc[slot * 8 + int(wave)] += v;
 }
 
