@@ -2544,26 +2544,36 @@ void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint6
         for (int j = 0, p = 0; p < n; ++p)
             if ((P >> p) & 1) a.pos[j++] = uint32_t(p);
         a.n_tiles = uint64_t(1) << (n - 6 - RB);
-        // the transposed tile of the first complex64 expectation pass: lane
-        // bits on lpos[4], lpos[5], rpos[0..3], element bits on lpos[0..3]
-        const bool transpose = for_expect && was_first && dtype == QC_C64;
-        uint32_t tl_pos[6] = {a.lpos[4], a.lpos[5], a.rpos[0], a.rpos[1], a.rpos[2], a.rpos[3]};
+        // the transposed tile of complex64 expectation passes (loaded tile
+        // bit j < 6 = lane bit j, 6 + i = element bit i).  First pass: the
+        // element bits of the transposed tile are lane bits 0..3 and its
+        // lane bits 0, 1 lane bits 4, 5 (DPP partners); later passes: its
+        // element bits 2, 3 are lane bits 4, 5.  Padding of one amplitude
+        // per 16 (first) or 64 (later) keeps both LDS access patterns free
+        // of bank conflicts.
+        const bool transpose = for_expect && dtype == QC_C64;
+        static const uint32_t tl_first[6] = {4, 5, 6, 7, 8, 9}, te_first[4] = {0, 1, 2, 3};
+        static const uint32_t tl_later[6] = {2, 3, 6, 7, 8, 9}, te_later[4] = {0, 1, 4, 5};
+        const uint32_t *tl = was_first ? tl_first : tl_later, *te = was_first ? te_first : te_later;
+        auto gpos = [&](uint32_t j) { return j < 6 ? a.lpos[j] : a.rpos[j - 6]; };
         auto on_tlanes = [&](uint64_t m) {
             uint32_t r = 0;
             for (int k = 0; k < 6; ++k)
-                if ((m >> tl_pos[k]) & 1) r |= 1u << k;
+                if ((m >> gpos(tl[k])) & 1) r |= 1u << k;
             return r;
         };
         auto on_telems = [&](uint64_t m) {
             uint32_t r = 0;
             for (int i = 0; i < RB; ++i)
-                if ((m >> a.lpos[i]) & 1) r |= 1u << i;
+                if ((m >> gpos(te[i])) & 1) r |= 1u << i;
             return r;
         };
-        // an X term on one lane bit goes to the transposed tile: bits 0..3
-        // become element bits there, bits 4, 5 lane bits 0, 1 (DPP partners)
+        // an X term on one lane bit goes to the transposed tile where that
+        // saves LDS permutes or DPP moves: lane bits 0..5 in the first pass,
+        // 4 and 5 in the later ones
         auto to_transposed = [&](int t) {
-            return transpose && on_elems(xm[t]) == 0 && __builtin_popcount(on_lanes(xm[t])) == 1;
+            if (!transpose || on_elems(xm[t]) != 0 || __builtin_popcount(on_lanes(xm[t])) != 1) return false;
+            return was_first || __builtin_ctz(on_lanes(xm[t])) >= 4;
         };
         auto term = [&](int t) {
             const bool tr = to_transposed(t);
@@ -2578,6 +2588,12 @@ void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint6
             e.ph = ph[t];
             e.hk = -1;
             e.ck = -1;
+            // X terms: element bit i -> mode i; a lane bit below 4 -> DPP
+            // partners, mode 4 + b; any other lane mask -> LDS permutes, mode 8
+            int mode = 8;
+            if (e.xr != 0) mode = __builtin_ctz(e.xr);
+            else if (__builtin_popcount(e.xl) == 1 && e.xl < 16) mode = 4 + __builtin_ctz(e.xl);
+            e.kind = 2 * mode + (ph[t] & 1);
             return e;
         };
         size_t xi = 0, di = 0;
@@ -2596,6 +2612,10 @@ void plan_register_passes(int n, int dtype, int n_terms, const std::vector<uint6
             RegLaunch L;
             L.a = a;
             L.a.n_xb = 0;
+            for (int k = 0; k < 6; ++k) L.a.tl[k] = tl[k];
+            for (int i = 0; i < RB; ++i) L.a.te[i] = te[i];
+            L.a.tsh = was_first ? 4 : 6;
+            L.a.tpad = 1;
             for (int pass_b = 0; pass_b < 2; ++pass_b)   // untransposed terms first
                 for (size_t k = xi; k < x1; ++k) {
                     if (to_transposed(xs[k]) != (pass_b == 1)) continue;

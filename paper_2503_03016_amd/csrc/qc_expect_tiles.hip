@@ -342,18 +342,6 @@ __device__ __forceinline__ double elem_pairs(const cx<R> *v, uint32_t zsign) {
     return 2.0 * acc;
 }
 
-// an element mask of one bit (the host gives the element slots no other)
-template <typename R, bool ODD>
-__device__ __forceinline__ double elem_term(const cx<R> *v, uint32_t xr, uint32_t zsign) {
-    switch (xr) {
-    case 1: return elem_pairs<R, 1, ODD>(v, zsign);
-    case 2: return elem_pairs<R, 2, ODD>(v, zsign);
-    case 4: return elem_pairs<R, 4, ODD>(v, zsign);
-    case 8: return elem_pairs<R, 8, ODD>(v, zsign);
-    default: return 0.0;
-    }
-}
-
 // amplitude of lane (lane ^ m) (m uniform)
 __device__ __forceinline__ cx<float> shfl_amp(cx<float> x, uint32_t m) {
     return cx<float>{__shfl_xor(x.re, int(m), 64), __shfl_xor(x.im, int(m), 64)};
@@ -410,21 +398,6 @@ __device__ __forceinline__ double lane_bit_term(const cx<double> *w, uint32_t zs
     return ((lane >> B) & 1u) ? 0.0 : 2.0 * acc;
 }
 
-// Lane bits 0..3 take their partner through DPP row shifts (VALU); bits 4
-// and 5, and masks of several bits, through LDS permutes: a permlane swap
-// needs copies of both registers and costs more VALU than the permute
-// leaves to the LDS.
-template <bool ODD>
-__device__ __forceinline__ double lane_any(const cx<double> *w, uint32_t xl, uint32_t zsign, uint32_t lane) {
-    switch (xl) {   // uniform
-    case 1: return lane_bit_term<0, ODD>(w, zsign, lane);
-    case 2: return lane_bit_term<1, ODD>(w, zsign, lane);
-    case 4: return lane_bit_term<2, ODD>(w, zsign, lane);
-    case 8: return lane_bit_term<3, ODD>(w, zsign, lane);
-    default: return lane_term<double, ODD>(w, xl, zsign);
-    }
-}
-
 // Register-tile pass.  Diagonal terms, with p_e = |psi|^2 of element e:
 //  - z_hi = 0 (every Z bit in the tile): the lane adds p_e over its tiles
 //    (pacc); after the last tile, sum_e (-1)^popc(e & zr) pacc_e with the
@@ -467,9 +440,17 @@ void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
     for (int k = 0; k < nx; ++k) xacc[64 * k] = 0.0;
     // lane k of rc: a pair's sum over the k-th tile of the current group
     double *rc = wlds + 64 * nx + lane;
-    // transposition buffer: amplitude i of the tile at i + pad (i / 16)
-    constexpr int pad = 16 / int(sizeof(cx<R>));
+    // transposition buffer: tile index j at j + tpad (j >> tsh); this lane's
+    // slot offsets for the loaded layout (index lane + 64 e) and for the
+    // transposed one (lane bits on tile bits tl, element bits on te); the
+    // bits of the two parts are disjoint, so their padded offsets add
     constexpr bool kTrans = sizeof(R) == 4;   // complex64 only (LDS budget)
+    auto padded = [&](uint32_t j) { return j + a.tpad * (j >> a.tsh); };
+    uint32_t tr_lane = 0;
+    for (int k = 0; k < 6; ++k)
+        if ((lane >> k) & 1u) tr_lane |= 1u << a.tl[k];
+    tr_lane = padded(tr_lane);
+    const uint32_t wr_lane = padded(lane);
     cx<R> *tb = reinterpret_cast<cx<R> *>(wlds + 64 * (nx + a.n_c));
     if (DIAG) {
         for (int d = int(lane); d < a.n_d; d += 64) red[wave][kExpRegMaxX + d] = 0.0;
@@ -505,10 +486,7 @@ void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
         const uint64_t base = cbase;
         if (kTrans && a.n_xb > 0) {   // uniform: the tile into the transposition buffer
 #pragma unroll
-            for (int e = 0; e < kRegE; ++e) {
-                const uint32_t i = lane + 64u * uint32_t(e);
-                tb[i + pad * (i >> 4)] = cur[e];
-            }
+            for (int e = 0; e < kRegE; ++e) tb[wr_lane + padded(64u * uint32_t(e))] = cur[e];
         }
         // the tile in FP64, converted once
         cx<double> w[kRegE];
@@ -519,22 +497,40 @@ void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
         auto x_terms = [&](int k0, int k1) {
             for (int k = k0; k < k1; ++k) {   // uniform
                 const ExpRegTerm tm = terms[k];
-                const bool odd_ph = tm.ph & 1;
                 // an empty asm that claims to change w: the pair products of
                 // every element mask would otherwise be hoisted out of the term
                 // loop (64 FP64 values held across it, spilled registers)
     #pragma unroll
                 for (int e = 0; e < kRegE; ++e) asm volatile("" : "+v"(w[e].re), "+v"(w[e].im));
-                double s;
-                if (tm.xr == 0)
-                    s = odd_ph ? lane_any<true>(w, tm.xl, tm.zsign, lane) : lane_any<false>(w, tm.xl, tm.zsign, lane);
-                else
-                    s = odd_ph ? elem_term<double, true>(w, tm.xr, tm.zsign) : elem_term<double, false>(w, tm.xr, tm.zsign);
+                double s = 0.0;
+                switch (tm.kind) {   // uniform, one dispatch per term
+                case 0: s = elem_pairs<double, 1, false>(w, tm.zsign); break;
+                case 1: s = elem_pairs<double, 1, true>(w, tm.zsign); break;
+                case 2: s = elem_pairs<double, 2, false>(w, tm.zsign); break;
+                case 3: s = elem_pairs<double, 2, true>(w, tm.zsign); break;
+                case 4: s = elem_pairs<double, 4, false>(w, tm.zsign); break;
+                case 5: s = elem_pairs<double, 4, true>(w, tm.zsign); break;
+                case 6: s = elem_pairs<double, 8, false>(w, tm.zsign); break;
+                case 7: s = elem_pairs<double, 8, true>(w, tm.zsign); break;
+                case 8: s = lane_bit_term<0, false>(w, tm.zsign, lane); break;
+                case 9: s = lane_bit_term<0, true>(w, tm.zsign, lane); break;
+                case 10: s = lane_bit_term<1, false>(w, tm.zsign, lane); break;
+                case 11: s = lane_bit_term<1, true>(w, tm.zsign, lane); break;
+                case 12: s = lane_bit_term<2, false>(w, tm.zsign, lane); break;
+                case 13: s = lane_bit_term<2, true>(w, tm.zsign, lane); break;
+                case 14: s = lane_bit_term<3, false>(w, tm.zsign, lane); break;
+                case 15: s = lane_bit_term<3, true>(w, tm.zsign, lane); break;
+                case 16: s = lane_term<double, false>(w, tm.xl, tm.zsign); break;
+                case 17: s = lane_term<double, true>(w, tm.xl, tm.zsign); break;
+                default: break;   // the host emits no other kinds
+                }
                 // Re[i^ph c]: ph 0 -> Re c, 1 -> -Im c, 2 -> -Re c, 3 -> Im c; then
                 // the signs of the Z bits on the lane and outside the tile
                 const uint32_t neg = uint32_t((tm.ph == 1 || tm.ph == 2) + __popc(lane & tm.zl) +
                                               __popcll(base & tm.z_hi)) & 1u;
-                xacc[64 * k] += neg ? -s : s;
+                // LDS add without return: no wait on the slot's old value
+                __hip_atomic_fetch_add(xacc + 64 * k, neg ? -s : s, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
         };
         x_terms(0, nxa);
@@ -582,7 +578,7 @@ void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
                 t_grp = t + nw;
             }
         }
-        if (kTrans && a.n_xb > 0) {   // uniform: the transposed tile, lane l holding 16 l .. 16 l + 15
+        if (kTrans && a.n_xb > 0) {   // uniform: the transposed tile
             // LDS accesses of one wavefront are performed in order: the
             // fences only keep the compiler from moving them
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -590,7 +586,11 @@ void k_expect_reg(const cx<R> *__restrict__ amp, const ExpRegArgs a,
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
             for (int f = 0; f < kRegE; ++f) {
-                const cx<R> x = tb[(16 + pad) * lane + uint32_t(f)];
+                uint32_t o = 0;
+#pragma unroll
+                for (int i = 0; i < kExpRegB; ++i)
+                    if ((f >> i) & 1) o |= 1u << a.te[i];
+                const cx<R> x = tb[tr_lane + padded(o)];
                 w[f] = cx<double>{double(x.re), double(x.im)};
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -788,7 +788,8 @@ hipError_t launch_expect_reg(const void *amp, int dtype, const ExpRegArgs &a,
         a.n_h < 0 || a.n_h > kExpRegMaxH || (a.n_d > 0 && a.n_h < 1) || a.n_tiles < 1 ||
         a.n_c < 0 || a.n_c > kExpRegMaxC || a.n_din < 0 || a.n_din > a.n_d)
         return hipErrorInvalidValue;
-    if (a.n_xb < 0 || a.n_xb > a.n_x || (a.n_xb > 0 && dtype != QC_C64)) return hipErrorInvalidValue;
+    if (a.n_xb < 0 || a.n_xb > a.n_x || (a.n_xb > 0 && (dtype != QC_C64 || a.tsh < 4 || a.tsh > 6)))
+        return hipErrorInvalidValue;
     const unsigned grid = expect_reg_grid(a.n_tiles);
     const bool diag = a.n_d > 0;
     const size_t lds = kRegWaves * expect_reg_wave_lds(a, dtype == QC_C64 ? 8 : 16);

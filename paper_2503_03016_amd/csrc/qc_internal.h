@@ -327,10 +327,12 @@ constexpr int kExpectLowBits = 6;          // lowest bits, always tile bits (run
 // hk of their zr in the launch's list of distinct element masks hval, and
 // those with z_hi != 0 the index ck of their (zsign, zl) pair in the
 // launch's list of such pairs (ck = -1 when z_hi = 0).
+// X terms carry kind = 2 mode + (ph odd): mode i < 4 the element bit i,
+// 4 + b lane bit b < 4, 8 any other lane mask.
 struct ExpRegTerm {
     uint64_t z_hi;
     uint32_t xl, xr, zl, zsign;
-    int32_t ph, hk, ck;
+    int32_t ph, hk, ck, kind;
 };
 constexpr int kExpRegB = 4;            // element bits per lane (16 amplitudes)
 constexpr int kExpRegMaxX = 16;        // X terms per launch (register accumulators)
@@ -348,16 +350,18 @@ struct ExpRegArgs {
     uint32_t clane[kExpRegMaxC];
     int32_t n_x, n_d, n_h;             // X terms (first in the term array), diagonal terms, masks
     int32_t n_c, n_din;                // pairs; diagonal terms with z_hi = 0
-    // the last n_xb X terms refer to the transposed tile: element bit i on
-    // lpos[i] (i < 4), lane bits 0, 1 on lpos[4], lpos[5], lane bits 2..5 on
-    // rpos[0..3] (complex64 only)
+    // the last n_xb X terms refer to the transposed tile (complex64 only):
+    // lane bit k on tile bit tl[k], element bit i on tile bit te[i] (tile
+    // bit j < 6 is lane bit j, 6 + i element bit i of the loaded layout);
+    // in LDS tile index j sits at j + tpad (j >> tsh)
     int32_t n_xb;
+    uint32_t tl[6], te[kExpRegB];
+    uint32_t tsh, tpad;
 };
 // LDS bytes per wavefront of a k_expect_reg launch: per-lane slots of the X
-// terms and of the (zsign, zl) pairs, then the transposition buffer (the
-// 2^10 amplitudes with 16 bytes of padding after every 16)
+// terms and of the (zsign, zl) pairs, then the transposition buffer
 __host__ __device__ inline size_t expect_reg_wave_lds(const ExpRegArgs &a, size_t amp_bytes) {
-    const size_t tb = a.n_xb > 0 ? (1024 + 64 * (16 / amp_bytes)) * amp_bytes : 0;
+    const size_t tb = a.n_xb > 0 ? (1024 + a.tpad * (1024u >> a.tsh)) * amp_bytes : 0;
     return size_t(a.n_x + a.n_c) * 64 * sizeof(double) + tb;
 }
 
