@@ -269,26 +269,24 @@ __global__ __launch_bounds__(kBlock) void k_expect_rows(const double *part, int 
     }
 }
 
-// ---- register tiles: one wavefront per tile, no LDS staging -----------------
+// ---- register tiles: one wavefront per tile ----------------------------------
 //
 // Lane l holds the 16 amplitudes e of its tile in registers, in the state's
-// precision; every product is formed in FP64.  For a term whose X bits lie
-// in the tile, the partner of element (l, e) is element (l ^ xl, e ^ xr).
-// The kernel takes the terms whose X bits are on the lanes only (the
-// partner comes from lane l ^ xl by a shuffle) or on one element bit (a
-// register of the lane itself, compile-time index per bit); each lane sums
-// over its elements
-//   Re[i^ph (-1)^popc(j & z) conj(psi_{j ^ x}) psi_j],
-// so the two members of a pair across lanes are counted on their own sides,
-// and a pair inside one lane is taken once and doubled.  The sign of the Z
-// bits outside the tile and on the lane bits is applied per tile and lane.
+// precision, and converts them to FP64 once; every product and sum is FP64.
+// For a term whose X bits lie in the tile, the partner of element (l, e) is
+// element (l ^ xl, e ^ xr).  The kernel takes the terms whose X bits are
+// one element bit (a register of the lane itself, compile-time index per
+// bit; each pair taken once and doubled), one lane bit below 4 (the partner
+// through a DPP row shift; the lane with the bit clear takes the pair twice)
+// or any lane mask (an LDS permute; each lane counts its own side).  The
+// host gives each X term a kind that names its case.  Complex64 passes
+// also write the tile to a padded LDS buffer and read it back under a
+// second layout in which the lane bits of some terms are element bits; the
+// host assigns those terms to the second layout.  The sign of the Z bits
+// outside the tile and on the lane bits is applied per tile and lane, and
+// each lane adds its term partials to its own LDS slots.
 //
-// Diagonal terms: |psi|^2 of the 16 elements, its Walsh transform over the
-// element bits, the entry of the term's element mask zr continued by a
-// Walsh transform over the lane bits (butterflies between lanes): lane f
-// then holds sum_j (-1)^popc(j & z) |psi_j|^2 for lane mask f, and lane d,
-// which owns diagonal term d, fetches the entry of its lane mask zl.  One
-// transform over the lanes serves every term with the same zr.
+// Diagonal terms: see k_expect_reg.
 //
 // The next tile's loads are issued before the current tile is evaluated.
 // Tiles are dealt to wavefronts round-robin for a fixed grid, and every
