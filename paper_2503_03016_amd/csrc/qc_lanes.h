@@ -60,6 +60,18 @@ __device__ __forceinline__ double swap_add(double x) {
     return a + b;
 }
 
+// OR over the 64 lanes, on every lane (same exchange pattern as the sum)
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    v |= uint32_t(__builtin_amdgcn_mov_dpp(int(v), kQuadXor1, 0xf, 0xf, false));
+    v |= uint32_t(__builtin_amdgcn_mov_dpp(int(v), kQuadXor2, 0xf, 0xf, false));
+    v |= uint32_t(__builtin_amdgcn_mov_dpp(int(v), kRowHalfMirror, 0xf, 0xf, false));
+    v |= uint32_t(__builtin_amdgcn_mov_dpp(int(v), kRowMirror, 0xf, 0xf, false));
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = r[0] | r[1];
+    const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return q[0] | q[1];
+}
+
 // sum over the 64 lanes, on every lane: pairs within quads, quads within
 // eights (half mirror), eights within rows (mirror), rows by swaps; the two
 // lanes of each exchange add the same two values, so every lane ends with

@@ -12,6 +12,7 @@
 // workgroup loads the tile at base and its partner, and writes each one,
 // permuted inside, to the other's place; a tile that is its own partner is
 // permuted in place.  The low positions keep the HBM runs contiguous.
+#include "qc_lanes.h"
 #include "qc_tile_ops.h"
 
 #include "../../include/qc.h"
@@ -53,7 +54,7 @@ __device__ inline int padded(int j) { return j + (j >> 5); }
 template <typename R>
 __device__ inline void put_permuted(cx<R> *amp, cx<R> *lds, const cx<R> (&v)[max_k<R>()],
                                     uint64_t dst, uint64_t off_lo, uint64_t mask, int T, int K,
-                                    const PermuteArgs &a) {
+                                    const uint32_t (&sq)[max_k<R>()]) {
 #pragma unroll
     for (int k = 0; k < max_k<R>(); ++k) {
         const int j = int(threadIdx.x) + k * kBlock;
@@ -64,10 +65,7 @@ __device__ inline void put_permuted(cx<R> *amp, cx<R> *lds, const cx<R> (&v)[max
 #pragma unroll
     for (int k = 0; k < max_k<R>(); ++k) {
         const int j = int(threadIdx.x) + k * kBlock;
-        if (k < K && j < T) {
-            const uint32_t s = a.sq_lo[j & 63] | a.sq_hi[j >> 6];
-            amp[dst + off_lo + d] = lds[padded(int(s))];
-        }
+        if (k < K && j < T) amp[dst + off_lo + d] = lds[padded(int(sq[k]))];
         d = tile::next_submask(d, mask);
     }
 }
@@ -81,29 +79,78 @@ __global__ __launch_bounds__(kBlock) void k_permute_pairs(cx<R> *amp, const Perm
         tile::deposit(uint32_t(threadIdx.x) & (T - 1), a.pos, a.m < tile::kLoBits ? a.m : tile::kLoBits);
     const uint64_t mask = tile::hi_mask(a.pos, a.m);
     const int K = T > kBlock ? T >> tile::kLoBits : 1;
-    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-        const uint64_t base = insert_zeros(t, a.pos, a.m);
-        uint64_t pb = 0;   // sigma(base): the bits outside Q, moved
-        for (uint64_t r = base; r; r &= r - 1) pb |= uint64_t(1) << a.sigma[__builtin_ctzll(r)];
-        if (pb < base) continue;   // the workgroup of the partner tile moves both (uniform)
+    // sigma_Q of this thread's elements, once: the tables sit in the kernel
+    // arguments, and a lookup with a per-thread index is a memory load
+    uint32_t sq[max_k<R>()];
+#pragma unroll
+    for (int k = 0; k < max_k<R>(); ++k) {
+        const int j = int(threadIdx.x) + k * kBlock;
+        sq[k] = k < K && j < T ? (a.sq_lo[j & 63] | a.sq_hi[j >> 6]) : 0u;
+    }
+    // tile t: its base (the bits of t around Q; a loop of fixed bound, so
+    // the positions are read once) and its partner's base sigma(base), the
+    // bits moved one per lane (lane p holds sigma(p)) and OR-ed across the
+    // wavefront: no chain of dependent scalar loads per tile
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t sig = lane < uint32_t(a.n) ? a.sigma[lane] : 0u;
+    auto tile_of = [&](uint64_t t, uint64_t &base, uint64_t &pb) {
+        uint64_t g = t;
+#pragma unroll
+        for (int j = 0; j < kPermMaxBits; ++j)
+            if (j < a.m) g = insert_zero(g, int(a.pos[j]));
+        base = g;
+        const uint64_t mine = lane < uint32_t(a.n) && ((g >> lane) & 1u) ? uint64_t(1) << sig : 0;
+        const uint32_t lo = lanes::wave_or(uint32_t(mine)), hi = lanes::wave_or(uint32_t(mine >> 32));
+        pb = (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(hi)))) << 32) |
+             uint32_t(__builtin_amdgcn_readfirstlane(int(lo)));
+    };
+    // the next tile from tt on whose partner does not precede it (the
+    // workgroup of the partner tile moves both); false past the last
+    auto next_pair = [&](uint64_t &tt, uint64_t &base, uint64_t &pb) {
+        for (; tt < a.n_tiles; tt += gridDim.x) {   // uniform
+            tile_of(tt, base, pb);
+            if (pb >= base) return true;
+        }
+        return false;
+    };
+    // both tiles' loads in flight before any is waited for
+    auto load_pair = [&](cx<R> (&x)[max_k<R>()], cx<R> (&y)[max_k<R>()], uint64_t base, uint64_t pb) {
         const bool pair = pb != base;
-        // both tiles' loads in flight before any is waited for
-        cx<R> va[max_k<R>()], vb[max_k<R>()];
         uint64_t d = 0;
 #pragma unroll
         for (int k = 0; k < max_k<R>(); ++k) {
-            va[k] = k < K ? amp[base + off_lo + d] : cx<R>{R(0), R(0)};
-            vb[k] = k < K && pair ? amp[pb + off_lo + d] : cx<R>{R(0), R(0)};
+            x[k] = k < K ? amp[base + off_lo + d] : cx<R>{R(0), R(0)};
+            y[k] = k < K && pair ? amp[pb + off_lo + d] : cx<R>{R(0), R(0)};
             d = tile::next_submask(d, mask);
         }
+    };
+    uint64_t t = blockIdx.x, base = 0, pb = 0;
+    bool have = next_pair(t, base, pb);
+    cx<R> va[max_k<R>()], vb[max_k<R>()];
+    if (have) load_pair(va, vb, base, pb);
+    while (have) {   // uniform
+        // the next pair's loads go out before this pair's stores
+        uint64_t t2 = t + gridDim.x, base2 = 0, pb2 = 0;
+        const bool have2 = next_pair(t2, base2, pb2);
+        cx<R> na[max_k<R>()], nb[max_k<R>()];
+        if (have2) load_pair(na, nb, base2, pb2);
         // new[sigma(i)] = old[i]: the tile at pb receives the tile at base,
         // permuted by sigma_Q, and the other way round
-        put_permuted<R>(amp, lds, va, pb, off_lo, mask, T, K, a);
-        if (pair) {
+        put_permuted<R>(amp, lds, va, pb, off_lo, mask, T, K, sq);
+        if (pb != base) {
             __syncthreads();
-            put_permuted<R>(amp, lds, vb, base, off_lo, mask, T, K, a);
+            put_permuted<R>(amp, lds, vb, base, off_lo, mask, T, K, sq);
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < max_k<R>(); ++k) {
+            va[k] = na[k];
+            vb[k] = nb[k];
+        }
+        t = t2;
+        base = base2;
+        pb = pb2;
+        have = have2;
     }
 }
 
