@@ -1706,6 +1706,74 @@ struct RtLowering {
         out.push_back(r);
     }
 
+    // a block of commuting diagonal rotations (backward pass): the element
+    // factors of the register-slot entries and the common factor in u, the
+    // thread-bit entries in lane / wave tables, the out-of-tile entries in
+    // window tables (as for a fan); gradient entries in the slot order the
+    // host assigned (in-tile by ascending compressed bit, then out-of-tile)
+    void dgrad(const qcx::TileOp &op) {
+        qcx::RtOp r{};
+        r.kind = qcx::rt_code(qcx::RT_DGRAD, 0);
+        const uint32_t in_mask = uint32_t(op.b1);
+        for (int e = 0; e < E(); ++e) {
+            cd g(op.u1[0], op.u1[1]);
+            for (int c = 0; c < m; ++c)
+                if (((in_mask >> c) & 1) && L.slot_of[c] < rb && ((e >> L.slot_of[c]) & 1))
+                    g *= cd(op.u[2 * c], op.u[2 * c + 1]);
+            put_c(r.u, e, g);
+        }
+        std::vector<cd> lane(64, cd(1.0)), wave(8, cd(1.0));
+        int nt = 0;
+        auto entry = [&](uint32_t loc) {
+            r.w[1 + nt] = loc | (uint32_t(op.b0 + nt) << 8);
+            ++nt;
+        };
+        for (int c = 0; c < m; ++c) {
+            if (!((in_mask >> c) & 1)) continue;
+            const int sl = L.slot_of[c];
+            if (sl < rb) {
+                entry(uint32_t(sl));
+                continue;
+            }
+            const int tbit = sl - rb;
+            entry(uint32_t(8 + tbit));
+            const cd p(op.u[2 * c], op.u[2 * c + 1]);
+            if (tbit < 6) {
+                for (int l = 0; l < 64; ++l)
+                    if ((l >> tbit) & 1) lane[l] *= p;
+            } else {
+                for (int w8 = 0; w8 < 8; ++w8)
+                    if ((w8 >> (tbit - 6)) & 1) wave[w8] *= p;
+            }
+        }
+        uint64_t hi_all = 0;
+        for (int h = 0; h < op.pad; ++h) {
+            hi_all |= op.fan_mask[h];
+            entry(uint32_t(32 + __builtin_ctzll(op.fan_mask[h])));
+        }
+        r.nt = nt;
+        const std::vector<int> win = windows_of(hi_all);
+        if (win.size() > size_t(qcx::kRtWindows)) too_wide = true;
+        r.w[0] = add_ctab(lblob, lane);
+        for (int w8 = 0; w8 < 8; ++w8) put_c(r.ph, w8, wave[w8]);
+        r.b = int(std::min(win.size(), size_t(qcx::kRtWindows)));
+        for (int j = r.b; j < qcx::kRtWindows; ++j)   // unused windows: factor 1
+            for (int x = 0; x < 8; ++x) put_c(r.ph, 8 + 8 * j + x, cd(1.0));
+        for (int j = 0; j < r.b; ++j) {
+            for (int x = 0; x < 8; ++x) {
+                cd t(1.0);
+                for (int h = 0; h < op.pad; ++h) {
+                    const int p = __builtin_ctzll(op.fan_mask[h]);
+                    if (p >= win[j] && p < win[j] + 3 && ((x >> (p - win[j])) & 1))
+                        t *= cd(op.fan_ph[2 * h], op.fan_ph[2 * h + 1]);
+                }
+                put_c(r.ph, 8 + 8 * j + x, t);
+            }
+            r.hw[j] = uint64_t(win[j]);
+        }
+        out.push_back(r);
+    }
+
     // a Hadamard followed by the fan on the same register slot: one op; two
     // such ops in a row on different slots: one RT_HFAN2 op and the second
     // one's data (the interpreter copies every element register once per
@@ -1781,6 +1849,7 @@ struct RtLowering {
         } break;
         case qcx::TILE_PHASES: phases_of(op, op.b0); break;
         case qcx::TILE_FAN: fan(op); break;
+        case qcx::TILE_DGRAD: dgrad(op); break;
         case qcx::TILE_GRAD:
         case qcx::TILE_GRAD_APPLY:
         case qcx::TILE_GRAD_APPLY_REAL:
@@ -3144,6 +3213,39 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
             extra[n_ops - 1 - k] = uint64_t(1) << bitpos(n, o.q0);   // reduction needs the bit
         }
     }
+    // register-tile backward runs take the diagonal rotations of a layer as
+    // one block (RT_DGRAD): every rotation with a non-diagonal matrix moves
+    // later in the backward list past the gates that do not act on its
+    // qubit (they commute with it and with its generator, so the gradients
+    // are unchanged), which leaves a layer's diagonal rotations next to each
+    // other; their bits then need not be tile bits
+    const bool rt_bwd = g_knob_tile_engine.load() == 1 && mb == qcx::rt_adj_reg_bits(psi.dtype) + 9 &&
+                        n - mb >= kRtMinTileBits;
+    auto diag_gate = [&](const qc_gate_t &g) {
+        const double *mu = g.matrix;
+        return g.n_targets == 1 && mu[2] == 0 && mu[3] == 0 && mu[4] == 0 && mu[5] == 0;
+    };
+    auto touches = [&](const qc_gate_t &g, int q) {
+        if (g.targets[0] == q) return true;
+        for (int i = 0; i < g.n_ctrls; ++i)
+            if (g.ctrls[i] == q) return true;
+        return false;
+    };
+    auto dblock_rot = [&](int k) { return rt_bwd && rot_row[k] >= 0 && gen_of[k] == 3 && diag_gate(bwd[k]); };
+    if (rt_bwd) {
+        for (int i = n_ops - 2; i >= 0; --i) {
+            if (rot_row[i] < 0 || diag_gate(bwd[i])) continue;
+            const int q = bwd[i].targets[0];
+            for (int j = i; j + 1 < n_ops && !touches(bwd[j + 1], q); ++j) {
+                std::swap(bwd[j], bwd[j + 1]);
+                std::swap(rot_row[j], rot_row[j + 1]);
+                std::swap(gen_of[j], gen_of[j + 1]);
+                std::swap(extra[j], extra[j + 1]);
+            }
+        }
+        for (int k = 0; k < n_ops; ++k)
+            if (dblock_rot(k)) extra[k] = 0;
+    }
     // forward: phi = U_L .. U_1 psi in LDS tile runs (at these sizes a fused
     // sweep is shorter than building its block matrices on the host)
     qc_exec_stats_t st{};
@@ -3159,8 +3261,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
     form_runs(n, mb, n_ops, bwd.data(), extra.data(), runs);
     std::vector<qcx::TileOp> tops;
     std::vector<int32_t> slot_row;
-    const bool rt = g_knob_tile_engine.load() == 1 && mb == qcx::rt_adj_reg_bits(psi.dtype) + 9 &&
-                    n - mb >= kRtMinTileBits;
+    const bool rt = rt_bwd;
     const int max_slots = rt ? qcx::kRtAdjSlots : qcx::kAdjointMaxSlots;
     std::vector<unsigned char> rbuf;
     auto flush = [&](uint64_t P) -> int {
@@ -3170,6 +3271,10 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
             qcx::RtArgs ra{};
             size_t tab_off = 0;
             rt_program(n, mb, psi.dtype, P, tops, ra, rbuf, tab_off, true);
+            bool has_dblock = false;
+            for (const qcx::TileOp &o : tops) has_dblock = has_dblock || o.kind == qcx::TILE_DGRAD;
+            if (ra.lds_tab_bytes > kRtLdsTabMax && has_dblock)   // the LDS engine has no such op
+                return fail(QC_ERR_UNSUPPORTED, "backward program exceeds the register-tile table budget");
             if (ra.lds_tab_bytes <= kRtLdsTabMax) {
                 void *pdev = nullptr, *sdev = nullptr;
                 int r2 = stage(c, rbuf.data(), rbuf.size(), hs, &pdev);
@@ -3199,13 +3304,81 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         slot_row.clear();
         return e2 == hipSuccess ? QC_OK : hip_fail(e2, "adjoint_tiles");
     };
+    // the pending block of diagonal rotations: global bit, gradient row,
+    // phase of the bit's set value; the common factor apart
+    struct DEnt {
+        int pos, row;
+        cd ph;
+    };
+    std::vector<DEnt> dblk;
+    cd dcommon(1.0);
+    int dblocks = 0;   // blocks in the current launch (16 lane tables at most)
+    auto emit_dblk = [&](TileOpBuilder &B, uint64_t P) {
+        if (dblk.empty()) return;
+        qcx::TileOp op{};
+        op.kind = qcx::TILE_DGRAD;
+        op.b0 = int32_t(slot_row.size());
+        std::vector<std::pair<int, int>> in;   // (compressed bit, entry)
+        for (int i = 0; i < int(dblk.size()); ++i)
+            if ((P >> dblk[i].pos) & 1) in.push_back({B.cidx(dblk[i].pos), i});
+        std::sort(in.begin(), in.end());
+        for (const auto &ci : in) {
+            op.b1 |= 1 << ci.first;
+            op.u[2 * ci.first] = dblk[ci.second].ph.real();
+            op.u[2 * ci.first + 1] = dblk[ci.second].ph.imag();
+            slot_row.push_back(dblk[ci.second].row);
+        }
+        for (const DEnt &d : dblk) {
+            if ((P >> d.pos) & 1) continue;
+            op.fan_mask[op.pad] = uint64_t(1) << d.pos;
+            op.fan_ph[2 * op.pad] = d.ph.real();
+            op.fan_ph[2 * op.pad + 1] = d.ph.imag();
+            ++op.pad;
+            slot_row.push_back(d.row);
+        }
+        op.u1[0] = dcommon.real();
+        op.u1[1] = dcommon.imag();
+        // one-qubit gates the builder still holds on the block's tile bits
+        // go out first
+        B.add_op(op, uint32_t(op.b1));
+        dblk.clear();
+        dcommon = cd(1.0);
+        ++dblocks;
+    };
     for (const TileRun &r : runs) {
         if (r.P == 0) return fail(QC_ERR_UNSUPPORTED, "adjoint op cannot be tiled");
         TileOpBuilder B(n, r.P, tops);
         B.kron_max = 1;   // k_adjoint_tiles is compiled without TILE_KRON
         B.fans = false;   // nor with the fan ops
         B.xperms = false;   // nor with the X permutations
+        dblocks = 0;
         for (int j : r.gates) {
+            if (dblock_rot(j)) {
+                const int pos = bitpos(n, bwd[j].targets[0]);
+                int n_out = 0;
+                bool dup = false;
+                for (const DEnt &d : dblk) {
+                    dup = dup || d.pos == pos;
+                    n_out += !((r.P >> d.pos) & 1);
+                }
+                // one entry per bit, at most 8 out-of-tile bits (one window
+                // each), 48 entries
+                if (dup || dblk.size() >= 48 || (!((r.P >> pos) & 1) && n_out == 8)) emit_dblk(B, r.P);
+                if (int(slot_row.size() + dblk.size()) + 1 > max_slots || (dblk.empty() && dblocks == 16)) {
+                    emit_dblk(B, r.P);
+                    B.finish();
+                    if ((rc = flush(r.P))) return rc;
+                    dblocks = 0;
+                }
+                const double *mu = bwd[j].matrix;
+                const cd d0(mu[0], mu[1]), d1(mu[6], mu[7]);
+                dcommon *= d0;
+                dblk.push_back({pos, rot_row[j], d1 / d0});
+                continue;
+            }
+            // any other op after the block (diagonal gates without a
+            // parameter commute with it and may stay behind)
+            if (rot_row[j] >= 0 || !diag_gate(bwd[j])) emit_dblk(B, r.P);
             if (rot_row[j] >= 0) {
                 if (int(slot_row.size()) == max_slots) {
                     B.finish();
@@ -3228,6 +3401,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
             }
             B.add_gate(bwd[j]);
         }
+        emit_dblk(B, r.P);
         B.finish();
         if ((rc = flush(r.P))) return rc;
     }

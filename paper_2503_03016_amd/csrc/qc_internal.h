@@ -136,7 +136,13 @@ enum TileKind {
     TILE_DENSE1 = 0, TILE_DENSE2 = 1, TILE_PHASE = 2, TILE_DIAG1 = 3, TILE_GRAD = 4,
     TILE_PHASES = 5, TILE_GRAD_APPLY = 6, TILE_GRAD_APPLY_REAL = 7, TILE_GRAD_APPLY_DIAG = 8,
     TILE_KRON = 9, TILE_DENSE1_PHASES = 10, TILE_FAN = 11, TILE_DENSE1_FAN = 12,
-    TILE_GRAD_APPLY2_DIAG_REAL = 13, TILE_XPERM = 14
+    TILE_GRAD_APPLY2_DIAG_REAL = 13, TILE_XPERM = 14,
+    // backward pass only: a block of commuting diagonal rotations (see
+    // RT_DGRAD): in-tile entries on the compressed bits of mask b1 (bit c:
+    // the phase of its set value u[2c], u[2c + 1]), out-of-tile entries
+    // fan_mask[h] / fan_ph[h] (h < pad), a common factor u1[0], u1[1];
+    // gradient slots b0, b0 + 1, ... in that order (in-tile by ascending c)
+    TILE_DGRAD = 15
 };
 constexpr int kXpermTerms = 12;
 constexpr int kKronMax = 3;
@@ -233,6 +239,16 @@ enum RtKind {
     // with this op's fan data, the second with the next op's (a data-only
     // op the interpreter skips); code rt_hfan2_code(a, b), kinds 19 and 20
     RT_HFAN2 = 19,
+    // backward only: a block of commuting diagonal rotations exp(-i t Z_q / 2)
+    // (their inverses).  Every gradient of the block is Im <lam|Z_q|phi> of
+    // the vectors at the block's start (diagonal gates commute with each
+    // other and with Z_q), so the op takes p = Im(conj(lam) phi) of each
+    // element once and sums it with the sign of bit q: entry i (i < nt) is
+    // w[1 + i] = loc | slot << 8, loc < 8 a register slot, 8 + k thread bit
+    // k, 32 + p global bit p outside the tile.  Then both vectors take the
+    // product of the inverses: element factor u[e] times the RT_FAN thread
+    // and window factors (w[0], ph, b, hw as for RT_FAN).
+    RT_DGRAD = 21,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

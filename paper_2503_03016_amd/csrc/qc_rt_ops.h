@@ -293,6 +293,38 @@ __device__ __forceinline__ void remap(cx<R> *v, cx<R> *lds, const RtOp &op, uint
     }
 }
 
+// remap of both vectors of the backward pass: the slot offsets once, then
+// one exchange after the other through the same LDS tile
+template <typename R, int RB>
+__device__ __forceinline__ void remap2(cx<R> *vp, cx<R> *vl, cx<R> *lds, const RtOp &op, uint32_t tid,
+                                       bool act) {
+    constexpr int E = 1 << RB;
+    constexpr int EB = swz_bits<R>();
+    uint32_t t_old = 0, t_new = 0;
+#pragma unroll
+    for (int k = 0; k < kRtMaxTB; ++k) {
+        const uint32_t bit = (tid >> k) & 1u;
+        t_old |= bit << op.w[32 + k];
+        t_new |= bit << op.w[48 + k];
+    }
+    t_old = rt_swizzle<EB>(t_old);
+    t_new = rt_swizzle<EB>(t_new);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        cx<R> *x = v ? vl : vp;
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds[t_old ^ op.w[16 + e]] = x[e];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = lds[t_new ^ op.w[e]];
+        }
+    }
+}
+
 // Run ops[0 .. n_ops) on the tile at `base` held in v.  The op code is
 // kind * 8 + register slot (rt_code), so one flat switch picks the code
 // for the op and its slot: one merge of the element registers per op
@@ -437,6 +469,46 @@ __device__ __forceinline__ void grad_op(cx<R> *vp, cx<R> *vl, double *gacc, cons
     }
 }
 
+// RT_DGRAD (see qc_internal.h): the block's gradients from the vectors at
+// its start, then the product of its inverse rotations on both
+template <typename R, int RB>
+__device__ __forceinline__ void dgrad(cx<R> *vp, cx<R> *vl, double *gacc, const RtOp &op, const Tabs &tb,
+                                      uint64_t base, uint32_t tid) {
+    constexpr int E = 1 << RB;
+    double T = 0.0, D[RB];
+#pragma unroll
+    for (int s = 0; s < RB; ++s) D[s] = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const double p = double(vl[e].re * vp[e].im - vl[e].im * vp[e].re);
+        T += p;
+#pragma unroll
+        for (int s = 0; s < RB; ++s) D[s] += ((e >> s) & 1) ? -p : p;
+    }
+    const int nt = op.nt;
+    for (int i = 0; i < nt; ++i) {   // uniform
+        const uint32_t ent = op.w[1 + i], loc = ent & 0xffu;
+        double v;
+        if (loc < 8) {
+            v = D[0];
+#pragma unroll
+            for (int s = 1; s < RB; ++s) v = loc == uint32_t(s) ? D[s] : v;
+        } else if (loc < 32) {
+            v = ((tid >> (loc - 8)) & 1u) ? -T : T;
+        } else {
+            v = ((base >> (loc - 32)) & 1u) ? -T : T;
+        }
+        grad_add(gacc, int(ent >> 8), tb.wave, v);
+    }
+    const cx<R> K = fan_factor<R>(op, tb, base);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const cx<R> f = cmul(K, ldu<R>(op.u, e));
+        vp[e] = cmul(f, vp[e]);
+        vl[e] = cmul(f, vl[e]);
+    }
+}
+
 template <typename R, int RB>
 __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, double *gacc, uint64_t base,
                                 uint32_t tid, bool act, const RtOp *__restrict__ ops, int n_ops,
@@ -482,10 +554,8 @@ __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, doubl
             terms<R, RB>(vp, op, tb, base);
             terms<R, RB>(vl, op, tb, base);
             break;
-        case rt_code(RT_REMAP, 0):
-            remap<R, RB>(vp, lds, op, tid, act);
-            remap<R, RB>(vl, lds, op, tid, act);
-            break;
+        case rt_code(RT_REMAP, 0): remap2<R, RB>(vp, vl, lds, op, tid, act); break;
+        case rt_code(RT_DGRAD, 0): dgrad<R, RB>(vp, vl, gacc, op, tb, base, tid); break;
         default: __builtin_unreachable();   // the backward programs hold no other codes
         }
     }
