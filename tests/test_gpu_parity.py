@@ -667,6 +667,58 @@ def test_adjoint_shared_parameters_and_all_kinds(qc):
     assert abs(e.item() - oracle.energy(oracle.run(ops, psi0, theta), terms)) < 1e-12
 
 
+def _dblock_case():
+    n = 20
+    ops = [W.Op("RY", (q,), pidx=q % 4) for q in range(n)]
+    ops += [W.Op("RZ", (q,), pidx=4 + (q % 3)) for q in range(n)]
+    ops += [W.Op("RZ", (7,), pidx=7)]                        # a second RZ on one qubit
+    ops += [W.Op("CZ", (q, q + 1)) for q in range(0, n - 1, 2)]
+    ops += [W.Op("H", (3,)), W.Op("X", (11,)), W.Op("RX", (5,), pidx=8), W.Op("CNOT", (2, 17)),
+            W.Op("Y", (19,)), W.Op("Z", (0,))]
+    ops += [W.Op("RZ", (q,), pidx=4 + (q % 2)) for q in range(0, n, 3)]
+    ops += [W.Op("RY", (q,), pidx=q % 4) for q in range(1, n, 4)]
+    terms = list(W.tfim_terms(n)) + [("XY" + "I" * (n - 4) + "ZX", 0.4)]
+    theta = np.random.default_rng(5).normal(size=9)
+    return n, ops, terms, theta, W.random_state(n, 91)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_register_backward_diagonal_blocks(qc, dt):
+    """20 qubits, so the backward runs use register tiles: a layer's RZ
+    rotations (on register slots, thread bits and bits outside the tile,
+    one qubit twice) run as one block whose gradients come from the block's
+    start, with fixed one-qubit gates, RX, CNOT and CZ between layers and
+    shared parameters.  Against the LDS-tile backward pass (one rotation at
+    a time), the oracle's energy and its central differences."""
+    n, ops, terms, theta, psi0 = _dblock_case()
+
+    def grad(engine, dtype):
+        old = qc.get_knob(qc.QC_KNOB_TILE_ENGINE)
+        qc.set_knob(qc.QC_KNOB_TILE_ENGINE, engine)
+        try:
+            psi = dev(psi0, dtype)
+            lam = qc.new_state(n, dtype)
+            e, g = qc.adjoint_grad(psi, lam, ops, theta, terms)
+            return e.item(), g.cpu().numpy()
+        finally:
+            qc.set_knob(qc.QC_KNOB_TILE_ENGINE, old)
+
+    e_rt, g_rt = grad(1, DT[dt])
+    e_ref = oracle.energy(oracle.run(ops, psi0, theta), terms)
+    if dt == "c128":
+        e_lds, g_lds = grad(0, torch.complex128)
+        np.testing.assert_allclose(g_rt, g_lds, atol=1e-12)
+        assert abs(e_rt - e_ref) < 1e-12
+        idx = [0, 4, 5, 7, 8]
+        g_fd = oracle.fd_grad(ops, theta, terms, psi0, indices=idx)
+        np.testing.assert_allclose(g_rt[idx], g_fd, atol=1e-7)
+    else:
+        _, g128 = grad(1, torch.complex128)
+        bound = 2 * sum(abs(c) for _, c in terms) * 1e-5
+        assert abs(e_rt - e_ref) < bound
+        assert np.max(np.abs(g_rt - g128)) < bound
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_adjoint_general_hamiltonian_register_passes(qc, dt):
     """lam = H phi on a 14-qubit register (register-tile passes): terms with
