@@ -3110,6 +3110,82 @@ void merge_grad_pairs(std::vector<qcx::TileOp> &ops) {
     ops.swap(out);
 }
 
+// A pending block of diagonal rotations exp(-i t Z_q / 2) (or their
+// inverses): the global bit of each, its gradient row (backward pass), the
+// phase of the bit's set value relative to its clear value; the product of
+// the clear values apart.  One entry per bit, at most 8 bits outside the
+// tile (one window each), 48 entries.
+struct DiagBlock {
+    struct Ent {
+        int pos, row;
+        cd ph;
+    };
+    std::vector<Ent> ents;
+    cd common = cd(1.0);
+    bool empty() const { return ents.empty(); }
+    size_t size() const { return ents.size(); }
+    bool fits(int pos, uint64_t P) const {
+        int n_out = 0;
+        for (const Ent &d : ents) {
+            if (d.pos == pos) return false;
+            n_out += !((P >> d.pos) & 1);
+        }
+        return ents.size() < 48 && (((P >> pos) & 1) || n_out < 8);
+    }
+    void add(int pos, int row, const double *mu) {
+        const cd d0(mu[0], mu[1]), d1(mu[6], mu[7]);
+        common *= d0;
+        ents.push_back({pos, row, d1 / d0});
+    }
+    // the TILE_DGRAD op: in-tile entries by ascending compressed bit, then
+    // the out-of-tile ones; their gradient rows appended to `rows` in that
+    // order when given (first slot b0 = rows->size())
+    qcx::TileOp op(uint64_t P, std::vector<int32_t> *rows) const {
+        qcx::TileOp o{};
+        o.kind = qcx::TILE_DGRAD;
+        o.b0 = rows ? int32_t(rows->size()) : 0;
+        auto cidx = [&](int p) { return __builtin_popcountll(P & ((uint64_t(1) << p) - 1)); };
+        std::vector<std::pair<int, int>> in;   // (compressed bit, entry)
+        for (int i = 0; i < int(ents.size()); ++i)
+            if ((P >> ents[i].pos) & 1) in.push_back({cidx(ents[i].pos), i});
+        std::sort(in.begin(), in.end());
+        for (const auto &ci : in) {
+            o.b1 |= 1 << ci.first;
+            o.u[2 * ci.first] = ents[ci.second].ph.real();
+            o.u[2 * ci.first + 1] = ents[ci.second].ph.imag();
+            if (rows) rows->push_back(ents[ci.second].row);
+        }
+        for (const Ent &d : ents) {
+            if ((P >> d.pos) & 1) continue;
+            o.fan_mask[o.pad] = uint64_t(1) << d.pos;
+            o.fan_ph[2 * o.pad] = d.ph.real();
+            o.fan_ph[2 * o.pad + 1] = d.ph.imag();
+            ++o.pad;
+            if (rows) rows->push_back(d.row);
+        }
+        o.u1[0] = common.real();
+        o.u1[1] = common.imag();
+        return o;
+    }
+    void clear() {
+        ents.clear();
+        common = cd(1.0);
+    }
+};
+
+bool diag_gate(const qc_gate_t &g) {
+    const double *mu = g.matrix;
+    return g.n_targets == 1 && mu[2] == 0 && mu[3] == 0 && mu[4] == 0 && mu[5] == 0;
+}
+
+bool gate_touches(const qc_gate_t &g, int q) {
+    for (int i = 0; i < g.n_targets; ++i)
+        if (g.targets[i] == q) return true;
+    for (int i = 0; i < g.n_ctrls; ++i)
+        if (g.ctrls[i] == q) return true;
+    return false;
+}
+
 }  // namespace
 
 int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_ops,
@@ -3221,22 +3297,12 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
     // other; their bits then need not be tile bits
     const bool rt_bwd = g_knob_tile_engine.load() == 1 && mb == qcx::rt_adj_reg_bits(psi.dtype) + 9 &&
                         n - mb >= kRtMinTileBits;
-    auto diag_gate = [&](const qc_gate_t &g) {
-        const double *mu = g.matrix;
-        return g.n_targets == 1 && mu[2] == 0 && mu[3] == 0 && mu[4] == 0 && mu[5] == 0;
-    };
-    auto touches = [&](const qc_gate_t &g, int q) {
-        if (g.targets[0] == q) return true;
-        for (int i = 0; i < g.n_ctrls; ++i)
-            if (g.ctrls[i] == q) return true;
-        return false;
-    };
     auto dblock_rot = [&](int k) { return rt_bwd && rot_row[k] >= 0 && gen_of[k] == 3 && diag_gate(bwd[k]); };
     if (rt_bwd) {
         for (int i = n_ops - 2; i >= 0; --i) {
             if (rot_row[i] < 0 || diag_gate(bwd[i])) continue;
             const int q = bwd[i].targets[0];
-            for (int j = i; j + 1 < n_ops && !touches(bwd[j + 1], q); ++j) {
+            for (int j = i; j + 1 < n_ops && !gate_touches(bwd[j + 1], q); ++j) {
                 std::swap(bwd[j], bwd[j + 1]);
                 std::swap(rot_row[j], rot_row[j + 1]);
                 std::swap(gen_of[j], gen_of[j + 1]);
@@ -3246,7 +3312,7 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         for (int k = 0; k < n_ops; ++k)
             if (dblock_rot(k)) extra[k] = 0;
     }
-    // forward: phi = U_L .. U_1 psi in LDS tile runs (at these sizes a fused
+    // forward: phi = U_L .. U_1 psi in tile runs (at these sizes a fused
     // sweep is shorter than building its block matrices on the host)
     qc_exec_stats_t st{};
     if ((rc = tiled_execute(psi, n_ops, fwd.data(), st, stream))) return rc;
@@ -3304,45 +3370,17 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         slot_row.clear();
         return e2 == hipSuccess ? QC_OK : hip_fail(e2, "adjoint_tiles");
     };
-    // the pending block of diagonal rotations: global bit, gradient row,
-    // phase of the bit's set value; the common factor apart
-    struct DEnt {
-        int pos, row;
-        cd ph;
-    };
-    std::vector<DEnt> dblk;
-    cd dcommon(1.0);
-    int dblocks = 0;   // blocks in the current launch (16 lane tables at most)
+    // the pending block of diagonal rotations and the blocks in the current
+    // launch (16 lane tables at most)
+    DiagBlock dblk;
+    int dblocks = 0;
     auto emit_dblk = [&](TileOpBuilder &B, uint64_t P) {
         if (dblk.empty()) return;
-        qcx::TileOp op{};
-        op.kind = qcx::TILE_DGRAD;
-        op.b0 = int32_t(slot_row.size());
-        std::vector<std::pair<int, int>> in;   // (compressed bit, entry)
-        for (int i = 0; i < int(dblk.size()); ++i)
-            if ((P >> dblk[i].pos) & 1) in.push_back({B.cidx(dblk[i].pos), i});
-        std::sort(in.begin(), in.end());
-        for (const auto &ci : in) {
-            op.b1 |= 1 << ci.first;
-            op.u[2 * ci.first] = dblk[ci.second].ph.real();
-            op.u[2 * ci.first + 1] = dblk[ci.second].ph.imag();
-            slot_row.push_back(dblk[ci.second].row);
-        }
-        for (const DEnt &d : dblk) {
-            if ((P >> d.pos) & 1) continue;
-            op.fan_mask[op.pad] = uint64_t(1) << d.pos;
-            op.fan_ph[2 * op.pad] = d.ph.real();
-            op.fan_ph[2 * op.pad + 1] = d.ph.imag();
-            ++op.pad;
-            slot_row.push_back(d.row);
-        }
-        op.u1[0] = dcommon.real();
-        op.u1[1] = dcommon.imag();
+        const qcx::TileOp op = dblk.op(P, &slot_row);
         // one-qubit gates the builder still holds on the block's tile bits
         // go out first
         B.add_op(op, uint32_t(op.b1));
         dblk.clear();
-        dcommon = cd(1.0);
         ++dblocks;
     };
     for (const TileRun &r : runs) {
@@ -3355,25 +3393,14 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         for (int j : r.gates) {
             if (dblock_rot(j)) {
                 const int pos = bitpos(n, bwd[j].targets[0]);
-                int n_out = 0;
-                bool dup = false;
-                for (const DEnt &d : dblk) {
-                    dup = dup || d.pos == pos;
-                    n_out += !((r.P >> d.pos) & 1);
-                }
-                // one entry per bit, at most 8 out-of-tile bits (one window
-                // each), 48 entries
-                if (dup || dblk.size() >= 48 || (!((r.P >> pos) & 1) && n_out == 8)) emit_dblk(B, r.P);
+                if (!dblk.fits(pos, r.P)) emit_dblk(B, r.P);
                 if (int(slot_row.size() + dblk.size()) + 1 > max_slots || (dblk.empty() && dblocks == 16)) {
                     emit_dblk(B, r.P);
                     B.finish();
                     if ((rc = flush(r.P))) return rc;
                     dblocks = 0;
                 }
-                const double *mu = bwd[j].matrix;
-                const cd d0(mu[0], mu[1]), d1(mu[6], mu[7]);
-                dcommon *= d0;
-                dblk.push_back({pos, rot_row[j], d1 / d0});
+                dblk.add(pos, rot_row[j], bwd[j].matrix);
                 continue;
             }
             // any other op after the block (diagonal gates without a
