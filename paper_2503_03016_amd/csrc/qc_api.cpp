@@ -1303,8 +1303,13 @@ void tile_ops_for(int n, const qc_gate_t *gs, const std::vector<int> &idx, uint6
 
 // LDS tile of the tile-run kernel: at most 64 KiB (2^13 complex64 or 2^12
 // complex128 amplitudes), capped by QC_KNOB_TILE_BITS and by n.
+constexpr int kRtMinTileBits = 8;           // register tiles need >= 2^8 tiles in the register
+
+// complex128 takes the wide register tiles (2^13 amplitudes) when the
+// register engine will run them, that is when there are tiles enough
 int tile_bits_for(const qc_state_t &s) {
-    return std::min({s.n, s.dtype == QC_C64 ? 13 : 12, g_knob_tile_bits.load()});
+    const bool wide = g_knob_tile_engine.load() == 1 && s.n - qcx::kRtWideBits >= kRtMinTileBits;
+    return std::min({s.n, s.dtype == QC_C64 || wide ? 13 : 12, g_knob_tile_bits.load()});
 }
 
 // Greedy run formation: starting from the earliest pending gate, a gate
@@ -1373,7 +1378,6 @@ qcx::TileArgs tile_args(int n, int m, uint64_t P, int n_ops) {
 // next use comes soonest (farthest next use leaves first), so one exchange
 // serves as many later ops as possible.
 constexpr uint32_t kRtLdsTabMax = 16384;   // LDS bytes for the lane tables of one program
-constexpr int kRtMinTileBits = 8;           // register tiles need >= 2^8 tiles in the register
 struct RtLayout {
     int m = 0, rb = 0;
     int bit_of[32];    // slot -> compressed tile bit
@@ -1393,6 +1397,7 @@ struct RtLowering {
     std::vector<unsigned char> lblob, gblob;
     bool too_wide = false;        // an op needs more out-of-tile windows than kRtWindows
     bool adjoint = false;         // backward program: gradient ops, no deferred scale
+    bool defer_scale = false;     // leave the Hadamard factor to the caller (no RT_SCALE)
 
     static uint32_t add_tab(std::vector<unsigned char> &b, const void *p, size_t bytes) {
         while (b.size() % 16) b.push_back(0);
@@ -1542,13 +1547,15 @@ struct RtLowering {
             keep |= 1u << b;
         }
         // bits already in registers stay in their slots; the others swap with
-        // register bits that leave
+        // register bits that leave, the sooner needed into the lower slot
         RtLayout nl = L;
         std::vector<int> leaving, arriving;
         for (int sl = 0; sl < rb; ++sl)
             if (!((keep >> L.bit_of[sl]) & 1)) leaving.push_back(sl);
         for (int b = 0; b < m; ++b)
             if (((keep >> b) & 1) && L.slot_of[b] >= rb) arriving.push_back(b);
+        std::stable_sort(arriving.begin(), arriving.end(),
+                         [&](int a, int b) { return next_use(a, i) < next_use(b, i); });
         // fewer arrivals than free slots: keep the rest of the leavers
         for (size_t k = 0; k < arriving.size(); ++k) {
             const int rs = leaving[k], ts = L.slot_of[arriving[k]];
@@ -1796,6 +1803,17 @@ struct RtLowering {
         out.clear();
         for (size_t i = 0; i < f.size(); ++i) {
             const int k = f[i].kind;
+            if (rb >= 4 && i + 3 < f.size() && k == qcx::rt_code(qcx::RT_HFAN, 0) &&
+                f[i + 1].kind == qcx::rt_code(qcx::RT_HFAN, 1) &&
+                f[i + 2].kind == qcx::rt_code(qcx::RT_HFAN, 2) &&
+                f[i + 3].kind == qcx::rt_code(qcx::RT_HFAN, 3)) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_code(qcx::RT_HFAN4, 0);
+                out.push_back(r);
+                for (int j = 1; j < 4; ++j) out.push_back(f[i + j]);   // data of the later steps
+                i += 3;
+                continue;
+            }
             if (i + 1 < f.size() && k / 8 == qcx::RT_HFAN && f[i + 1].kind / 8 == qcx::RT_HFAN &&
                 f[i + 1].kind % 8 != k % 8 && k % 8 < rb && f[i + 1].kind % 8 < rb) {
                 qcx::RtOp r = f[i];
@@ -1908,7 +1926,7 @@ struct RtLowering {
         const RtLayout first = L;
         for (int i = 0; i < n_ops; ++i) lower(i);
         fuse_h_fan();
-        if (scale != 1.0) {
+        if (scale != 1.0 && !defer_scale) {
             qcx::RtOp r{};
             r.kind = qcx::rt_code(qcx::RT_SCALE, 0);
             put(r.u, 0, scale);
@@ -1953,6 +1971,7 @@ struct RtLowering {
         }
         while (lblob.size() % 16) lblob.push_back(0);
         a = qcx::RtArgs{};
+        a.st_scale = 1.0;
         a.lds_tab_bytes = uint32_t(lblob.size());
         a.m = m;
         a.tb = m - rb;
@@ -2019,15 +2038,20 @@ void rt_expand(const std::vector<qcx::TileOp> &in, std::vector<qcx::TileOp> &out
 // RT program of one tile run (m tile bits P, TileOp list ops), as one
 // host buffer: the RtOps, then the table blob (lane tables first).
 // adjoint: a backward program for the two-vector kernel.
+// scale_out: if given, the program leaves the product of its Hadamards'
+// 1/sqrt2 factors out and returns it there (the caller applies it at a
+// later store)
 void rt_program(int n, int m, int dtype, uint64_t P, const std::vector<qcx::TileOp> &ops,
                 qcx::RtArgs &a, std::vector<unsigned char> &buf, size_t &tab_off,
-                bool adjoint = false) {
+                bool adjoint = false, double *scale_out = nullptr) {
     std::vector<qcx::TileOp> flat;
     rt_expand(ops, flat);
-    const int rb = adjoint ? qcx::rt_adj_reg_bits(dtype) : qcx::rt_reg_bits(dtype);
+    const int rb = adjoint ? qcx::rt_adj_reg_bits(dtype) : qcx::rt_reg_bits(dtype, m);
     RtLowering lw{n, m, rb, dtype, P, flat.data(), int(flat.size())};
     lw.adjoint = adjoint;
+    lw.defer_scale = scale_out != nullptr && !adjoint;
     lw.run(a);
+    if (scale_out) *scale_out = lw.defer_scale ? lw.scale : 1.0;
     if (lw.too_wide) a.lds_tab_bytes = ~0u;   // not expressible: the caller takes the LDS engine
     const size_t ob = lw.out.size() * sizeof(qcx::RtOp);
     tab_off = ob;
@@ -2050,7 +2074,18 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
     form_runs(n, m, ng, gs, nullptr, runs);
     std::vector<qcx::TileOp> ops;
     std::vector<unsigned char> rbuf;
-    for (const TileRun &r : runs) {
+    // register tiles pay off when there are tiles enough for every CU;
+    // a few tiles (small registers) are latency-bound per op, where the
+    // LDS-resident engine's cheaper ops win
+    const bool rt_ok = g_knob_tile_engine.load() == 1 && m >= qcx::rt_reg_bits(s.dtype, m) &&
+                       n - m >= kRtMinTileBits;
+    // Register-tile programs leave their Hadamards' 1/sqrt2 factors out; the
+    // product is applied at the store of the last register-tile run before
+    // a standalone gate or the end, or by a scaling op in front of an
+    // LDS-engine run (each run is planned while the previous one runs)
+    double pending = 1.0;
+    for (size_t i = 0; i < runs.size(); ++i) {
+        const TileRun &r = runs[i];
         if (r.P == 0) {
             if ((rc = apply_gate_unfused(s, gs[r.gates[0]], st, stream))) return rc;
             continue;
@@ -2061,17 +2096,25 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         hipError_t e;
         qcx::RtArgs ra{};
         size_t tab_off = 0;
-        // register tiles pay off when there are tiles enough for every CU;
-        // a few tiles (small registers) are latency-bound per op, where the
-        // LDS-resident engine's cheaper ops win
-        const bool rt = g_knob_tile_engine.load() == 1 && m >= qcx::rt_reg_bits(s.dtype) &&
-                        n - m >= kRtMinTileBits;
-        if (rt) rt_program(n, m, s.dtype, r.P, ops, ra, rbuf, tab_off);
-        if (rt && ra.lds_tab_bytes <= kRtLdsTabMax) {
+        double scale = 1.0;
+        if (rt_ok) rt_program(n, m, s.dtype, r.P, ops, ra, rbuf, tab_off, false, &scale);
+        if (rt_ok && ra.lds_tab_bytes <= kRtLdsTabMax) {
+            pending *= scale;
+            if (i + 1 == runs.size() || runs[i + 1].P == 0) {
+                ra.st_scale = pending;
+                pending = 1.0;
+            }
             if ((rc = stage(c, rbuf.data(), rbuf.size(), hs, &dev))) return rc;
             e = qcx::launch_rt_run(s.amp, s.dtype, ra, static_cast<const qcx::RtOp *>(dev),
                                    static_cast<const unsigned char *>(dev) + tab_off, hs);
         } else {   // LDS-resident tiles (also for programs whose lane tables exceed the LDS budget)
+            if (pending != 1.0) {
+                qcx::TileOp sc{};
+                sc.kind = qcx::TILE_DIAG1;
+                sc.u[0] = sc.u[2] = pending;
+                ops.insert(ops.begin(), sc);
+                pending = 1.0;
+            }
             const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
             if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
             e = qcx::launch_tile_run(s.amp, s.dtype, n, a, static_cast<const qcx::TileOp *>(dev), hs);

@@ -249,6 +249,10 @@ enum RtKind {
     // product of the inverses: element factor u[e] times the RT_FAN thread
     // and window factors (w[0], ph, b, hw as for RT_FAN).
     RT_DGRAD = 21,
+    // forward only, 16 registers: RT_HFAN steps on register slots 0, 1, 2
+    // and 3 in that order, with this op's fan data and the next three ops'
+    // (data-only ops the interpreter skips)
+    RT_HFAN4 = 22,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
@@ -320,6 +324,7 @@ struct RtArgs {
     uint32_t ld_reg[kRtMaxRB];   // global position of element bit i when loading
     uint32_t st_reg[kRtMaxRB];   // ... and when storing
     uint32_t lds_tab_bytes;      // leading bytes of the table blob that go to LDS
+    double st_scale;             // factor of every amplitude at the store (1: none)
 };
 
 // One Pauli term of a tile pass of the expectation: X bits xc and Z bits zc
@@ -458,7 +463,11 @@ hipError_t launch_diff(const void *a, int dt_a, const void *b, int dt_b, uint64_
 hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const TileOp *ops_dev,
                            hipStream_t s);
 // register bits of the register-resident tile kernel for an element type
-constexpr int rt_reg_bits(int dtype) { return dtype == 1 ? 4 : 3; }
+// and tile size: complex64 keeps 16 amplitudes per thread; complex128 keeps
+// 8 in tiles of up to 2^12 amplitudes (two workgroups per CU) and 16 in the
+// wide 2^13-amplitude tiles (a 128 KiB exchange area, one workgroup per CU)
+constexpr int kRtWideBits = 13;
+constexpr int rt_reg_bits(int dtype, int m) { return dtype == 1 ? 4 : (m >= kRtWideBits ? 4 : 3); }
 hipError_t launch_rt_run(void *amp, int dtype, const RtArgs &a, const RtOp *ops_dev,
                          const unsigned char *tabs_dev, hipStream_t s);
 // new[sigma(i)] = old[i], sigma moving bit position p to sigma[p] (a

@@ -373,6 +373,19 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             QC_RT_HFAN2_CASE(1, 0) QC_RT_HFAN2_CASE(1, 2) QC_RT_HFAN2_CASE(1, 3)
             QC_RT_HFAN2_CASE(2, 0) QC_RT_HFAN2_CASE(2, 1) QC_RT_HFAN2_CASE(2, 3)
             QC_RT_HFAN2_CASE(3, 0) QC_RT_HFAN2_CASE(3, 1) QC_RT_HFAN2_CASE(3, 2)
+        case rt_code(RT_HFAN4, 0):
+            if constexpr (RB >= 4) {
+                h_slot<R, RB, 0>(v);
+                fan_slot<R, RB, 0>(v, op, fan_factor<R>(op, tb, base));
+                h_slot<R, RB, 1>(v);
+                fan_slot<R, RB, 1>(v, ops[o + 1], fan_factor<R>(ops[o + 1], tb, base));
+                h_slot<R, RB, 2>(v);
+                fan_slot<R, RB, 2>(v, ops[o + 2], fan_factor<R>(ops[o + 2], tb, base));
+                h_slot<R, RB, 3>(v);
+                fan_slot<R, RB, 3>(v, ops[o + 3], fan_factor<R>(ops[o + 3], tb, base));
+            }
+            o += 3;
+            break;
             QC_RT_SLOT_CASES(RT_CX, (xgate_slot<R, RB, S>(v, op.rm, op.rv, tc)))
         case rt_code(RT_DIAG1, kRtThreadSlot): diag1_thread<R, RB>(v, op, tid); break;
         case rt_code(RT_FAN, kRtThreadSlot): fan_thread<R, RB>(v, op, tb, base); break;

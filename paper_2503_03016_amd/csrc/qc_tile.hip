@@ -46,10 +46,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_run(cx<R> *amp, const TileArgs 
 // program runs on the registers (LDS only for RT_REMAP), and the elements
 // are stored under the final layout.
 template <typename R, int RB, bool PF>
-__global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(4)))
-void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
-                                                      const RtOp *__restrict__ ops,
-                                                      const unsigned char *__restrict__ tabs) {
+__device__ __forceinline__ void rt_run_body(cx<R> *__restrict__ amp, const RtArgs &a,
+                                            const RtOp *__restrict__ ops,
+                                            const unsigned char *__restrict__ tabs) {
     constexpr int E = 1 << RB;
     extern __shared__ unsigned char smem[];
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
@@ -97,6 +96,11 @@ void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
         }
         rt::run_ops<R, RB>(v, lds, base, tid, act, ops, a.n_ops, tb);
         if (act) {
+            if (a.st_scale != 1.0) {   // uniform: the deferred Hadamard factors of the circuit
+                const R sc = R(a.st_scale);
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = cx<R>{v[e].re * sc, v[e].im * sc};
+            }
             cx<R> *dst = amp + base + thr_st;
 #pragma unroll
             for (int e = 0; e < E; ++e) dst[rt::reg_offset<RB>(e, a.st_reg)] = v[e];
@@ -104,28 +108,52 @@ void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a,
     }
 }
 
+// 2^12-amplitude (complex128) and 2^13-amplitude (complex64) tiles: two
+// workgroups per CU, so at most 128 VGPRs
+template <typename R, int RB, bool PF>
+__global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_rt_run(cx<R> *__restrict__ amp, const RtArgs a, const RtOp *__restrict__ ops,
+              const unsigned char *__restrict__ tabs) {
+    rt_run_body<R, RB, PF>(amp, a, ops, tabs);
+}
+
+// wide complex128 tiles (2^13 amplitudes, 16 per thread): the 128 KiB
+// exchange area leaves one workgroup per CU, whose two wavefronts per SIMD
+// may take the whole register file (the prefetch set included)
+template <typename R, int RB, bool PF>
+__global__ __launch_bounds__(rt::kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void k_rt_run_wide(cx<R> *__restrict__ amp, const RtArgs a, const RtOp *__restrict__ ops,
+                   const unsigned char *__restrict__ tabs) {
+    rt_run_body<R, RB, PF>(amp, a, ops, tabs);
+}
+
 }  // namespace
 
 hipError_t launch_rt_run(void *amp, int dtype, const RtArgs &a, const RtOp *ops_dev,
                          const unsigned char *tabs_dev, hipStream_t s) {
-    const int rb = rt_reg_bits(dtype);
+    const int rb = rt_reg_bits(dtype, a.m);
     if (a.m < rb || a.m > rb + kRtMaxTB || a.tb != a.m - rb || a.m > kTileMaxBits)
         return hipErrorInvalidValue;
     const size_t elem = dtype == QC_C64 ? 8 : 16;
-    if ((size_t(1) << a.m) * elem > 65536 || a.lds_tab_bytes % 16 || a.lds_tab_bytes > 16384)
+    const bool wide = dtype == QC_C128 && rb == 4;
+    if ((size_t(1) << a.m) * elem > (wide ? 131072u : 65536u) || a.lds_tab_bytes % 16 ||
+        a.lds_tab_bytes > 16384)
         return hipErrorInvalidValue;
     const size_t lds = (size_t(1) << a.m) * elem + a.lds_tab_bytes;
     uint64_t grid = a.n_tiles;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t cap = uint64_t(cus) * uint64_t(knob(QC_KNOB_TILE_WG_PER_CU));
+    const uint64_t cap = uint64_t(cus) * uint64_t(wide ? 1 : knob(QC_KNOB_TILE_WG_PER_CU));
     if (grid > cap) grid = cap;
     const unsigned threads = 1u << (a.tb < 6 ? 6 : a.tb);
     const int tok = timer_begin(dtype == QC_C64 ? "rt_run_c64" : "rt_run_c128", s);
     if (dtype == QC_C64)
         hipLaunchKernelGGL((k_rt_run<float, 4, true>), dim3(unsigned(grid)), dim3(threads), lds, s,
                            static_cast<cx<float> *>(amp), a, ops_dev, tabs_dev);
+    else if (wide)
+        hipLaunchKernelGGL((k_rt_run_wide<double, 4, true>), dim3(unsigned(grid)), dim3(threads), lds,
+                           s, static_cast<cx<double> *>(amp), a, ops_dev, tabs_dev);
     else
         hipLaunchKernelGGL((k_rt_run<double, 3, false>), dim3(unsigned(grid)), dim3(threads), lds, s,
                            static_cast<cx<double> *>(amp), a, ops_dev, tabs_dev);
@@ -138,7 +166,7 @@ hipError_t launch_tile_run(void *amp, int dtype, int n, const TileArgs &a, const
     if (a.m < 1 || a.m > n || a.m > kTileMaxBits) return hipErrorInvalidValue;
     const size_t elem = dtype == QC_C64 ? 8 : 16;
     const size_t lds = (size_t(1) << a.m) * elem;
-    if (lds > 65536) return hipErrorInvalidValue;
+    if (lds > 131072) return hipErrorInvalidValue;   // 2^13 complex128 amplitudes
     uint64_t grid = a.n_tiles;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);

@@ -4,7 +4,7 @@ Every value here comes from the FP64 oracle (``oracle/``) on the seeded
 synthetic inputs of ``workloads``; nothing is read from the GPU library.
 Run from the repository root:
 
-    python tests/golden/make_golden.py [batch512] [adjoint24] [qft28]
+    python tests/golden/make_golden.py [batch512] [adjoint24] [qft28] [tfim28]
 
 * ``batch512_energies.json``: <H> of all 512 circuits of the batch workload
   (qubit counts uniform in [10, 20], 8-layer hardware-efficient ansatz,
@@ -14,6 +14,9 @@ Run from the repository root:
   and RZ), each from two oracle forwards.
 * ``qft28_amplitudes.json``: 16 output amplitudes of the 28-qubit QFT of the
   seeded random state, each from the discrete Fourier sum.
+* ``tfim28_terms.json``: <P_t> of each of the 55 Pauli terms of the 28-qubit
+  open-chain transverse-field Ising H on the same seeded random state, and
+  the energy sum_t c_t <P_t>.
 """
 import json
 import os
@@ -76,7 +79,21 @@ def qft28():
               open(os.path.join(HERE, "qft28_amplitudes.json"), "w"))
 
 
+def tfim28():
+    n = 28
+    terms = W.tfim_terms(n)
+    psi = W.random_state(n, seed=28)
+    t0 = time.time()
+    vals = [oracle.expect_pauli(psi, p).real for p, _ in terms]
+    print("tfim28: %d terms (%.0f s)" % (len(vals), time.time() - t0), flush=True)
+    json.dump({"about": "FP64 oracle <P_t> of the 55 open-chain TFIM terms on the 28-qubit "
+                        "seeded random state (seed 28), written by tests/golden/make_golden.py",
+               "terms": [p for p, _ in terms], "values": vals,
+               "energy": float(sum(c * v for (_, c), v in zip(terms, vals)))},
+              open(os.path.join(HERE, "tfim28_terms.json"), "w"))
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["batch512", "adjoint24", "qft28"]
+    which = sys.argv[1:] or ["batch512", "adjoint24", "qft28", "tfim28"]
     for w in which:
         globals()[w]()

@@ -6,6 +6,8 @@
   output amplitudes against the FP64 oracle's discrete Fourier sums
   (stored by tests/golden/make_golden.py, which calls only the oracle).
 * 512-circuit batch: all 512 energies against the oracle's.
+* 28-qubit TFIM expectation: all 55 per-term values and the energy, complex128
+  and complex64, against the oracle's (tests/golden/tfim28_terms.json).
 * 24-qubit adjoint gradient: every one of the 768 complex128 gradients
   against central differences (eps = 1e-4) of complex128 forward runs, the
   energy and six gradients against the oracle's energy and parameter-shift
@@ -167,3 +169,30 @@ def test_adjoint24_complex64_vs_complex128(qc):
     bound = 2 * (2 * n - 1) * 1e-5
     assert abs(e64 - gold["energy"]) < bound
     assert dg < bound
+
+
+def test_tfim28_every_term_vs_oracle(qc):
+    """The 28-qubit TFIM expectation that bench.py times (energy only) and
+    with per-term output, complex128 and complex64, against the oracle's
+    <P_t> of all 55 terms.  Bounds: complex128 1e-12 per term (the terms
+    are O(1e-4) on this state); complex64 4 * 2^-24 per term, from the
+    rounding of the state to complex64 (relative 2^-24 per component, so
+    |d<P>| <= 2 ||dpsi|| + ||dpsi||^2) plus the single-precision products."""
+    n = 28
+    terms = W.tfim_terms(n)
+    gold = golden("tfim28_terms.json")
+    assert gold["terms"] == [p for p, _ in terms]
+    want = np.array(gold["values"])
+    host = torch.from_numpy(W.random_state(n, seed=28))
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 4 * 2.0 ** -24)):
+        psi = host.to(dt).cuda()
+        e = qc.expect_pauli(psi, terms)[0].item()
+        v = qc.expect_pauli(psi, terms, per_term=True).cpu().numpy()
+        err = np.abs(v[1:] - want)
+        print("tfim28 %s: |dE| = %.3e, max per-term error %.3e"
+              % (dt, abs(e - gold["energy"]), err.max()))
+        assert err.max() < tol, (dt, int(np.argmax(err)), float(err.max()))
+        assert abs(e - gold["energy"]) < tol * sum(abs(c) for _, c in terms)
+        assert abs(v[0] - e) < tol * sum(abs(c) for _, c in terms)
+        del psi
+        torch.cuda.empty_cache()

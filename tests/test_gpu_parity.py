@@ -255,17 +255,11 @@ def test_apply_multiplexed(qc, dt, n, k, c):
 
 # ---------------------------------------------------------------- circuits
 
-@pytest.mark.parametrize("tile_bits", [13, 10, 7])
-@pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n", [6, 13, 17])
-def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
-    """LDS tile runs: dense 1q/2q gates, diagonal gates on bits inside and
-    outside the tile, controls inside and outside the tile, open controls,
-    gates that cannot join a run (3-qubit), across several tiles; at the
-    default tile size and two smaller ones (QC_KNOB_TILE_BITS)."""
-    rng = np.random.default_rng(n)
+def _mixed_ops(n, rng, count=60):
+    """Dense 1q/2q/3q gates, CZ, CP, RZ, CNOT and open-control MCX gates on
+    random qubits."""
     ops = []
-    for _ in range(60):
+    for _ in range(count):
         kind = rng.integers(0, 8)
         q = [int(x) for x in rng.permutation(n)[:4]]
         if kind == 0:
@@ -284,6 +278,19 @@ def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
             ops.append(W.Op("U", (q[0], q[1], q[2]), matrix=random_unitary(8, rng)))
         else:
             ops.append(W.Op("CNOT", (q[0], q[1])))
+    return ops
+
+
+@pytest.mark.parametrize("tile_bits", [13, 10, 7])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [6, 13, 17])
+def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
+    """LDS tile runs: dense 1q/2q gates, diagonal gates on bits inside and
+    outside the tile, controls inside and outside the tile, open controls,
+    gates that cannot join a run (3-qubit), across several tiles; at the
+    default tile size and two smaller ones (QC_KNOB_TILE_BITS)."""
+    rng = np.random.default_rng(n)
+    ops = _mixed_ops(n, rng)
     psi0 = W.random_state(n, 50 + n)
     ref = oracle.run(ops, psi0)
     t = dev(psi0, DT[dt])
@@ -295,6 +302,31 @@ def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
         qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
     assert st["sweeps"] < len(ops)
     check(host(t), ref, DT[dt], ngates=len(ops))
+
+
+@pytest.mark.parametrize("n", [21, 22])
+def test_tiled_wide_complex128(qc, G, n):
+    """complex128 tile runs in the wide register tiles (2^13 amplitudes, 16
+    per thread, taken when there are >= 2^8 tiles): mixed gates and the
+    QFT against the oracle, and against the 2^12-amplitude tiles
+    (QC_KNOB_TILE_BITS = 12) over the whole state."""
+    rng = np.random.default_rng(300 + n)
+    for ops in (_mixed_ops(n, rng), W.qft(n)):
+        psi0 = W.random_state(n, 310 + n)
+        ref = oracle.run(ops, psi0)
+        gl = qc.GateList(G.gate_tuples(ops))
+        t = dev(psi0, torch.complex128)
+        st = qc.apply_circuit(t, gl, mode=2)
+        assert st["sweeps"] < len(ops)
+        check(host(t), ref, torch.complex128, ngates=len(ops))
+        narrow = dev(psi0, torch.complex128)
+        old = qc.get_knob(qc.QC_KNOB_TILE_BITS)
+        try:
+            qc.set_knob(qc.QC_KNOB_TILE_BITS, 12)
+            qc.apply_circuit(narrow, gl, mode=2)
+        finally:
+            qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
+        assert np.max(np.abs(host(t) - host(narrow))) < 1e-12
 
 
 @pytest.mark.parametrize("tile_bits", [13, 10, 7])
