@@ -1017,7 +1017,12 @@ struct TileOpBuilder {
     // kPhaseTableBits tile bits, in order (the terms commute), a lone term
     // or one testing more bits as a TILE_PHASE op.
     void emit_phases() {
-        if (!terms.empty() && !(fans && terms.size() > 1 && emit_fan())) {
+        // a lone term joins the fan form only behind a one-qubit gate on one
+        // of its bits (the pair becomes one dense-then-fan op)
+        const bool behind_dense = !out.empty() && out.back().kind == qcx::TILE_DENSE1 &&
+                                  out.back().cmask_lo == 0 && out.back().cmask_hi == 0;
+        if (!terms.empty() &&
+            !(fans && (terms.size() > 1 || behind_dense) && emit_fan())) {
             qcx::TileOp op{};
             int nt = 0;
             uint32_t bits = 0;
@@ -1075,7 +1080,13 @@ struct TileOpBuilder {
             common &= tm.mlo;
         }
         if (!common) return false;
-        const int t = __builtin_ctz(common);
+        // the target: the bit of the one-qubit gate just before, if the terms
+        // share it (the two then merge into one op), else the lowest shared bit
+        int t = __builtin_ctz(common);
+        if (!out.empty() && out.back().kind == qcx::TILE_DENSE1 && ((common >> out.back().b0) & 1))
+            t = out.back().b0;
+        else if (terms.size() == 1)
+            return false;
         cd bitph[qcx::kTileMaxBits];
         for (auto &v : bitph) v = 1.0;
         uint32_t ctl = 0;
