@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -2073,6 +2074,76 @@ void rt_program(int n, int m, int dtype, uint64_t P, const std::vector<qcx::Tile
         std::memcpy(buf.data() + ob + lw.lblob.size(), lw.gblob.data(), lw.gblob.size());
 }
 
+// Plans of recently applied tiled circuits.  A circuit applied again with
+// the same gates (matrices included), register size, precision and tile
+// settings reuses its runs' programs; the device work is the same.
+struct TiledPlanRun {
+    uint64_t P = 0;
+    int gate = -1;                      // the standalone gate (P == 0)
+    bool rt = false;
+    qcx::RtArgs ra{};
+    size_t tab_off = 0;
+    int n_ops = 0;                      // LDS-engine runs: TileOp count
+    std::vector<unsigned char> bytes;   // register-tile program and tables, or the TileOps
+};
+struct TiledPlan {
+    std::vector<unsigned char> key;
+    std::vector<TiledPlanRun> runs;
+};
+constexpr size_t kPlanCacheEntries = 4;
+constexpr size_t kPlanKeyMaxBytes = size_t(1) << 20;
+std::mutex g_plan_mu;
+std::vector<std::shared_ptr<const TiledPlan>> g_plans;   // most recent first
+
+// the key of a tiled circuit; false if it is too large to keep
+bool plan_key(const qc_state_t &s, int m, int ng, const qc_gate_t *gs, std::vector<unsigned char> &k) {
+    size_t bytes = 5 * sizeof(int);
+    for (int i = 0; i < ng; ++i)
+        bytes += sizeof(int32_t) * (2 + gs[i].n_targets + 2 * gs[i].n_ctrls) +
+                 sizeof(double) * 2 * (size_t(1) << (2 * gs[i].n_targets));
+    if (bytes > kPlanKeyMaxBytes) return false;
+    k.clear();
+    k.reserve(bytes);
+    auto put = [&](const void *p, size_t b) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        k.insert(k.end(), c, c + b);
+    };
+    const int hdr[5] = {s.n, s.dtype, m, g_knob_tile_engine.load(), ng};
+    put(hdr, sizeof(hdr));
+    for (int i = 0; i < ng; ++i) {
+        const qc_gate_t &g = gs[i];
+        put(&g.n_targets, sizeof(int32_t));
+        put(&g.n_ctrls, sizeof(int32_t));
+        put(g.targets, sizeof(int32_t) * g.n_targets);
+        put(g.ctrls, sizeof(int32_t) * g.n_ctrls);
+        put(g.ctrl_vals, sizeof(int32_t) * g.n_ctrls);
+        put(g.matrix, sizeof(double) * 2 * (size_t(1) << (2 * g.n_targets)));
+    }
+    return true;
+}
+
+int launch_plan_run(qc_state_t s, int m, const qc_gate_t *gs, const TiledPlanRun &pr, DevCtx *c,
+                    qc_exec_stats_t &st, void *stream) {
+    if (pr.P == 0) return apply_gate_unfused(s, gs[pr.gate], st, stream);
+    const hipStream_t hs = (hipStream_t)stream;
+    void *dev = nullptr;
+    int rc = stage(c, pr.bytes.data(), pr.bytes.size(), hs, &dev);
+    if (rc) return rc;
+    hipError_t e;
+    if (pr.rt) {
+        e = qcx::launch_rt_run(s.amp, s.dtype, pr.ra, static_cast<const qcx::RtOp *>(dev),
+                               static_cast<const unsigned char *>(dev) + pr.tab_off, hs);
+    } else {
+        const qcx::TileArgs a = tile_args(s.n, m, pr.P, pr.n_ops);
+        e = qcx::launch_tile_run(s.amp, s.dtype, s.n, a, static_cast<const qcx::TileOp *>(dev), hs);
+    }
+    if (e != hipSuccess) return hip_fail(e, "tile_run");
+    st.launches += 1;
+    st.sweeps += 1;
+    st.state_bytes += sweep_bytes(s.n, s.dtype);
+    return QC_OK;
+}
+
 int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st,
                   void *stream) {
     DevCtx *c;
@@ -2080,11 +2151,29 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
     if (rc) return rc;
     const int n = s.n;
     const int m = tile_bits_for(s);
-    const hipStream_t hs = (hipStream_t)stream;
+    auto plan = std::make_shared<TiledPlan>();
+    const bool keep = plan_key(s, m, ng, gs, plan->key);
+    if (keep) {
+        std::shared_ptr<const TiledPlan> hit;
+        {
+            std::lock_guard<std::mutex> lk(g_plan_mu);
+            for (size_t i = 0; i < g_plans.size(); ++i)
+                if (g_plans[i]->key == plan->key) {
+                    hit = g_plans[i];
+                    g_plans.erase(g_plans.begin() + long(i));
+                    g_plans.insert(g_plans.begin(), hit);
+                    break;
+                }
+        }
+        if (hit) {
+            for (const TiledPlanRun &pr : hit->runs)
+                if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream))) return rc;
+            return QC_OK;
+        }
+    }
     std::vector<TileRun> runs;
     form_runs(n, m, ng, gs, nullptr, runs);
     std::vector<qcx::TileOp> ops;
-    std::vector<unsigned char> rbuf;
     // register tiles pay off when there are tiles enough for every CU;
     // a few tiles (small registers) are latency-bound per op, where the
     // LDS-resident engine's cheaper ops win
@@ -2095,29 +2184,27 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
     // a standalone gate or the end, or by a scaling op in front of an
     // LDS-engine run (each run is planned while the previous one runs)
     double pending = 1.0;
+    plan->runs.resize(runs.size());
     for (size_t i = 0; i < runs.size(); ++i) {
         const TileRun &r = runs[i];
+        TiledPlanRun &pr = plan->runs[i];
+        pr.P = r.P;
         if (r.P == 0) {
-            if ((rc = apply_gate_unfused(s, gs[r.gates[0]], st, stream))) return rc;
+            pr.gate = r.gates[0];
+            if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream))) return rc;
             continue;
         }
         ops.clear();
         tile_ops_for(n, gs, r.gates, r.P, ops);
-        void *dev = nullptr;
-        hipError_t e;
-        qcx::RtArgs ra{};
-        size_t tab_off = 0;
         double scale = 1.0;
-        if (rt_ok) rt_program(n, m, s.dtype, r.P, ops, ra, rbuf, tab_off, false, &scale);
-        if (rt_ok && ra.lds_tab_bytes <= kRtLdsTabMax) {
+        if (rt_ok) rt_program(n, m, s.dtype, r.P, ops, pr.ra, pr.bytes, pr.tab_off, false, &scale);
+        pr.rt = rt_ok && pr.ra.lds_tab_bytes <= kRtLdsTabMax;
+        if (pr.rt) {
             pending *= scale;
             if (i + 1 == runs.size() || runs[i + 1].P == 0) {
-                ra.st_scale = pending;
+                pr.ra.st_scale = pending;
                 pending = 1.0;
             }
-            if ((rc = stage(c, rbuf.data(), rbuf.size(), hs, &dev))) return rc;
-            e = qcx::launch_rt_run(s.amp, s.dtype, ra, static_cast<const qcx::RtOp *>(dev),
-                                   static_cast<const unsigned char *>(dev) + tab_off, hs);
         } else {   // LDS-resident tiles (also for programs whose lane tables exceed the LDS budget)
             if (pending != 1.0) {
                 qcx::TileOp sc{};
@@ -2126,14 +2213,16 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
                 ops.insert(ops.begin(), sc);
                 pending = 1.0;
             }
-            const qcx::TileArgs a = tile_args(n, m, r.P, int(ops.size()));
-            if ((rc = stage(c, ops.data(), ops.size() * sizeof(qcx::TileOp), hs, &dev))) return rc;
-            e = qcx::launch_tile_run(s.amp, s.dtype, n, a, static_cast<const qcx::TileOp *>(dev), hs);
+            pr.n_ops = int(ops.size());
+            const unsigned char *b = reinterpret_cast<const unsigned char *>(ops.data());
+            pr.bytes.assign(b, b + ops.size() * sizeof(qcx::TileOp));
         }
-        if (e != hipSuccess) return hip_fail(e, "tile_run");
-        st.launches += 1;
-        st.sweeps += 1;
-        st.state_bytes += sweep_bytes(n, s.dtype);
+        if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream))) return rc;
+    }
+    if (keep) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans.insert(g_plans.begin(), std::move(plan));
+        if (g_plans.size() > kPlanCacheEntries) g_plans.pop_back();
     }
     return QC_OK;
 }

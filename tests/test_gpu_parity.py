@@ -329,6 +329,33 @@ def test_tiled_wide_complex128(qc, G, n):
         assert np.max(np.abs(host(t) - host(narrow))) < 1e-12
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_tiled_plan_reuse(qc, G, dt):
+    """A tiled circuit applied again reuses its plan: two applications of
+    one gate list to fresh states, then the same list with one matrix
+    changed in place (the plan must not be reused), each against the
+    oracle."""
+    n = 21
+    rng = np.random.default_rng(77)
+    ops = _mixed_ops(n, rng, count=40)
+    psi0 = W.random_state(n, 78)
+    gl = qc.GateList(G.gate_tuples(ops))
+    ref = oracle.run(ops, psi0)
+    for _ in range(2):
+        t = dev(psi0, DT[dt])
+        qc.apply_circuit(t, gl, mode=2)
+        check(host(t), ref, DT[dt], ngates=len(ops))
+    k = next(i for i, op in enumerate(ops) if op.kind == "U" and len(op.qubits) == 1)
+    u = random_unitary(2, rng)
+    off = sum(np.asarray(g[3]).size for g in G.gate_tuples(ops[:k]))
+    gl._mats[off:off + 4] = u.reshape(-1)
+    ops2 = list(ops)
+    ops2[k] = W.Op("U", ops[k].qubits, matrix=u)
+    t = dev(psi0, DT[dt])
+    qc.apply_circuit(t, gl, mode=2)
+    check(host(t), oracle.run(ops2, psi0), DT[dt], ngates=len(ops))
+
+
 @pytest.mark.parametrize("tile_bits", [13, 10, 7])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n", [8, 16])
