@@ -412,6 +412,10 @@ int qc_batch_destroy(qc_batch_t *b);
 #define QC_KNOB_TILE_ENGINE 6      /* QC_EXEC_TILED engine: 1 = register-resident tiles
                                       (amplitudes in registers, LDS only to exchange index
                                       bits; default), 0 = LDS-resident tiles               */
+#define QC_KNOB_WIDE_MIN_TILES 7   /* complex128 register tiles of 2^13 amplitudes (16 per
+                                      thread, one workgroup per CU) when the register holds
+                                      at least 2^value such tiles, else 2^12 (8..30;
+                                      default 12)                                          */
 int qc_set_knob(int knob, int value);
 int qc_get_knob(int knob, int *value);
 

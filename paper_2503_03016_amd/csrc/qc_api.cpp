@@ -143,6 +143,7 @@ std::atomic<int> g_knob_look{16};
 std::atomic<int> g_knob_tbits{13};
 std::atomic<int> g_knob_tile_bits{13};
 std::atomic<int> g_knob_tile_engine{1};
+std::atomic<int> g_knob_wide{12};
 
 // ---------------------------------------------------------------- validation
 
@@ -532,6 +533,7 @@ int knob(int which) {
     case QC_KNOB_MFMA_TILE_BITS: return g_knob_tbits.load();
     case QC_KNOB_TILE_BITS: return g_knob_tile_bits.load();
     case QC_KNOB_TILE_ENGINE: return g_knob_tile_engine.load();
+    case QC_KNOB_WIDE_MIN_TILES: return g_knob_wide.load();
     default: return g_knob_look.load();
     }
 }
@@ -657,6 +659,11 @@ int qc_set_knob(int knob, int value) {
         g_knob_tile_engine.store(value);
         return QC_OK;
     }
+    if (knob == QC_KNOB_WIDE_MIN_TILES) {
+        if (value < 8 || value > 30) return fail(QC_ERR_ARG, "wide-tile minimum must be 8..30");
+        g_knob_wide.store(value);
+        return QC_OK;
+    }
     return fail(QC_ERR_ARG, "unknown knob");
 }
 
@@ -664,7 +671,7 @@ int qc_get_knob(int knob, int *value) {
     if (!value) return fail(QC_ERR_ARG, "NULL argument");
     if (knob != QC_KNOB_MFMA_WG_PER_CU && knob != QC_KNOB_TILE_WG_PER_CU &&
         knob != QC_KNOB_FUSE_LOOKAHEAD && knob != QC_KNOB_MFMA_TILE_BITS &&
-        knob != QC_KNOB_TILE_BITS && knob != QC_KNOB_TILE_ENGINE)
+        knob != QC_KNOB_TILE_BITS && knob != QC_KNOB_TILE_ENGINE && knob != QC_KNOB_WIDE_MIN_TILES)
         return fail(QC_ERR_ARG, "unknown knob");
     *value = qcx::knob(knob);
     return QC_OK;
@@ -1318,9 +1325,12 @@ void tile_ops_for(int n, const qc_gate_t *gs, const std::vector<int> &idx, uint6
 constexpr int kRtMinTileBits = 8;           // register tiles need >= 2^8 tiles in the register
 
 // complex128 takes the wide register tiles (2^13 amplitudes) when the
-// register engine will run them, that is when there are tiles enough
+// register engine runs them and there are 2^QC_KNOB_WIDE_MIN_TILES of them:
+// one workgroup per CU needs more tiles per workgroup to hide its latency
+// (at 24 qubits the 2^12 tiles are faster, at 28 the wide ones)
 int tile_bits_for(const qc_state_t &s) {
-    const bool wide = g_knob_tile_engine.load() == 1 && s.n - qcx::kRtWideBits >= kRtMinTileBits;
+    const bool wide = g_knob_tile_engine.load() == 1 &&
+                      s.n - qcx::kRtWideBits >= std::max(kRtMinTileBits, g_knob_wide.load());
     return std::min({s.n, s.dtype == QC_C64 || wide ? 13 : 12, g_knob_tile_bits.load()});
 }
 

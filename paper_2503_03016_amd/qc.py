@@ -36,7 +36,7 @@ EXPORTS = [
 ]
 QC_MAX_COUNT_QUBITS, QC_MAX_COUNT_SHOTS = 24, 1 << 21
 (QC_KNOB_MFMA_WG_PER_CU, QC_KNOB_TILE_WG_PER_CU, QC_KNOB_FUSE_LOOKAHEAD, QC_KNOB_MFMA_TILE_BITS,
- QC_KNOB_TILE_BITS, QC_KNOB_TILE_ENGINE) = 1, 2, 3, 4, 5, 6
+ QC_KNOB_TILE_BITS, QC_KNOB_TILE_ENGINE, QC_KNOB_WIDE_MIN_TILES) = 1, 2, 3, 4, 5, 6, 7
 
 
 class QcError(RuntimeError):

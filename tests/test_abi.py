@@ -35,7 +35,8 @@ def test_package_modules_import_and_constants_match_header():
     text = open(HEADER).read()
     for name in ("QC_C64", "QC_C128", "QC_EXEC_UNFUSED", "QC_EXEC_FUSED", "QC_EXEC_TILED",
                  "QC_MAX_FUSED", "QC_MAX_CTRLS", "QC_MAX_SEL", "QC_KNOB_MFMA_WG_PER_CU",
-                 "QC_KNOB_TILE_WG_PER_CU", "QC_KNOB_FUSE_LOOKAHEAD", "QC_KNOB_MFMA_TILE_BITS", "QC_KNOB_TILE_BITS"):
+                 "QC_KNOB_TILE_WG_PER_CU", "QC_KNOB_FUSE_LOOKAHEAD", "QC_KNOB_MFMA_TILE_BITS", "QC_KNOB_TILE_BITS",
+                 "QC_KNOB_TILE_ENGINE", "QC_KNOB_WIDE_MIN_TILES"):
         m = re.search(r"#define\s+%s\s+(-?\d+)" % name, text)
         assert m and getattr(q, name) == int(m.group(1)), name
     for kind, code in q.OP_KIND.items():
@@ -187,6 +188,9 @@ def test_knobs(qc):
     assert qc.lib.qc_set_knob(qc.QC_KNOB_TILE_BITS, 5) == -1
     assert qc.lib.qc_set_knob(qc.QC_KNOB_TILE_BITS, 14) == -1
     assert qc.get_knob(qc.QC_KNOB_TILE_BITS) == 13
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_WIDE_MIN_TILES, 7) == -1
+    assert qc.lib.qc_set_knob(qc.QC_KNOB_WIDE_MIN_TILES, 31) == -1
+    assert qc.get_knob(qc.QC_KNOB_WIDE_MIN_TILES) == 12
     assert qc.lib.qc_set_knob(99, 1) == -1
     qc.set_knob(qc.QC_KNOB_MFMA_WG_PER_CU, 3)
     assert qc.get_knob(qc.QC_KNOB_MFMA_WG_PER_CU) == 3

@@ -307,16 +307,21 @@ def test_tiled_runs_mixed_gates(qc, G, dt, n, tile_bits):
 @pytest.mark.parametrize("n", [21, 22])
 def test_tiled_wide_complex128(qc, G, n):
     """complex128 tile runs in the wide register tiles (2^13 amplitudes, 16
-    per thread, taken when there are >= 2^8 tiles): mixed gates and the
-    QFT against the oracle, and against the 2^12-amplitude tiles
-    (QC_KNOB_TILE_BITS = 12) over the whole state."""
+    per thread; QC_KNOB_WIDE_MIN_TILES lowered to 8 so that 21 and 22 qubits
+    take them): mixed gates and the QFT against the oracle, and against the
+    2^12-amplitude tiles (QC_KNOB_TILE_BITS = 12) over the whole state."""
     rng = np.random.default_rng(300 + n)
     for ops in (_mixed_ops(n, rng), W.qft(n)):
         psi0 = W.random_state(n, 310 + n)
         ref = oracle.run(ops, psi0)
         gl = qc.GateList(G.gate_tuples(ops))
         t = dev(psi0, torch.complex128)
-        st = qc.apply_circuit(t, gl, mode=2)
+        old_wide = qc.get_knob(qc.QC_KNOB_WIDE_MIN_TILES)
+        try:
+            qc.set_knob(qc.QC_KNOB_WIDE_MIN_TILES, 8)
+            st = qc.apply_circuit(t, gl, mode=2)
+        finally:
+            qc.set_knob(qc.QC_KNOB_WIDE_MIN_TILES, old_wide)
         assert st["sweeps"] < len(ops)
         check(host(t), ref, torch.complex128, ngates=len(ops))
         narrow = dev(psi0, torch.complex128)
