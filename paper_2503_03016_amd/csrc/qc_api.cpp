@@ -1420,6 +1420,7 @@ struct RtLowering {
     bool too_wide = false;        // an op needs more out-of-tile windows than kRtWindows
     bool adjoint = false;         // backward program: gradient ops, no deferred scale
     bool defer_scale = false;     // leave the Hadamard factor to the caller (no RT_SCALE)
+    bool had_remap = false;       // an RT_REMAP was emitted before
 
     static uint32_t add_tab(std::vector<unsigned char> &b, const void *p, size_t bytes) {
         while (b.size() % 16) b.push_back(0);
@@ -1535,6 +1536,15 @@ struct RtLowering {
     void emit_remap(const RtLayout &nl) {
         qcx::RtOp r{};
         r.kind = qcx::rt_code(qcx::RT_REMAP, 0);
+        // b = 1: every wavefront keeps its wavefront bits, so it reads back
+        // only the LDS slots it wrote, which are those it read in the
+        // previous exchange of the same tile: no workgroup barrier (the
+        // first exchange of a program keeps them, since the previous
+        // tile's last exchange may have had other wavefronts on its slots)
+        bool same_waves = true;
+        for (int k = 6; k < m - rb; ++k) same_waves = same_waves && L.bit_of[rb + k] == nl.bit_of[rb + k];
+        r.b = same_waves && had_remap ? 1 : 0;
+        had_remap = true;
         for (int e = 0; e < E(); ++e) {
             r.w[e] = swz(dep_reg(nl, e));
             r.w[16 + e] = swz(dep_reg(L, e));

@@ -267,7 +267,10 @@ __device__ __forceinline__ void xgate_slot(cx<R> *v, uint32_t rm, uint32_t rv, b
 // Exchange through LDS: every thread writes its elements at their slots
 // under the old layout, then reads the elements of the new layout.  The
 // first barrier keeps the writes behind every read of the previous
-// exchange.  Threads past the tile (act false) only take the barriers.
+// exchange.  Threads past the tile (act false) only take the barriers.  An
+// exchange that keeps every wavefront's bits (op.b, set by the host only
+// behind an earlier exchange of the same tile) needs neither barrier: each
+// wavefront then writes and reads back only the slots it read last.
 template <typename R, int RB>
 __device__ __forceinline__ void remap(cx<R> *v, cx<R> *lds, const RtOp &op, uint32_t tid, bool act) {
     constexpr int E = 1 << RB;
@@ -281,12 +284,19 @@ __device__ __forceinline__ void remap(cx<R> *v, cx<R> *lds, const RtOp &op, uint
     }
     t_old = rt_swizzle<EB>(t_old);
     t_new = rt_swizzle<EB>(t_new);
-    __syncthreads();
+    const bool waves_kept = op.b != 0;   // uniform: the exchange stays inside each wavefront
+    if (!waves_kept) __syncthreads();
     if (act) {
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[t_old ^ op.w[16 + e]] = v[e];
     }
-    __syncthreads();
+    if (waves_kept) {   // one wavefront's LDS operations complete in order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
     if (act) {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = lds[t_new ^ op.w[e]];
