@@ -2109,6 +2109,8 @@ struct TiledPlanRun {
 struct TiledPlan {
     std::vector<unsigned char> key;
     std::vector<TiledPlanRun> runs;
+    std::vector<unsigned char> blob;   // every run's bytes, 256-byte aligned
+    std::vector<size_t> off;           // run i's bytes at blob + off[i]
 };
 constexpr size_t kPlanCacheEntries = 4;
 constexpr size_t kPlanKeyMaxBytes = size_t(1) << 20;
@@ -2142,13 +2144,15 @@ bool plan_key(const qc_state_t &s, int m, int ng, const qc_gate_t *gs, std::vect
     return true;
 }
 
+// one run: its bytes staged now, or already on the device at `dev`
 int launch_plan_run(qc_state_t s, int m, const qc_gate_t *gs, const TiledPlanRun &pr, DevCtx *c,
-                    qc_exec_stats_t &st, void *stream) {
+                    qc_exec_stats_t &st, void *stream, void *dev = nullptr) {
     if (pr.P == 0) return apply_gate_unfused(s, gs[pr.gate], st, stream);
     const hipStream_t hs = (hipStream_t)stream;
-    void *dev = nullptr;
-    int rc = stage(c, pr.bytes.data(), pr.bytes.size(), hs, &dev);
-    if (rc) return rc;
+    if (!dev) {
+        const int rc = stage(c, pr.bytes.data(), pr.bytes.size(), hs, &dev);
+        if (rc) return rc;
+    }
     hipError_t e;
     if (pr.rt) {
         e = qcx::launch_rt_run(s.amp, s.dtype, pr.ra, static_cast<const qcx::RtOp *>(dev),
@@ -2185,9 +2189,15 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
                     break;
                 }
         }
-        if (hit) {
-            for (const TiledPlanRun &pr : hit->runs)
-                if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream))) return rc;
+        if (hit) {   // every program in one copy, then the launches back to back
+            void *bdev = nullptr;
+            if (!hit->blob.empty() &&
+                (rc = stage(c, hit->blob.data(), hit->blob.size(), (hipStream_t)stream, &bdev)))
+                return rc;
+            for (size_t i = 0; i < hit->runs.size(); ++i)
+                if ((rc = launch_plan_run(s, m, gs, hit->runs[i], c, st, stream,
+                                          static_cast<char *>(bdev) + hit->off[i])))
+                    return rc;
             return QC_OK;
         }
     }
@@ -2240,6 +2250,15 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
         if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream))) return rc;
     }
     if (keep) {
+        plan->off.resize(plan->runs.size(), 0);
+        for (size_t i = 0; i < plan->runs.size(); ++i) {
+            const std::vector<unsigned char> &b = plan->runs[i].bytes;
+            if (b.empty()) continue;
+            plan->blob.resize((plan->blob.size() + 255) & ~size_t(255));
+            plan->off[i] = plan->blob.size();
+            plan->blob.insert(plan->blob.end(), b.begin(), b.end());
+        }
+        if (plan->blob.size() > kRingBytes / 4) return QC_OK;   // too large to stage at once: not kept
         std::lock_guard<std::mutex> lk(g_plan_mu);
         g_plans.insert(g_plans.begin(), std::move(plan));
         if (g_plans.size() > kPlanCacheEntries) g_plans.pop_back();
@@ -3493,45 +3512,49 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
     const bool rt = rt_bwd;
     const int max_slots = rt ? qcx::kRtAdjSlots : qcx::kAdjointMaxSlots;
     std::vector<unsigned char> rbuf;
+    // the backward launches are planned first and their programs staged in
+    // one copy (the forward runs, the energy and lambda are on the GPU
+    // meanwhile), then launched back to back
+    struct BwdLaunch {
+        bool rt;
+        qcx::RtArgs ra;
+        qcx::TileArgs ta;
+        size_t prog, tab_off, slots;
+        int n_slots;
+    };
+    std::vector<BwdLaunch> launches;
+    std::vector<unsigned char> blob;
+    auto append = [&](const void *p, size_t bytes) {
+        blob.resize((blob.size() + 255) & ~size_t(255));
+        const size_t off = blob.size();
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        blob.insert(blob.end(), b, b + bytes);
+        return off;
+    };
     auto flush = [&](uint64_t P) -> int {
         if (tops.empty()) return QC_OK;
         merge_grad_pairs(tops);
+        BwdLaunch L{};
+        L.n_slots = int(slot_row.size());
         if (rt) {   // register tiles: both vectors in registers
-            qcx::RtArgs ra{};
-            size_t tab_off = 0;
-            rt_program(n, mb, psi.dtype, P, tops, ra, rbuf, tab_off, true);
+            rt_program(n, mb, psi.dtype, P, tops, L.ra, rbuf, L.tab_off, true);
             bool has_dblock = false;
             for (const qcx::TileOp &o : tops) has_dblock = has_dblock || o.kind == qcx::TILE_DGRAD;
-            if (ra.lds_tab_bytes > kRtLdsTabMax && has_dblock)   // the LDS engine has no such op
+            if (L.ra.lds_tab_bytes > kRtLdsTabMax && has_dblock)   // the LDS engine has no such op
                 return fail(QC_ERR_UNSUPPORTED, "backward program exceeds the register-tile table budget");
-            if (ra.lds_tab_bytes <= kRtLdsTabMax) {
-                void *pdev = nullptr, *sdev = nullptr;
-                int r2 = stage(c, rbuf.data(), rbuf.size(), hs, &pdev);
-                if (!r2 && !slot_row.empty())
-                    r2 = stage(c, slot_row.data(), slot_row.size() * sizeof(int32_t), hs, &sdev);
-                if (r2) return r2;
-                hipError_t e2 = qcx::launch_rt_adjoint(
-                    psi.amp, lam.amp, psi.dtype, ra, static_cast<const qcx::RtOp *>(pdev),
-                    static_cast<const unsigned char *>(pdev) + tab_off,
-                    static_cast<const int32_t *>(sdev), int(slot_row.size()), partial, cols, hs);
-                tops.clear();
-                slot_row.clear();
-                return e2 == hipSuccess ? QC_OK : hip_fail(e2, "rt_adjoint");
-            }
+            L.rt = L.ra.lds_tab_bytes <= kRtLdsTabMax;
         }
-        const qcx::TileArgs a = tile_args(n, mb, P, int(tops.size()));
-        void *odev = nullptr, *sdev = nullptr;
-        int r2 = stage(c, tops.data(), tops.size() * sizeof(qcx::TileOp), hs, &odev);
-        if (!r2 && !slot_row.empty())
-            r2 = stage(c, slot_row.data(), slot_row.size() * sizeof(int32_t), hs, &sdev);
-        if (r2) return r2;
-        hipError_t e2 = qcx::launch_adjoint_tiles(psi.amp, lam.amp, psi.dtype, a,
-                                                  static_cast<const qcx::TileOp *>(odev),
-                                                  static_cast<const int32_t *>(sdev),
-                                                  int(slot_row.size()), partial, cols, hs);
+        if (L.rt) {
+            L.prog = append(rbuf.data(), rbuf.size());
+        } else {
+            L.ta = tile_args(n, mb, P, int(tops.size()));
+            L.prog = append(tops.data(), tops.size() * sizeof(qcx::TileOp));
+        }
+        L.slots = slot_row.empty() ? 0 : append(slot_row.data(), slot_row.size() * sizeof(int32_t));
+        launches.push_back(L);
         tops.clear();
         slot_row.clear();
-        return e2 == hipSuccess ? QC_OK : hip_fail(e2, "adjoint_tiles");
+        return QC_OK;
     };
     // the pending block of diagonal rotations and the blocks in the current
     // launch (16 lane tables at most)
@@ -3594,6 +3617,24 @@ int qc_adjoint_grad(qc_state_t psi, qc_state_t lam, const qc_op_t *ops, int n_op
         emit_dblk(B, r.P);
         B.finish();
         if ((rc = flush(r.P))) return rc;
+    }
+    if (!launches.empty()) {
+        void *bdev = nullptr;
+        if ((rc = stage(c, blob.data(), blob.size(), hs, &bdev))) return rc;
+        const unsigned char *base = static_cast<const unsigned char *>(bdev);
+        for (const BwdLaunch &L : launches) {
+            const int32_t *sl = L.n_slots ? reinterpret_cast<const int32_t *>(base + L.slots) : nullptr;
+            hipError_t e2;
+            if (L.rt)
+                e2 = qcx::launch_rt_adjoint(psi.amp, lam.amp, psi.dtype, L.ra,
+                                            reinterpret_cast<const qcx::RtOp *>(base + L.prog),
+                                            base + L.prog + L.tab_off, sl, L.n_slots, partial, cols, hs);
+            else
+                e2 = qcx::launch_adjoint_tiles(psi.amp, lam.amp, psi.dtype, L.ta,
+                                               reinterpret_cast<const qcx::TileOp *>(base + L.prog), sl,
+                                               L.n_slots, partial, cols, hs);
+            if (e2 != hipSuccess) return hip_fail(e2, L.rt ? "rt_adjoint" : "adjoint_tiles");
+        }
     }
     // grad[p] = sum of the rotation rows that use parameter p
     std::vector<int> csr(size_t(n_params) + 1 + size_t(n_rot), 0);

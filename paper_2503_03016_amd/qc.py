@@ -444,17 +444,32 @@ def autotune(scratch: torch.Tensor, gates: GateList, reps: int = 3) -> List[dict
     return [ents[i].as_dict() for i in range(cnt.value)]
 
 
+_OPS_MEMO = {}   # the last op list marshalled: id -> (snapshot, array, count)
+
+
 def make_ops(ops) -> Tuple[ctypes.Array, int]:
-    """qc_op_t array from workloads.Op entries of kinds RX/RY/RZ/H/X/Y/Z/CZ/CNOT."""
-    arr = (QcOp * max(1, len(ops)))()
-    for o, op in zip(arr, ops):
-        if op.kind not in OP_KIND:
+    """qc_op_t array from workloads.Op entries of kinds RX/RY/RZ/H/X/Y/Z/CZ/CNOT
+    (filled through one int32 array of the same layout).  The array of the
+    last list is kept and returned again while the list holds the same ops
+    (a gradient loop passes one list with new angles)."""
+    snap = tuple(ops)
+    hit = _OPS_MEMO.get(id(ops))
+    if hit is not None and hit[0] == snap:
+        return hit[1], hit[2]
+    flat = []
+    put = flat.extend
+    for op in snap:
+        kind = OP_KIND.get(op.kind)
+        if kind is None:
             raise ValueError("op kind %s is not supported by qc_adjoint_grad" % op.kind)
-        o.kind = OP_KIND[op.kind]
-        o.q0 = int(op.qubits[0])
-        o.q1 = int(op.qubits[1]) if len(op.qubits) > 1 else 0
-        o.param = int(op.pidx) if op.pidx is not None else -1
-    return arr, len(ops)
+        q = op.qubits
+        put((kind, q[0], q[1] if len(q) > 1 else 0, -1 if op.pidx is None else op.pidx))
+    buf = np.fromiter(flat if flat else (0, 0, 0, 0), dtype=np.int32)
+    assert 4 * 4 == ctypes.sizeof(QcOp)
+    arr = (QcOp * (buf.size // 4)).from_buffer(buf)   # keeps buf alive
+    _OPS_MEMO.clear()
+    _OPS_MEMO[id(ops)] = (snap, arr, len(snap))
+    return arr, len(snap)
 
 
 def adjoint_grad(psi: torch.Tensor, lam: torch.Tensor, ops, theta, terms):
