@@ -1817,6 +1817,21 @@ struct RtLowering {
     // such ops in a row on different slots: one RT_HFAN2 op and the second
     // one's data (the interpreter copies every element register once per
     // op, so fewer ops means fewer copies)
+    // the element factors of a fan on slot S depend only on the register
+    // bits above S: u at e equals u at e with the bits below S cleared
+    bool upper_only(const qcx::RtOp &op, int S) const {
+        for (int e = 0; e < E(); ++e) {
+            if (!((e >> S) & 1)) continue;
+            const int e0 = e & ~((1 << S) - 1);
+            for (int c = 0; c < 2; ++c) {
+                const bool same = is64() ? qcx::rt_vals<float>(op.u)[2 * e + c] == qcx::rt_vals<float>(op.u)[2 * e0 + c]
+                                         : op.u[2 * e + c] == op.u[2 * e0 + c];
+                if (!same) return false;
+            }
+        }
+        return true;
+    }
+
     void fuse_h_fan() {
         std::vector<qcx::RtOp> f;
         f.reserve(out.size());
@@ -1840,7 +1855,9 @@ struct RtLowering {
                 f[i + 2].kind == qcx::rt_code(qcx::RT_HFAN, 2) &&
                 f[i + 3].kind == qcx::rt_code(qcx::RT_HFAN, 3)) {
                 qcx::RtOp r = f[i];
-                r.kind = qcx::rt_code(qcx::RT_HFAN4, 0);
+                bool upper = rb == 4;
+                for (int k = 0; k < 4; ++k) upper = upper && upper_only(f[i + k], k);
+                r.kind = qcx::rt_code(upper ? qcx::RT_HFAN4U : qcx::RT_HFAN4, 0);
                 out.push_back(r);
                 for (int j = 1; j < 4; ++j) out.push_back(f[i + j]);   // data of the later steps
                 i += 3;

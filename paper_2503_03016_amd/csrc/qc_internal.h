@@ -253,6 +253,10 @@ enum RtKind {
     // and 3 in that order, with this op's fan data and the next three ops'
     // (data-only ops the interpreter skips)
     RT_HFAN4 = 22,
+    // RT_HFAN4 where the element factor of step k depends only on the
+    // register bits of slots above k (the QFT's fans: their in-register
+    // controls are the later targets), so step k forms 2^(3-k) products
+    RT_HFAN4U = 23,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

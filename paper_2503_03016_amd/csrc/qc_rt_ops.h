@@ -237,6 +237,21 @@ __device__ __forceinline__ void fan_slot(cx<R> *v, const RtOp &op, cx<R> f) {
         if ((e >> S) & 1) v[e] = cmul(cmul(f, ldu<R>(op.u, e)), v[e]);
 }
 
+// fan_slot when the element factor depends only on the register bits above
+// slot S (u[e] equals u at e with the bits below S cleared): one product
+// with f per distinct factor
+template <typename R, int RB, int S>
+__device__ __forceinline__ void fan_slot_upper(cx<R> *v, const RtOp &op, cx<R> f) {
+    constexpr int H = 1 << (RB - 1 - S);   // values of the bits above S
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int e1 = (h << (S + 1)) | (1 << S);
+        const cx<R> g = cmul(f, ldu<R>(op.u, e1));
+#pragma unroll
+        for (int lo = 0; lo < (1 << S); ++lo) v[e1 | lo] = cmul(g, v[e1 | lo]);
+    }
+}
+
 // a fan whose target is thread bit a: every element of the threads that
 // have it set
 template <typename R, int RB>
@@ -383,6 +398,19 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             QC_RT_HFAN2_CASE(1, 0) QC_RT_HFAN2_CASE(1, 2) QC_RT_HFAN2_CASE(1, 3)
             QC_RT_HFAN2_CASE(2, 0) QC_RT_HFAN2_CASE(2, 1) QC_RT_HFAN2_CASE(2, 3)
             QC_RT_HFAN2_CASE(3, 0) QC_RT_HFAN2_CASE(3, 1) QC_RT_HFAN2_CASE(3, 2)
+        case rt_code(RT_HFAN4U, 0):
+            if constexpr (RB == 4) {
+                h_slot<R, RB, 0>(v);
+                fan_slot_upper<R, RB, 0>(v, op, fan_factor<R>(op, tb, base));
+                h_slot<R, RB, 1>(v);
+                fan_slot_upper<R, RB, 1>(v, ops[o + 1], fan_factor<R>(ops[o + 1], tb, base));
+                h_slot<R, RB, 2>(v);
+                fan_slot_upper<R, RB, 2>(v, ops[o + 2], fan_factor<R>(ops[o + 2], tb, base));
+                h_slot<R, RB, 3>(v);
+                fan_slot_upper<R, RB, 3>(v, ops[o + 3], fan_factor<R>(ops[o + 3], tb, base));
+            }
+            o += 3;
+            break;
         case rt_code(RT_HFAN4, 0):
             if constexpr (RB >= 4) {
                 h_slot<R, RB, 0>(v);
