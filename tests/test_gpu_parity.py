@@ -334,6 +334,57 @@ def test_tiled_wide_complex128(qc, G, n):
         assert np.max(np.abs(host(t) - host(narrow))) < 1e-12
 
 
+def test_tiled_wide_lds_fallback(qc, G):
+    """A complex128 run in wide tiles whose controlled-phase fans carry more
+    lane tables than the register engine's LDS budget (24 fans, one lane
+    table each) runs on the LDS-resident engine
+    with 2^13-amplitude tiles (128 KiB of LDS), behind a register-tile run of
+    Hadamards whose deferred factor it applies; against the oracle and
+    against the same circuit in 2^12-amplitude tiles."""
+    n = 21
+    rng = np.random.default_rng(404)
+    ops = []
+    targets = [0, 1, 2, 3, 4, 5, 6, 7]          # qubits 0..7 = bits 20..13
+    # first a register-tile run with Hadamards (their 1/sqrt2 factors are
+    # left pending for the next run, here the LDS-engine one)
+    for q in range(13, 18):
+        ops.append(W.Op("H", (q,)))
+        if q < 17:
+            ops.append(W.Op("CP", (q + 1, q), angle=0.7))
+    for r in range(24):
+        q = targets[r % 8]
+        ops.append(W.Op("U", (q,), matrix=random_unitary(2, rng)))
+        # controls: the next two targets (the next gate then closes this
+        # fan) and one low-bit qubit
+        for c in (targets[(r + 1) % 8], targets[(r + 2) % 8], 16 + r % 5):
+            ops.append(W.Op("CP", (int(c), q), angle=float(rng.uniform(0, 6))))
+    psi0 = W.random_state(n, 405)
+    ref = oracle.run(ops, psi0)
+    gl = qc.GateList(G.gate_tuples(ops))
+    old_wide = qc.get_knob(qc.QC_KNOB_WIDE_MIN_TILES)
+    calls0, _ = qc.timing_query("tile_run_c128")
+    try:
+        qc.set_knob(qc.QC_KNOB_WIDE_MIN_TILES, 8)
+        t = dev(psi0, torch.complex128)
+        qc.timing_enable(True)
+        qc.apply_circuit(t, gl, mode=2)
+        torch.cuda.synchronize()
+        calls, _ = qc.timing_query("tile_run_c128")
+    finally:
+        qc.timing_enable(False)
+        qc.set_knob(qc.QC_KNOB_WIDE_MIN_TILES, old_wide)
+    assert calls > calls0, "the run did not take the LDS-resident engine"
+    check(host(t), ref, torch.complex128, ngates=len(ops))
+    narrow = dev(psi0, torch.complex128)
+    old = qc.get_knob(qc.QC_KNOB_TILE_BITS)
+    try:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, 12)
+        qc.apply_circuit(narrow, gl, mode=2)
+    finally:
+        qc.set_knob(qc.QC_KNOB_TILE_BITS, old)
+    assert np.max(np.abs(host(t) - host(narrow))) < 1e-12
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_tiled_plan_reuse(qc, G, dt):
     """A tiled circuit applied again reuses its plan: two applications of
