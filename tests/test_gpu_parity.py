@@ -386,6 +386,29 @@ def test_tiled_wide_lds_fallback(qc, G):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_tiled_hadamard_factor_before_standalone_gates(qc, G, dt):
+    """Register-tile runs of Hadamards separated by gates that no tile run
+    takes (three-qubit dense gates): the 1/sqrt2 factors a run leaves out
+    are applied before each such gate and at the end; against the oracle."""
+    n = 21
+    rng = np.random.default_rng(91)
+    ops = []
+    for block in range(3):
+        for q in rng.permutation(n)[:7]:
+            ops.append(W.Op("H", (int(q),)))
+            a, b = [int(x) for x in rng.permutation(n)[:2]]
+            ops.append(W.Op("CP", (a, b), angle=float(rng.uniform(0, 6))))
+        q3 = [int(x) for x in rng.permutation(n)[:3]]
+        ops.append(W.Op("U", tuple(q3), matrix=random_unitary(8, rng)))
+    ops.append(W.Op("H", (3,)))
+    psi0 = W.random_state(n, 92)
+    t = dev(psi0, DT[dt])
+    st = qc.apply_circuit(t, qc.GateList(G.gate_tuples(ops)), mode=2)
+    assert st["sweeps"] < len(ops)
+    check(host(t), oracle.run(ops, psi0), DT[dt], ngates=len(ops))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_tiled_plan_reuse(qc, G, dt):
     """A tiled circuit applied again reuses its plan: two applications of
     one gate list to fresh states, then the same list with one matrix
