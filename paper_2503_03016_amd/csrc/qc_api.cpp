@@ -1832,6 +1832,34 @@ struct RtLowering {
         return true;
     }
 
+    // backward programs: real-rotation gradient steps on slots 0, 1, 2 (or
+    // 0, 1) in a row become one op, the later steps kept as its data
+    void fuse_grads() {
+        std::vector<qcx::RtOp> f;
+        f.swap(out);
+        auto is_gr = [&](size_t i, int slot) {
+            return i < f.size() && f[i].kind == qcx::rt_code(qcx::RT_GRADR, slot);
+        };
+        for (size_t i = 0; i < f.size(); ++i) {
+            if (rb >= 3 && is_gr(i, 0) && is_gr(i + 1, 1) && is_gr(i + 2, 2)) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_code(qcx::RT_GRADR3, 0);
+                out.push_back(r);
+                out.push_back(f[i + 1]);
+                out.push_back(f[i + 2]);
+                i += 2;
+            } else if (rb >= 2 && is_gr(i, 0) && is_gr(i + 1, 1)) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_code(qcx::RT_GRADR2, 0);
+                out.push_back(r);
+                out.push_back(f[i + 1]);
+                i += 1;
+            } else {
+                out.push_back(f[i]);
+            }
+        }
+    }
+
     void fuse_h_fan() {
         std::vector<qcx::RtOp> f;
         f.reserve(out.size());
@@ -1975,6 +2003,7 @@ struct RtLowering {
         const RtLayout first = L;
         for (int i = 0; i < n_ops; ++i) lower(i);
         fuse_h_fan();
+        if (adjoint) fuse_grads();
         if (scale != 1.0 && !defer_scale) {
             qcx::RtOp r{};
             r.kind = qcx::rt_code(qcx::RT_SCALE, 0);

@@ -257,6 +257,11 @@ enum RtKind {
     // register bits of slots above k (the QFT's fans: their in-register
     // controls are the later targets), so step k forms 2^(3-k) products
     RT_HFAN4U = 23,
+    // backward only: RT_GRADR steps on register slots 0, 1, 2 (RT_GRADR3)
+    // or 0, 1 (RT_GRADR2) in that order, with this op's data and the next
+    // ops' (data-only ops the interpreter skips)
+    RT_GRADR3 = 24,
+    RT_GRADR2 = 25,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

@@ -574,6 +574,21 @@ __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, doubl
             QC_RT_SLOT_CASES(RT_GRADR, (grad_op<R, RB, S, 2>(vp, vl, gacc, op, tb.wave)))
             QC_RT_SLOT_CASES(RT_GRADD, (grad_op<R, RB, S, 3>(vp, vl, gacc, op, tb.wave)))
             QC_RT_SLOT_CASES(RT_GRAD2, (grad_op<R, RB, S, 4>(vp, vl, gacc, op, tb.wave)))
+        case rt_code(RT_GRADR3, 0):
+            if constexpr (RB >= 3) {
+                grad_op<R, RB, 0, 2>(vp, vl, gacc, op, tb.wave);
+                grad_op<R, RB, 1, 2>(vp, vl, gacc, ops[o + 1], tb.wave);
+                grad_op<R, RB, 2, 2>(vp, vl, gacc, ops[o + 2], tb.wave);
+            }
+            o += 2;
+            break;
+        case rt_code(RT_GRADR2, 0):
+            if constexpr (RB >= 2) {
+                grad_op<R, RB, 0, 2>(vp, vl, gacc, op, tb.wave);
+                grad_op<R, RB, 1, 2>(vp, vl, gacc, ops[o + 1], tb.wave);
+            }
+            o += 1;
+            break;
             QC_RT_SLOT_CASES2(RT_U1, (u1_slot<R, RB, S, false, false>(V, op, tc)))
             QC_RT_SLOT_CASES2(RT_U1C, (u1_slot<R, RB, S, false, true>(V, op, tc)))
             QC_RT_SLOT_CASES2(RT_U1R, (u1_slot<R, RB, S, true, false>(V, op, tc)))
