@@ -1860,6 +1860,26 @@ struct RtLowering {
         }
     }
 
+    // forward programs: unconditioned one-qubit steps on slots 0..3 (or
+    // 0..2) in a row become one op, the later steps kept as its data
+    void fuse_u1() {
+        std::vector<qcx::RtOp> f;
+        f.swap(out);
+        auto is_u1 = [&](size_t i, int slot) {
+            return i < f.size() && f[i].kind == qcx::rt_code(qcx::RT_U1, slot);
+        };
+        for (size_t i = 0; i < f.size(); ++i) {
+            const int len = rb >= 4 && is_u1(i, 0) && is_u1(i + 1, 1) && is_u1(i + 2, 2) && is_u1(i + 3, 3) ? 4
+                            : rb >= 3 && is_u1(i, 0) && is_u1(i + 1, 1) && is_u1(i + 2, 2)             ? 3
+                                                                                                    : 1;
+            qcx::RtOp r = f[i];
+            if (len > 1) r.kind = qcx::rt_code(len == 4 ? qcx::RT_U1X4 : qcx::RT_U1X3, 0);
+            out.push_back(r);
+            for (int j = 1; j < len; ++j) out.push_back(f[i + j]);
+            i += len - 1;
+        }
+    }
+
     void fuse_h_fan() {
         std::vector<qcx::RtOp> f;
         f.reserve(out.size());
@@ -2004,6 +2024,7 @@ struct RtLowering {
         for (int i = 0; i < n_ops; ++i) lower(i);
         fuse_h_fan();
         if (adjoint) fuse_grads();
+        else fuse_u1();
         if (scale != 1.0 && !defer_scale) {
             qcx::RtOp r{};
             r.kind = qcx::rt_code(qcx::RT_SCALE, 0);

@@ -262,6 +262,11 @@ enum RtKind {
     // ops' (data-only ops the interpreter skips)
     RT_GRADR3 = 24,
     RT_GRADR2 = 25,
+    // forward only: unconditioned RT_U1 steps on register slots 0, 1, 2, 3
+    // (RT_U1X4) or 0, 1, 2 (RT_U1X3) in that order, with this op's matrix
+    // and the next ops' (data-only ops the interpreter skips)
+    RT_U1X4 = 26,
+    RT_U1X3 = 27,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

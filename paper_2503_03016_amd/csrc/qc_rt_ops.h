@@ -398,6 +398,23 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             QC_RT_HFAN2_CASE(1, 0) QC_RT_HFAN2_CASE(1, 2) QC_RT_HFAN2_CASE(1, 3)
             QC_RT_HFAN2_CASE(2, 0) QC_RT_HFAN2_CASE(2, 1) QC_RT_HFAN2_CASE(2, 3)
             QC_RT_HFAN2_CASE(3, 0) QC_RT_HFAN2_CASE(3, 1) QC_RT_HFAN2_CASE(3, 2)
+        case rt_code(RT_U1X4, 0):
+            if constexpr (RB >= 4) {
+                u1_slot<R, RB, 0, false, false>(v, op, true);
+                u1_slot<R, RB, 1, false, false>(v, ops[o + 1], true);
+                u1_slot<R, RB, 2, false, false>(v, ops[o + 2], true);
+                u1_slot<R, RB, 3, false, false>(v, ops[o + 3], true);
+            }
+            o += 3;
+            break;
+        case rt_code(RT_U1X3, 0):
+            if constexpr (RB >= 3) {
+                u1_slot<R, RB, 0, false, false>(v, op, true);
+                u1_slot<R, RB, 1, false, false>(v, ops[o + 1], true);
+                u1_slot<R, RB, 2, false, false>(v, ops[o + 2], true);
+            }
+            o += 2;
+            break;
         case rt_code(RT_HFAN4U, 0):
             if constexpr (RB == 4) {
                 h_slot<R, RB, 0>(v);
