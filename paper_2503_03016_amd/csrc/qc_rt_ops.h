@@ -334,15 +334,28 @@ __device__ __forceinline__ void remap2(cx<R> *vp, cx<R> *vl, cx<R> *lds, const R
     }
     t_old = rt_swizzle<EB>(t_old);
     t_new = rt_swizzle<EB>(t_new);
+    // op.b: the exchange keeps every wavefront's bits (see remap), so each
+    // wavefront only ever touches its own LDS slots and in-order LDS
+    // operations replace the barriers
+    const bool waves_kept = op.b != 0;
+    auto order = [&]() {
+        if (waves_kept) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
         cx<R> *x = v ? vl : vp;
-        __syncthreads();
+        order();
         if (act) {
 #pragma unroll
             for (int e = 0; e < E; ++e) lds[t_old ^ op.w[16 + e]] = x[e];
         }
-        __syncthreads();
+        order();
         if (act) {
 #pragma unroll
             for (int e = 0; e < E; ++e) x[e] = lds[t_new ^ op.w[e]];
