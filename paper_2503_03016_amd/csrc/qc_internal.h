@@ -267,6 +267,10 @@ enum RtKind {
     // and the next ops' (data-only ops the interpreter skips)
     RT_U1X4 = 26,
     RT_U1X3 = 27,
+    // RT_GRADR3 (backward) / RT_U1X4 (forward) followed by the RT_REMAP op
+    // that comes after its data ops, in one interpreter step
+    RT_GRADR3X = 28,
+    RT_U1X4X = 29,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }
