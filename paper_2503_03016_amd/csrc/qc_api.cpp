@@ -1852,11 +1852,13 @@ struct RtLowering {
                 if (x) out.push_back(f[i + 3]);
                 i += x ? 3 : 2;
             } else if (rb >= 2 && is_gr(i, 0) && is_gr(i + 1, 1)) {
+                const bool x = i + 2 < f.size() && f[i + 2].kind == qcx::rt_code(qcx::RT_REMAP, 0);
                 qcx::RtOp r = f[i];
-                r.kind = qcx::rt_code(qcx::RT_GRADR2, 0);
+                r.kind = qcx::rt_code(x ? qcx::RT_GRADR2X : qcx::RT_GRADR2, 0);
                 out.push_back(r);
                 out.push_back(f[i + 1]);
-                i += 1;
+                if (x) out.push_back(f[i + 2]);
+                i += x ? 2 : 1;
             } else {
                 out.push_back(f[i]);
             }
@@ -1875,11 +1877,13 @@ struct RtLowering {
             const int len = rb >= 4 && is_u1(i, 0) && is_u1(i + 1, 1) && is_u1(i + 2, 2) && is_u1(i + 3, 3) ? 4
                             : rb >= 3 && is_u1(i, 0) && is_u1(i + 1, 1) && is_u1(i + 2, 2)             ? 3
                                                                                                     : 1;
-            // an exchange right behind four steps joins the op
-            const bool x = len == 4 && i + 4 < f.size() && f[i + 4].kind == qcx::rt_code(qcx::RT_REMAP, 0);
+            // an exchange right behind the steps joins the op
+            const bool x = (len == 4 || (len == 3 && rb == 3)) && i + len < f.size() &&
+                           f[i + len].kind == qcx::rt_code(qcx::RT_REMAP, 0);
             qcx::RtOp r = f[i];
             if (len > 1)
-                r.kind = qcx::rt_code(len == 4 ? (x ? qcx::RT_U1X4X : qcx::RT_U1X4) : qcx::RT_U1X3, 0);
+                r.kind = qcx::rt_code(len == 4 ? (x ? qcx::RT_U1X4X : qcx::RT_U1X4)
+                                               : (x ? qcx::RT_U1X3X : qcx::RT_U1X3), 0);
             out.push_back(r);
             for (int j = 1; j < len + (x ? 1 : 0); ++j) out.push_back(f[i + j]);
             i += len - 1 + (x ? 1 : 0);

@@ -271,6 +271,9 @@ enum RtKind {
     // that comes after its data ops, in one interpreter step
     RT_GRADR3X = 28,
     RT_U1X4X = 29,
+    // the same for RT_GRADR2 and RT_U1X3 (the latter in 8-register programs)
+    RT_GRADR2X = 30,
+    RT_U1X3X = 31,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

@@ -430,6 +430,15 @@ __device__ __forceinline__ void run_ops(cx<R> *v, cx<R> *lds, uint64_t base, uin
             }
             o += 4;
             break;
+        case rt_code(RT_U1X3X, 0):
+            if constexpr (RB == 3) {   // the host emits it for 8-register programs only
+                u1_slot<R, RB, 0, false, false>(v, op, true);
+                u1_slot<R, RB, 1, false, false>(v, ops[o + 1], true);
+                u1_slot<R, RB, 2, false, false>(v, ops[o + 2], true);
+                remap<R, RB>(v, lds, ops[o + 3], tid, act);
+            }
+            o += 3;
+            break;
         case rt_code(RT_U1X3, 0):
             if constexpr (RB >= 3) {
                 u1_slot<R, RB, 0, false, false>(v, op, true);
@@ -630,6 +639,14 @@ __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, doubl
                 remap2<R, RB>(vp, vl, lds, ops[o + 3], tid, act);
             }
             o += 3;
+            break;
+        case rt_code(RT_GRADR2X, 0):
+            if constexpr (RB >= 2) {
+                grad_op<R, RB, 0, 2>(vp, vl, gacc, op, tb.wave);
+                grad_op<R, RB, 1, 2>(vp, vl, gacc, ops[o + 1], tb.wave);
+                remap2<R, RB>(vp, vl, lds, ops[o + 2], tid, act);
+            }
+            o += 2;
             break;
         case rt_code(RT_GRADR2, 0):
             if constexpr (RB >= 2) {
