@@ -1833,7 +1833,9 @@ struct RtLowering {
     }
 
     // backward programs: real-rotation gradient steps on slots 0, 1, 2 (or
-    // 0, 1) in a row become one op, the later steps kept as its data
+    // 0, 1, or 1, 0) in a row become one op, the later steps kept as its
+    // data (with the exchange behind them, if any); so does a sign op with
+    // the diagonal-rotation block behind it
     void fuse_grads() {
         std::vector<qcx::RtOp> f;
         f.swap(out);
@@ -1859,6 +1861,19 @@ struct RtLowering {
                 out.push_back(f[i + 1]);
                 if (x) out.push_back(f[i + 2]);
                 i += x ? 2 : 1;
+            } else if (is_gr(i, 1) && is_gr(i + 1, 0)) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_code(qcx::RT_GRADR2R, 0);
+                out.push_back(r);
+                out.push_back(f[i + 1]);
+                i += 1;
+            } else if (f[i].kind == qcx::rt_code(qcx::RT_SIGN, 0) && i + 1 < f.size() &&
+                       f[i + 1].kind == qcx::rt_code(qcx::RT_DGRAD, 0)) {
+                qcx::RtOp r = f[i];
+                r.kind = qcx::rt_code(qcx::RT_SIGNDG, 0);
+                out.push_back(r);
+                out.push_back(f[i + 1]);
+                i += 1;
             } else {
                 out.push_back(f[i]);
             }

@@ -274,6 +274,10 @@ enum RtKind {
     // the same for RT_GRADR2 and RT_U1X3 (the latter in 8-register programs)
     RT_GRADR2X = 30,
     RT_U1X3X = 31,
+    // backward only: RT_GRADR steps on slots 1 then 0; an RT_SIGN op and the
+    // RT_DGRAD op behind it
+    RT_GRADR2R = 32,
+    RT_SIGNDG = 33,
 };
 constexpr int kRtThreadSlot = 7;
 __host__ __device__ constexpr int rt_code(int kind, int sub) { return kind * 8 + sub; }

@@ -569,6 +569,18 @@ __device__ __forceinline__ void grad_op(cx<R> *vp, cx<R> *vl, double *gacc, cons
     }
 }
 
+// RT_SIGN on both vectors
+template <typename R, int RB>
+__device__ __forceinline__ void sign2(cx<R> *vp, cx<R> *vl, const RtOp &op, const Tabs &tb, uint64_t base) {
+    const uint32_t L = terms_live(op, tb, base);
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        const uint32_t odd = uint32_t(__builtin_popcount(L & op.w[32 + e])) & 1u;
+        vp[e] = negate_if(vp[e], odd);
+        vl[e] = negate_if(vl[e], odd);
+    }
+}
+
 // RT_DGRAD (see qc_internal.h): the block's gradients from the vectors at
 // its start, then the product of its inverse rotations on both
 template <typename R, int RB>
@@ -673,15 +685,19 @@ __device__ __forceinline__ void run_ops2(cx<R> *vp, cx<R> *vl, cx<R> *lds, doubl
             u2<R, RB, true>(vp, op, tc);
             u2<R, RB, true>(vl, op, tc);
             break;
-        case rt_code(RT_SIGN, 0): {
-            const uint32_t L = terms_live(op, tb, base);
-#pragma unroll
-            for (int e = 0; e < (1 << RB); ++e) {
-                const uint32_t odd = uint32_t(__builtin_popcount(L & op.w[32 + e])) & 1u;
-                vp[e] = negate_if(vp[e], odd);
-                vl[e] = negate_if(vl[e], odd);
+        case rt_code(RT_SIGN, 0): sign2<R, RB>(vp, vl, op, tb, base); break;
+        case rt_code(RT_SIGNDG, 0):
+            sign2<R, RB>(vp, vl, op, tb, base);
+            dgrad<R, RB>(vp, vl, gacc, ops[o + 1], tb, base, tid);
+            o += 1;
+            break;
+        case rt_code(RT_GRADR2R, 0):
+            if constexpr (RB >= 2) {
+                grad_op<R, RB, 1, 2>(vp, vl, gacc, op, tb.wave);
+                grad_op<R, RB, 0, 2>(vp, vl, gacc, ops[o + 1], tb.wave);
             }
-        } break;
+            o += 1;
+            break;
         case rt_code(RT_TERMS, 0):
             terms<R, RB>(vp, op, tb, base);
             terms<R, RB>(vl, op, tb, base);
