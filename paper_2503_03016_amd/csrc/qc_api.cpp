@@ -2281,15 +2281,31 @@ int tiled_execute(qc_state_t s, int ng, const qc_gate_t *gs, qc_exec_stats_t &st
                     break;
                 }
         }
-        if (hit) {   // every program in one copy, then the launches back to back
-            void *bdev = nullptr;
-            if (!hit->blob.empty() &&
-                (rc = stage(c, hit->blob.data(), hit->blob.size(), (hipStream_t)stream, &bdev)))
-                return rc;
-            for (size_t i = 0; i < hit->runs.size(); ++i)
-                if ((rc = launch_plan_run(s, m, gs, hit->runs[i], c, st, stream,
-                                          static_cast<char *>(bdev) + hit->off[i])))
-                    return rc;
+        if (hit) {
+            // the first program in a copy of its own and its launch, then
+            // every later program in one copy (made while the first run is
+            // on the GPU) and their launches back to back
+            bool first = true;
+            char *rest = nullptr;   // the later programs on the device, from blob offset rest_off
+            size_t rest_off = 0;
+            for (size_t i = 0; i < hit->runs.size(); ++i) {
+                const TiledPlanRun &pr = hit->runs[i];
+                void *dev = nullptr;
+                if (pr.P != 0 && first) {
+                    first = false;   // staged by launch_plan_run
+                } else if (pr.P != 0) {
+                    if (!rest) {
+                        rest_off = hit->off[i];
+                        void *d = nullptr;
+                        if ((rc = stage(c, hit->blob.data() + rest_off, hit->blob.size() - rest_off,
+                                        (hipStream_t)stream, &d)))
+                            return rc;
+                        rest = static_cast<char *>(d);
+                    }
+                    dev = rest + (hit->off[i] - rest_off);
+                }
+                if ((rc = launch_plan_run(s, m, gs, pr, c, st, stream, dev))) return rc;
+            }
             return QC_OK;
         }
     }
