@@ -3088,11 +3088,25 @@ int expect_register_passes(qc_state_t s, int n_terms, const std::vector<uint64_t
                            int &slot, std::vector<int> &left) {
     std::vector<RegLaunch> launches;
     plan_register_passes(s.n, s.dtype, n_terms, xm, zm, ph, launches, left, true);
+    // every pass's terms in one copy
+    std::vector<unsigned char> blob;
+    std::vector<size_t> off;
     for (const RegLaunch &L : launches) {
-        for (size_t k = 0; k < L.ids.size(); ++k) where[L.ids[k]] = slot + int(k);
-        void *tdev = nullptr;
-        int rc = stage(c, L.terms.data(), L.terms.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
+        blob.resize((blob.size() + 255) & ~size_t(255));
+        off.push_back(blob.size());
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(L.terms.data());
+        blob.insert(blob.end(), b, b + L.terms.size() * sizeof(qcx::ExpRegTerm));
+    }
+    void *bdev = nullptr;
+    if (!launches.empty()) {
+        if (blob.empty()) blob.resize(16, 0);   // a valid device address for term-less passes
+        const int rc = stage(c, blob.data(), blob.size(), hs, &bdev);
         if (rc) return rc;
+    }
+    for (size_t i = 0; i < launches.size(); ++i) {
+        const RegLaunch &L = launches[i];
+        for (size_t k = 0; k < L.ids.size(); ++k) where[L.ids[k]] = slot + int(k);
+        const void *tdev = static_cast<const unsigned char *>(bdev) + off[i];
         hipError_t e = qcx::launch_expect_reg(s.amp, s.dtype, L.a,
                                               static_cast<const qcx::ExpRegTerm *>(tdev),
                                               vals + slot, part, hs);
