@@ -3055,16 +3055,33 @@ int pauli_apply(qc_state_t psi, qc_state_t lam, const std::vector<qcx::PauliTerm
         for (int t = 0; t < nt; ++t) left.push_back(t);
     }
     bool written = false;
+    // every pass's terms and coefficients in one copy
+    std::vector<unsigned char> blob(16, 0);   // a valid device address for term-less passes
+    std::vector<size_t> toff, coff;
+    auto append = [&](const void *p, size_t bytes) {
+        blob.resize((blob.size() + 255) & ~size_t(255));
+        const size_t at = blob.size();
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        blob.insert(blob.end(), b, b + bytes);
+        return at;
+    };
     for (const RegLaunch &L : launches) {
         std::vector<double> coef(L.ids.size());
         for (size_t k = 0; k < L.ids.size(); ++k) coef[k] = terms[L.ids[k]].c;
-        void *tdev = nullptr, *cdev = nullptr;
-        int rc = stage(c, L.terms.data(), L.terms.size() * sizeof(qcx::ExpRegTerm), hs, &tdev);
-        if (!rc) rc = stage(c, coef.data(), coef.size() * sizeof(double), hs, &cdev);
+        toff.push_back(append(L.terms.data(), L.terms.size() * sizeof(qcx::ExpRegTerm)));
+        coff.push_back(append(coef.data(), coef.size() * sizeof(double)));
+    }
+    void *bdev = nullptr;
+    if (!launches.empty()) {
+        const int rc = stage(c, blob.data(), blob.size(), hs, &bdev);
         if (rc) return rc;
+    }
+    for (size_t i = 0; i < launches.size(); ++i) {
+        const RegLaunch &L = launches[i];
+        const unsigned char *base = static_cast<const unsigned char *>(bdev);
         hipError_t e = qcx::launch_pauli_reg(psi.amp, lam.amp, psi.dtype, L.a,
-                                             static_cast<const qcx::ExpRegTerm *>(tdev),
-                                             static_cast<const double *>(cdev), written, hs);
+                                             reinterpret_cast<const qcx::ExpRegTerm *>(base + toff[i]),
+                                             reinterpret_cast<const double *>(base + coff[i]), written, hs);
         if (e != hipSuccess) return hip_fail(e, "pauli_reg");
         written = true;
     }
